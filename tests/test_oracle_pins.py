@@ -1,0 +1,338 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each check uses an independent route to the same numbers (GaKCo, Singh et
+al. 2017):
+  * the values printed in the Fig. 2 worked example;
+  * brute force over every g-mer pair (Hamming distances, Definition 1 and
+    Eq. 5), with C_m rebuilt by Eq. 8 and K by Eqs. 6-7;
+  * the gapped k-mer feature map of Eq. 4, enumerated explicitly;
+  * the k = g special case, which is the g-spectrum kernel of Eq. 3;
+  * the k = 0 whole-profile invariant (Eq. 8 at m = g);
+  * structural properties (symmetry, N_m >= 0, unit normalised diagonal,
+    positive semidefinite K) and invariances (sequence permutation, alphabet
+    relabelling);
+  * per-mask group tables against a dictionary grouping.
+Plausible slips in the oracle -- a dropped inclusion-exclusion term, a wrong
+binomial index, skipped singleton groups on the diagonal, a transposed
+output -- each break at least one of these.
+"""
+import itertools
+import json
+import math
+import os
+from collections import Counter, defaultdict
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1704_07468_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers --
+def split(seqs, lens):
+    out, off = [], 0
+    for l in lens:
+        out.append(np.asarray(seqs[off:off + l], dtype=np.int64))
+        off += int(l)
+    return out
+
+
+def bf_gmers(seq, g):
+    return [tuple(int(c) for c in seq[p:p + g]) for p in range(len(seq) - g + 1)] if len(seq) >= g else []
+
+
+def bf_hamming_profile(seqs, lens, g):
+    """N_d(X, Y) for d = 0..g by comparing every g-mer pair (Definition 1)."""
+    parts = split(seqs, lens)
+    N = len(parts)
+    gm = [np.array(bf_gmers(s, g), dtype=np.int64).reshape(-1, g) for s in parts]
+    prof = np.zeros((g + 1, N, N), dtype=np.int64)
+    for x in range(N):
+        for y in range(N):
+            if len(gm[x]) == 0 or len(gm[y]) == 0:
+                continue
+            d = (gm[x][:, None, :] != gm[y][None, :, :]).sum(axis=2)
+            prof[:, x, y] = np.bincount(d.ravel(), minlength=g + 1)
+    return prof
+
+
+def eq8_cumulative(prof, g, M):
+    """Eq. 8: C_m = sum_{d<=m} C(g-d, m-d) N_d."""
+    return np.stack([sum(math.comb(g - d, m - d) * prof[d] for d in range(m + 1)) for m in range(M + 1)])
+
+
+def eq7_kernel(prof, g, k):
+    """Eqs. 6-7 with N_d from brute force: K = sum_d C(g-d, k) N_d."""
+    return sum(math.comb(g - d, k) * prof[d] for d in range(g - k + 1))
+
+
+def feature_map_kernel(seqs, lens, g, k):
+    """Eq. 4: K(x,x') = sum over gapped k-mer features of c_x * c_x'."""
+    parts = split(seqs, lens)
+    feats = []
+    for s in parts:
+        c = Counter()
+        for gmer in bf_gmers(s, g):
+            for pos in itertools.combinations(range(g), k):
+                c[(pos, tuple(gmer[p] for p in pos))] += 1
+        feats.append(c)
+    N = len(parts)
+    K = np.zeros((N, N), dtype=np.int64)
+    for i in range(N):
+        for j in range(N):
+            a, b = feats[i], feats[j]
+            if len(a) > len(b):
+                a, b = b, a
+            K[i, j] = sum(v * b.get(f, 0) for f, v in a.items())
+    return K
+
+
+def cosine(K):
+    d = np.diag(K).astype(np.float64)
+    out = np.zeros(K.shape, dtype=np.float64)
+    nz = d > 0
+    out[np.ix_(nz, nz)] = K[np.ix_(nz, nz)] / np.sqrt(np.outer(d[nz], d[nz]))
+    return out
+
+
+def tiny_cases():
+    rng = np.random.default_rng(12345)
+    cases = []
+    for trial in range(10):
+        N = int(rng.integers(1, 7))
+        sigma = int(rng.choice([2, 3, 4, 5]))
+        g = int(rng.integers(2, 7))
+        seqs, lens = wl.random_small(rng, N, max(0, g - 2), 12, sigma)
+        for k in sorted({0, 1, g // 2, g - 1, g}):
+            cases.append((seqs, lens, g, k))
+    return cases
+
+
+# ------------------------------------------------------------ worked example --
+def load_fig2():
+    with open(os.path.join(GOLDEN, "fig2_worked_example.json")) as f:
+        fx = json.load(f)
+    enc = {c: i for i, c in enumerate(fx["alphabet"])}
+    s = np.array([enc[c] for c in fx["S"]], dtype=np.int8)
+    t = np.array([enc[c] for c in fx["T"]], dtype=np.int8)
+    return fx, enc, np.concatenate([s, t]), np.array([len(s), len(t)], dtype=np.int32)
+
+
+def test_fig2_gmers():
+    fx, enc, seqs, lens = load_fig2()
+    sym, sid = orc.gmers(seqs, lens, fx["g"])
+    dec = {v: k for k, v in enc.items()}
+    as_str = ["".join(dec[int(c)] for c in row) for row in sym]
+    assert [a for a, s in zip(as_str, sid) if s == 0] == fx["gmers_S"]
+    assert [a for a, s in zip(as_str, sid) if s == 1] == fx["gmers_T"]
+
+
+def test_fig2_printed_values():
+    fx, enc, seqs, lens = load_fig2()
+    C, Nm = orc.mismatch_profile(seqs, lens, fx["g"], 1)
+    assert Nm[0, 0, 1] == fx["N0_ST"]
+    assert C[1, 0, 1] == fx["C1_ST"]
+    assert Nm[1, 0, 1] == fx["N1_ST"]
+
+
+def test_fig2_gpairs1_groups():
+    """The printed g-pair_1 list: pairs of g-mers (one of S, one of T) at
+    Hamming distance exactly 1, with multiplicities."""
+    fx, enc, seqs, lens = load_fig2()
+    dec = {v: k for k, v in enc.items()}
+    parts = split(seqs, lens)
+    gs = [bf_gmers(p, fx["g"]) for p in parts]
+    pairs = Counter()
+    for a in gs[0]:
+        for b in gs[1]:
+            if sum(x != y for x, y in zip(a, b)) == 1:
+                pairs[("".join(dec[c] for c in a), "".join(dec[c] for c in b))] += 1
+    want = Counter()
+    for (ga, _, ca), (gb, _, cb) in fx["gpairs1"]:
+        want[(ga, gb)] += ca * cb
+    assert pairs == want
+    C, Nm = orc.mismatch_profile(seqs, lens, fx["g"], 1)
+    assert Nm[1, 0, 1] == sum(want.values())
+
+
+# ------------------------------------------------------------- brute force --
+@pytest.mark.parametrize("case", range(len(tiny_cases())))
+def test_bruteforce_pairwise(case):
+    seqs, lens, g, k = tiny_cases()[case]
+    M = g - k
+    prof = bf_hamming_profile(seqs, lens, g)
+    r = orc.kernel(seqs, lens, g, k)
+    np.testing.assert_array_equal(r["Nm"], prof[:M + 1])
+    np.testing.assert_array_equal(r["C"], eq8_cumulative(prof, g, M))
+    K = eq7_kernel(prof, g, k)
+    np.testing.assert_array_equal(r["K"], K)
+    np.testing.assert_allclose(r["Kn"], cosine(K), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("case", range(0, len(tiny_cases()), 3))
+def test_feature_map_eq4(case):
+    seqs, lens, g, k = tiny_cases()[case]
+    r = orc.kernel(seqs, lens, g, k)
+    np.testing.assert_array_equal(r["K"], feature_map_kernel(seqs, lens, g, k))
+
+
+def test_k_equals_g_is_spectrum_kernel():
+    rng = np.random.default_rng(7)
+    seqs, lens = wl.random_small(rng, 8, 3, 30, 3)
+    g = 4
+    r = orc.kernel(seqs, lens, g, g)
+    counts = [Counter(bf_gmers(s, g)) for s in split(seqs, lens)]
+    spec = np.array([[sum(v * b.get(f, 0) for f, v in a.items()) for b in counts] for a in counts])
+    np.testing.assert_array_equal(r["K"], spec)
+    np.testing.assert_array_equal(r["Nm"][0], spec)
+
+
+def test_k0_whole_profile_invariant():
+    rng = np.random.default_rng(8)
+    seqs, lens = wl.random_small(rng, 6, 2, 16, 4)
+    g = 4
+    C, Nm = orc.mismatch_profile(seqs, lens, g, g)
+    ng = np.array([max(0, l - g + 1) for l in lens], dtype=np.int64)
+    np.testing.assert_array_equal(C[g], np.outer(ng, ng))
+    np.testing.assert_array_equal(Nm.sum(axis=0), np.outer(ng, ng))
+
+
+def test_dna_config_full_bruteforce():
+    """The whole DNA workload (N=200, l=100, g=6, k=4) against pairwise
+    Hamming counting over all 19000^2 g-mer pairs."""
+    d = wl.dna()
+    g, k, M = d.g, d.k, d.M
+    r = orc.kernel(d.seqs, d.lens, g, k)
+    parts = split(d.seqs, d.lens)
+    gm = np.stack([np.lib.stride_tricks.sliding_window_view(p, g) for p in parts])  # [N, 95, g]
+    flat = gm.reshape(-1, g)
+    owner = np.repeat(np.arange(d.N), gm.shape[1])
+    for x in range(d.N):
+        dist = (gm[x][:, None, :] != flat[None, :, :]).sum(axis=2)  # [95, T]
+        for dd in range(M + 1):
+            hit = (dist == dd).sum(axis=0)
+            row = np.bincount(owner, weights=hit, minlength=d.N).astype(np.int64)
+            np.testing.assert_array_equal(r["Nm"][dd, x], row)
+
+
+# ---------------------------------------------------------------- structure --
+def test_structure_and_psd():
+    d = wl.dna(N=60)
+    r = orc.kernel(d.seqs, d.lens, d.g, d.k)
+    for m in range(d.M + 1):
+        np.testing.assert_array_equal(r["Nm"][m], r["Nm"][m].T)
+        np.testing.assert_array_equal(r["C"][m], r["C"][m].T)
+        assert (r["Nm"][m] >= 0).all()
+    np.testing.assert_array_equal(r["K"], r["K"].T)
+    np.testing.assert_allclose(np.diag(r["Kn"]), 1.0, rtol=0, atol=1e-15)
+    w = np.linalg.eigvalsh(r["K"].astype(np.float64))
+    assert w.min() >= -1e-9 * w.max()
+    ng = (d.lens - d.g + 1).astype(np.int64)
+    for m in range(d.M + 1):
+        assert (r["C"][m] <= math.comb(d.g, m) * np.outer(ng, ng)).all()
+
+
+def test_permutation_and_relabel_invariance():
+    rng = np.random.default_rng(11)
+    seqs, lens = wl.random_small(rng, 7, 4, 20, 5)
+    g, k = 5, 2
+    base = orc.kernel(seqs, lens, g, k)
+    parts = split(seqs, lens)
+    perm = rng.permutation(len(parts))
+    seqs_p = np.concatenate([parts[i] for i in perm]).astype(np.int8)
+    lens_p = lens[perm]
+    rp = orc.kernel(seqs_p, lens_p, g, k)
+    np.testing.assert_array_equal(rp["Nm"], base["Nm"][:, perm][:, :, perm])
+    relabel = rng.permutation(5)
+    rr = orc.kernel(relabel[seqs].astype(np.int8), lens, g, k)
+    np.testing.assert_array_equal(rr["Nm"], base["Nm"])
+
+
+def test_short_sequences_are_zero():
+    seqs = np.array([0, 1, 2, 3, 0, 1, 1, 2, 0], dtype=np.int8)
+    lens = np.array([5, 0, 2, 2], dtype=np.int32)  # only the first has g-mers at g=3
+    r = orc.kernel(seqs, lens, 3, 1)
+    assert r["K"][0, 0] > 0
+    assert (r["K"][1:, :] == 0).all() and (r["K"][:, 1:] == 0).all()
+    assert (r["Kn"][1:, :] == 0).all() and r["Kn"][0, 0] == 1.0
+
+
+# ----------------------------------------------------------------- per mask --
+def test_mask_groups_match_dictionary_grouping():
+    rng = np.random.default_rng(21)
+    seqs, lens = wl.random_small(rng, 9, 5, 25, 3)
+    g = 5
+    parts = split(seqs, lens)
+    allg = [(gm, x) for x, p in enumerate(parts) for gm in bf_gmers(p, g)]
+    for removed in [(), (0,), (4,), (1, 3), (0, 2, 4)]:
+        groups = orc.mask_groups(seqs, lens, g, removed)
+        want = defaultdict(Counter)
+        for gm, x in allg:
+            want[tuple(c for j, c in enumerate(gm) if j not in removed)][x] += 1
+        got = {}
+        for rep, ents in groups:
+            key = tuple(c for j, c in enumerate(allg[rep][0]) if j not in removed)
+            assert key not in got
+            assert [s for s, _ in ents] == sorted(s for s, _ in ents)
+            got[key] = Counter(dict(ents))
+        assert got == dict(want)
+        # per-mask total: sum_{X,Y} C^mask(X,Y) = sum_keys multiplicity^2
+        total = sum(sum(c.values()) ** 2 for c in want.values())
+        assert total == sum(sum(c for _, c in e) ** 2 for _, e in groups)
+
+
+def test_cumulative_is_sum_over_masks():
+    rng = np.random.default_rng(22)
+    seqs, lens = wl.random_small(rng, 5, 4, 14, 3)
+    g, M = 4, 2
+    C, _ = orc.mismatch_profile(seqs, lens, g, M)
+    N = len(lens)
+    for m in range(M + 1):
+        acc = np.zeros((N, N), dtype=np.int64)
+        for P in itertools.combinations(range(g), m):
+            for _, ents in orc.mask_groups(seqs, lens, g, P):
+                for sa, ca in ents:
+                    for sb, cb in ents:
+                        acc[sa, sb] += ca * cb
+        np.testing.assert_array_equal(C[m], acc)
+
+
+# --------------------------------------------------------------------- rows --
+def test_rows_match_gram_block_and_decision():
+    rng = np.random.default_rng(31)
+    sv_seqs, sv_lens = wl.random_small(rng, 9, 8, 30, 4)
+    q_seqs, q_lens = wl.random_small(rng, 4, 3, 40, 4)
+    g, k = 6, 3
+    alpha = rng.standard_normal(9)
+    r = orc.rows(sv_seqs, sv_lens, q_seqs, q_lens, g, k, alpha=alpha, bias=0.25)
+    allseqs = np.concatenate([sv_seqs, q_seqs])
+    alllens = np.concatenate([sv_lens, q_lens])
+    prof = bf_hamming_profile(allseqs, alllens, g)
+    K = eq7_kernel(prof, g, k)
+    Kn = cosine(K)
+    np.testing.assert_array_equal(r["Nm"], prof[:g - k + 1, 9:, :9])
+    np.testing.assert_allclose(r["Krows"], Kn[9:, :9], rtol=1e-14, atol=0)
+    dec = np.array([0.25 + sum(alpha[i] * Kn[9 + q, i] for i in range(9)) for q in range(4)])
+    np.testing.assert_allclose(r["decision"], dec, rtol=1e-13, atol=1e-15)
+
+
+def test_pair_entry_matches_full_gram():
+    d = wl.protein(N=40, lmin=20, lmax=60)
+    r = orc.kernel(d.seqs, d.lens, d.g, d.k)
+    for (x, y) in [(0, 1), (3, 17), (39, 2), (5, 5)]:
+        nm, K, kn = orc.pair_entry(d.seq(x), d.seq(y), d.g, d.k)
+        if x != y:
+            np.testing.assert_array_equal(nm, r["Nm"][:, x, y])
+            assert K == r["K"][x, y]
+            assert abs(kn - r["Kn"][x, y]) <= 1e-14 * abs(kn)
+
+
+def test_threaded_equals_sequential():
+    d = wl.protein(N=30, lmin=20, lmax=80)
+    a = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=1)
+    b = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=4)
+    np.testing.assert_array_equal(a["C"], b["C"])
+    np.testing.assert_array_equal(a["Kn"], b["Kn"])
