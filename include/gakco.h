@@ -1,0 +1,218 @@
+/*
+ * gakco.h -- C ABI of the MI355X (gfx950) gapped k-mer string kernel library.
+ *
+ * The library computes the GaKCo gapped k-mer kernel (Singh et al.,
+ * "GaKCo: a Fast Gapped k-mer string Kernel using Counting",
+ * arXiv:1704.07468) on one AMD Instinct MI355X:
+ *
+ *   g-mers     every contiguous length-g substring of every sequence
+ *              (Section 2.2, step 1).
+ *   C_m        cumulative mismatch profile: for each of the C(g,m) sets of m
+ *              positions, the positions are dropped from every g-mer, equal
+ *              reduced strings are grouped, and every pair of sequences (X,Y)
+ *              in a group gains count_X * count_Y  (Section 2.2, step 3;
+ *              Algorithm 1).
+ *   N_m        exact mismatch profile, N_m = C_m - sum_{j<m} C(g-j,m-j) N_j
+ *              (Eq. 9).
+ *   K          sum_{m=0}^{g-k} C(g-m,k) N_m  (Eqs. 6-7), reported cosine-
+ *              normalised in FP64: K_ij / sqrt(K_ii K_jj), 0 where a diagonal
+ *              entry is 0 (the paper's "normalized" counts, Eq. 3).
+ *
+ * Conventions shared by every entry point:
+ *   - Sequences are symbol codes in [0, sigma), one int8 per symbol, all
+ *     sequences concatenated; lens[i] is the length of sequence i.  Mapping
+ *     characters (including an unknown-character symbol, Section S:5.2) to
+ *     codes is the caller's job.
+ *   - Unless stated otherwise every pointer argument is a DEVICE pointer on
+ *     the context's device; the caller owns it.  No pointer is retained after
+ *     a call returns.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t, NULL = the default
+ *     stream) and the call synchronises that stream before it returns, so
+ *     data-dependent errors can be reported.  Outputs are unspecified when a
+ *     call fails.
+ *   - Matrices are row-major: Nm[m][i][j] at ((m*N)+i)*N+j.  M = g - k.
+ *   - Integer outputs are exact; the normalised kernel is FP64.
+ *   - Sequences shorter than g have no g-mers: their rows and columns are 0,
+ *     including the normalised diagonal.
+ *   - Symbol width b = max(1, ceil(log2 sigma)); g*b must be <= 64.
+ *
+ * Errors: every gakco_status-returning function returns GAKCO_OK (0) or a
+ * negative code; gakco_last_error() then gives a description for the calling
+ * thread.
+ */
+#ifndef GAKCO_H
+#define GAKCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gakco_status;
+#define GAKCO_OK 0
+#define GAKCO_EINVAL (-1)      /* bad argument (sizes, sigma, g, k, NULL pointers) */
+#define GAKCO_ERANGE (-2)      /* a symbol code outside [0, sigma)                 */
+#define GAKCO_EUNSUPPORTED (-3) /* a valid request outside the library's limits    */
+#define GAKCO_EBUDGET (-4)     /* scratch + outputs exceed the context's HBM budget */
+#define GAKCO_EHIP (-5)        /* a HIP runtime call failed                         */
+#define GAKCO_ECANCELLED (-6)  /* a serving request was cancelled                   */
+#define GAKCO_EAGAIN (-7)      /* serving: nothing to return yet / queue full       */
+
+/* Text for the last failing call made by this thread ("" if none). */
+const char *gakco_last_error(void);
+/* Library version string. */
+const char *gakco_version(void);
+
+/* ------------------------------------------------------------------------
+ * Context: a device, a grow-only scratch arena bounded by hbm_budget bytes
+ * (0 = half of the device's memory), and tuning parameters.
+ * tune_json (nullable) is a JSON object with any of the integer keys
+ *   "dense_tau"     minimum distinct sequences for a group to be summed by
+ *                   the int8 matrix-core path (0 disables that path)
+ *   "bucket_avg"    target g-mers per hash bucket of the partition sort
+ * Missing keys keep their defaults.  Not thread-safe: one context per host
+ * thread (serving uses its own internal contexts).
+ * ------------------------------------------------------------------------ */
+typedef struct gakco_ctx gakco_ctx;
+gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_json, gakco_ctx **out);
+void gakco_ctx_destroy(gakco_ctx *ctx);
+/* Set one tuning parameter by name (same keys as tune_json). */
+gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value);
+
+/* ------------------------------------------------------------------------
+ * gakco_gram -- the N x N kernel of one dataset (Algorithm 1 plus the
+ * normalisation).
+ *   seqs    int8  [sum(lens)]   symbol codes
+ *   lens    int32 [N]           sequence lengths (>= 0)
+ *   N       number of sequences, >= 1
+ *   sigma   alphabet size, 1..127
+ *   g, k    g >= 1, 0 <= k <= g
+ *   K_out   double [N][N]       normalised kernel (nullable)
+ *   Nm_out  int64 [g-k+1][N][N] exact mismatch profiles N_m (nullable)
+ *   Cm_out  int64 [g-k+1][N][N] cumulative profiles C_m (nullable)
+ * Returns GAKCO_EINVAL for bad sizes or NULL seqs/lens, GAKCO_ERANGE for a
+ * symbol outside [0, sigma), GAKCO_EUNSUPPORTED when g*b > 64 or a count
+ * bound of the kernels would be exceeded, GAKCO_EBUDGET when the scratch and
+ * outputs do not fit the context's budget, GAKCO_EHIP on a runtime failure.
+ * ------------------------------------------------------------------------ */
+gakco_status gakco_gram(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N,
+                        int32_t sigma, int32_t g, int32_t k, double *K_out, int64_t *Nm_out,
+                        int64_t *Cm_out, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Stage entry points (the first steps of the Gram path on their own; used for
+ * stage-level parity).
+ *
+ * gakco_extract: the g-mer array of Section 2.2 step 1.  keys_out[t] packs
+ * g-mer t with its first symbol most significant: sum_j x[p+j] << (b*(g-1-j));
+ * sid_out[t] is its sequence.  g-mers are in sequence order, then position
+ * order.  keys_out: uint64 [T], sid_out: int32 [T], T = sum max(0, l-g+1)
+ * (query it with gakco_count_gmers).  Device pointers.
+ * ------------------------------------------------------------------------ */
+gakco_status gakco_count_gmers(const int32_t *lens_host, int32_t N, int32_t g, int64_t *T_out);
+gakco_status gakco_extract(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N,
+                           int32_t sigma, int32_t g, uint64_t *keys_out, int32_t *sid_out,
+                           void *hip_stream);
+
+/* gakco_mask_groups: the groups of the sorted reduced list for ONE set of
+ * removed positions (Algorithm 1, removePosition + sort + the grouping of
+ * countAndUpdate).  removed_host: int32 [m] positions in [0, g) (HOST
+ * pointer).  Outputs are HOST arrays of capacity cap: group q owns entries
+ * [grp_off[q], grp_off[q+1]) of (ent_sid, ent_cnt), sorted by sequence;
+ * grp_rep[q] is the extraction index of one g-mer of the group; grp_off has
+ * cap+1 slots.  Group order is unspecified.  *n_groups_out receives the
+ * number of groups.  GAKCO_EINVAL if cap is too small. */
+gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N,
+                               int32_t sigma, int32_t g, const int32_t *removed_host, int32_t m,
+                               int32_t *grp_off, int32_t *grp_rep, int32_t *ent_sid,
+                               int32_t *ent_cnt, int64_t cap, int64_t *n_groups_out,
+                               void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched Gram jobs: every job of the list is planned together and all its
+ * position sets run in shared launches.  Pointers inside gakco_job are device
+ * pointers except status_out (HOST, nullable), which receives each job's
+ * status.  Returns the first failing job's status (or GAKCO_OK).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const int8_t *seqs;
+    const int32_t *lens;
+    int32_t N, sigma, g, k;
+    double *K_out;      /* [N][N], nullable             */
+    int64_t *Nm_out;    /* [g-k+1][N][N], nullable      */
+    gakco_status *status_out; /* host, nullable          */
+} gakco_job;
+gakco_status gakco_gram_batch(gakco_ctx *ctx, const gakco_job *jobs_host, int32_t n_jobs,
+                              void *hip_stream);
+
+/* A reusable plan for a fixed list of job shapes: planning reads the lengths
+ * once; gakco_batch_run replays the captured launch sequence (a hipGraph) on
+ * the jobs' current buffer contents.  The job buffers must stay valid and
+ * keep their shapes while the plan lives. */
+typedef struct gakco_batch_plan gakco_batch_plan;
+gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host, int32_t n_jobs,
+                                     void *hip_stream, gakco_batch_plan **out);
+gakco_status gakco_batch_run(gakco_batch_plan *plan, void *hip_stream);
+void gakco_batch_plan_destroy(gakco_batch_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Serving: a resident set (e.g. an SVM's support vectors) kept on the device
+ * as per-position-set group tables, and kernel rows of queries against it.
+ *
+ * gakco_resident_create copies the resident sequences (device pointers) and
+ * builds the tables; dual_coef (HOST, nullable) holds alpha_i*y_i of Eq. 1
+ * and bias is b.
+ * gakco_rows: for n_q queries (device q_seqs/q_lens), K_rows [n_q][n_sv]
+ * receives the normalised kernel rows K-hat(q, sv_i); Nm_rows (nullable)
+ * [g-k+1][n_q][n_sv] the exact mismatch profiles; decision (nullable) [n_q]
+ * f(q) = b + sum_i alpha_i K-hat(sv_i, q) (Eq. 1), summed in ascending i with
+ * a fixed per-query order so that a query's result does not depend on the
+ * other queries of the batch.
+ * ------------------------------------------------------------------------ */
+typedef struct gakco_resident gakco_resident;
+gakco_status gakco_resident_create(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens,
+                                   int32_t n_sv, int32_t sigma, int32_t g, int32_t k,
+                                   const double *dual_coef_host, double bias,
+                                   gakco_resident **out);
+void gakco_resident_destroy(gakco_resident *res);
+gakco_status gakco_resident_info(const gakco_resident *res, int32_t *n_sv, int32_t *sigma,
+                                 int32_t *g, int32_t *k, size_t *device_bytes);
+gakco_status gakco_rows(gakco_ctx *ctx, const gakco_resident *res, const int8_t *q_seqs,
+                        const int32_t *q_lens, int32_t n_q, double *K_rows, int64_t *Nm_rows,
+                        double *decision, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching server over a resident set.  Queries are HOST arrays
+ * (copied at submit).  A scheduler thread admits queued requests into device
+ * batches whenever a batch slot and HBM budget are free, so requests that
+ * arrive while others run are admitted as capacity frees up; up to
+ * `n_streams` batches are in flight on separate HIP streams.  Results are
+ * returned by gakco_server_poll in completion order; K_row points into
+ * server-owned memory that stays valid until the next poll on this server.
+ * Timestamps are seconds on a monotonic clock.
+ * ------------------------------------------------------------------------ */
+typedef struct gakco_server gakco_server;
+typedef struct {
+    uint64_t tag;
+    gakco_status status;
+    double decision;
+    const double *K_row; /* [n_sv] host memory, NULL if cancelled */
+    double t_submit, t_start, t_done;
+    int32_t batch_size;  /* number of queries in the device batch that ran it */
+} gakco_result;
+gakco_status gakco_server_create(const gakco_resident *res, int32_t device, int32_t max_batch,
+                                 int32_t n_streams, size_t hbm_budget, gakco_server **out);
+gakco_status gakco_server_submit(gakco_server *srv, const int8_t *q_host, int32_t len, uint64_t tag);
+gakco_status gakco_server_cancel(gakco_server *srv, uint64_t tag);
+gakco_status gakco_server_poll(gakco_server *srv, gakco_result *out, int32_t max, int32_t *n_out,
+                               int32_t wait_us);
+/* Stops admission, finishes in-flight batches, cancels what is still queued
+ * and frees everything. */
+gakco_status gakco_server_destroy(gakco_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GAKCO_H */

@@ -1,0 +1,230 @@
+// C ABI of the library: context, Gram, stage entry points.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+
+#include "launch.h"
+#include "plan.h"
+
+namespace gk {
+const char *last_error();
+void clear_error();
+hipError_t init_kernel_attributes(size_t acc_lds);
+}  // namespace gk
+
+using namespace gk;
+
+static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
+{
+    if (!strcmp(name, "dense_tau")) {
+        if (v < 0) { set_error("dense_tau must be >= 0"); return GAKCO_EINVAL; }
+        ctx->dense_tau = (int)v;
+    } else if (!strcmp(name, "bucket_avg")) {
+        if (v < 16 || v > kSortCap) { set_error("bucket_avg must be in 16..%d", kSortCap); return GAKCO_EINVAL; }
+        ctx->bucket_avg = (int)v;
+    } else {
+        set_error("unknown parameter '%s'", name);
+        return GAKCO_EINVAL;
+    }
+    return GAKCO_OK;
+}
+
+// Minimal reader of a flat JSON object of integer values.
+static gakco_status apply_json(gakco_ctx *ctx, const char *js)
+{
+    const char *p = js;
+    while ((p = strchr(p, '"')) != nullptr) {
+        const char *q = strchr(p + 1, '"');
+        if (!q) break;
+        std::string key(p + 1, (size_t)(q - p - 1));
+        const char *c = strchr(q, ':');
+        if (!c) break;
+        char *end = nullptr;
+        const long long v = strtoll(c + 1, &end, 10);
+        if (end == c + 1) { set_error("tune json: value of '%s' is not an integer", key.c_str()); return GAKCO_EINVAL; }
+        GK_TRY(apply_param(ctx, key.c_str(), v));
+        p = end;
+    }
+    return GAKCO_OK;
+}
+
+extern "C" {
+
+const char *gakco_last_error(void) { return last_error(); }
+const char *gakco_version(void) { return "gakco-mi355x 0.1 (gfx950)"; }
+
+gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_json, gakco_ctx **out)
+{
+    clear_error();
+    if (!out) { set_error("out is NULL"); return GAKCO_EINVAL; }
+    *out = nullptr;
+    int ndev = 0;
+    GK_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) { set_error("device %d out of range (%d devices)", device, ndev); return GAKCO_EINVAL; }
+    GK_HIP(hipSetDevice(device));
+    size_t total = 0;
+    GK_HIP(hipDeviceTotalMem(&total, device));
+    int lds = 0;
+    GK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    auto *ctx = new gakco_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget ? hbm_budget : total / 2;
+    // the row accumulation keeps ~5 KB of static LDS next to its rows
+    ctx->lds_max = (size_t)lds > 8192 ? (size_t)lds - 8192 : 0;
+    if (tune_json) {
+        gakco_status s = apply_json(ctx, tune_json);
+        if (s != GAKCO_OK) { delete ctx; return s; }
+    }
+    if (init_kernel_attributes(ctx->lds_max) != hipSuccess) {
+        set_error("hipFuncSetAttribute failed");
+        delete ctx;
+        return GAKCO_EHIP;
+    }
+    *out = ctx;
+    return GAKCO_OK;
+}
+
+void gakco_ctx_destroy(gakco_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->arena) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->arena);
+    }
+    delete ctx;
+}
+
+gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value)
+{
+    clear_error();
+    if (!ctx || !name) { set_error("ctx/name is NULL"); return GAKCO_EINVAL; }
+    return apply_param(ctx, name, value);
+}
+
+gakco_status gakco_count_gmers(const int32_t *lens_host, int32_t N, int32_t g, int64_t *T_out)
+{
+    clear_error();
+    if (!T_out || N < 0 || g < 1 || (N > 0 && !lens_host)) { set_error("bad arguments"); return GAKCO_EINVAL; }
+    int64_t T = 0;
+    for (int i = 0; i < N; ++i) {
+        if (lens_host[i] < 0) { set_error("lens[%d] is negative", i); return GAKCO_EINVAL; }
+        T += lens_host[i] >= g ? lens_host[i] - g + 1 : 0;
+    }
+    *T_out = T;
+    return GAKCO_OK;
+}
+
+gakco_status gakco_gram(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma, int32_t g,
+                        int32_t k, double *K_out, int64_t *Nm_out, int64_t *Cm_out, void *hip_stream)
+{
+    clear_error();
+    if (!ctx) { set_error("ctx is NULL"); return GAKCO_EINVAL; }
+    GK_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Plan p;
+    p.jobs.resize(1);
+    JobPlan &jp = p.jobs[0];
+    jp.seqs = seqs; jp.lens_dev = lens; jp.N = N; jp.sigma = sigma; jp.g = g; jp.k = k;
+    jp.K_out = K_out; jp.Nm_out = Nm_out; jp.Cm_out = Cm_out;
+    if (N < 1) { set_error("N must be >= 1 (got %d)", N); return GAKCO_EINVAL; }
+    if (!seqs || !lens) { set_error("seqs and lens must not be NULL"); return GAKCO_EINVAL; }
+    GK_TRY(fetch_lens(jp, st));
+    GK_TRY(plan_shape(ctx, jp, nullptr, 0));
+    GK_TRY(plan_layout(ctx, p));
+    GK_TRY(plan_bind(ctx, p));
+    GK_TRY(plan_upload(p, st));
+    GK_TRY(plan_launch(ctx, p, st));
+    return plan_check_errors(p, st);
+}
+
+gakco_status gakco_extract(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma, int32_t g,
+                           uint64_t *keys_out, int32_t *sid_out, void *hip_stream)
+{
+    clear_error();
+    if (!ctx) { set_error("ctx is NULL"); return GAKCO_EINVAL; }
+    GK_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Plan p;
+    p.jobs.resize(1);
+    JobPlan &jp = p.jobs[0];
+    jp.seqs = seqs; jp.lens_dev = lens; jp.N = N; jp.sigma = sigma; jp.g = g; jp.k = g;
+    jp.want_kernel = false;
+    if (N < 1 || !seqs || !lens) { set_error("bad arguments"); return GAKCO_EINVAL; }
+    GK_TRY(fetch_lens(jp, st));
+    GK_TRY(plan_shape(ctx, jp, nullptr, 0));
+    jp.masks.clear();  // extraction only
+    if (jp.T && (!keys_out || !sid_out)) { set_error("keys_out/sid_out must not be NULL"); return GAKCO_EINVAL; }
+    jp.key_override = keys_out;
+    jp.sid_override = reinterpret_cast<uint32_t *>(sid_out);
+    GK_TRY(plan_layout(ctx, p));
+    GK_TRY(plan_bind(ctx, p));
+    GK_TRY(plan_upload(p, st));
+    GK_TRY(plan_launch(ctx, p, st));
+    return plan_check_errors(p, st);
+}
+
+gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma,
+                               int32_t g, const int32_t *removed_host, int32_t m, int32_t *grp_off, int32_t *grp_rep,
+                               int32_t *ent_sid, int32_t *ent_cnt, int64_t cap, int64_t *n_groups_out, void *hip_stream)
+{
+    clear_error();
+    if (!ctx) { set_error("ctx is NULL"); return GAKCO_EINVAL; }
+    if (m < 0 || m > g || (m > 0 && !removed_host) || !grp_off || !grp_rep || !ent_sid || !ent_cnt || !n_groups_out) {
+        set_error("bad arguments");
+        return GAKCO_EINVAL;
+    }
+    GK_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    Plan p;
+    p.jobs.resize(1);
+    JobPlan &jp = p.jobs[0];
+    jp.seqs = seqs; jp.lens_dev = lens; jp.N = N; jp.sigma = sigma; jp.g = g; jp.k = g - m;
+    jp.want_kernel = false;
+    if (N < 1 || !seqs || !lens) { set_error("bad arguments"); return GAKCO_EINVAL; }
+    GK_TRY(fetch_lens(jp, st));
+    static const int32_t none[1] = {0};
+    GK_TRY(plan_shape(ctx, jp, m ? removed_host : none, m));
+    GK_TRY(plan_layout(ctx, p));
+    GK_TRY(plan_bind(ctx, p));
+    GK_TRY(plan_upload(p, st));
+    GK_TRY(plan_launch(ctx, p, st));
+    GK_TRY(plan_check_errors(p, st));
+    const MaskWork &W = p.mw[0];
+    const uint32_t T = jp.T;
+    std::vector<uint32_t> E(T);
+    std::vector<uint2> info(T);
+    if (T) {
+        GK_HIP(hipMemcpyAsync(E.data(), W.E, (size_t)T * 4, hipMemcpyDeviceToHost, st));
+        GK_HIP(hipMemcpyAsync(info.data(), W.info, (size_t)T * 8, hipMemcpyDeviceToHost, st));
+        GK_HIP(hipStreamSynchronize(st));
+    }
+    // a group is [first entry, end): its first entry's leader has the
+    // longest tail; every leader of the group shares the same end
+    std::map<uint32_t, std::pair<uint32_t, uint32_t>> groups;  // end -> (first entry, rep g-mer)
+    for (uint32_t t = 0; t < T; ++t) {
+        if (!info[t].y) continue;
+        const uint32_t end = info[t].x + info[t].y;
+        auto it = groups.find(end);
+        if (it == groups.end() || info[t].x < it->second.first) groups[end] = {info[t].x, t};
+    }
+    const uint32_t sidmask = (uint32_t)((1ull << jp.sb) - 1);
+    int64_t ng = 0, ne = 0;
+    grp_off[0] = 0;
+    for (auto &kv : groups) {
+        const uint32_t a = kv.second.first, b = kv.first;
+        if (ng + 1 > cap || ne + (int64_t)(b - a) > cap) { set_error("cap %lld too small", (long long)cap); return GAKCO_EINVAL; }
+        grp_rep[ng] = (int32_t)kv.second.second;
+        for (uint32_t e = a; e < b; ++e, ++ne) {
+            ent_sid[ne] = (int32_t)(E[e] & sidmask);
+            ent_cnt[ne] = (int32_t)(E[e] >> jp.sb);
+        }
+        ++ng;
+        grp_off[ng] = (int32_t)ne;
+    }
+    *n_groups_out = ng;
+    return GAKCO_OK;
+}
+
+}  // extern "C"

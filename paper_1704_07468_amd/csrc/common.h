@@ -1,0 +1,323 @@
+// Device-side data structures and block-level primitives of the gfx950
+// gapped k-mer kernel library.  Wave size is 64 everywhere; blocks have
+// kThreads = 256 threads (4 waves).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gk {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxRuns = 33;     // kept positions form at most min(g-m, m+1) <= 33 runs (g <= 64)
+constexpr int kTile = 2048;      // g-mers per block in the partition kernels
+constexpr int kMaxBucketBits = 12;
+constexpr int kSortCap = 2048;   // bucket size sorted entirely in LDS
+
+// One set of removed positions ("mask"), as the runs of kept symbol fields:
+// reduced = OR_r ((key >> src[r]) & (2^wid[r]-1)) << dst[r].  The kept
+// symbols keep their order, first kept symbol most significant, so equal
+// reduced keys <=> equal (g-m)-mers (Section 2.2, step 3).
+struct MaskDesc {
+    int32_t level;  // m
+    int32_t nrun;
+    uint8_t rsrc[kMaxRuns];
+    uint8_t rwid[kMaxRuns];
+    uint8_t rdst[kMaxRuns];
+};
+
+// Per-dataset ("job") state.
+struct JobDev {
+    const int8_t *seqs;      // concatenated symbol codes
+    const int64_t *seq_off;  // [N+1] symbol offset of each sequence
+    const uint32_t *gstart;  // [N+1] first g-mer of each sequence
+    int32_t N, sigma, g, k, M, b, sb;  // sb = bits of a sequence id
+    uint32_t T;              // number of g-mers
+    int64_t nsym;            // total symbols
+    uint64_t *key;           // [T] packed g-mers, first symbol most significant
+    uint32_t *sid;           // [T] sequence of each g-mer
+    int32_t *err;            // bit 0: a symbol outside [0, sigma)
+    int64_t *C;              // [M+1][N][N] cumulative profiles (upper triangle accumulated)
+    int64_t *Kd;             // [N] unnormalised K diagonal
+    const int64_t *coef;     // [(M+1)*(M+1)] C(g-j, m-j) at [m*(M+1)+j]
+    const int64_t *hco;      // [M+1] C(g-m, k)
+    double *K_out;
+    int64_t *Nm_out;
+    int64_t *Cm_out;
+};
+
+// Per (job, mask) work of the partition sort and its outputs.
+struct MaskWork {
+    MaskDesc md;
+    int32_t job;
+    uint32_t T;
+    int32_t w;   // bits of the reduced key
+    int32_t B;   // bucket bits (top bits of the hashed reduced key)
+    int32_t hb;  // remaining hash bits, w - B
+    int32_t sb;  // sequence-id bits
+    int32_t cb;  // composite sort bits, hb + sb
+    const uint64_t *key;
+    const uint32_t *sid;
+    uint32_t *bcnt;   // [2^B]
+    uint32_t *boff;   // [2^B + 1]
+    uint32_t *bcur;   // [2^B]
+    uint64_t *comp;   // [T] composite (hash rest, sequence) of each bucketed g-mer
+    uint32_t *idx;    // [T] its g-mer index
+    uint64_t *comp2;  // [T] ping-pong buffers for buckets sorted in global memory
+    uint32_t *idx2;   // [T]
+    uint32_t *E;      // [T] run entries: sequence | count << sb, grouped, sequence-sorted
+    uint2 *info;      // [T] per g-mer: (entry index, entries to group end) for run leaders
+    // int8 matrix-core path for groups with many distinct sequences
+    int8_t *D;         // rows of Npad counts (nullable)
+    uint32_t *dcount;  // rows used
+    uint32_t dcap;
+    int32_t Npad;
+    int32_t tau;       // min distinct sequences of a dense group (0 = off)
+};
+
+// Row accumulation work: rows of one job over a range of masks.
+struct AccWork {
+    int32_t job;
+    int32_t mfirst;  // first MaskWork index
+    int32_t nmask;
+    int32_t lev0, nlev;
+    int32_t Npad;    // LDS row stride
+};
+
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+__device__ __forceinline__ uint64_t bits_mask(int w) { return (w >= 64) ? ~0ull : ((1ull << w) - 1ull); }
+
+// Bijection on w-bit integers (odd multiplies and right xor-shifts, each
+// invertible modulo 2^w).  Equal inputs <=> equal outputs, and the top bits
+// spread skewed key distributions evenly over the buckets.
+__device__ __forceinline__ uint64_t mix_w(uint64_t x, int w)
+{
+    if (w <= 0) return 0;
+    const uint64_t m = bits_mask(w);
+    const int s = (w + 1) >> 1;
+    x = (x * 0x9E3779B97F4A7C15ull) & m;
+    x ^= x >> s;
+    x = (x * 0xC2B2AE3D27D4EB4Full) & m;
+    x ^= x >> s;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t compact_key(uint64_t key, const MaskDesc &md)
+{
+    uint64_t r = 0;
+    for (int i = 0; i < md.nrun; ++i)
+        r |= ((key >> md.rsrc[i]) & bits_mask(md.rwid[i])) << md.rdst[i];
+    return r;
+}
+
+// Index i with prefix[i] <= v < prefix[i+1]; prefix has n+1 entries.
+__device__ __forceinline__ int find_item(const uint32_t *prefix, int n, uint32_t v)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    const int l = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+// Block-wide exclusive scan of one value per thread (kThreads threads).
+// Contains two barriers; every thread of the block must call it.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    const uint32_t inc = wave_incl_scan(v);
+    const int wid = threadIdx.x >> 6;
+    if (__lane_id() == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t s = wsum[w];
+        pre += (w < wid) ? s : 0u;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc - v;
+}
+
+struct SortScratch {
+    uint32_t hist[256];
+    uint32_t base[256];
+    uint32_t wcnt[kWaves][256];
+    uint32_t wsum[kWaves];
+};
+
+// Stable LSD radix sort of n (key, value) pairs by the low `bits` bits of the
+// key, 8 bits per pass, ping-ponging between (k0,v0) and (k1,v1).  Each pass:
+// an LDS digit histogram, a block scan of it, then rounds of 256 elements in
+// which every wave ranks its lanes by digit with ballots (the lanes holding
+// the same digit form a ballot mask; a lane's rank is the population count of
+// that mask below it) and the waves' digit counts are combined in LDS.
+// `which` says where the data is on entry (0: k0/v0) and is updated.
+// Passes whose digit is the same for every element are skipped.
+template <typename KP, typename VP>
+__device__ __forceinline__ void block_radix_sort(KP k0, VP v0, KP k1, VP v1, uint32_t n, int bits,
+                                                 SortScratch &s, int &which)
+{
+    const int tid = threadIdx.x, wid = tid >> 6;
+    for (int shift = 0; shift < bits; shift += 8) {
+        KP sk = which ? k1 : k0;
+        VP sv = which ? v1 : v0;
+        KP dk = which ? k0 : k1;
+        VP dv = which ? v0 : v1;
+        s.hist[tid] = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s.wcnt[w][tid] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kThreads)
+            atomicAdd(&s.hist[(uint32_t)(sk[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        const uint32_t c = s.hist[tid];
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(c, s.wsum, &tot);
+        if (__syncthreads_or(c == n)) continue;  // one digit only: order unchanged
+        s.base[tid] = ex;
+        __syncthreads();
+        for (uint32_t r0 = 0; r0 < n; r0 += kThreads) {
+            const uint32_t i = r0 + tid;
+            const bool valid = i < n;
+            const uint64_t kk = valid ? (uint64_t)sk[i] : 0ull;
+            const uint32_t vv = valid ? (uint32_t)sv[i] : 0u;
+            const uint32_t d = (uint32_t)(kk >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb) {
+                const uint64_t m = __ballot((d >> bb) & 1u);
+                peers &= ((d >> bb) & 1u) ? m : ~m;
+            }
+            const uint32_t rank = __popcll(peers & lanemask_lt());
+            if (valid && rank == 0) s.wcnt[wid][d] = __popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t off = s.base[d];
+                for (int w = 0; w < wid; ++w) off += s.wcnt[w][d];
+                dk[off + rank] = kk;
+                dv[off + rank] = vv;
+            }
+            __syncthreads();
+            uint32_t add = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                add += s.wcnt[w][tid];
+                s.wcnt[w][tid] = 0;
+            }
+            s.base[tid] += add;
+            __syncthreads();
+        }
+        which ^= 1;
+    }
+}
+
+// Largest i in [0, n) with a[i] <= v (a ascending, a[0] <= v).
+template <typename UP>
+__device__ __forceinline__ uint32_t last_le(UP a, uint32_t n, uint32_t v)
+{
+    uint32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Segment a bucket sorted by (hash rest, sequence): runs of equal composite
+// are one (reduced g-mer, sequence) pair; groups of equal hash rest are one
+// reduced g-mer.  Writes one run entry (sequence | count << sb) per run into
+// E[ebase + r] -- so each group's entries are contiguous and sequence-sorted
+// -- and for every g-mer its info: the leader of a run (its first element)
+// gets (entry index, entries left to the group end), every other g-mer
+// (0, 0).  Groups with at least tau distinct sequences and counts <= 127
+// become rows of the int8 matrix-core path instead (info length 0).
+// rpos, gsr, gaux: scratch of n entries each.
+template <typename KP, typename VP, typename UP>
+__device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos, UP gsr, UP gaux,
+                                              const MaskWork &W, uint32_t ebase, uint32_t *wsum)
+{
+    const int tid = threadIdx.x;
+    const int sb = W.sb;
+    const uint64_t sidmask = bits_mask(sb);
+    // runs
+    uint32_t R = 0;
+    for (uint32_t r0 = 0; r0 < n; r0 += kThreads) {
+        const uint32_t i = r0 + tid;
+        const bool rs = (i < n) && (i == 0 || fk[i] != fk[i - 1]);
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(rs ? 1u : 0u, wsum, &tot);
+        if (rs) rpos[R + ex] = i;
+        R += tot;
+    }
+    __syncthreads();
+    // groups (in run indices)
+    uint32_t G = 0;
+    for (uint32_t r0 = 0; r0 < R; r0 += kThreads) {
+        const uint32_t r = r0 + tid;
+        const bool gs = (r < R) && (r == 0 || (fk[rpos[r]] >> sb) != (fk[rpos[r - 1]] >> sb));
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(gs ? 1u : 0u, wsum, &tot);
+        if (gs) gsr[G + ex] = r;
+        G += tot;
+    }
+    __syncthreads();
+    const bool dense_on = (W.tau > 0) && (W.D != nullptr);
+    if (dense_on) {
+        for (uint32_t gi = tid; gi < G; gi += kThreads) gaux[gi] = 0;
+        __syncthreads();
+        for (uint32_t r = tid; r < R; r += kThreads) {
+            const uint32_t pe = (r + 1 < R) ? rpos[r + 1] : n;
+            atomicMax(&gaux[last_le(gsr, G, r)], pe - rpos[r]);
+        }
+        __syncthreads();
+        for (uint32_t gi = tid; gi < G; gi += kThreads) {
+            const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
+            uint32_t row = 0xFFFFFFFFu;
+            if (re - gsr[gi] >= (uint32_t)W.tau && gaux[gi] <= 127u) {
+                row = atomicAdd(W.dcount, 1u);
+                if (row >= W.dcap) row = 0xFFFFFFFFu;
+            }
+            gaux[gi] = row;
+        }
+        __syncthreads();
+    }
+    for (uint32_t r = tid; r < R; r += kThreads) {
+        const uint32_t p = rpos[r];
+        const uint32_t pe = (r + 1 < R) ? rpos[r + 1] : n;
+        const uint32_t cnt = pe - p;
+        const uint32_t sid = (uint32_t)(fk[p] & sidmask);
+        const uint32_t gi = last_le(gsr, G, r);
+        const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
+        const uint32_t e = ebase + r;
+        W.E[e] = sid | (cnt << sb);
+        uint32_t len = re - r;
+        if (dense_on) {
+            const uint32_t row = gaux[gi];
+            if (row != 0xFFFFFFFFu) {
+                W.D[(size_t)row * (size_t)W.Npad + sid] = (int8_t)cnt;
+                len = 0;
+            }
+        }
+        W.info[fv[p]] = make_uint2(e, len);
+    }
+    for (uint32_t i = tid; i < n; i += kThreads)
+        if (i > 0 && fk[i] == fk[i - 1]) W.info[fv[i]] = make_uint2(0u, 0u);
+}
+
+}  // namespace gk

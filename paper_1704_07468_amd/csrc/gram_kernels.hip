@@ -1,0 +1,449 @@
+// gfx950 kernels of the plain Gram path: validation, g-mer extraction,
+// hash-bucket partition (count / scan / scatter), per-bucket LDS radix sort
+// with group segmentation, row-owned accumulation of the cumulative mismatch
+// profiles, and the inclusion-exclusion / kernel / normalisation epilogue.
+#include "common.h"
+#include "launch.h"
+
+namespace gk {
+
+// ---------------------------------------------------------------- fills --
+__global__ void k_fill_u64(uint64_t *p, size_t n, uint64_t v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ------------------------------------------------------------ validation --
+// Every symbol code must lie in [0, sigma); a violation sets bit 0 of err.
+__global__ __launch_bounds__(kThreads) void k_validate(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
+{
+    const int j = find_item(bprefix, njobs, blockIdx.x);
+    const JobDev &J = jobs[j];
+    const int64_t i0 = (int64_t)(blockIdx.x - bprefix[j]) * (kThreads * 16);
+    bool bad = false;
+    for (int q = 0; q < 16; ++q) {
+        const int64_t i = i0 + q * kThreads + threadIdx.x;
+        if (i < J.nsym) bad |= ((uint8_t)J.seqs[i] >= (uint32_t)J.sigma);
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(J.err, 1);
+}
+
+// ------------------------------------------------------------- extraction --
+// g-mer t of sequence X at position p: key = sum_j x[p+j] << (b*(g-1-j))
+// (Section 2.2, step 1).  One thread per g-mer.
+__global__ __launch_bounds__(kThreads) void k_extract(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
+{
+    const int j = find_item(bprefix, njobs, blockIdx.x);
+    const JobDev &J = jobs[j];
+    const uint32_t t = (blockIdx.x - bprefix[j]) * kThreads + threadIdx.x;
+    if (t >= J.T) return;
+    const int X = (int)last_le(J.gstart, (uint32_t)J.N + 1u, t);
+    const uint32_t p = t - J.gstart[X];
+    const int8_t *s = J.seqs + J.seq_off[X] + p;
+    const uint64_t fm = (1ull << J.b) - 1ull;
+    uint64_t key = 0;
+    for (int q = 0; q < J.g; ++q) key = (key << J.b) | ((uint64_t)(uint8_t)s[q] & fm);
+    J.key[t] = key;
+    J.sid[t] = (uint32_t)X;
+}
+
+// --------------------------------------------------------- bucket count --
+// Histogram of bucket = top B bits of mix_w(reduced key) per mask.
+__global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix, int nitems)
+{
+    extern __shared__ uint32_t hist[];
+    const int it = find_item(bprefix, nitems, blockIdx.x);
+    const MaskWork &W = items[it];
+    const uint32_t t0 = (blockIdx.x - bprefix[it]) * kTile;
+    const uint32_t nb = 1u << W.B;
+    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
+    __syncthreads();
+    for (int q = 0; q < kTile / kThreads; ++q) {
+        const uint32_t t = t0 + q * kThreads + threadIdx.x;
+        if (t < W.T) {
+            const uint64_t h = mix_w(compact_key(W.key[t], W.md), W.w);
+            atomicAdd(&hist[(uint32_t)(h >> W.hb)], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += kThreads)
+        if (hist[i]) atomicAdd(&W.bcnt[i], hist[i]);
+}
+
+// ---------------------------------------------------------- bucket scan --
+// Exclusive scan of the bucket counts of one mask (one block per mask).
+__global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__restrict__ items)
+{
+    __shared__ uint32_t wsum[kWaves];
+    const MaskWork &W = items[blockIdx.x];
+    const uint32_t nb = 1u << W.B;
+    const uint32_t per = (nb + kThreads - 1) / kThreads;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t loc = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < nb) loc += W.bcnt[b0 + i];
+    uint32_t tot;
+    uint32_t run = block_excl_scan(loc, wsum, &tot);
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < nb) {
+            W.boff[b0 + i] = run;
+            W.bcur[b0 + i] = run;
+            run += W.bcnt[b0 + i];
+        }
+    if (threadIdx.x == 0) W.boff[nb] = tot;
+}
+
+// ------------------------------------------------------- bucket scatter --
+// Place (composite, g-mer index) of every g-mer into its bucket.  The order
+// inside a bucket is arbitrary; the bucket sort restores it.
+__global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix, int nitems)
+{
+    extern __shared__ uint32_t hist[];
+    const int it = find_item(bprefix, nitems, blockIdx.x);
+    const MaskWork &W = items[it];
+    const uint32_t t0 = (blockIdx.x - bprefix[it]) * kTile;
+    const uint32_t nb = 1u << W.B;
+    constexpr int Q = kTile / kThreads;
+    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
+    __syncthreads();
+    uint32_t bk[Q], rk[Q];
+    uint64_t cp[Q];
+    const uint64_t hmask = bits_mask(W.hb);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t t = t0 + q * kThreads + threadIdx.x;
+        bk[q] = 0xFFFFFFFFu;
+        if (t < W.T) {
+            const uint64_t h = mix_w(compact_key(W.key[t], W.md), W.w);
+            bk[q] = (uint32_t)(h >> W.hb);
+            cp[q] = ((h & hmask) << W.sb) | (uint64_t)W.sid[t];
+            rk[q] = atomicAdd(&hist[bk[q]], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) {
+        const uint32_t c = hist[i];
+        if (c) hist[i] = atomicAdd(&W.bcur[i], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (bk[q] != 0xFFFFFFFFu) {
+            const uint32_t pos = hist[bk[q]] + rk[q];
+            W.comp[pos] = cp[q];
+            W.idx[pos] = t0 + q * kThreads + threadIdx.x;
+        }
+    }
+}
+
+// ---------------------------------------------------- bucket sort+segment --
+// One block per (mask, bucket): radix-sort the bucket by (hash rest,
+// sequence) -- in LDS when it fits, else in global memory -- then segment it
+// into groups and runs.
+__global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix, int nitems)
+{
+    __shared__ uint64_t kA[kSortCap], kB[kSortCap];
+    __shared__ uint32_t vA[kSortCap], vB[kSortCap];
+    __shared__ SortScratch ss;
+    const int it = find_item(bprefix, nitems, blockIdx.x);
+    const MaskWork &W = items[it];
+    const uint32_t bucket = blockIdx.x - bprefix[it];
+    const uint32_t base = W.boff[bucket];
+    const uint32_t n = W.boff[bucket + 1] - base;
+    if (n == 0) return;
+    if (n <= (uint32_t)kSortCap) {
+        for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
+            kA[i] = W.comp[base + i];
+            vA[i] = W.idx[base + i];
+        }
+        __syncthreads();
+        int which = 0;
+        block_radix_sort(kA, vA, kB, vB, n, W.cb, ss, which);
+        __syncthreads();
+        uint64_t *fk = which ? kB : kA;
+        uint32_t *fv = which ? vB : vA;
+        uint32_t *fr = reinterpret_cast<uint32_t *>(which ? kA : kB);
+        uint32_t *fx = which ? vA : vB;
+        block_segment(fk, fv, n, fr, fr + kSortCap, fx, W, base, ss.wsum);
+    } else {
+        int which = 0;
+        block_radix_sort(W.comp + base, W.idx + base, W.comp2 + base, W.idx2 + base, n, W.cb, ss, which);
+        __syncthreads();
+        uint64_t *fk = (which ? W.comp2 : W.comp) + base;
+        uint32_t *fv = (which ? W.idx2 : W.idx) + base;
+        uint32_t *fr = reinterpret_cast<uint32_t *>((which ? W.comp : W.comp2) + base);
+        uint32_t *fx = (which ? W.idx : W.idx2) + base;
+        block_segment(fk, fv, n, fr, fr + n, fx, W, base, ss.wsum);
+    }
+}
+
+// ---------------------------------------------------------- accumulation --
+// One block owns row X of every C_m in its level range, as int32 counters in
+// LDS.  For each mask and each g-mer of X that leads a run (X's entry in its
+// group), the entries from X's own to the group end -- exactly the sequences
+// Y >= X of the group, since entries are sequence-sorted -- add
+// count_X * count_Y to row[m][Y] (Algorithm 1 countAndUpdate, upper
+// triangle).  The work of 256 runs at a time is spread evenly over the
+// threads by a scan of the run lengths.  The rows are then added into the
+// int64 C_m.
+__global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
+                                                         const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
+{
+    extern __shared__ uint32_t acc[];
+    __shared__ uint32_t pre[kThreads];
+    __shared__ uint64_t iptr[kThreads];
+    __shared__ uint32_t icx[kThreads];
+    __shared__ uint32_t ilev[kThreads];
+    __shared__ uint32_t wsum[kWaves];
+    const int a = find_item(bprefix, nacc, blockIdx.x);
+    const AccWork &A = aw[a];
+    const JobDev &J = jobs[A.job];
+    const int X = (int)(blockIdx.x - bprefix[a]);
+    const int N = J.N;
+    const int tid = threadIdx.x;
+    const int sb = J.sb;
+    const uint32_t sidmask = (uint32_t)bits_mask(sb);
+    const uint32_t t0 = J.gstart[X];
+    const uint32_t ng = J.gstart[X + 1] - t0;
+    if (ng == 0) return;  // no g-mers: the row stays 0
+    const int npad = A.Npad;
+    for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
+    __syncthreads();
+    const uint32_t total = (uint32_t)A.nmask * ng;
+    for (uint32_t q0 = 0; q0 < total; q0 += kThreads) {
+        const uint32_t q = q0 + tid;
+        uint32_t len = 0;
+        if (q < total) {
+            const uint32_t s = q / ng;
+            const uint32_t t = t0 + (q - s * ng);
+            const MaskWork &W = items[A.mfirst + s];
+            const uint2 inf = W.info[t];
+            len = inf.y;
+            if (len) {
+                const uint32_t *ep = W.E + inf.x;
+                iptr[tid] = reinterpret_cast<uint64_t>(ep);
+                icx[tid] = ep[0] >> sb;
+                ilev[tid] = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
+            }
+        }
+        uint32_t work;
+        const uint32_t ex = block_excl_scan(len, wsum, &work);
+        pre[tid] = ex;
+        __syncthreads();
+        for (uint32_t w = tid; w < work; w += kThreads) {
+            const uint32_t i = last_le(pre, kThreads, w);
+            const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[i])[w - pre[i]];
+            atomicAdd(&acc[ilev[i] + (ent & sidmask)], icx[i] * (ent >> sb));
+        }
+        __syncthreads();
+    }
+    for (int l = 0; l < A.nlev; ++l) {
+        int64_t *crow = J.C + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
+        const uint32_t *arow = acc + l * npad;
+        for (int Y = X + tid; Y < N; Y += kThreads) {
+            const uint32_t v = arow[Y];
+            if (v) crow[Y] += (int64_t)v;
+        }
+    }
+}
+
+// -------------------------------------------------------------- epilogue --
+// K_XX from the diagonal of C: Eq. 9 then Eq. 7.
+template <int MM>
+__global__ __launch_bounds__(kThreads) void k_diag(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
+{
+    const int j = find_item(bprefix, njobs, blockIdx.x);
+    const JobDev &J = jobs[j];
+    const int X = (int)((blockIdx.x - bprefix[j]) * kThreads + threadIdx.x);
+    if (X >= J.N) return;
+    const int M = J.M, N = J.N;
+    int64_t nv[MM];
+    int64_t kx = 0;
+    for (int m = 0; m <= M; ++m) {
+        int64_t v = J.C[((size_t)m * N + X) * N + X];
+        for (int jj = 0; jj < m; ++jj) v -= J.coef[m * (M + 1) + jj] * nv[jj];
+        nv[m] = v;
+        kx += J.hco[m] * v;
+    }
+    J.Kd[X] = kx;
+}
+
+// One block per 32x32 tile (I <= J) of the upper triangle: inclusion-
+// exclusion (Eq. 9), K (Eq. 7) and the cosine normalisation for every entry
+// x <= y, written to (x, y) and, through an LDS transpose, to (y, x).
+template <int MM>
+__global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
+{
+    __shared__ int64_t coef[MM * MM];
+    __shared__ int64_t hco[MM];
+    __shared__ int64_t tile[32][33];
+    const int j = find_item(bprefix, njobs, blockIdx.x);
+    const JobDev &Jb = jobs[j];
+    const int N = Jb.N, M = Jb.M;
+    const int nt = (N + 31) / 32;
+    const int flat = (int)(blockIdx.x - bprefix[j]);
+    const int I = flat / nt, Jt = flat % nt;
+    if (I > Jt) return;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < (M + 1) * (M + 1); i += kThreads) coef[(i / (M + 1)) * MM + (i % (M + 1))] = Jb.coef[i];
+    for (int i = tid; i <= M; i += kThreads) hco[i] = Jb.hco[i];
+    __syncthreads();
+    const int c = tid & 31;
+    int64_t nv[4][MM];
+    int64_t kv[4];
+    bool valid[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = (tid >> 5) + 8 * q;
+        const int x = I * 32 + r, y = Jt * 32 + c;
+        valid[q] = (x < N) && (y < N) && (I < Jt || r <= c);
+        kv[q] = 0;
+        if (valid[q]) {
+            for (int m = 0; m <= M; ++m) {
+                int64_t v = Jb.C[((size_t)m * N + x) * N + y];
+                for (int jj = 0; jj < m; ++jj) v -= coef[m * MM + jj] * nv[q][jj];
+                nv[q][m] = v;
+                kv[q] += hco[m] * v;
+            }
+        }
+    }
+    __syncthreads();  // every read of C precedes any write (C may alias Nm_out)
+    auto emit = [&](int64_t *out, auto value_of) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = (tid >> 5) + 8 * q;
+            if (valid[q]) {
+                const int64_t v = value_of(q);
+                out[(size_t)(I * 32 + r) * N + (Jt * 32 + c)] = v;
+                tile[r][c] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = (tid >> 5) + 8 * q;
+            const int sx = I * 32 + c, sy = Jt * 32 + r;  // source element (sx, sy), sx <= sy
+            if (sx < N && sy < N && (I < Jt || c <= r)) out[(size_t)sy * N + sx] = tile[c][r];
+        }
+        __syncthreads();
+    };
+    if (Jb.Nm_out) {
+        for (int m = 0; m <= M; ++m)
+            emit(Jb.Nm_out + (size_t)m * N * N, [&](int q) { return nv[q][m]; });
+    }
+    if (Jb.Cm_out) {
+        for (int m = 0; m <= M; ++m) {
+            emit(Jb.Cm_out + (size_t)m * N * N, [&](int q) {
+                int64_t v = nv[q][m];
+                for (int jj = 0; jj < m; ++jj) v += coef[m * MM + jj] * nv[q][jj];
+                return v;
+            });
+        }
+    }
+    if (Jb.K_out) {
+        int64_t *kout = reinterpret_cast<int64_t *>(Jb.K_out);
+        emit(kout, [&](int q) {
+            const int r = (tid >> 5) + 8 * q;
+            const int64_t kx = Jb.Kd[I * 32 + r], ky = Jb.Kd[Jt * 32 + c];
+            const double kh = (kx == 0 || ky == 0) ? 0.0 : (double)kv[q] / sqrt((double)kx * (double)ky);
+            return __double_as_longlong(kh);
+        });
+    }
+}
+
+// --------------------------------------------------------------- launchers --
+static inline unsigned nblk(size_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_fill_u64(uint64_t *p, size_t n, uint64_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    unsigned g = nblk(n, kThreads);
+    if (g > 65536u) g = 65536u;
+    hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kThreads), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    unsigned g = nblk(n, kThreads);
+    if (g > 65536u) g = 65536u;
+    hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(kThreads), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_validate(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_validate, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    return hipGetLastError();
+}
+hipError_t launch_extract(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_extract, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    return hipGetLastError();
+}
+hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_count, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems);
+    return hipGetLastError();
+}
+hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st)
+{
+    if (!nitems) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_scan, dim3(nitems), dim3(kThreads), 0, st, items);
+    return hipGetLastError();
+}
+hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems);
+    return hipGetLastError();
+}
+hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems);
+    return hipGetLastError();
+}
+hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
+                             uint32_t nblocks, size_t lds_bytes, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_accumulate, dim3(nblocks), dim3(kThreads), lds_bytes, st, jobs, items, aw, bprefix, nacc);
+    return hipGetLastError();
+}
+hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    if (maxM < 8) hipLaunchKernelGGL(k_diag<8>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    else if (maxM < 16) hipLaunchKernelGGL(k_diag<16>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    else hipLaunchKernelGGL(k_diag<65>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    return hipGetLastError();
+}
+hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st)
+{
+    if (!nblocks) return hipSuccess;
+    if (maxM < 8) hipLaunchKernelGGL(k_finalize<8>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    else if (maxM < 16) hipLaunchKernelGGL(k_finalize<16>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    else hipLaunchKernelGGL(k_finalize<65>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    return hipGetLastError();
+}
+
+}  // namespace gk
+
+namespace gk {
+// The row accumulation may keep several levels of a long row in LDS (up to
+// the device's per-block limit).
+hipError_t init_kernel_attributes(size_t acc_lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_accumulate),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)acc_lds);
+}
+}  // namespace gk

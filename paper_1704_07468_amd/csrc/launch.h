@@ -1,0 +1,25 @@
+// Host-side launchers of the gfx950 kernels (one per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gk {
+struct JobDev;
+struct MaskWork;
+struct AccWork;
+struct DenseWork;
+struct RowsWork;
+
+hipError_t launch_fill_u64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_validate(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st);
+hipError_t launch_extract(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st);
+hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st);
+hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st);
+hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st);
+hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, hipStream_t st);
+hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
+                             uint32_t nblocks, size_t lds_bytes, hipStream_t st);
+hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
+hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
+}  // namespace gk

@@ -1,0 +1,472 @@
+// Planning and launch sequence of Gram jobs (host side).
+#include "plan.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "launch.h"
+
+namespace gk {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+const char *last_error() { return g_err.c_str(); }
+void clear_error() { g_err.clear(); }
+const char *hip_name(hipError_t e) { return hipGetErrorString(e); }
+
+int64_t binom64(int n, int r)
+{
+    if (r < 0 || n < 0 || r > n) return 0;
+    int64_t v = 1;
+    for (int i = 1; i <= r; ++i) v = v * (n - r + i) / i;
+    return v;
+}
+
+int symbol_bits(int sigma)
+{
+    int b = 0;
+    while ((1 << b) < sigma) ++b;
+    return b < 1 ? 1 : b;
+}
+
+static int ceil_log2(uint64_t x)
+{
+    int b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+gakco_status fetch_lens(JobPlan &jp, hipStream_t st)
+{
+    jp.lens.assign((size_t)jp.N, 0);
+    GK_HIP(hipMemcpyAsync(jp.lens.data(), jp.lens_dev, sizeof(int32_t) * (size_t)jp.N, hipMemcpyDeviceToHost, st));
+    GK_HIP(hipStreamSynchronize(st));
+    return GAKCO_OK;
+}
+
+// The kept positions of a mask as runs of consecutive symbol fields.
+static MaskDesc make_mask(int g, int b, const int *removed, int m)
+{
+    MaskDesc md{};
+    md.level = m;
+    std::vector<char> drop((size_t)g, 0);
+    for (int i = 0; i < m; ++i) drop[(size_t)removed[i]] = 1;
+    int q = 0, j = 0;
+    while (j < g) {
+        if (drop[(size_t)j]) { ++j; continue; }
+        int L = 0;
+        while (j + L < g && !drop[(size_t)(j + L)]) ++L;
+        md.rsrc[md.nrun] = (uint8_t)((g - j - L) * b);
+        md.rwid[md.nrun] = (uint8_t)(L * b);
+        md.rdst[md.nrun] = (uint8_t)((g - m - q - L) * b);
+        md.nrun += 1;
+        q += L;
+        j += L;
+    }
+    return md;
+}
+
+gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one, int m_one)
+{
+    if (jp.N < 1) { set_error("N must be >= 1 (got %d)", jp.N); return GAKCO_EINVAL; }
+    if (jp.sigma < 1 || jp.sigma > 127) { set_error("sigma must be in 1..127 (got %d)", jp.sigma); return GAKCO_EINVAL; }
+    if (jp.g < 1) { set_error("g must be >= 1 (got %d)", jp.g); return GAKCO_EINVAL; }
+    if (jp.k < 0 || jp.k > jp.g) { set_error("k must be in 0..g (got k=%d, g=%d)", jp.k, jp.g); return GAKCO_EINVAL; }
+    if (!jp.seqs || !jp.lens_dev) { set_error("seqs and lens must not be NULL"); return GAKCO_EINVAL; }
+    jp.b = symbol_bits(jp.sigma);
+    if (jp.g * jp.b > 64) {
+        set_error("g*b = %d*%d exceeds the 64-bit packed g-mer", jp.g, jp.b);
+        return GAKCO_EUNSUPPORTED;
+    }
+    jp.M = jp.g - jp.k;
+    const int N = jp.N;
+    jp.gstart.assign((size_t)N + 1, 0);
+    jp.seq_off.assign((size_t)N + 1, 0);
+    uint64_t T = 0;
+    uint32_t maxng = 0;
+    for (int i = 0; i < N; ++i) {
+        const int32_t l = jp.lens[(size_t)i];
+        if (l < 0) { set_error("lens[%d] = %d is negative", i, l); return GAKCO_EINVAL; }
+        const uint32_t ng = (l >= jp.g) ? (uint32_t)(l - jp.g + 1) : 0u;
+        jp.gstart[(size_t)i] = (uint32_t)T;
+        jp.seq_off[(size_t)i + 1] = jp.seq_off[(size_t)i] + l;
+        T += ng;
+        maxng = std::max(maxng, ng);
+        if (T >= (1ull << 31)) { set_error("more than 2^31 g-mers"); return GAKCO_EUNSUPPORTED; }
+    }
+    jp.gstart[(size_t)N] = (uint32_t)T;
+    jp.T = (uint32_t)T;
+    jp.maxng = maxng;
+    jp.nsym = jp.seq_off[(size_t)N];
+    jp.sb = std::max(1, ceil_log2((uint64_t)N));
+    if (jp.sb > 24 || (uint64_t)maxng >= (1ull << (32 - jp.sb))) {
+        set_error("N=%d with %u g-mers in one sequence exceeds the 32-bit run entry", N, maxng);
+        return GAKCO_EUNSUPPORTED;
+    }
+    // masks
+    jp.masks.clear();
+    if (removed_one) {
+        for (int i = 0; i < m_one; ++i)
+            if (removed_one[i] < 0 || removed_one[i] >= jp.g || (i && removed_one[i] <= removed_one[i - 1])) {
+                set_error("removed positions must be increasing and in [0, g)");
+                return GAKCO_EINVAL;
+            }
+        jp.masks.push_back(make_mask(jp.g, jp.b, removed_one, m_one));
+    } else {
+        uint64_t total = 0;
+        for (int m = 0; m <= jp.M; ++m) total += (uint64_t)binom64(jp.g, m);
+        if (total > (1u << 20)) { set_error("%llu position sets exceed the limit", (unsigned long long)total); return GAKCO_EUNSUPPORTED; }
+        for (int m = 0; m <= jp.M; ++m) {
+            const int64_t cgm = binom64(jp.g, m);
+            if ((double)cgm * (double)maxng * (double)maxng >= 2147483648.0) {
+                set_error("C(g,m)*maxng^2 overflows the int32 row counters (g=%d, m=%d, maxng=%u)", jp.g, m, maxng);
+                return GAKCO_EUNSUPPORTED;
+            }
+            std::vector<int> P((size_t)m);
+            for (int i = 0; i < m; ++i) P[(size_t)i] = i;
+            while (true) {
+                jp.masks.push_back(make_mask(jp.g, jp.b, P.data(), m));
+                int i = m - 1;
+                while (i >= 0 && P[(size_t)i] == jp.g - m + i) --i;
+                if (i < 0) break;
+                P[(size_t)i] += 1;
+                for (int q = i + 1; q < m; ++q) P[(size_t)q] = P[(size_t)q - 1] + 1;
+            }
+        }
+    }
+    // bucket geometry per level
+    jp.level_B.assign((size_t)jp.g + 1, 0);
+    for (int m = 0; m <= jp.g; ++m) {
+        const int w = (jp.g - m) * jp.b;
+        const uint64_t want = (T + (uint64_t)ctx->bucket_avg - 1) / (uint64_t)std::max(1, ctx->bucket_avg);
+        int B = ceil_log2(std::max<uint64_t>(1, want));
+        const int Bmax = std::min(w, kMaxBucketBits);
+        B = std::min(B, Bmax);
+        while (w - B + jp.sb > 64 && B < Bmax) ++B;
+        if (w - B + jp.sb > 64) { set_error("reduced key + sequence id exceed 64 bits"); return GAKCO_EUNSUPPORTED; }
+        jp.level_B[(size_t)m] = B;
+    }
+    jp.Npad = (N + 63) / 64 * 64;
+    return GAKCO_OK;
+}
+
+static size_t mask_bytes(uint32_t T, int B)
+{
+    Layout l;
+    const size_t nb = (size_t)1 << B;
+    l.take((nb + 1) * 4);  // boff
+    l.take(nb * 4);        // bcur
+    l.take((size_t)T * 8); // comp
+    l.take((size_t)T * 4); // idx
+    l.take((size_t)T * 8); // comp2
+    l.take((size_t)T * 4); // idx2
+    l.take((size_t)T * 4); // E
+    l.take((size_t)T * 8); // info
+    return l.size;
+}
+
+gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
+{
+    Layout &L = p.lay;
+    L = Layout{};
+    p.output_bytes = 0;
+    p.maxB = 0;
+    p.maxM = 0;
+    size_t nmask = 0, nb_total = 0;
+    for (auto &jp : p.jobs) {
+        const size_t N = (size_t)jp.N, M1 = (size_t)jp.M + 1;
+        jp.o_seqoff = L.take((N + 1) * 8);
+        jp.o_gstart = L.take((N + 1) * 4);
+        if (!jp.key_override) {
+            jp.o_key = L.take((size_t)jp.T * 8);
+            jp.o_sid = L.take((size_t)jp.T * 4);
+        }
+        if (jp.want_kernel) {
+            jp.own_C = !jp.Cm_out && !jp.Nm_out;
+            if (jp.own_C) jp.o_C = L.take(M1 * N * N * 8);
+            jp.o_Kd = L.take(N * 8);
+            jp.o_coef = L.take(M1 * M1 * 8);
+            jp.o_hco = L.take(M1 * 8);
+            p.output_bytes += N * N * 8 * ((jp.K_out ? 1 : 0) + (jp.Nm_out ? M1 : 0) + (jp.Cm_out ? M1 : 0));
+            p.maxM = std::max(p.maxM, jp.M);
+        }
+        jp.o_mask.resize(jp.masks.size());
+        for (size_t i = 0; i < jp.masks.size(); ++i) {
+            const int B = jp.level_B[(size_t)jp.masks[i].level];
+            jp.o_mask[i] = L.take(mask_bytes(jp.T, B));
+            nb_total += (size_t)1 << B;
+            p.maxB = std::max(p.maxB, B);
+        }
+        nmask += jp.masks.size();
+    }
+    // flags (err per job) and the bucket counters of every mask, contiguous
+    // so that one fill clears them
+    p.mw.resize(nmask);
+    p.o_flags = L.take(p.jobs.size() * 4);
+    p.o_bcnt = L.take(nb_total * 4);
+    // descriptor blob
+    Layout d;
+    p.d_jobs = d.take(sizeof(JobDev) * p.jobs.size(), 64);
+    p.d_masks = d.take(sizeof(MaskWork) * nmask, 64);
+    // accumulate works: level groups that fit the LDS budget
+    p.aw.clear();
+    p.acc_groups.clear();
+    p.acc_lds.clear();
+    std::vector<std::vector<AccWork>> per_group;
+    int mfirst_global = 0;
+    for (size_t j = 0; j < p.jobs.size(); ++j) {
+        auto &jp = p.jobs[j];
+        jp.mask_first = mfirst_global;
+        mfirst_global += (int)jp.masks.size();
+        if (!jp.want_kernel) continue;
+        const size_t row_bytes = (size_t)jp.Npad * 4;
+        const int lpg = (int)std::min<size_t>((size_t)jp.M + 1, ctx->lds_max / row_bytes);
+        if (lpg < 1) {
+            set_error("N=%d needs %zu bytes of LDS per level row; %zu available", jp.N, row_bytes, ctx->lds_max);
+            return GAKCO_EUNSUPPORTED;
+        }
+        int gi = 0;
+        for (int lev0 = 0; lev0 <= jp.M; lev0 += lpg, ++gi) {
+            const int nlev = std::min(lpg, jp.M + 1 - lev0);
+            int first = -1, cnt = 0;
+            for (size_t i = 0; i < jp.masks.size(); ++i)
+                if (jp.masks[i].level >= lev0 && jp.masks[i].level < lev0 + nlev) {
+                    if (first < 0) first = (int)i;
+                    ++cnt;
+                }
+            AccWork a{};
+            a.job = (int)j;
+            a.mfirst = jp.mask_first + std::max(first, 0);
+            a.nmask = cnt;
+            a.lev0 = lev0;
+            a.nlev = nlev;
+            a.Npad = jp.Npad;
+            if ((size_t)gi >= per_group.size()) per_group.emplace_back();
+            per_group[(size_t)gi].push_back(a);
+        }
+    }
+    p.acc_prefix.clear();
+    for (auto &grp : per_group) {
+        const int first = (int)p.aw.size();
+        size_t lds = 0;
+        std::vector<uint32_t> pre(1, 0);
+        for (auto &a : grp) {
+            p.aw.push_back(a);
+            lds = std::max(lds, (size_t)a.nlev * (size_t)a.Npad * 4);
+            pre.push_back(pre.back() + (uint32_t)p.jobs[(size_t)a.job].N);
+        }
+        p.acc_groups.emplace_back(first, (int)grp.size());
+        p.acc_lds.push_back(lds);
+        p.acc_prefix.push_back(pre);
+    }
+    p.d_acc = d.take(sizeof(AccWork) * std::max<size_t>(1, p.aw.size()), 64);
+    const size_t nj = p.jobs.size();
+    p.d_pv = d.take((nj + 1) * 4, 64);
+    p.d_px = d.take((nj + 1) * 4, 64);
+    p.d_pt = d.take((nmask + 1) * 4, 64);
+    p.d_pb = d.take((nmask + 1) * 4, 64);
+    p.d_pd = d.take((nj + 1) * 4, 64);
+    p.d_pf = d.take((nj + 1) * 4, 64);
+    p.d_pacc.clear();
+    for (auto &pre : p.acc_prefix) p.d_pacc.push_back(d.take(pre.size() * 4, 64));
+    p.desc_bytes = d.size;
+    p.o_desc = L.take(p.desc_bytes);
+    if (L.size + p.output_bytes > ctx->budget) {
+        set_error("scratch %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB", L.size / 1e9,
+                  p.output_bytes / 1e9, ctx->budget / 1e9);
+        return GAKCO_EBUDGET;
+    }
+    return GAKCO_OK;
+}
+
+static gakco_status reserve_arena(gakco_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->arena_cap) return GAKCO_OK;
+    if (ctx->arena) {
+        GK_HIP(hipDeviceSynchronize());
+        GK_HIP(hipFree(ctx->arena));
+        ctx->arena = nullptr;
+        ctx->arena_cap = 0;
+    }
+    const size_t cap = (bytes + (64ull << 20) - 1) / (64ull << 20) * (64ull << 20);
+    GK_HIP(hipMalloc(&ctx->arena, cap));
+    ctx->arena_cap = cap;
+    return GAKCO_OK;
+}
+
+gakco_status plan_bind(gakco_ctx *ctx, Plan &p)
+{
+    GK_TRY(reserve_arena(ctx, p.lay.size));
+    char *base = (char *)ctx->arena;
+    p.base = base;
+    const size_t o_flags = p.o_flags, o_bcnt = p.o_bcnt;
+    p.desc_host.assign(p.desc_bytes, 0);
+    char *blob = p.desc_host.data();
+    JobDev *jd = reinterpret_cast<JobDev *>(blob + p.d_jobs);
+    std::vector<uint32_t> pv(1, 0), px(1, 0), pt(1, 0), pb(1, 0), pd(1, 0), pf(1, 0);
+    size_t mi = 0, bc = 0;
+    for (size_t j = 0; j < p.jobs.size(); ++j) {
+        auto &jp = p.jobs[j];
+        JobDev &J = jp.dev;
+        J = JobDev{};
+        J.seqs = jp.seqs;
+        J.seq_off = reinterpret_cast<const int64_t *>(base + jp.o_seqoff);
+        J.gstart = reinterpret_cast<const uint32_t *>(base + jp.o_gstart);
+        J.N = jp.N; J.sigma = jp.sigma; J.g = jp.g; J.k = jp.k; J.M = jp.M; J.b = jp.b; J.sb = jp.sb;
+        J.T = jp.T;
+        J.nsym = jp.nsym;
+        J.key = jp.key_override ? jp.key_override : reinterpret_cast<uint64_t *>(base + jp.o_key);
+        J.sid = jp.sid_override ? jp.sid_override : reinterpret_cast<uint32_t *>(base + jp.o_sid);
+        J.err = reinterpret_cast<int32_t *>(base + o_flags) + j;
+        if (jp.want_kernel) {
+            J.C = jp.own_C ? reinterpret_cast<int64_t *>(base + jp.o_C) : (jp.Cm_out ? jp.Cm_out : jp.Nm_out);
+            J.Kd = reinterpret_cast<int64_t *>(base + jp.o_Kd);
+            J.coef = reinterpret_cast<const int64_t *>(base + jp.o_coef);
+            J.hco = reinterpret_cast<const int64_t *>(base + jp.o_hco);
+            J.K_out = jp.K_out;
+            J.Nm_out = jp.Nm_out;
+            J.Cm_out = jp.Cm_out;
+        }
+        jd[j] = J;
+        pv.push_back(pv.back() + (uint32_t)((jp.nsym + kThreads * 16 - 1) / (kThreads * 16)));
+        px.push_back(px.back() + (jp.T + kThreads - 1) / kThreads);
+        pd.push_back(pd.back() + (jp.want_kernel ? (uint32_t)((jp.N + kThreads - 1) / kThreads) : 0u));
+        const uint32_t nt = (uint32_t)((jp.N + 31) / 32);
+        pf.push_back(pf.back() + (jp.want_kernel ? nt * nt : 0u));
+        for (size_t i = 0; i < jp.masks.size(); ++i, ++mi) {
+            MaskWork &W = p.mw[mi];
+            W = MaskWork{};
+            W.md = jp.masks[i];
+            W.job = (int)j;
+            W.T = jp.T;
+            const int m = W.md.level;
+            W.w = (jp.g - m) * jp.b;
+            W.B = jp.level_B[(size_t)m];
+            W.hb = W.w - W.B;
+            W.sb = jp.sb;
+            W.cb = W.hb + W.sb;
+            W.key = J.key;
+            W.sid = J.sid;
+            const size_t nb = (size_t)1 << W.B;
+            W.bcnt = reinterpret_cast<uint32_t *>(base + o_bcnt) + bc;
+            bc += nb;
+            Layout l;
+            char *mb = base + jp.o_mask[i];
+            W.boff = reinterpret_cast<uint32_t *>(mb + l.take((nb + 1) * 4));
+            W.bcur = reinterpret_cast<uint32_t *>(mb + l.take(nb * 4));
+            W.comp = reinterpret_cast<uint64_t *>(mb + l.take((size_t)jp.T * 8));
+            W.idx = reinterpret_cast<uint32_t *>(mb + l.take((size_t)jp.T * 4));
+            W.comp2 = reinterpret_cast<uint64_t *>(mb + l.take((size_t)jp.T * 8));
+            W.idx2 = reinterpret_cast<uint32_t *>(mb + l.take((size_t)jp.T * 4));
+            W.E = reinterpret_cast<uint32_t *>(mb + l.take((size_t)jp.T * 4));
+            W.info = reinterpret_cast<uint2 *>(mb + l.take((size_t)jp.T * 8));
+            W.D = nullptr;
+            W.dcount = nullptr;
+            W.dcap = 0;
+            W.Npad = jp.Npad;
+            W.tau = 0;
+            pt.push_back(pt.back() + (jp.T + kTile - 1) / kTile);
+            pb.push_back(pb.back() + (uint32_t)nb);
+        }
+    }
+    if (!p.mw.empty()) memcpy(blob + p.d_masks, p.mw.data(), sizeof(MaskWork) * p.mw.size());
+    if (!p.aw.empty()) memcpy(blob + p.d_acc, p.aw.data(), sizeof(AccWork) * p.aw.size());
+    auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
+    put(p.d_pv, pv); put(p.d_px, px); put(p.d_pt, pt); put(p.d_pb, pb); put(p.d_pd, pd); put(p.d_pf, pf);
+    for (size_t i = 0; i < p.acc_prefix.size(); ++i) put(p.d_pacc[i], p.acc_prefix[i]);
+    p.nb_v = pv.back(); p.nb_x = px.back(); p.nb_t = pt.back(); p.nb_b = pb.back(); p.nb_d = pd.back(); p.nb_f = pf.back();
+    return GAKCO_OK;
+}
+
+gakco_status plan_upload(Plan &p, hipStream_t st)
+{
+    char *base = p.base;
+    for (auto &jp : p.jobs) {
+        GK_HIP(hipMemcpyAsync(base + jp.o_seqoff, jp.seq_off.data(), jp.seq_off.size() * 8, hipMemcpyHostToDevice, st));
+        GK_HIP(hipMemcpyAsync(base + jp.o_gstart, jp.gstart.data(), jp.gstart.size() * 4, hipMemcpyHostToDevice, st));
+        if (jp.want_kernel) {
+            const int M1 = jp.M + 1;
+            std::vector<int64_t> coef((size_t)M1 * M1, 0), hco((size_t)M1, 0);
+            for (int m = 0; m < M1; ++m) {
+                hco[(size_t)m] = binom64(jp.g - m, jp.k);           // Eq. 6
+                for (int j = 0; j < m; ++j) coef[(size_t)m * M1 + j] = binom64(jp.g - j, m - j);  // Eq. 9
+            }
+            GK_HIP(hipMemcpyAsync(base + jp.o_coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, st));
+            GK_HIP(hipMemcpyAsync(base + jp.o_hco, hco.data(), hco.size() * 8, hipMemcpyHostToDevice, st));
+            // the copies above read pageable host memory that dies with this
+            // scope: wait for them
+            GK_HIP(hipStreamSynchronize(st));
+        }
+    }
+    GK_HIP(hipMemcpyAsync(base + p.o_desc, p.desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice, st));
+    return GAKCO_OK;
+}
+
+gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
+{
+    (void)ctx;
+    char *d = p.base + p.o_desc;
+    const JobDev *jobs = reinterpret_cast<const JobDev *>(d + p.d_jobs);
+    const MaskWork *masks = reinterpret_cast<const MaskWork *>(d + p.d_masks);
+    const AccWork *acc = reinterpret_cast<const AccWork *>(d + p.d_acc);
+    auto P = [&](size_t off) { return reinterpret_cast<const uint32_t *>(d + off); };
+    const int nj = (int)p.jobs.size(), nm = (int)p.mw.size();
+    // clear flags and bucket counters (one contiguous region)
+    const size_t o_flags = p.o_flags, o_bcnt = p.o_bcnt;
+    size_t nbc = 0;
+    for (auto &W : p.mw) nbc += (size_t)1 << W.B;
+    GK_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_flags), (size_t)nj, 0u, st));
+    GK_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_bcnt), nbc, 0u, st));
+    for (auto &jp : p.jobs)
+        if (jp.want_kernel)
+            GK_HIP(launch_fill_u64(reinterpret_cast<uint64_t *>(jp.dev.C), (size_t)(jp.M + 1) * jp.N * jp.N, 0ull, st));
+    GK_HIP(launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
+    GK_HIP(launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
+    if (nm) {
+        GK_HIP(launch_bucket_count(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
+        GK_HIP(launch_bucket_scan(masks, nm, st));
+        GK_HIP(launch_bucket_scatter(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
+        GK_HIP(launch_bucket_sort(masks, P(p.d_pb), nm, p.nb_b, st));
+    }
+    for (size_t gi = 0; gi < p.acc_groups.size(); ++gi) {
+        const auto &grp = p.acc_groups[gi];
+        GK_HIP(launch_accumulate(jobs, masks, acc + grp.first, P(p.d_pacc[gi]), grp.second,
+                                 p.acc_prefix[gi].back(), p.acc_lds[gi], st));
+    }
+    if (p.nb_d) {
+        GK_HIP(launch_diag(jobs, P(p.d_pd), nj, p.nb_d, p.maxM, st));
+        GK_HIP(launch_finalize(jobs, P(p.d_pf), nj, p.nb_f, p.maxM, st));
+    }
+    return GAKCO_OK;
+}
+
+gakco_status plan_check_errors(Plan &p, hipStream_t st)
+{
+    std::vector<int32_t> flags(p.jobs.size(), 0);
+    GK_HIP(hipMemcpyAsync(flags.data(), p.base + p.o_flags, flags.size() * 4, hipMemcpyDeviceToHost, st));
+    GK_HIP(hipStreamSynchronize(st));
+    gakco_status first = GAKCO_OK;
+    for (size_t j = 0; j < flags.size(); ++j) {
+        if (flags[j] & 1) {
+            p.jobs[j].status = GAKCO_ERANGE;
+            if (first == GAKCO_OK) {
+                set_error("job %zu: a symbol code lies outside [0, sigma=%d)", j, p.jobs[j].sigma);
+                first = GAKCO_ERANGE;
+            }
+        }
+    }
+    return first;
+}
+
+}  // namespace gk

@@ -1,0 +1,125 @@
+// Host-side planning of Gram jobs: validation, g-mer offsets, position sets,
+// bucket geometry, device memory layout and the launch sequence.  Shared by
+// the single-job path, the batched path and the resident-set builder.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gakco.h"
+#include "common.h"
+
+struct gakco_ctx {
+    int device = 0;
+    size_t budget = 0;
+    int dense_tau = 0;     // 0 = int8 matrix-core path off
+    int bucket_avg = 512;  // target g-mers per hash bucket
+    void *arena = nullptr;
+    size_t arena_cap = 0;
+    size_t lds_max = 0;    // dynamic LDS available to the row accumulation
+};
+
+namespace gk {
+
+void set_error(const char *fmt, ...);
+const char *hip_name(hipError_t e);
+
+#define GK_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (call);                                                        \
+        if (_e != hipSuccess) {                                                        \
+            ::gk::set_error("%s failed: %s (%s:%d)", #call, ::gk::hip_name(_e), __FILE__, \
+                            __LINE__);                                                 \
+            return GAKCO_EHIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+#define GK_TRY(expr)                  \
+    do {                              \
+        gakco_status _s = (expr);     \
+        if (_s != GAKCO_OK) return _s; \
+    } while (0)
+
+int64_t binom64(int n, int r);
+int symbol_bits(int sigma);
+
+// Bump layout over one device allocation: offsets first, pointers after the
+// arena is sized.
+struct Layout {
+    size_t size = 0;
+    size_t take(size_t bytes, size_t align = 256)
+    {
+        size = (size + align - 1) / align * align;
+        size_t off = size;
+        size += bytes;
+        return off;
+    }
+};
+
+struct JobPlan {
+    // request
+    const int8_t *seqs = nullptr;
+    const int32_t *lens_dev = nullptr;
+    int32_t N = 0, sigma = 0, g = 0, k = 0;
+    double *K_out = nullptr;
+    int64_t *Nm_out = nullptr;
+    int64_t *Cm_out = nullptr;
+    bool want_kernel = true;  // run accumulation + epilogue (false: partition only)
+    // host-side shape
+    std::vector<int32_t> lens;
+    int M = 0, b = 0, sb = 0;
+    uint32_t T = 0, maxng = 0;
+    int64_t nsym = 0;
+    std::vector<uint32_t> gstart;
+    std::vector<int64_t> seq_off;
+    std::vector<MaskDesc> masks;
+    std::vector<int> level_B;  // bucket bits per level
+    // layout offsets
+    size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_err = 0, o_C = 0, o_Kd = 0, o_coef = 0,
+           o_hco = 0;
+    size_t o_D = 0, o_dcount = 0;
+    std::vector<size_t> o_mask;  // per mask: base of its buffers
+    std::vector<uint32_t> dcap;  // per level dense row capacity
+    size_t dense_row_bytes = 0;
+    int Npad = 0;
+    bool own_C = false;
+    uint64_t *key_override = nullptr;  // write g-mers to caller buffers (stage entry point)
+    uint32_t *sid_override = nullptr;
+    // device view
+    JobDev dev{};
+    int mask_first = 0;
+    int status = GAKCO_OK;
+};
+
+// The whole plan of one call (one or more jobs).
+struct Plan {
+    std::vector<JobPlan> jobs;
+    Layout lay;
+    size_t o_desc = 0, desc_bytes = 0;
+    size_t o_flags = 0, o_bcnt = 0;  // per-job error flags; bucket counters of every mask
+    std::vector<char> desc_host;  // staged descriptor blob
+    // descriptor offsets inside the blob
+    size_t d_jobs = 0, d_masks = 0, d_acc = 0;
+    size_t d_pv = 0, d_px = 0, d_pt = 0, d_pb = 0, d_pa = 0, d_pd = 0, d_pf = 0;
+    uint32_t nb_v = 0, nb_x = 0, nb_t = 0, nb_b = 0, nb_a = 0, nb_d = 0, nb_f = 0;
+    int maxB = 0, maxM = 0;
+    std::vector<MaskWork> mw;
+    std::vector<AccWork> aw;
+    std::vector<size_t> acc_lds;      // dynamic LDS of each accumulate launch group
+    std::vector<std::pair<int, int>> acc_groups;  // [first, count) of aw per launch
+    std::vector<std::vector<uint32_t>> acc_prefix;
+    std::vector<size_t> d_pacc;
+    char *base = nullptr;             // arena base
+    size_t output_bytes = 0;
+};
+
+gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one, int m_one);
+gakco_status plan_layout(gakco_ctx *ctx, Plan &p);
+gakco_status plan_bind(gakco_ctx *ctx, Plan &p);  // arena + pointers + descriptor blob
+gakco_status plan_upload(Plan &p, hipStream_t st);
+gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st);
+gakco_status fetch_lens(JobPlan &jp, hipStream_t st);
+gakco_status plan_check_errors(Plan &p, hipStream_t st);
+
+}  // namespace gk

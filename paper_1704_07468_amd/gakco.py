@@ -1,0 +1,193 @@
+"""Python binding of libgakco.so (the gfx950 gapped k-mer kernel library).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library; torch supplies device memory and the current stream.  Importing this
+module does not touch the GPU; loading the library fails loudly when it has
+not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgakco.so")
+
+OK, EINVAL, ERANGE, EUNSUPPORTED, EBUDGET, EHIP, ECANCELLED, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
+_NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", EUNSUPPORTED: "EUNSUPPORTED", EBUDGET: "EBUDGET",
+          EHIP: "EHIP", ECANCELLED: "ECANCELLED", EAGAIN: "EAGAIN"}
+
+_lib = None
+_lock = threading.Lock()
+
+
+class GakcoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (_NAMES.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("seqs", ctypes.c_void_p), ("lens", ctypes.c_void_p), ("N", ctypes.c_int32),
+                ("sigma", ctypes.c_int32), ("g", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("K_out", ctypes.c_void_p), ("Nm_out", ctypes.c_void_p), ("status_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("decision", ctypes.c_double),
+                ("K_row", ctypes.c_void_p), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("batch_size", ctypes.c_int32)]
+
+
+def lib():
+    """Load libgakco.so (raises if it is missing)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libgakco.so is not built (run __graft_entry__.build())")
+            L = ctypes.CDLL(LIB_PATH)
+            P, i32, i64, sz, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+            sig = {
+                "gakco_last_error": ([], ctypes.c_char_p),
+                "gakco_version": ([], ctypes.c_char_p),
+                "gakco_ctx_create": ([ctypes.c_int, sz, ctypes.c_char_p, P], i32),
+                "gakco_ctx_destroy": ([P], None),
+                "gakco_ctx_set_param": ([P, ctypes.c_char_p, i64], i32),
+                "gakco_count_gmers": ([P, i32, i32, P], i32),
+                "gakco_gram": ([P, P, P, i32, i32, i32, i32, P, P, P, P], i32),
+                "gakco_extract": ([P, P, P, i32, i32, i32, P, P, P], i32),
+                "gakco_mask_groups": ([P, P, P, i32, i32, i32, P, i32, P, P, P, P, i64, P, P], i32),
+                "gakco_gram_batch": ([P, P, i32, P], i32),
+                "gakco_batch_plan_create": ([P, P, i32, P, P], i32),
+                "gakco_batch_run": ([P, P], i32),
+                "gakco_batch_plan_destroy": ([P], None),
+                "gakco_resident_create": ([P, P, P, i32, i32, i32, i32, P, f64, P], i32),
+                "gakco_resident_destroy": ([P], None),
+                "gakco_resident_info": ([P, P, P, P, P, P], i32),
+                "gakco_rows": ([P, P, P, P, i32, P, P, P, P], i32),
+                "gakco_server_create": ([P, i32, i32, i32, sz, P], i32),
+                "gakco_server_submit": ([P, P, i32, ctypes.c_uint64], i32),
+                "gakco_server_cancel": ([P, ctypes.c_uint64], i32),
+                "gakco_server_poll": ([P, P, i32, P, i32], i32),
+                "gakco_server_destroy": ([P], i32),
+            }
+            for name, (args, res) in sig.items():
+                fn = getattr(L, name, None)
+                if fn is None:
+                    continue
+                fn.argtypes = args
+                fn.restype = res
+            _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise GakcoError(status, lib().gakco_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_inputs(seqs, lens, device):
+    seqs = torch.as_tensor(seqs).to(device=device, dtype=torch.int8).contiguous()
+    lens = torch.as_tensor(lens).to(device=device, dtype=torch.int32).contiguous()
+    if seqs.numel() == 0:
+        seqs = torch.zeros(1, dtype=torch.int8, device=device)
+    return seqs, lens
+
+
+class Context:
+    """A device, a scratch arena bounded by `hbm_budget` bytes, tuning knobs."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, tune: dict | None = None):
+        import json
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        js = json.dumps(tune).encode() if tune else None
+        _check(lib().gakco_ctx_create(device, hbm_budget, js, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gakco_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_param(self, name: str, value: int):
+        _check(lib().gakco_ctx_set_param(self._h, name.encode(), int(value)))
+
+    # ---------------------------------------------------------------- Gram --
+    def gram(self, seqs, lens, sigma: int, g: int, k: int, want_K: bool = True, want_Nm: bool = True,
+             want_Cm: bool = False, out: dict | None = None):
+        """Normalised kernel K [N,N] f64, N_m [M+1,N,N] i64, C_m [M+1,N,N] i64 (as requested)."""
+        seqs, lens = _dev_inputs(seqs, lens, self.device)
+        N, M = int(lens.numel()), g - k
+        out = dict(out or {})
+        if want_K and "K" not in out:
+            out["K"] = torch.empty((N, N), dtype=torch.float64, device=self.device)
+        if want_Nm and "Nm" not in out:
+            out["Nm"] = torch.empty((M + 1, N, N), dtype=torch.int64, device=self.device)
+        if want_Cm and "Cm" not in out:
+            out["Cm"] = torch.empty((M + 1, N, N), dtype=torch.int64, device=self.device)
+        _check(lib().gakco_gram(self._h, _ptr(seqs), _ptr(lens), N, sigma, g, k, _ptr(out.get("K")),
+                                _ptr(out.get("Nm")), _ptr(out.get("Cm")), _stream(self.device)))
+        return out
+
+    def gram_into(self, seqs, lens, N, sigma, g, k, K=None, Nm=None, Cm=None):
+        """Gram on device tensors already in place (no allocation here)."""
+        _check(lib().gakco_gram(self._h, _ptr(seqs), _ptr(lens), N, sigma, g, k, _ptr(K), _ptr(Nm), _ptr(Cm),
+                                _stream(self.device)))
+
+    def extract(self, seqs, lens, sigma: int, g: int):
+        seqs, lens = _dev_inputs(seqs, lens, self.device)
+        lh = lens.cpu().numpy()
+        T = ctypes.c_int64()
+        _check(lib().gakco_count_gmers(lh.ctypes.data_as(ctypes.c_void_p), len(lh), g, ctypes.byref(T)))
+        keys = torch.empty(max(T.value, 1), dtype=torch.int64, device=self.device)
+        sid = torch.empty(max(T.value, 1), dtype=torch.int32, device=self.device)
+        _check(lib().gakco_extract(self._h, _ptr(seqs), _ptr(lens), len(lh), sigma, g, _ptr(keys), _ptr(sid),
+                                   _stream(self.device)))
+        return keys[:T.value], sid[:T.value]
+
+    def mask_groups(self, seqs, lens, sigma: int, g: int, removed):
+        """Groups of one position set: list of (rep_index, [(sid, count), ...])."""
+        import numpy as np
+        seqs, lens = _dev_inputs(seqs, lens, self.device)
+        lh = lens.cpu().numpy()
+        T = ctypes.c_int64()
+        _check(lib().gakco_count_gmers(lh.ctypes.data_as(ctypes.c_void_p), len(lh), g, ctypes.byref(T)))
+        cap = max(T.value, 1)
+        rem = np.ascontiguousarray(sorted(removed), dtype=np.int32)
+        grp_off = np.zeros(cap + 1, dtype=np.int32)
+        grp_rep = np.zeros(cap, dtype=np.int32)
+        ent_sid = np.zeros(cap, dtype=np.int32)
+        ent_cnt = np.zeros(cap, dtype=np.int32)
+        ng = ctypes.c_int64()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().gakco_mask_groups(self._h, _ptr(seqs), _ptr(lens), len(lh), sigma, g,
+                                       vp(rem) if len(rem) else None, len(rem), vp(grp_off), vp(grp_rep),
+                                       vp(ent_sid), vp(ent_cnt), cap, ctypes.byref(ng), _stream(self.device)))
+        out = []
+        for q in range(ng.value):
+            a, b = grp_off[q], grp_off[q + 1]
+            out.append((int(grp_rep[q]), list(zip(ent_sid[a:b].tolist(), ent_cnt[a:b].tolist()))))
+        return out
+
+
+def version() -> str:
+    return lib().gakco_version().decode()

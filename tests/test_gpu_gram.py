@@ -1,0 +1,211 @@
+"""GPU parity of the Gram path against the CPU oracle (same seeded inputs).
+
+Integer outputs (g-mers, groups, C_m, N_m) must be bit-exact; the FP64
+normalised kernel must agree within 1e-12 relative error (the same formula,
+one sqrt and one division, evaluated in a possibly different order).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1704_07468_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def gk():
+    import torch
+    from paper_1704_07468_amd import gakco
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = gakco.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def oracle():
+    from oracle import oracle as orc
+    return orc
+
+
+def check_kn(got, want):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    zero = want == 0
+    assert (got[zero] == 0).all()
+    np.testing.assert_allclose(got[~zero], want[~zero], rtol=RTOL, atol=0)
+
+
+def run_and_compare(gk, d: wl.GramInput, want_cm=True):
+    print("case:", d.name, "N=%d sigma=%d g=%d k=%d" % (d.N, d.sigma, d.g, d.k), flush=True)
+    r = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k, want_Cm=want_cm)
+    o = oracle().kernel(d.seqs, d.lens, d.g, d.k)
+    np.testing.assert_array_equal(r["Nm"].cpu().numpy(), o["Nm"])
+    if want_cm:
+        np.testing.assert_array_equal(r["Cm"].cpu().numpy(), o["C"])
+    check_kn(r["K"].cpu().numpy(), o["Kn"])
+    return r, o
+
+
+# ------------------------------------------------------------------ stages --
+def test_extract_matches_oracle_gmers(gk):
+    for d in [wl.dna(N=30), wl.protein(N=40, lmin=3, lmax=60), wl.text(N=12, lmin=5, lmax=80)]:
+        keys, sid = gk.extract(d.seqs, d.lens, d.sigma, d.g)
+        sym, osid = oracle().gmers(d.seqs, d.lens, d.g)
+        b = max(1, int(np.ceil(np.log2(d.sigma))))
+        k = keys.cpu().numpy().view(np.uint64)
+        unpacked = np.stack([(k >> np.uint64(b * (d.g - 1 - j))) & np.uint64((1 << b) - 1)
+                             for j in range(d.g)], axis=1)
+        np.testing.assert_array_equal(unpacked.astype(np.int64), sym.astype(np.int64))
+        np.testing.assert_array_equal(sid.cpu().numpy(), osid)
+
+
+def _canon(groups, sym, removed):
+    out = {}
+    for rep, ents in groups:
+        key = tuple(int(c) for j, c in enumerate(sym[rep]) if j not in removed)
+        assert key not in out, "a reduced g-mer appears in two groups"
+        out[key] = tuple(ents)
+    return out
+
+
+@pytest.mark.parametrize("name", ["dna", "protein", "text"])
+def test_mask_groups_match_oracle(gk, name):
+    d = {"dna": wl.dna(N=40), "protein": wl.protein(N=60, lmin=5, lmax=120),
+         "text": wl.text(N=20, lmin=20, lmax=200)}[name]
+    sym, _ = oracle().gmers(d.seqs, d.lens, d.g)
+    rng = np.random.default_rng(5)
+    masks = [()] + [tuple(sorted(rng.choice(d.g, size=m, replace=False).tolist())) for m in range(1, d.M + 1)]
+    for removed in masks:
+        got = _canon(gk.mask_groups(d.seqs, d.lens, d.sigma, d.g, removed), sym, removed)
+        want = _canon(oracle().mask_groups(d.seqs, d.lens, d.g, removed), sym, removed)
+        assert got == want, "groups differ for removed positions %s" % (removed,)
+
+
+# ------------------------------------------------------------------- Gram --
+def test_gram_dna_full_config(gk):
+    run_and_compare(gk, wl.dna())
+
+
+def test_gram_protein_reduced(gk):
+    run_and_compare(gk, wl.protein(N=300))
+
+
+def test_gram_text_reduced(gk):
+    run_and_compare(gk, wl.text(N=60, lmin=200, lmax=600))
+
+
+def test_gram_fig2_example(gk):
+    seqs = np.array([0, 1, 0, 1, 0, 0, 0, 0, 1, 0], dtype=np.int8)
+    lens = np.array([5, 5], dtype=np.int32)
+    r = gk.gram(seqs, lens, 2, 3, 2, want_Cm=True)
+    assert r["Nm"][0, 0, 1].item() == 2
+    assert r["Cm"][1, 0, 1].item() == 9
+    assert r["Nm"][1, 0, 1].item() == 3
+
+
+@pytest.mark.parametrize("case", ["k_eq_g", "k_zero", "single_seq", "short_seqs", "sigma1", "gb64",
+                                  "many_buckets", "heavy_keys"])
+def test_gram_edge_cases(gk, case):
+    rng = np.random.default_rng(99)
+    if case == "k_eq_g":
+        d = wl.protein(N=50, lmin=5, lmax=80, g=5, k=5)
+    elif case == "k_zero":
+        d = wl.dna(N=20, length=15, g=5, k=0)
+    elif case == "single_seq":
+        d = wl.protein(N=1, lmin=30, lmax=30)
+    elif case == "short_seqs":
+        seqs, lens = wl.random_small(rng, 25, 0, 9, 4)
+        d = wl.GramInput("short", seqs, lens, 4, 6, 3)
+    elif case == "sigma1":
+        seqs, lens = wl.random_small(rng, 8, 0, 20, 1)
+        d = wl.GramInput("sigma1", seqs, lens, 1, 4, 2)
+    elif case == "gb64":  # 16 symbols of 4 bits fill the 64-bit key
+        seqs, lens = wl.random_small(rng, 12, 10, 40, 16)
+        d = wl.GramInput("gb64", seqs, lens, 16, 16, 14)
+    elif case == "many_buckets":
+        d = wl.protein(N=500, lmin=50, lmax=200, g=7, k=5)
+    elif case == "heavy_keys":  # small key space: buckets far above the LDS capacity
+        seqs, lens = wl.random_small(rng, 120, 100, 400, 2)
+        d = wl.GramInput("heavy", seqs, lens, 2, 8, 5)
+    run_and_compare(gk, d)
+
+
+def test_gram_symbol_out_of_range(gk):
+    from paper_1704_07468_amd import gakco
+    d = wl.dna(N=10)
+    bad = d.seqs.copy()
+    bad[17] = 4
+    with pytest.raises(gakco.GakcoError) as e:
+        gk.gram(bad, d.lens, 4, 6, 4)
+    assert e.value.status == gakco.ERANGE
+
+
+def test_gram_invalid_args(gk):
+    from paper_1704_07468_amd import gakco
+    d = wl.dna(N=10)
+    for sigma, g, k in [(0, 6, 4), (4, 0, 0), (4, 6, 7), (200, 6, 4)]:
+        with pytest.raises(gakco.GakcoError) as e:
+            gk.gram(d.seqs, d.lens, sigma, g, k)
+        assert e.value.status == gakco.EINVAL
+    with pytest.raises(gakco.GakcoError) as e:
+        gk.gram(d.seqs, d.lens, 36, 11, 4)  # 11 * 6 bits > 64
+    assert e.value.status == gakco.EUNSUPPORTED
+
+
+def test_gram_tuning_invariance(gk):
+    """Different bucket geometries give bit-identical integers (race check)."""
+    from paper_1704_07468_amd import gakco
+    d = wl.protein(N=200, lmin=50, lmax=300)
+    base = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+    for avg in (64, 2000):
+        c2 = gakco.Context(0, tune={"bucket_avg": avg})
+        r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+        assert (r["Nm"] == base["Nm"]).all().item()
+        assert (r["K"] == base["K"]).all().item()
+        c2.close()
+
+
+def test_gram_repeat_deterministic(gk):
+    d = wl.protein(N=150, lmin=50, lmax=300)
+    a = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+    b = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+    assert (a["Nm"] == b["Nm"]).all().item()
+    assert (a["K"] == b["K"]).all().item()
+
+
+def _sampled_full_config(gk, d, nsample, seed):
+    import torch
+    r = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+    Nm = r["Nm"]
+    K = r["K"]
+    # properties at full size
+    assert torch.equal(K, K.T)
+    assert torch.equal(Nm, Nm.transpose(1, 2))
+    dg = torch.diagonal(K)
+    assert torch.all((dg == 1.0) | (dg - 1.0).abs().le(1e-15))
+    assert (Nm >= 0).all().item()
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(0, d.N, size=nsample)
+    ys = rng.integers(0, d.N, size=nsample)
+    Nm_h = Nm[:, torch.as_tensor(xs), torch.as_tensor(ys)].cpu().numpy()
+    K_h = K[torch.as_tensor(xs), torch.as_tensor(ys)].cpu().numpy()
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        if x == y:
+            continue
+        nm, kk, kn = oracle().pair_entry(d.seq(int(x)), d.seq(int(y)), d.g, d.k)
+        np.testing.assert_array_equal(Nm_h[:, i], nm, err_msg="entry (%d,%d)" % (x, y))
+        assert abs(K_h[i] - kn) <= RTOL * abs(kn), (x, y, K_h[i], kn)
+
+
+def test_gram_protein_full_size_sampled(gk):
+    """The benchmark workload (N=3312) in the benchmark's configuration; sampled
+    entries recomputed one by one by the oracle on the pair."""
+    _sampled_full_config(gk, wl.protein(), 150, 1)
+
+
+def test_gram_text_full_size_sampled(gk):
+    _sampled_full_config(gk, wl.text(), 20, 2)
