@@ -72,6 +72,8 @@ const char *gakco_version(void);
  *   "dense_tau"     minimum distinct sequences for a group to be summed by
  *                   the int8 matrix-core path (0 disables that path)
  *   "bucket_avg"    target g-mers per hash bucket of the partition sort
+ *   "profile"       1 = time every launch phase with HIP events (see
+ *                   gakco_profile_get)
  * Missing keys keep their defaults.  Not thread-safe: one context per host
  * thread (serving uses its own internal contexts).
  * ------------------------------------------------------------------------ */
@@ -80,6 +82,15 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
 void gakco_ctx_destroy(gakco_ctx *ctx);
 /* Set one tuning parameter by name (same keys as tune_json). */
 gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value);
+
+/* Event profiler (enable with the "profile" parameter): per launch phase of
+ * the calls made on this context, the summed device time between HIP events
+ * recorded on the call's stream around the phase's launches, and the number
+ * of timed launches.  Phases are numbered 0 .. gakco_profile_phases()-1. */
+int32_t gakco_profile_phases(void);
+gakco_status gakco_profile_get(const gakco_ctx *ctx, int32_t phase, const char **name, double *total_ms,
+                               int64_t *launches);
+void gakco_profile_reset(gakco_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * gakco_gram -- the N x N kernel of one dataset (Algorithm 1 plus the

@@ -20,6 +20,8 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
     if (!strcmp(name, "dense_tau")) {
         if (v < 0) { set_error("dense_tau must be >= 0"); return GAKCO_EINVAL; }
         ctx->dense_tau = (int)v;
+    } else if (!strcmp(name, "profile")) {
+        ctx->prof_on = v != 0;
     } else if (!strcmp(name, "bucket_avg")) {
         if (v < 16 || v > kSortCap) { set_error("bucket_avg must be in 16..%d", kSortCap); return GAKCO_EINVAL; }
         ctx->bucket_avg = (int)v;
@@ -70,6 +72,7 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
     auto *ctx = new gakco_ctx();
     ctx->device = device;
     ctx->budget = hbm_budget ? hbm_budget : total / 2;
+    ctx->dense_tau = 64;
     // the row accumulation keeps ~5 KB of static LDS next to its rows
     ctx->lds_max = (size_t)lds > 8192 ? (size_t)lds - 8192 : 0;
     if (tune_json) {
@@ -88,6 +91,12 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
 void gakco_ctx_destroy(gakco_ctx *ctx)
 {
     if (!ctx) return;
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->dense_buf) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->dense_buf);
+    }
     if (ctx->arena) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
@@ -133,10 +142,10 @@ gakco_status gakco_gram(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens,
     GK_TRY(fetch_lens(jp, st));
     GK_TRY(plan_shape(ctx, jp, nullptr, 0));
     GK_TRY(plan_layout(ctx, p));
-    GK_TRY(plan_bind(ctx, p));
+    GK_TRY(plan_bind(ctx, p, st));
     GK_TRY(plan_upload(p, st));
     GK_TRY(plan_launch(ctx, p, st));
-    return plan_check_errors(p, st);
+    return plan_check_errors(ctx, p, st);
 }
 
 gakco_status gakco_extract(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma, int32_t g,
@@ -159,10 +168,10 @@ gakco_status gakco_extract(gakco_ctx *ctx, const int8_t *seqs, const int32_t *le
     jp.key_override = keys_out;
     jp.sid_override = reinterpret_cast<uint32_t *>(sid_out);
     GK_TRY(plan_layout(ctx, p));
-    GK_TRY(plan_bind(ctx, p));
+    GK_TRY(plan_bind(ctx, p, st));
     GK_TRY(plan_upload(p, st));
     GK_TRY(plan_launch(ctx, p, st));
-    return plan_check_errors(p, st);
+    return plan_check_errors(ctx, p, st);
 }
 
 gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma,
@@ -187,10 +196,10 @@ gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t
     static const int32_t none[1] = {0};
     GK_TRY(plan_shape(ctx, jp, m ? removed_host : none, m));
     GK_TRY(plan_layout(ctx, p));
-    GK_TRY(plan_bind(ctx, p));
+    GK_TRY(plan_bind(ctx, p, st));
     GK_TRY(plan_upload(p, st));
     GK_TRY(plan_launch(ctx, p, st));
-    GK_TRY(plan_check_errors(p, st));
+    GK_TRY(plan_check_errors(ctx, p, st));
     const MaskWork &W = p.mw[0];
     const uint32_t T = jp.T;
     std::vector<uint32_t> E(T);
@@ -225,6 +234,28 @@ gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t
     }
     *n_groups_out = ng;
     return GAKCO_OK;
+}
+
+int32_t gakco_profile_phases(void) { return PH_COUNT; }
+
+gakco_status gakco_profile_get(const gakco_ctx *ctx, int32_t phase, const char **name, double *total_ms,
+                               int64_t *launches)
+{
+    clear_error();
+    if (!ctx || phase < 0 || phase >= PH_COUNT) { set_error("bad arguments"); return GAKCO_EINVAL; }
+    if (name) *name = phase_name(phase);
+    if (total_ms) *total_ms = ctx->prof_ms[phase];
+    if (launches) *launches = ctx->prof_n[phase];
+    return GAKCO_OK;
+}
+
+void gakco_profile_reset(gakco_ctx *ctx)
+{
+    if (!ctx) return;
+    for (int i = 0; i < PH_COUNT; ++i) {
+        ctx->prof_ms[i] = 0;
+        ctx->prof_n[i] = 0;
+    }
 }
 
 }  // extern "C"

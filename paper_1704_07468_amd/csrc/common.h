@@ -68,10 +68,10 @@ struct MaskWork {
     uint32_t *E;      // [T] run entries: sequence | count << sb, grouped, sequence-sorted
     uint2 *info;      // [T] per g-mer: (entry index, entries to group end) for run leaders
     // int8 matrix-core path for groups with many distinct sequences
-    int8_t *D;         // rows of Npad counts (nullable)
+    int8_t *D;         // level's count matrix, sequence-major: D[sid * dstride + row] (nullable)
     uint32_t *dcount;  // rows used
-    uint32_t dcap;
-    int32_t Npad;
+    uint32_t dcap;     // row capacity
+    uint32_t dstride;  // bytes per sequence
     int32_t tau;       // min distinct sequences of a dense group (0 = off)
 };
 
@@ -310,7 +310,7 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         if (dense_on) {
             const uint32_t row = gaux[gi];
             if (row != 0xFFFFFFFFu) {
-                W.D[(size_t)row * (size_t)W.Npad + sid] = (int8_t)cnt;
+                W.D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)cnt;
                 len = 0;
             }
         }

@@ -21,5 +21,10 @@ hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, in
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
                              uint32_t nblocks, size_t lds_bytes, hipStream_t st);
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
+hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st);
+hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st);
+size_t dense_work_size();
+void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt,
+                     int64_t *C);
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
 }  // namespace gk

@@ -181,6 +181,8 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     Layout &L = p.lay;
     L = Layout{};
     p.output_bytes = 0;
+    p.dense_bytes = 0;
+    p.n_dense = 0;
     p.maxB = 0;
     p.maxM = 0;
     size_t nmask = 0, nb_total = 0;
@@ -201,6 +203,32 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
             p.output_bytes += N * N * 8 * ((jp.K_out ? 1 : 0) + (jp.Nm_out ? M1 : 0) + (jp.Cm_out ? M1 : 0));
             p.maxM = std::max(p.maxM, jp.M);
         }
+        // int8 matrix-core path: per level a sequence-major count matrix in
+        // the context's dense buffer, capacity bounded by the number of groups
+        // that can have tau distinct sequences
+        jp.dcap.assign((size_t)jp.M + 1, 0);
+        jp.o_dense.assign((size_t)jp.M + 1, 0);
+        jp.Ntile = (jp.N + 127) / 128 * 128;
+        if (jp.want_kernel && ctx->dense_tau > 0 && !jp.masks.empty()) {
+            const size_t limit = std::min<size_t>(ctx->budget / 8, 8ull << 30);
+            std::vector<double> want((size_t)jp.M + 1, 0.0);
+            double tot = 0;
+            for (int m = 0; m <= jp.M; ++m) {
+                want[(size_t)m] = (double)binom64(jp.g, m) * ((double)jp.T / ctx->dense_tau + 1.0);
+                tot += want[(size_t)m] * jp.Ntile;
+            }
+            const double scale = tot > (double)limit ? (double)limit / tot : 1.0;
+            for (int m = 0; m <= jp.M; ++m) {
+                uint64_t c = (uint64_t)(want[(size_t)m] * scale);
+                c = std::min<uint64_t>(c, 1u << 30);
+                c = (c + 31) / 32 * 32;
+                if (c < 32) continue;
+                jp.dcap[(size_t)m] = (uint32_t)c;
+                jp.o_dense[(size_t)m] = p.dense_bytes;
+                p.dense_bytes += (size_t)jp.Ntile * c;
+                p.n_dense += 1;
+            }
+        }
         jp.o_mask.resize(jp.masks.size());
         for (size_t i = 0; i < jp.masks.size(); ++i) {
             const int B = jp.level_B[(size_t)jp.masks[i].level];
@@ -213,7 +241,9 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     // flags (err per job) and the bucket counters of every mask, contiguous
     // so that one fill clears them
     p.mw.resize(nmask);
-    p.o_flags = L.take(p.jobs.size() * 4);
+    size_t nlev_total = 0;
+    for (auto &jp : p.jobs) nlev_total += (size_t)jp.M + 1;
+    p.o_flags = L.take((p.jobs.size() + nlev_total) * 4);  // error flags, then dense row counters
     p.o_bcnt = L.take(nb_total * 4);
     // descriptor blob
     Layout d;
@@ -271,6 +301,8 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         p.acc_prefix.push_back(pre);
     }
     p.d_acc = d.take(sizeof(AccWork) * std::max<size_t>(1, p.aw.size()), 64);
+    p.d_dense = d.take(dense_work_size() * std::max(1, p.n_dense), 64);
+    p.d_pdense = d.take(((size_t)p.n_dense + 1) * 4, 64);
     const size_t nj = p.jobs.size();
     p.d_pv = d.take((nj + 1) * 4, 64);
     p.d_px = d.take((nj + 1) * 4, 64);
@@ -282,9 +314,9 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     for (auto &pre : p.acc_prefix) p.d_pacc.push_back(d.take(pre.size() * 4, 64));
     p.desc_bytes = d.size;
     p.o_desc = L.take(p.desc_bytes);
-    if (L.size + p.output_bytes > ctx->budget) {
-        set_error("scratch %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB", L.size / 1e9,
-                  p.output_bytes / 1e9, ctx->budget / 1e9);
+    if (L.size + p.dense_bytes + p.output_bytes > ctx->budget) {
+        set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB",
+                  L.size / 1e9, p.dense_bytes / 1e9, p.output_bytes / 1e9, ctx->budget / 1e9);
         return GAKCO_EBUDGET;
     }
     return GAKCO_OK;
@@ -305,17 +337,33 @@ static gakco_status reserve_arena(gakco_ctx *ctx, size_t bytes)
     return GAKCO_OK;
 }
 
-gakco_status plan_bind(gakco_ctx *ctx, Plan &p)
+gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
     GK_TRY(reserve_arena(ctx, p.lay.size));
+    if (p.dense_bytes > ctx->dense_cap) {
+        if (ctx->dense_buf) {
+            GK_HIP(hipDeviceSynchronize());
+            GK_HIP(hipFree(ctx->dense_buf));
+            ctx->dense_buf = nullptr;
+            ctx->dense_cap = 0;
+        }
+        GK_HIP(hipMalloc(&ctx->dense_buf, p.dense_bytes));
+        ctx->dense_cap = p.dense_bytes;
+        ctx->dense_dirty = true;
+    }
+    if (ctx->dense_dirty && ctx->dense_buf) {
+        GK_HIP(launch_fill_u64(reinterpret_cast<uint64_t *>(ctx->dense_buf), ctx->dense_cap / 8, 0ull, st));
+        ctx->dense_dirty = false;
+    }
     char *base = (char *)ctx->arena;
     p.base = base;
     const size_t o_flags = p.o_flags, o_bcnt = p.o_bcnt;
     p.desc_host.assign(p.desc_bytes, 0);
     char *blob = p.desc_host.data();
     JobDev *jd = reinterpret_cast<JobDev *>(blob + p.d_jobs);
-    std::vector<uint32_t> pv(1, 0), px(1, 0), pt(1, 0), pb(1, 0), pd(1, 0), pf(1, 0);
-    size_t mi = 0, bc = 0;
+    std::vector<uint32_t> pv(1, 0), px(1, 0), pt(1, 0), pb(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0);
+    size_t mi = 0, bc = 0, lev_base = 0;
+    int di = 0;
     for (size_t j = 0; j < p.jobs.size(); ++j) {
         auto &jp = p.jobs[j];
         JobDev &J = jp.dev;
@@ -344,6 +392,18 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p)
         pd.push_back(pd.back() + (jp.want_kernel ? (uint32_t)((jp.N + kThreads - 1) / kThreads) : 0u));
         const uint32_t nt = (uint32_t)((jp.N + 31) / 32);
         pf.push_back(pf.back() + (jp.want_kernel ? nt * nt : 0u));
+        if (jp.want_kernel) {
+            const int ntile = jp.Ntile / 128;
+            for (int m = 0; m <= jp.M; ++m) {
+                if (!jp.dcap[(size_t)m]) continue;
+                dense_work_fill(blob + p.d_dense + dense_work_size() * (size_t)di, ctx->dense_buf + jp.o_dense[(size_t)m],
+                                reinterpret_cast<uint32_t *>(base + o_flags) + p.jobs.size() + lev_base + m,
+                                jp.dcap[(size_t)m], jp.dcap[(size_t)m], jp.N, ntile,
+                                J.C + (size_t)m * jp.N * jp.N);
+                pdn.push_back(pdn.back() + (uint32_t)(ntile * (ntile + 1) / 2));
+                ++di;
+            }
+        }
         for (size_t i = 0; i < jp.masks.size(); ++i, ++mi) {
             MaskWork &W = p.mw[mi];
             W = MaskWork{};
@@ -374,17 +434,27 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p)
             W.D = nullptr;
             W.dcount = nullptr;
             W.dcap = 0;
-            W.Npad = jp.Npad;
+            W.dstride = 0;
             W.tau = 0;
+            if (jp.want_kernel && (size_t)m < jp.dcap.size() && jp.dcap[(size_t)m]) {
+                W.D = ctx->dense_buf + jp.o_dense[(size_t)m];
+                W.dcount = reinterpret_cast<uint32_t *>(base + o_flags) + p.jobs.size() + lev_base + m;
+                W.dcap = jp.dcap[(size_t)m];
+                W.dstride = jp.dcap[(size_t)m];
+                W.tau = ctx->dense_tau;
+            }
             pt.push_back(pt.back() + (jp.T + kTile - 1) / kTile);
             pb.push_back(pb.back() + (uint32_t)nb);
         }
+        lev_base += (size_t)jp.M + 1;
     }
     if (!p.mw.empty()) memcpy(blob + p.d_masks, p.mw.data(), sizeof(MaskWork) * p.mw.size());
     if (!p.aw.empty()) memcpy(blob + p.d_acc, p.aw.data(), sizeof(AccWork) * p.aw.size());
     auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
     put(p.d_pv, pv); put(p.d_px, px); put(p.d_pt, pt); put(p.d_pb, pb); put(p.d_pd, pd); put(p.d_pf, pf);
     for (size_t i = 0; i < p.acc_prefix.size(); ++i) put(p.d_pacc[i], p.acc_prefix[i]);
+    put(p.d_pdense, pdn);
+    p.nb_dense = pdn.back();
     p.nb_v = pv.back(); p.nb_x = px.back(); p.nb_t = pt.back(); p.nb_b = pb.back(); p.nb_d = pd.back(); p.nb_f = pf.back();
     return GAKCO_OK;
 }
@@ -413,9 +483,58 @@ gakco_status plan_upload(Plan &p, hipStream_t st)
     return GAKCO_OK;
 }
 
+static const char *kPhaseNames[PH_COUNT] = {"fill", "validate", "extract", "bucket_count", "bucket_scan",
+                                            "bucket_scatter", "bucket_sort", "accumulate", "dense_mfma",
+                                            "diag", "finalize", "rows"};
+const char *phase_name(int phase) { return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : ""; }
+
+gakco_status prof_begin(gakco_ctx *ctx, hipStream_t st, size_t *slot)
+{
+    if (!ctx->prof_on) return GAKCO_OK;
+    while (ctx->ev_pool.size() < ctx->ev_used + 2) {
+        hipEvent_t e;
+        GK_HIP(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
+    *slot = ctx->ev_used;
+    ctx->ev_used += 2;
+    GK_HIP(hipEventRecord(ctx->ev_pool[*slot], st));
+    return GAKCO_OK;
+}
+
+gakco_status prof_end(gakco_ctx *ctx, hipStream_t st, int phase, size_t slot)
+{
+    if (!ctx->prof_on) return GAKCO_OK;
+    GK_HIP(hipEventRecord(ctx->ev_pool[slot + 1], st));
+    ctx->ev_pending.emplace_back(phase, slot);
+    return GAKCO_OK;
+}
+
+gakco_status prof_collect(gakco_ctx *ctx)
+{
+    for (auto &pe : ctx->ev_pending) {
+        float ms = 0.f;
+        GK_HIP(hipEventSynchronize(ctx->ev_pool[pe.second + 1]));
+        GK_HIP(hipEventElapsedTime(&ms, ctx->ev_pool[pe.second], ctx->ev_pool[pe.second + 1]));
+        ctx->prof_ms[pe.first] += ms;
+        ctx->prof_n[pe.first] += 1;
+    }
+    ctx->ev_pending.clear();
+    ctx->ev_used = 0;
+    return GAKCO_OK;
+}
+
+// Runs `launch` between two profiler events of phase `ph`.
+#define GK_PHASE(ph, launch)                         \
+    do {                                             \
+        size_t _slot = 0;                            \
+        GK_TRY(prof_begin(ctx, st, &_slot));         \
+        GK_HIP(launch);                              \
+        GK_TRY(prof_end(ctx, st, (ph), _slot));      \
+    } while (0)
+
 gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
-    (void)ctx;
     char *d = p.base + p.o_desc;
     const JobDev *jobs = reinterpret_cast<const JobDev *>(d + p.d_jobs);
     const MaskWork *masks = reinterpret_cast<const MaskWork *>(d + p.d_masks);
@@ -426,36 +545,47 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     const size_t o_flags = p.o_flags, o_bcnt = p.o_bcnt;
     size_t nbc = 0;
     for (auto &W : p.mw) nbc += (size_t)1 << W.B;
-    GK_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_flags), (size_t)nj, 0u, st));
-    GK_HIP(launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_bcnt), nbc, 0u, st));
+    size_t nflags = (size_t)nj;
+    for (auto &jp : p.jobs) nflags += (size_t)jp.M + 1;
+    GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_flags), nflags, 0u, st));
+    GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_bcnt), nbc, 0u, st));
     for (auto &jp : p.jobs)
         if (jp.want_kernel)
-            GK_HIP(launch_fill_u64(reinterpret_cast<uint64_t *>(jp.dev.C), (size_t)(jp.M + 1) * jp.N * jp.N, 0ull, st));
-    GK_HIP(launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
-    GK_HIP(launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
+            GK_PHASE(PH_FILL, launch_fill_u64(reinterpret_cast<uint64_t *>(jp.dev.C), (size_t)(jp.M + 1) * jp.N * jp.N, 0ull, st));
+    GK_PHASE(PH_VALIDATE, launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
+    GK_PHASE(PH_EXTRACT, launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
+    if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
     if (nm) {
-        GK_HIP(launch_bucket_count(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
-        GK_HIP(launch_bucket_scan(masks, nm, st));
-        GK_HIP(launch_bucket_scatter(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
-        GK_HIP(launch_bucket_sort(masks, P(p.d_pb), nm, p.nb_b, st));
+        GK_PHASE(PH_BCOUNT, launch_bucket_count(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
+        GK_PHASE(PH_BSCAN, launch_bucket_scan(masks, nm, st));
+        GK_PHASE(PH_BSCATTER, launch_bucket_scatter(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
+        GK_PHASE(PH_BSORT, launch_bucket_sort(masks, P(p.d_pb), nm, p.nb_b, st));
     }
     for (size_t gi = 0; gi < p.acc_groups.size(); ++gi) {
         const auto &grp = p.acc_groups[gi];
-        GK_HIP(launch_accumulate(jobs, masks, acc + grp.first, P(p.d_pacc[gi]), grp.second,
-                                 p.acc_prefix[gi].back(), p.acc_lds[gi], st));
+        GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, acc + grp.first, P(p.d_pacc[gi]), grp.second,
+                                             p.acc_prefix[gi].back(), p.acc_lds[gi], st));
+    }
+    if (p.n_dense) {
+        const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
+        ctx->dense_dirty = true;
+        GK_PHASE(PH_DENSE, launch_dense(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));
+        GK_PHASE(PH_DENSE, launch_dense_clear(dw, p.n_dense, st));
+        ctx->dense_dirty = false;
     }
     if (p.nb_d) {
-        GK_HIP(launch_diag(jobs, P(p.d_pd), nj, p.nb_d, p.maxM, st));
-        GK_HIP(launch_finalize(jobs, P(p.d_pf), nj, p.nb_f, p.maxM, st));
+        GK_PHASE(PH_DIAG, launch_diag(jobs, P(p.d_pd), nj, p.nb_d, p.maxM, st));
+        GK_PHASE(PH_FINALIZE, launch_finalize(jobs, P(p.d_pf), nj, p.nb_f, p.maxM, st));
     }
     return GAKCO_OK;
 }
 
-gakco_status plan_check_errors(Plan &p, hipStream_t st)
+gakco_status plan_check_errors(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
     std::vector<int32_t> flags(p.jobs.size(), 0);
     GK_HIP(hipMemcpyAsync(flags.data(), p.base + p.o_flags, flags.size() * 4, hipMemcpyDeviceToHost, st));
     GK_HIP(hipStreamSynchronize(st));
+    GK_TRY(prof_collect(ctx));
     gakco_status first = GAKCO_OK;
     for (size_t j = 0; j < flags.size(); ++j) {
         if (flags[j] & 1) {

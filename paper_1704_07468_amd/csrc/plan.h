@@ -9,15 +9,31 @@
 
 #include "../../include/gakco.h"
 #include "common.h"
+#include "launch.h"
+
+// Phases timed by the optional event profiler (hipEvents around launches).
+enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_BSORT, PH_ACCUM, PH_DENSE,
+               PH_DIAG, PH_FINALIZE, PH_ROWS, PH_COUNT };
 
 struct gakco_ctx {
     int device = 0;
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_pending;  // (phase, first of two events)
+    double prof_ms[PH_COUNT] = {};
+    int64_t prof_n[PH_COUNT] = {};
     size_t budget = 0;
     int dense_tau = 0;     // 0 = int8 matrix-core path off
     int bucket_avg = 512;  // target g-mers per hash bucket
     void *arena = nullptr;
     size_t arena_cap = 0;
     size_t lds_max = 0;    // dynamic LDS available to the row accumulation
+    // count matrices of the int8 matrix-core path: kept all-zero between
+    // calls (each call clears the rows it used)
+    int8_t *dense_buf = nullptr;
+    size_t dense_cap = 0;
+    bool dense_dirty = false;
 };
 
 namespace gk {
@@ -78,11 +94,11 @@ struct JobPlan {
     // layout offsets
     size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_err = 0, o_C = 0, o_Kd = 0, o_coef = 0,
            o_hco = 0;
-    size_t o_D = 0, o_dcount = 0;
     std::vector<size_t> o_mask;  // per mask: base of its buffers
-    std::vector<uint32_t> dcap;  // per level dense row capacity
-    size_t dense_row_bytes = 0;
-    int Npad = 0;
+    std::vector<uint32_t> dcap;  // per level dense row capacity (0 = level has no dense path)
+    std::vector<size_t> o_dense; // per level offset in the context's dense buffer
+    int Npad = 0;                // LDS row stride of the accumulation
+    int Ntile = 0;               // sequences padded to the dense tile edge
     bool own_C = false;
     uint64_t *key_override = nullptr;  // write g-mers to caller buffers (stage entry point)
     uint32_t *sid_override = nullptr;
@@ -110,16 +126,29 @@ struct Plan {
     std::vector<std::pair<int, int>> acc_groups;  // [first, count) of aw per launch
     std::vector<std::vector<uint32_t>> acc_prefix;
     std::vector<size_t> d_pacc;
+    // dense path
+    size_t d_dense = 0, d_pdense = 0;
+    uint32_t nb_dense = 0;
+    int n_dense = 0;
+    size_t dense_bytes = 0;
     char *base = nullptr;             // arena base
     size_t output_bytes = 0;
 };
 
 gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one, int m_one);
 gakco_status plan_layout(gakco_ctx *ctx, Plan &p);
-gakco_status plan_bind(gakco_ctx *ctx, Plan &p);  // arena + pointers + descriptor blob
+gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st);  // arena + pointers + descriptor blob
 gakco_status plan_upload(Plan &p, hipStream_t st);
 gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st);
 gakco_status fetch_lens(JobPlan &jp, hipStream_t st);
-gakco_status plan_check_errors(Plan &p, hipStream_t st);
+gakco_status plan_check_errors(gakco_ctx *ctx, Plan &p, hipStream_t st);
+
+// Event profiler: prof_begin/prof_end bracket one phase on a stream (no-ops
+// unless the context's profiler is on); prof_collect adds the elapsed times
+// of completed brackets after the stream has been synchronised.
+gakco_status prof_begin(gakco_ctx *ctx, hipStream_t st, size_t *slot);
+gakco_status prof_end(gakco_ctx *ctx, hipStream_t st, int phase, size_t slot);
+gakco_status prof_collect(gakco_ctx *ctx);
+const char *phase_name(int phase);
 
 }  // namespace gk

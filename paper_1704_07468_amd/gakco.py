@@ -74,6 +74,9 @@ def lib():
                 "gakco_server_cancel": ([P, ctypes.c_uint64], i32),
                 "gakco_server_poll": ([P, P, i32, P, i32], i32),
                 "gakco_server_destroy": ([P], i32),
+                "gakco_profile_phases": ([], i32),
+                "gakco_profile_get": ([P, i32, P, P, P], i32),
+                "gakco_profile_reset": ([P], None),
             }
             for name, (args, res) in sig.items():
                 fn = getattr(L, name, None)
@@ -130,6 +133,18 @@ class Context:
 
     def set_param(self, name: str, value: int):
         _check(lib().gakco_ctx_set_param(self._h, name.encode(), int(value)))
+
+    def profile(self) -> dict:
+        """{phase: (total_ms, launches)} from the event profiler."""
+        out = {}
+        for i in range(lib().gakco_profile_phases()):
+            nm, ms, n = ctypes.c_char_p(), ctypes.c_double(), ctypes.c_int64()
+            _check(lib().gakco_profile_get(self._h, i, ctypes.byref(nm), ctypes.byref(ms), ctypes.byref(n)))
+            out[nm.value.decode()] = (ms.value, n.value)
+        return out
+
+    def profile_reset(self):
+        lib().gakco_profile_reset(self._h)
 
     # ---------------------------------------------------------------- Gram --
     def gram(self, seqs, lens, sigma: int, g: int, k: int, want_K: bool = True, want_Nm: bool = True,

@@ -169,6 +169,43 @@ def test_gram_tuning_invariance(gk):
         c2.close()
 
 
+@pytest.mark.parametrize("tau", [0, 2, 16, 64])
+def test_gram_dense_path_parity(gk, tau):
+    """The int8 matrix-core path (groups with >= tau distinct sequences) gives
+    the oracle's integers for every threshold, including tau=2 where nearly
+    every group goes through it and tau=0 where none does."""
+    from paper_1704_07468_amd import gakco
+    c2 = gakco.Context(0, tune={"dense_tau": tau})
+    try:
+        for d in [wl.protein(N=300), wl.dna(N=150, length=120, g=6, k=3), wl.text(N=40, lmin=200, lmax=500)]:
+            print("case:", d.name, "tau", tau, flush=True)
+            r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k, want_Cm=True)
+            o = oracle().kernel(d.seqs, d.lens, d.g, d.k)
+            np.testing.assert_array_equal(r["Cm"].cpu().numpy(), o["C"])
+            np.testing.assert_array_equal(r["Nm"].cpu().numpy(), o["Nm"])
+            check_kn(r["K"].cpu().numpy(), o["Kn"])
+    finally:
+        c2.close()
+
+
+def test_gram_dense_counts_above_int8(gk):
+    """Groups whose per-sequence count exceeds 127 must stay on the exact
+    sparse path: long low-complexity sequences give counts in the hundreds."""
+    from paper_1704_07468_amd import gakco
+    rng = np.random.default_rng(3)
+    parts = [np.zeros(400, dtype=np.int8) for _ in range(6)] + [rng.integers(0, 2, 300).astype(np.int8) for _ in range(30)]
+    seqs = np.concatenate(parts)
+    lens = np.array([len(p) for p in parts], dtype=np.int32)
+    d = wl.GramInput("lowcomplexity", seqs, lens, 2, 6, 4)
+    c2 = gakco.Context(0, tune={"dense_tau": 2})
+    try:
+        r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k, want_Cm=True)
+        o = oracle().kernel(d.seqs, d.lens, d.g, d.k)
+        np.testing.assert_array_equal(r["Cm"].cpu().numpy(), o["C"])
+    finally:
+        c2.close()
+
+
 def test_gram_repeat_deterministic(gk):
     d = wl.protein(N=150, lmin=50, lmax=300)
     a = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
