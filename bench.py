@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=900, help="sequences in the oracle's sub-Gram")
     ap.add_argument("--profile-phases", action="store_true", help="print the per-phase table to stderr")
+    ap.add_argument("--dense-tau", type=int, default=None, help="override the int8 matrix-core threshold")
+    ap.add_argument("--bucket-avg", type=int, default=None, help="override the partition bucket size")
     return ap.parse_args()
 
 
@@ -88,7 +90,12 @@ def main():
     N, M = d.N, d.M
     K = torch.empty((N, N), dtype=torch.float64, device=dev)
     Nm = torch.empty((M + 1, N, N), dtype=torch.int64, device=dev)
-    ctx = gakco.Context(0)
+    tune = {}
+    if args.dense_tau is not None:
+        tune["dense_tau"] = args.dense_tau
+    if args.bucket_avg is not None:
+        tune["bucket_avg"] = args.bucket_avg
+    ctx = gakco.Context(0, tune=tune or None)
     for _ in range(args.warmup):
         ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
     torch.cuda.synchronize()

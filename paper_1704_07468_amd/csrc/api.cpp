@@ -72,7 +72,7 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
     auto *ctx = new gakco_ctx();
     ctx->device = device;
     ctx->budget = hbm_budget ? hbm_budget : total / 2;
-    ctx->dense_tau = 64;
+    ctx->dense_tau = 128;
     // the row accumulation keeps ~5 KB of static LDS next to its rows
     ctx->lds_max = (size_t)lds > 8192 ? (size_t)lds - 8192 : 0;
     if (tune_json) {
@@ -213,8 +213,9 @@ gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t
     // longest tail; every leader of the group shares the same end
     std::map<uint32_t, std::pair<uint32_t, uint32_t>> groups;  // end -> (first entry, rep g-mer)
     for (uint32_t t = 0; t < T; ++t) {
-        if (!info[t].y) continue;
-        const uint32_t end = info[t].x + info[t].y;
+        const uint32_t len = info[t].y & (uint32_t)((2ull << jp.sb) - 1);
+        if (!len) continue;
+        const uint32_t end = info[t].x + len;
         auto it = groups.find(end);
         if (it == groups.end() || info[t].x < it->second.first) groups[end] = {info[t].x, t};
     }

@@ -161,19 +161,24 @@ struct SortScratch {
     uint32_t wsum[kWaves];
 };
 
+constexpr int kE = 4;  // elements per thread per round of the radix passes and the segmentation
+
 // Stable LSD radix sort of n (key, value) pairs by the low `bits` bits of the
-// key, 8 bits per pass, ping-ponging between (k0,v0) and (k1,v1).  Each pass:
-// an LDS digit histogram, a block scan of it, then rounds of 256 elements in
-// which every wave ranks its lanes by digit with ballots (the lanes holding
-// the same digit form a ballot mask; a lane's rank is the population count of
-// that mask below it) and the waves' digit counts are combined in LDS.
-// `which` says where the data is on entry (0: k0/v0) and is updated.
-// Passes whose digit is the same for every element are skipped.
-template <typename KP, typename VP>
+// key, 8 bits per pass, ping-ponging between (k0,v0) and (k1,v1).  A pass is
+// an LDS digit histogram, a block scan of it, and rounds of 1024 elements: in
+// each round every wave ranks 4 consecutive groups of 64 elements by digit
+// with ballots -- the lanes holding the same digit form a ballot mask, a
+// lane's rank is the population count of that mask below it, and the lowest
+// lane of the mask advances the wave's running count of the digit with one
+// LDS atomic whose old value it shares by shuffle -- then the waves' counts
+// are combined.  Passes whose digit is the same for every element are
+// skipped.  `which` says where the data is on entry (0: k0/v0) and is updated.
+template <typename K, typename KP, typename VP>
 __device__ __forceinline__ void block_radix_sort(KP k0, VP v0, KP k1, VP v1, uint32_t n, int bits,
                                                  SortScratch &s, int &which)
 {
-    const int tid = threadIdx.x, wid = tid >> 6;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = __lane_id();
+    const uint64_t lt = lanemask_lt();
     for (int shift = 0; shift < bits; shift += 8) {
         KP sk = which ? k1 : k0;
         VP sv = which ? v1 : v0;
@@ -192,26 +197,38 @@ __device__ __forceinline__ void block_radix_sort(KP k0, VP v0, KP k1, VP v1, uin
         if (__syncthreads_or(c == n)) continue;  // one digit only: order unchanged
         s.base[tid] = ex;
         __syncthreads();
-        for (uint32_t r0 = 0; r0 < n; r0 += kThreads) {
-            const uint32_t i = r0 + tid;
-            const bool valid = i < n;
-            const uint64_t kk = valid ? (uint64_t)sk[i] : 0ull;
-            const uint32_t vv = valid ? (uint32_t)sv[i] : 0u;
-            const uint32_t d = (uint32_t)(kk >> shift) & 255u;
-            uint64_t peers = __ballot(valid);
+        for (uint32_t r0 = 0; r0 < n; r0 += kThreads * kE) {
+            K kk[kE];
+            uint32_t vv[kE], dd[kE], pp[kE];
 #pragma unroll
-            for (int bb = 0; bb < 8; ++bb) {
-                const uint64_t m = __ballot((d >> bb) & 1u);
-                peers &= ((d >> bb) & 1u) ? m : ~m;
+            for (int e = 0; e < kE; ++e) {
+                const uint32_t i = r0 + (uint32_t)(wid * 64 * kE + e * 64 + lane);
+                const bool ok = i < n;
+                kk[e] = ok ? (K)sk[i] : (K)0;
+                vv[e] = ok ? (uint32_t)sv[i] : 0u;
+                dd[e] = ok ? ((uint32_t)(kk[e] >> shift) & 255u) : 256u;
+                uint64_t peers = __ballot(ok);
+#pragma unroll
+                for (int bb = 0; bb < 8; ++bb) {
+                    const uint64_t m = __ballot((dd[e] >> bb) & 1u);
+                    peers &= ((dd[e] >> bb) & 1u) ? m : ~m;
+                }
+                const uint32_t rank = __popcll(peers & lt);
+                uint32_t old = 0;
+                if (ok && rank == 0) old = atomicAdd(&s.wcnt[wid][dd[e]], (uint32_t)__popcll(peers));
+                const int leader = peers ? (__ffsll((long long)peers) - 1) : lane;
+                old = __shfl(old, leader, 64);
+                pp[e] = old + rank;
             }
-            const uint32_t rank = __popcll(peers & lanemask_lt());
-            if (valid && rank == 0) s.wcnt[wid][d] = __popcll(peers);
             __syncthreads();
-            if (valid) {
-                uint32_t off = s.base[d];
-                for (int w = 0; w < wid; ++w) off += s.wcnt[w][d];
-                dk[off + rank] = kk;
-                dv[off + rank] = vv;
+#pragma unroll
+            for (int e = 0; e < kE; ++e) {
+                if (dd[e] < 256u) {
+                    uint32_t off = s.base[dd[e]];
+                    for (int w = 0; w < wid; ++w) off += s.wcnt[w][dd[e]];
+                    dk[off + pp[e]] = kk[e];
+                    dv[off + pp[e]] = vv[e];
+                }
             }
             __syncthreads();
             uint32_t add = 0;
@@ -247,7 +264,9 @@ __device__ __forceinline__ uint32_t last_le(UP a, uint32_t n, uint32_t v)
 // gets (entry index, entries left to the group end), every other g-mer
 // (0, 0).  Groups with at least tau distinct sequences and counts <= 127
 // become rows of the int8 matrix-core path instead (info length 0).
-// rpos, gsr, gaux: scratch of n entries each.
+// rpos, gsr, gaux: scratch of n entries each.  Runs and groups are found in
+// rounds of 1024 elements, 4 consecutive ones per thread, with one block scan
+// per round for each.
 template <typename KP, typename VP, typename UP>
 __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos, UP gsr, UP gaux,
                                               const MaskWork &W, uint32_t ebase, uint32_t *wsum)
@@ -255,26 +274,31 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
     const int tid = threadIdx.x;
     const int sb = W.sb;
     const uint64_t sidmask = bits_mask(sb);
-    // runs
-    uint32_t R = 0;
-    for (uint32_t r0 = 0; r0 < n; r0 += kThreads) {
-        const uint32_t i = r0 + tid;
-        const bool rs = (i < n) && (i == 0 || fk[i] != fk[i - 1]);
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(rs ? 1u : 0u, wsum, &tot);
-        if (rs) rpos[R + ex] = i;
-        R += tot;
-    }
-    __syncthreads();
-    // groups (in run indices)
-    uint32_t G = 0;
-    for (uint32_t r0 = 0; r0 < R; r0 += kThreads) {
-        const uint32_t r = r0 + tid;
-        const bool gs = (r < R) && (r == 0 || (fk[rpos[r]] >> sb) != (fk[rpos[r - 1]] >> sb));
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(gs ? 1u : 0u, wsum, &tot);
-        if (gs) gsr[G + ex] = r;
-        G += tot;
+    uint32_t R = 0, G = 0;
+    for (uint32_t r0 = 0; r0 < n; r0 += kThreads * kE) {
+        const uint32_t i0 = r0 + (uint32_t)tid * kE;
+        uint32_t rsf = 0, gsf = 0;  // bit e: element i0+e starts a run / a group
+        uint64_t prev = (i0 > 0 && i0 <= n) ? (uint64_t)fk[i0 - 1] : 0ull;
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const uint32_t i = i0 + e;
+            if (i < n) {
+                const uint64_t cur = (uint64_t)fk[i];
+                if (i == 0 || cur != prev) rsf |= 1u << e;
+                if (i == 0 || (cur >> sb) != (prev >> sb)) gsf |= 1u << e;
+                prev = cur;
+            }
+        }
+        uint32_t rtot, gtot;
+        uint32_t rx = block_excl_scan((uint32_t)__popc(rsf), wsum, &rtot);
+        uint32_t gx = block_excl_scan((uint32_t)__popc(gsf), wsum, &gtot);
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            if (gsf & (1u << e)) gsr[G + gx++] = R + rx;
+            if (rsf & (1u << e)) rpos[R + rx++] = i0 + e;
+        }
+        R += rtot;
+        G += gtot;
     }
     __syncthreads();
     const bool dense_on = (W.tau > 0) && (W.D != nullptr);
@@ -301,7 +325,7 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         const uint32_t p = rpos[r];
         const uint32_t pe = (r + 1 < R) ? rpos[r + 1] : n;
         const uint32_t cnt = pe - p;
-        const uint32_t sid = (uint32_t)(fk[p] & sidmask);
+        const uint32_t sid = (uint32_t)((uint64_t)fk[p] & sidmask);
         const uint32_t gi = last_le(gsr, G, r);
         const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
         const uint32_t e = ebase + r;
@@ -314,10 +338,25 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
                 len = 0;
             }
         }
-        W.info[fv[p]] = make_uint2(e, len);
+        // y: entries to the group end in the low sb+1 bits, the run count above
+        W.info[fv[p]] = make_uint2(e, len ? (len | (cnt << (sb + 1))) : 0u);
     }
     for (uint32_t i = tid; i < n; i += kThreads)
         if (i > 0 && fk[i] == fk[i - 1]) W.info[fv[i]] = make_uint2(0u, 0u);
+}
+
+// Block -> (item, block within item): arithmetic when every item has the
+// same number of blocks, else a search of the per-item block prefix.
+__device__ __forceinline__ void map_block(const uint32_t *prefix, int n, uint32_t uniform, uint32_t bid, int &item,
+                                          uint32_t &sub)
+{
+    if (uniform) {
+        item = (int)(bid / uniform);
+        sub = bid - (uint32_t)item * uniform;
+    } else {
+        item = find_item(prefix, n, bid);
+        sub = bid - prefix[item];
+    }
 }
 
 }  // namespace gk

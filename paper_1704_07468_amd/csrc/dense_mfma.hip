@@ -19,68 +19,146 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kDTile = 128;           // output tile edge
-constexpr uint32_t kDFlush = 65536;   // rows per exact int32 partial sum
+constexpr int kDK = 64;               // rows (k) staged per LDS buffer
+constexpr int kDRow = kDK + 16;       // padded LDS row: 80 bytes keeps 16-byte reads conflict-free
+constexpr uint32_t kDSplitRows = 65536;  // rows per split: int32 partials stay exact
 
 struct DenseWork {
     int8_t *Dt;              // [Npad][stride] counts, zero beyond the used rows
     const uint32_t *count;   // rows used (device counter)
-    uint32_t cap;            // row capacity
-    uint32_t stride;         // bytes per sequence (multiple of 32, >= cap)
-    int32_t N, nt;           // sequences, tiles per edge
+    uint32_t cap;            // row capacity (<= S * kDSplitRows)
+    uint32_t stride;         // bytes per sequence (multiple of kDK, >= cap)
+    int32_t N, nt, S;        // sequences, tiles per edge, row splits
     int64_t *C;              // C_m [N][N]
+    int32_t *P;              // partial tiles [nt*(nt+1)/2][S][128*128]
 };
+
+// Rows [r0, r1) of split s when R rows are used.
+__device__ __forceinline__ void split_range(uint32_t R, int S, int s, uint32_t &r0, uint32_t &r1)
+{
+    const uint32_t per = ((R + S - 1) / S + kDK - 1) / kDK * kDK;
+    r0 = min(R, per * (uint32_t)s);
+    r1 = min(R, r0 + per);
+}
+
+__device__ __forceinline__ void tile_of(int f, int nt, int &I, int &J)
+{
+    I = 0;
+    while (f >= nt - I) {
+        f -= nt - I;
+        ++I;
+    }
+    J = I + f;
+}
 
 // v_mfma_i32_32x32x32_i8 operand layout: lane l supplies row/column (l % 32)
 // and 16 consecutive k values starting at 16*(l/32); accumulator v of lane l
 // is element (8*(v/4) + 4*(l/32) + v%4, l % 32).
+// One block = one 128x128 upper tile x one split of the rows.  The A (rows
+// of the tile) and B (columns) operand slabs of 64 rows are staged through
+// double-buffered LDS with coalesced 16-byte loads; each wave computes a
+// 64x64 quarter as 2x2 MFMA tiles.  The exact int32 partial tile is stored
+// for the reduction.
 __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__restrict__ dw, const uint32_t *__restrict__ bprefix,
                                                          int nwork)
 {
+    __shared__ __attribute__((aligned(16))) int8_t sA[2][kDTile][kDRow];
+    __shared__ __attribute__((aligned(16))) int8_t sB[2][kDTile][kDRow];
     const int wi = find_item(bprefix, nwork, blockIdx.x);
     const DenseWork &W = dw[wi];
     const uint32_t R = min(*W.count, W.cap);
-    if (R == 0) return;
-    // flat upper-tile index -> (I, J), I <= J
-    int f = (int)(blockIdx.x - bprefix[wi]);
-    int I = 0;
-    while (f >= W.nt - I) {
-        f -= W.nt - I;
-        ++I;
-    }
-    const int J = I + f;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int flat = (int)(blockIdx.x - bprefix[wi]);
+    const int f = flat / W.S, sp = flat - f * W.S;
+    uint32_t r0, r1;
+    split_range(R, W.S, sp, r0, r1);
+    if (r0 >= r1) return;
+    int I, J;
+    tile_of(f, W.nt, I, J);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wx = wave & 1, wy = wave >> 1;
-    const int x0 = I * kDTile + wx * 64, y0 = J * kDTile + wy * 64;
-    const int8_t *pa0 = W.Dt + (size_t)(x0 + (lane & 31)) * W.stride + 16 * (lane >> 5);
-    const int8_t *pa1 = pa0 + (size_t)32 * W.stride;
-    const int8_t *pb0 = W.Dt + (size_t)(y0 + (lane & 31)) * W.stride + 16 * (lane >> 5);
-    const int8_t *pb1 = pb0 + (size_t)32 * W.stride;
-    const int N = W.N;
-    for (uint32_t r0 = 0; r0 < R; r0 += kDFlush) {
-        const uint32_t r1 = min(R, r0 + kDFlush);
-        v16i acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-        for (uint32_t r = r0; r < r1; r += 32) {
-            const v4i a0 = *reinterpret_cast<const v4i *>(pa0 + r);
-            const v4i a1 = *reinterpret_cast<const v4i *>(pa1 + r);
-            const v4i b0 = *reinterpret_cast<const v4i *>(pb0 + r);
-            const v4i b1 = *reinterpret_cast<const v4i *>(pb1 + r);
+    // staging: thread -> (row, 16-byte column) pairs of the 128 x 64 slabs
+    const int lr = tid >> 2, lc = (tid & 3) * 16;  // rows lr and lr + 64
+    const int8_t *ga = W.Dt + (size_t)(I * kDTile + lr) * W.stride + lc;
+    const int8_t *gb = W.Dt + (size_t)(J * kDTile + lr) * W.stride + lc;
+    const size_t s64 = (size_t)64 * W.stride;
+    v4i pa0, pa1, pb0, pb1;
+    auto gload = [&](uint32_t r) {
+        pa0 = *reinterpret_cast<const v4i *>(ga + r);
+        pa1 = *reinterpret_cast<const v4i *>(ga + s64 + r);
+        pb0 = *reinterpret_cast<const v4i *>(gb + r);
+        pb1 = *reinterpret_cast<const v4i *>(gb + s64 + r);
+    };
+    auto lstore = [&](int buf) {
+        *reinterpret_cast<v4i *>(&sA[buf][lr][lc]) = pa0;
+        *reinterpret_cast<v4i *>(&sA[buf][lr + 64][lc]) = pa1;
+        *reinterpret_cast<v4i *>(&sB[buf][lr][lc]) = pb0;
+        *reinterpret_cast<v4i *>(&sB[buf][lr + 64][lc]) = pb1;
+    };
+    v16i acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+    const int fr = lane & 31, fk = 16 * (lane >> 5);
+    gload(r0);
+    lstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (uint32_t r = r0; r < r1; r += kDK) {
+        const bool more = r + kDK < r1;
+        if (more) gload(r + kDK);
+#pragma unroll
+        for (int kk = 0; kk < kDK; kk += 32) {
+            const v4i a0 = *reinterpret_cast<const v4i *>(&sA[buf][wx * 64 + fr][kk + fk]);
+            const v4i a1 = *reinterpret_cast<const v4i *>(&sA[buf][wx * 64 + 32 + fr][kk + fk]);
+            const v4i b0 = *reinterpret_cast<const v4i *>(&sB[buf][wy * 64 + fr][kk + fk]);
+            const v4i b1 = *reinterpret_cast<const v4i *>(&sB[buf][wy * 64 + 32 + fr][kk + fk]);
             acc00 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc00, 0, 0, 0);
             acc01 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b1, acc01, 0, 0, 0);
             acc10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, acc10, 0, 0, 0);
             acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc11, 0, 0, 0);
         }
-        auto flush = [&](const v16i &acc, int xb, int yb) {
-            const int y = yb + (lane & 31);
+        if (more) {
+            lstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    int32_t *P = W.P + ((size_t)f * W.S + sp) * (kDTile * kDTile);
+    auto put = [&](const v16i &acc, int xb, int yb) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int x = xb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                if (x < N && y < N && x <= y && acc[v]) W.C[(size_t)x * N + y] += (int64_t)acc[v];
-            }
-        };
-        flush(acc00, x0, y0);
-        flush(acc01, x0, y0 + 32);
-        flush(acc10, x0 + 32, y0);
-        flush(acc11, x0 + 32, y0 + 32);
+        for (int v = 0; v < 16; ++v) {
+            const int xl = xb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            P[xl * kDTile + yb + (lane & 31)] = acc[v];
+        }
+    };
+    put(acc00, wx * 64, wy * 64);
+    put(acc01, wx * 64, wy * 64 + 32);
+    put(acc10, wx * 64 + 32, wy * 64);
+    put(acc11, wx * 64 + 32, wy * 64 + 32);
+}
+
+// C_m[x][y] += sum over the non-empty splits of the partial tiles (x <= y).
+__global__ __launch_bounds__(kThreads) void k_dense_reduce(const DenseWork *__restrict__ dw, const uint32_t *__restrict__ tprefix,
+                                                           int nwork)
+{
+    const int wi = find_item(tprefix, nwork, blockIdx.x);
+    const DenseWork &W = dw[wi];
+    const uint32_t R = min(*W.count, W.cap);
+    if (R == 0) return;
+    const int f = (int)(blockIdx.x - tprefix[wi]);
+    int I, J;
+    tile_of(f, W.nt, I, J);
+    int ns = 0;
+    for (int s = 0; s < W.S; ++s) {
+        uint32_t r0, r1;
+        split_range(R, W.S, s, r0, r1);
+        if (r0 < r1) ns = s + 1;
+    }
+    const int N = W.N;
+    const int32_t *P = W.P + (size_t)f * W.S * (kDTile * kDTile);
+    for (int e = threadIdx.x; e < kDTile * kDTile; e += kThreads) {
+        const int x = I * kDTile + e / kDTile, y = J * kDTile + e % kDTile;
+        if (x >= N || y >= N || x > y) continue;
+        int64_t sum = 0;
+        for (int s = 0; s < ns; ++s) sum += P[(size_t)s * (kDTile * kDTile) + e];
+        if (sum) W.C[(size_t)x * N + y] += sum;
     }
 }
 
@@ -89,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_clear(const DenseWork *__res
 {
     const DenseWork &W = dw[blockIdx.y];
     const uint32_t R = min(*W.count, W.cap);
-    const uint32_t nv = (R + 15) / 16;  // 16-byte words per sequence row (stride is a multiple of 32)
+    const uint32_t nv = (R + 15) / 16;  // 16-byte words per sequence row (stride is a multiple of 64)
     const size_t total = (size_t)W.N * nv;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (size_t)gridDim.x * kThreads) {
         const size_t x = i / nv, q = i - x * nv;
@@ -98,10 +176,14 @@ __global__ __launch_bounds__(kThreads) void k_dense_clear(const DenseWork *__res
     (void)nwork;
 }
 
-hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st)
+hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks,
+                        const uint32_t *tprefix, uint32_t ntiles, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
     hipLaunchKernelGGL(k_dense_syrk, dim3(nblocks), dim3(kThreads), 0, st, dw, bprefix, nwork);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dense_reduce, dim3(ntiles), dim3(kThreads), 0, st, dw, tprefix, nwork);
     return hipGetLastError();
 }
 
@@ -113,11 +195,14 @@ hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st)
 }
 
 size_t dense_work_size() { return sizeof(DenseWork); }
+int dense_tile() { return kDTile; }
+int dense_kchunk() { return kDK; }
+uint32_t dense_split_rows() { return kDSplitRows; }
 
-void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt,
-                     int64_t *C)
+void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt, int S,
+                     int64_t *C, int32_t *P)
 {
-    DenseWork w{Dt, count, cap, stride, N, nt, C};
+    DenseWork w{Dt, count, cap, stride, N, nt, S, C, P};
     *reinterpret_cast<DenseWork *>(dst) = w;
 }
 

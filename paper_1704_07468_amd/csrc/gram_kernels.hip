@@ -55,12 +55,16 @@ __global__ __launch_bounds__(kThreads) void k_extract(const JobDev *__restrict__
 
 // --------------------------------------------------------- bucket count --
 // Histogram of bucket = top B bits of mix_w(reduced key) per mask.
-__global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix, int nitems)
+__global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
+                                                           int nitems, uint32_t uniform)
 {
     extern __shared__ uint32_t hist[];
-    const int it = find_item(bprefix, nitems, blockIdx.x);
+    int it;
+    uint32_t tile;
+    map_block(bprefix, nitems, uniform, blockIdx.x, it, tile);
     const MaskWork &W = items[it];
-    const uint32_t t0 = (blockIdx.x - bprefix[it]) * kTile;
+    const uint32_t t0 = tile * kTile;
+    if (t0 >= W.T) return;
     const uint32_t nb = 1u << W.B;
     for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
     __syncthreads();
@@ -100,14 +104,19 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
 }
 
 // ------------------------------------------------------- bucket scatter --
-// Place (composite, g-mer index) of every g-mer into its bucket.  The order
-// inside a bucket is arbitrary; the bucket sort restores it.
-__global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix, int nitems)
+// Place (composite, g-mer index) of every g-mer into its bucket; composites
+// of at most 32 bits are stored as 32-bit words.  The order inside a bucket
+// is arbitrary; the bucket sort restores it.
+__global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
+                                                             int nitems, uint32_t uniform)
 {
     extern __shared__ uint32_t hist[];
-    const int it = find_item(bprefix, nitems, blockIdx.x);
+    int it;
+    uint32_t tile;
+    map_block(bprefix, nitems, uniform, blockIdx.x, it, tile);
     const MaskWork &W = items[it];
-    const uint32_t t0 = (blockIdx.x - bprefix[it]) * kTile;
+    const uint32_t t0 = tile * kTile;
+    if (t0 >= W.T) return;
     const uint32_t nb = 1u << W.B;
     constexpr int Q = kTile / kThreads;
     for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
@@ -132,11 +141,13 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
         if (c) hist[i] = atomicAdd(&W.bcur[i], c);
     }
     __syncthreads();
+    const bool narrow = W.cb <= 32;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (bk[q] != 0xFFFFFFFFu) {
             const uint32_t pos = hist[bk[q]] + rk[q];
-            W.comp[pos] = cp[q];
+            if (narrow) reinterpret_cast<uint32_t *>(W.comp)[pos] = (uint32_t)cp[q];
+            else W.comp[pos] = cp[q];
             W.idx[pos] = t0 + q * kThreads + threadIdx.x;
         }
     }
@@ -144,105 +155,127 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
 
 // ---------------------------------------------------- bucket sort+segment --
 // One block per (mask, bucket): radix-sort the bucket by (hash rest,
-// sequence) -- in LDS when it fits, else in global memory -- then segment it
-// into groups and runs.
-__global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix, int nitems)
+// sequence) -- in LDS when it holds at most CAP g-mers, else in global
+// memory -- then segment it into groups and runs.  K is the composite word
+// (32 or 64 bits).  The small variant takes buckets of 1..kSmallCap g-mers,
+// the big one the rest.
+constexpr int kSmallCap = 1024;
+
+template <typename K, int CAP, bool BIG>
+__global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
+                                                          int nitems, uint32_t uniform)
 {
-    __shared__ uint64_t kA[kSortCap], kB[kSortCap];
-    __shared__ uint32_t vA[kSortCap], vB[kSortCap];
+    constexpr bool W64 = sizeof(K) == 8;
+    __shared__ K kA[CAP], kB[CAP];
+    __shared__ uint32_t vA[CAP], vB[CAP];
+    __shared__ uint32_t xs[W64 ? 1 : CAP];
     __shared__ SortScratch ss;
-    const int it = find_item(bprefix, nitems, blockIdx.x);
+    int it;
+    uint32_t bucket;
+    map_block(bprefix, nitems, uniform, blockIdx.x, it, bucket);
     const MaskWork &W = items[it];
-    const uint32_t bucket = blockIdx.x - bprefix[it];
+    if (bucket >= (1u << W.B)) return;
     const uint32_t base = W.boff[bucket];
     const uint32_t n = W.boff[bucket + 1] - base;
-    if (n == 0) return;
-    if (n <= (uint32_t)kSortCap) {
+    if (n == 0 || (!BIG && n > (uint32_t)kSmallCap) || (BIG && n <= (uint32_t)kSmallCap)) return;
+    K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
+    if (n <= (uint32_t)CAP) {
         for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
-            kA[i] = W.comp[base + i];
+            kA[i] = gc[base + i];
             vA[i] = W.idx[base + i];
         }
         __syncthreads();
         int which = 0;
-        block_radix_sort(kA, vA, kB, vB, n, W.cb, ss, which);
+        block_radix_sort<K>(kA, vA, kB, vB, n, W.cb, ss, which);
         __syncthreads();
-        uint64_t *fk = which ? kB : kA;
+        K *fk = which ? kB : kA;
         uint32_t *fv = which ? vB : vA;
         uint32_t *fr = reinterpret_cast<uint32_t *>(which ? kA : kB);
         uint32_t *fx = which ? vA : vB;
-        block_segment(fk, fv, n, fr, fr + kSortCap, fx, W, base, ss.wsum);
+        if (W64) block_segment(fk, fv, n, fr, fr + CAP, fx, W, base, ss.wsum);
+        else block_segment(fk, fv, n, fr, fx, xs, W, base, ss.wsum);
     } else {
         int which = 0;
-        block_radix_sort(W.comp + base, W.idx + base, W.comp2 + base, W.idx2 + base, n, W.cb, ss, which);
+        block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which);
         __syncthreads();
-        uint64_t *fk = (which ? W.comp2 : W.comp) + base;
+        K *fk = (which ? gc2 : gc) + base;
         uint32_t *fv = (which ? W.idx2 : W.idx) + base;
-        uint32_t *fr = reinterpret_cast<uint32_t *>((which ? W.comp : W.comp2) + base);
+        uint32_t *fr = reinterpret_cast<uint32_t *>(which ? gc : gc2);
         uint32_t *fx = (which ? W.idx : W.idx2) + base;
-        block_segment(fk, fv, n, fr, fr + n, fx, W, base, ss.wsum);
+        // scratch: this bucket's slice of the free composite array (2n
+        // words), or for 32-bit composites its slice of each half
+        if (W64) block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum);
+        else block_segment(fk, fv, n, fr + base, fr + (size_t)W.T + base, fx, W, base, ss.wsum);
     }
 }
 
 // ---------------------------------------------------------- accumulation --
-// One block owns row X of every C_m in its level range, as int32 counters in
-// LDS.  For each mask and each g-mer of X that leads a run (X's entry in its
-// group), the entries from X's own to the group end -- exactly the sequences
-// Y >= X of the group, since entries are sequence-sorted -- add
-// count_X * count_Y to row[m][Y] (Algorithm 1 countAndUpdate, upper
-// triangle).  The work of 256 runs at a time is spread evenly over the
-// threads by a scan of the run lengths.  The rows are then added into the
-// int64 C_m.
+// One block owns row X of C_m for one level m, as int32 counters in LDS.  For
+// each mask of the level and each g-mer of X that leads a run (X's entry in
+// its group), the entries from X's own to the group end -- exactly the
+// sequences Y >= X of the group, since entries are sequence-sorted -- add
+// count_X * count_Y to row[Y] (Algorithm 1 countAndUpdate, upper triangle).
+// Each wave consumes its own chunks of 64 (mask, g-mer) items; a wave scan of
+// their run lengths spreads the chunk's updates evenly over the lanes, so the
+// loop has no block barrier.  The row is then added into the int64 C_m.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
                                                          const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
 {
     extern __shared__ uint32_t acc[];
-    __shared__ uint32_t pre[kThreads];
-    __shared__ uint64_t iptr[kThreads];
-    __shared__ uint32_t icx[kThreads];
-    __shared__ uint32_t ilev[kThreads];
-    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t pre[kWaves][64];
+    __shared__ uint64_t iptr[kWaves][64];
+    __shared__ uint32_t icx[kWaves][64];
+    __shared__ uint32_t ioff[kWaves][64];
     const int a = find_item(bprefix, nacc, blockIdx.x);
     const AccWork &A = aw[a];
     const JobDev &J = jobs[A.job];
     const int X = (int)(blockIdx.x - bprefix[a]);
     const int N = J.N;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     const int sb = J.sb;
     const uint32_t sidmask = (uint32_t)bits_mask(sb);
+    const uint32_t lmask = (uint32_t)bits_mask(sb + 1);
     const uint32_t t0 = J.gstart[X];
     const uint32_t ng = J.gstart[X + 1] - t0;
-    if (ng == 0) return;  // no g-mers: the row stays 0
+    if (ng == 0 || A.nmask == 0) return;  // nothing to add: the row stays 0
     const int npad = A.Npad;
     for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
     __syncthreads();
     const uint32_t total = (uint32_t)A.nmask * ng;
-    for (uint32_t q0 = 0; q0 < total; q0 += kThreads) {
-        const uint32_t q = q0 + tid;
+    for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
+        const uint32_t q = c0 + lane;
         uint32_t len = 0;
         if (q < total) {
             const uint32_t s = q / ng;
             const uint32_t t = t0 + (q - s * ng);
             const MaskWork &W = items[A.mfirst + s];
             const uint2 inf = W.info[t];
-            len = inf.y;
+            len = inf.y & lmask;
             if (len) {
-                const uint32_t *ep = W.E + inf.x;
-                iptr[tid] = reinterpret_cast<uint64_t>(ep);
-                icx[tid] = ep[0] >> sb;
-                ilev[tid] = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
+                iptr[wid][lane] = reinterpret_cast<uint64_t>(W.E + inf.x);
+                icx[wid][lane] = inf.y >> (sb + 1);
+                ioff[wid][lane] = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
             }
         }
-        uint32_t work;
-        const uint32_t ex = block_excl_scan(len, wsum, &work);
-        pre[tid] = ex;
-        __syncthreads();
-        for (uint32_t w = tid; w < work; w += kThreads) {
-            const uint32_t i = last_le(pre, kThreads, w);
-            const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[i])[w - pre[i]];
-            atomicAdd(&acc[ilev[i] + (ent & sidmask)], icx[i] * (ent >> sb));
+        const uint32_t inc = wave_incl_scan(len);
+        const uint32_t work = __shfl(inc, 63, 64);
+        pre[wid][lane] = inc - len;
+        wave_sync();
+        for (uint32_t w = lane; w < work; w += 64) {
+            const uint32_t i = last_le(pre[wid], 64u, w);
+            const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[wid][i])[w - pre[wid][i]];
+            atomicAdd(&acc[ioff[wid][i] + (ent & sidmask)], icx[wid][i] * (ent >> sb));
         }
-        __syncthreads();
+        wave_sync();
     }
+    __syncthreads();
     for (int l = 0; l < A.nlev; ++l) {
         int64_t *crow = J.C + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
         const uint32_t *arow = acc + l * npad;
@@ -388,10 +421,11 @@ hipError_t launch_extract(const JobDev *jobs, const uint32_t *bprefix, int njobs
     hipLaunchKernelGGL(k_extract, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
     return hipGetLastError();
 }
-hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st)
+hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
+                               int maxB, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_count, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems);
+    hipLaunchKernelGGL(k_bucket_count, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
     return hipGetLastError();
 }
 hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st)
@@ -400,16 +434,25 @@ hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st)
     hipLaunchKernelGGL(k_bucket_scan, dim3(nitems), dim3(kThreads), 0, st, items);
     return hipGetLastError();
 }
-hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st)
+hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
+                                 int maxB, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
     return hipGetLastError();
 }
-hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, hipStream_t st)
+// Items [0, nitems) of `items` share the composite width (wide: 64-bit).
+hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
+                              bool wide, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_sort, dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems);
+    if (wide) {
+        hipLaunchKernelGGL((k_bucket_sort<uint64_t, kSmallCap, false>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
+        hipLaunchKernelGGL((k_bucket_sort<uint64_t, 4096, true>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
+    } else {
+        hipLaunchKernelGGL((k_bucket_sort<uint32_t, kSmallCap, false>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
+        hipLaunchKernelGGL((k_bucket_sort<uint32_t, 6144, true>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
+    }
     return hipGetLastError();
 }
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,

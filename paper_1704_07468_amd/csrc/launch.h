@@ -14,17 +14,24 @@ hipError_t launch_fill_u64(uint64_t *p, size_t n, uint64_t v, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_validate(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st);
 hipError_t launch_extract(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st);
-hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st);
+hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
+                               int maxB, hipStream_t st);
 hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st);
-hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, int maxB, hipStream_t st);
-hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t nblocks, hipStream_t st);
+hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
+                                 int maxB, hipStream_t st);
+hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
+                              bool wide, hipStream_t st);
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
                              uint32_t nblocks, size_t lds_bytes, hipStream_t st);
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
-hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st);
+hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks,
+                        const uint32_t *tprefix, uint32_t ntiles, hipStream_t st);
 hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st);
 size_t dense_work_size();
-void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt,
-                     int64_t *C);
+int dense_tile();
+int dense_kchunk();
+uint32_t dense_split_rows();
+void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt, int S,
+                     int64_t *C, int32_t *P);
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
 }  // namespace gk

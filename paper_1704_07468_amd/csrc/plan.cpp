@@ -110,7 +110,7 @@ gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one,
     jp.maxng = maxng;
     jp.nsym = jp.seq_off[(size_t)N];
     jp.sb = std::max(1, ceil_log2((uint64_t)N));
-    if (jp.sb > 24 || (uint64_t)maxng >= (1ull << (32 - jp.sb))) {
+    if (jp.sb > 24 || (uint64_t)maxng >= (1ull << (31 - jp.sb))) {
         set_error("N=%d with %u g-mers in one sequence exceeds the 32-bit run entry", N, maxng);
         return GAKCO_EUNSUPPORTED;
     }
@@ -208,7 +208,8 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         // that can have tau distinct sequences
         jp.dcap.assign((size_t)jp.M + 1, 0);
         jp.o_dense.assign((size_t)jp.M + 1, 0);
-        jp.Ntile = (jp.N + 127) / 128 * 128;
+        jp.o_P.assign((size_t)jp.M + 1, 0);
+        jp.Ntile = (jp.N + dense_tile() - 1) / dense_tile() * dense_tile();
         if (jp.want_kernel && ctx->dense_tau > 0 && !jp.masks.empty()) {
             const size_t limit = std::min<size_t>(ctx->budget / 8, 8ull << 30);
             std::vector<double> want((size_t)jp.M + 1, 0.0);
@@ -218,14 +219,22 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 tot += want[(size_t)m] * jp.Ntile;
             }
             const double scale = tot > (double)limit ? (double)limit / tot : 1.0;
+            // rows of a level are split over dS blocks per output tile so
+            // that about 1024 blocks run; a split holds at most 65536 rows so
+            // its int32 partial sums stay exact
+            const int ntile = jp.Ntile / dense_tile();
+            const int tiles = ntile * (ntile + 1) / 2;
+            jp.dS = std::max(1, std::min(8, (1024 + tiles - 1) / tiles));
+            const uint64_t kc = (uint64_t)dense_kchunk();
             for (int m = 0; m <= jp.M; ++m) {
                 uint64_t c = (uint64_t)(want[(size_t)m] * scale);
-                c = std::min<uint64_t>(c, 1u << 30);
-                c = (c + 31) / 32 * 32;
-                if (c < 32) continue;
+                c = std::min<uint64_t>(c, (uint64_t)jp.dS * dense_split_rows());
+                c = c / kc * kc;
+                if (c < kc) continue;
                 jp.dcap[(size_t)m] = (uint32_t)c;
                 jp.o_dense[(size_t)m] = p.dense_bytes;
                 p.dense_bytes += (size_t)jp.Ntile * c;
+                jp.o_P[(size_t)m] = L.take((size_t)tiles * jp.dS * dense_tile() * dense_tile() * 4);
                 p.n_dense += 1;
             }
         }
@@ -261,29 +270,28 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         mfirst_global += (int)jp.masks.size();
         if (!jp.want_kernel) continue;
         const size_t row_bytes = (size_t)jp.Npad * 4;
-        const int lpg = (int)std::min<size_t>((size_t)jp.M + 1, ctx->lds_max / row_bytes);
-        if (lpg < 1) {
-            set_error("N=%d needs %zu bytes of LDS per level row; %zu available", jp.N, row_bytes, ctx->lds_max);
+        if (row_bytes > ctx->lds_max) {
+            set_error("N=%d needs %zu bytes of LDS per row; %zu available", jp.N, row_bytes, ctx->lds_max);
             return GAKCO_EUNSUPPORTED;
         }
-        int gi = 0;
-        for (int lev0 = 0; lev0 <= jp.M; lev0 += lpg, ++gi) {
-            const int nlev = std::min(lpg, jp.M + 1 - lev0);
+        // one block per (level, row); the levels with the most masks first
+        for (int lev = jp.M; lev >= 0; --lev) {
             int first = -1, cnt = 0;
             for (size_t i = 0; i < jp.masks.size(); ++i)
-                if (jp.masks[i].level >= lev0 && jp.masks[i].level < lev0 + nlev) {
+                if (jp.masks[i].level == lev) {
                     if (first < 0) first = (int)i;
                     ++cnt;
                 }
+            if (!cnt) continue;
             AccWork a{};
             a.job = (int)j;
-            a.mfirst = jp.mask_first + std::max(first, 0);
+            a.mfirst = jp.mask_first + first;
             a.nmask = cnt;
-            a.lev0 = lev0;
-            a.nlev = nlev;
+            a.lev0 = lev;
+            a.nlev = 1;
             a.Npad = jp.Npad;
-            if ((size_t)gi >= per_group.size()) per_group.emplace_back();
-            per_group[(size_t)gi].push_back(a);
+            if (per_group.empty()) per_group.emplace_back();
+            per_group[0].push_back(a);
         }
     }
     p.acc_prefix.clear();
@@ -303,11 +311,14 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.d_acc = d.take(sizeof(AccWork) * std::max<size_t>(1, p.aw.size()), 64);
     p.d_dense = d.take(dense_work_size() * std::max(1, p.n_dense), 64);
     p.d_pdense = d.take(((size_t)p.n_dense + 1) * 4, 64);
+    p.d_pdtile = d.take(((size_t)p.n_dense + 1) * 4, 64);
     const size_t nj = p.jobs.size();
     p.d_pv = d.take((nj + 1) * 4, 64);
     p.d_px = d.take((nj + 1) * 4, 64);
     p.d_pt = d.take((nmask + 1) * 4, 64);
-    p.d_pb = d.take((nmask + 1) * 4, 64);
+    p.d_masks_cls = d.take(sizeof(MaskWork) * std::max<size_t>(1, nmask), 64);
+    p.d_pbw = d.take((nmask + 1) * 4, 64);
+    p.d_pbn = d.take((nmask + 1) * 4, 64);
     p.d_pd = d.take((nj + 1) * 4, 64);
     p.d_pf = d.take((nj + 1) * 4, 64);
     p.d_pacc.clear();
@@ -361,7 +372,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     p.desc_host.assign(p.desc_bytes, 0);
     char *blob = p.desc_host.data();
     JobDev *jd = reinterpret_cast<JobDev *>(blob + p.d_jobs);
-    std::vector<uint32_t> pv(1, 0), px(1, 0), pt(1, 0), pb(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0);
+    std::vector<uint32_t> pv(1, 0), px(1, 0), pt(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0);
     size_t mi = 0, bc = 0, lev_base = 0;
     int di = 0;
     for (size_t j = 0; j < p.jobs.size(); ++j) {
@@ -393,14 +404,16 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         const uint32_t nt = (uint32_t)((jp.N + 31) / 32);
         pf.push_back(pf.back() + (jp.want_kernel ? nt * nt : 0u));
         if (jp.want_kernel) {
-            const int ntile = jp.Ntile / 128;
+            const int ntile = jp.Ntile / dense_tile();
+            const uint32_t tiles = (uint32_t)(ntile * (ntile + 1) / 2);
             for (int m = 0; m <= jp.M; ++m) {
                 if (!jp.dcap[(size_t)m]) continue;
                 dense_work_fill(blob + p.d_dense + dense_work_size() * (size_t)di, ctx->dense_buf + jp.o_dense[(size_t)m],
                                 reinterpret_cast<uint32_t *>(base + o_flags) + p.jobs.size() + lev_base + m,
-                                jp.dcap[(size_t)m], jp.dcap[(size_t)m], jp.N, ntile,
-                                J.C + (size_t)m * jp.N * jp.N);
-                pdn.push_back(pdn.back() + (uint32_t)(ntile * (ntile + 1) / 2));
+                                jp.dcap[(size_t)m], jp.dcap[(size_t)m], jp.N, ntile, jp.dS,
+                                J.C + (size_t)m * jp.N * jp.N, reinterpret_cast<int32_t *>(base + jp.o_P[(size_t)m]));
+                pdn.push_back(pdn.back() + tiles * (uint32_t)jp.dS);
+                pdt.push_back(pdt.back() + tiles);
                 ++di;
             }
         }
@@ -444,18 +457,40 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
                 W.tau = ctx->dense_tau;
             }
             pt.push_back(pt.back() + (jp.T + kTile - 1) / kTile);
-            pb.push_back(pb.back() + (uint32_t)nb);
         }
         lev_base += (size_t)jp.M + 1;
     }
     if (!p.mw.empty()) memcpy(blob + p.d_masks, p.mw.data(), sizeof(MaskWork) * p.mw.size());
     if (!p.aw.empty()) memcpy(blob + p.d_acc, p.aw.data(), sizeof(AccWork) * p.aw.size());
     auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
-    put(p.d_pv, pv); put(p.d_px, px); put(p.d_pt, pt); put(p.d_pb, pb); put(p.d_pd, pd); put(p.d_pf, pf);
+    // bucket-sort classes: 64-bit composites first
+    std::vector<MaskWork> cls;
+    std::vector<uint32_t> pbw(1, 0), pbn(1, 0);
+    for (auto &W : p.mw)
+        if (W.cb > 32) { cls.push_back(W); pbw.push_back(pbw.back() + (1u << W.B)); }
+    p.nwide = (int)cls.size();
+    for (auto &W : p.mw)
+        if (W.cb <= 32) { cls.push_back(W); pbn.push_back(pbn.back() + (1u << W.B)); }
+    if (!cls.empty()) memcpy(blob + p.d_masks_cls, cls.data(), sizeof(MaskWork) * cls.size());
+    auto uniform = [](const std::vector<uint32_t> &pre) -> uint32_t {
+        if (pre.size() < 2) return 0;
+        const uint32_t u = pre[1] - pre[0];
+        for (size_t i = 1; i < pre.size(); ++i)
+            if (pre[i] - pre[i - 1] != u) return 0;
+        return u;
+    };
+    p.uni_t = uniform(pt);
+    p.uni_bw = uniform(pbw);
+    p.uni_bn = uniform(pbn);
+    p.nb_bw = pbw.back();
+    p.nb_bn = pbn.back();
+    put(p.d_pv, pv); put(p.d_px, px); put(p.d_pt, pt); put(p.d_pbw, pbw); put(p.d_pbn, pbn); put(p.d_pd, pd); put(p.d_pf, pf);
     for (size_t i = 0; i < p.acc_prefix.size(); ++i) put(p.d_pacc[i], p.acc_prefix[i]);
     put(p.d_pdense, pdn);
+    put(p.d_pdtile, pdt);
     p.nb_dense = pdn.back();
-    p.nb_v = pv.back(); p.nb_x = px.back(); p.nb_t = pt.back(); p.nb_b = pb.back(); p.nb_d = pd.back(); p.nb_f = pf.back();
+    p.nb_dtile = pdt.back();
+    p.nb_v = pv.back(); p.nb_x = px.back(); p.nb_t = pt.back(); p.nb_d = pd.back(); p.nb_f = pf.back();
     return GAKCO_OK;
 }
 
@@ -556,10 +591,12 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     GK_PHASE(PH_EXTRACT, launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
     if (nm) {
-        GK_PHASE(PH_BCOUNT, launch_bucket_count(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
+        const MaskWork *cls = reinterpret_cast<const MaskWork *>(d + p.d_masks_cls);
+        GK_PHASE(PH_BCOUNT, launch_bucket_count(masks, P(p.d_pt), nm, p.uni_t, p.nb_t, p.maxB, st));
         GK_PHASE(PH_BSCAN, launch_bucket_scan(masks, nm, st));
-        GK_PHASE(PH_BSCATTER, launch_bucket_scatter(masks, P(p.d_pt), nm, p.nb_t, p.maxB, st));
-        GK_PHASE(PH_BSORT, launch_bucket_sort(masks, P(p.d_pb), nm, p.nb_b, st));
+        GK_PHASE(PH_BSCATTER, launch_bucket_scatter(masks, P(p.d_pt), nm, p.uni_t, p.nb_t, p.maxB, st));
+        GK_PHASE(PH_BSORT, launch_bucket_sort(cls, P(p.d_pbw), p.nwide, p.uni_bw, p.nb_bw, true, st));
+        GK_PHASE(PH_BSORT, launch_bucket_sort(cls + p.nwide, P(p.d_pbn), nm - p.nwide, p.uni_bn, p.nb_bn, false, st));
     }
     for (size_t gi = 0; gi < p.acc_groups.size(); ++gi) {
         const auto &grp = p.acc_groups[gi];
@@ -569,7 +606,7 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     if (p.n_dense) {
         const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
         ctx->dense_dirty = true;
-        GK_PHASE(PH_DENSE, launch_dense(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));
+        GK_PHASE(PH_DENSE, launch_dense(dw, P(p.d_pdense), p.n_dense, p.nb_dense, P(p.d_pdtile), p.nb_dtile, st));
         GK_PHASE(PH_DENSE, launch_dense_clear(dw, p.n_dense, st));
         ctx->dense_dirty = false;
     }

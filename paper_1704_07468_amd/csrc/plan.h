@@ -97,6 +97,8 @@ struct JobPlan {
     std::vector<size_t> o_mask;  // per mask: base of its buffers
     std::vector<uint32_t> dcap;  // per level dense row capacity (0 = level has no dense path)
     std::vector<size_t> o_dense; // per level offset in the context's dense buffer
+    std::vector<size_t> o_P;     // per level partial tiles of the split rows
+    int dS = 1;                  // row splits per dense output tile
     int Npad = 0;                // LDS row stride of the accumulation
     int Ntile = 0;               // sequences padded to the dense tile edge
     bool own_C = false;
@@ -117,8 +119,13 @@ struct Plan {
     std::vector<char> desc_host;  // staged descriptor blob
     // descriptor offsets inside the blob
     size_t d_jobs = 0, d_masks = 0, d_acc = 0;
-    size_t d_pv = 0, d_px = 0, d_pt = 0, d_pb = 0, d_pa = 0, d_pd = 0, d_pf = 0;
-    uint32_t nb_v = 0, nb_x = 0, nb_t = 0, nb_b = 0, nb_a = 0, nb_d = 0, nb_f = 0;
+    size_t d_pv = 0, d_px = 0, d_pt = 0, d_pd = 0, d_pf = 0;
+    uint32_t nb_v = 0, nb_x = 0, nb_t = 0, nb_d = 0, nb_f = 0;
+    // bucket sort: the mask works again, 64-bit-composite masks first, then
+    // 32-bit ones; per class a block prefix (or a uniform blocks-per-mask)
+    size_t d_masks_cls = 0, d_pbw = 0, d_pbn = 0;
+    uint32_t nb_bw = 0, nb_bn = 0, uni_t = 0, uni_bw = 0, uni_bn = 0;
+    int nwide = 0;
     int maxB = 0, maxM = 0;
     std::vector<MaskWork> mw;
     std::vector<AccWork> aw;
@@ -127,8 +134,8 @@ struct Plan {
     std::vector<std::vector<uint32_t>> acc_prefix;
     std::vector<size_t> d_pacc;
     // dense path
-    size_t d_dense = 0, d_pdense = 0;
-    uint32_t nb_dense = 0;
+    size_t d_dense = 0, d_pdense = 0, d_pdtile = 0;
+    uint32_t nb_dense = 0, nb_dtile = 0;
     int n_dense = 0;
     size_t dense_bytes = 0;
     char *base = nullptr;             // arena base
