@@ -74,6 +74,9 @@ const char *gakco_version(void);
  *   "bucket_avg"    target g-mers per hash bucket of the partition sort
  *   "profile"       1 = time every launch phase with HIP events (see
  *                   gakco_profile_get)
+ *   "pool_mb"       cap of the buffer pool reused by chunks of position sets
+ *   "tau_b<B>_g<G>" dense_tau for jobs with B-bit symbols and this g (as
+ *                   written by gakco_autotune)
  * Missing keys keep their defaults.  Not thread-safe: one context per host
  * thread (serving uses its own internal contexts).
  * ------------------------------------------------------------------------ */
@@ -82,6 +85,10 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
 void gakco_ctx_destroy(gakco_ctx *ctx);
 /* Set one tuning parameter by name (same keys as tune_json). */
 gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value);
+/* Read a value about the context or its last Gram call: "dense_rows" (groups
+ * summed by the int8 matrix-core path), "chunks" (position-set chunks),
+ * "dense_tau", "bucket_avg", "arena_bytes", "dense_bytes". */
+gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *value);
 
 /* Event profiler (enable with the "profile" parameter): per launch phase of
  * the calls made on this context, the summed device time between HIP events
@@ -167,6 +174,15 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
                                      void *hip_stream, gakco_batch_plan **out);
 gakco_status gakco_batch_run(gakco_batch_plan *plan, void *hip_stream);
 void gakco_batch_plan_destroy(gakco_batch_plan *plan);
+
+/* Autotuner: times candidate settings of the given jobs on the device (best
+ * of `reps` runs after a warm-up, HIP events) and keeps the fastest: the
+ * int8 matrix-core threshold per job class (symbol bits, g), then the hash
+ * bucket size.  The choice is applied to ctx and, if out_json is not NULL,
+ * written there as a tune_json object (GAKCO_EINVAL if out_cap is too
+ * small).  The jobs' outputs are overwritten. */
+gakco_status gakco_autotune(gakco_ctx *ctx, const gakco_job *jobs_host, int32_t n_jobs, int32_t reps,
+                            void *hip_stream, char *out_json, size_t out_cap);
 
 /* ------------------------------------------------------------------------
  * Serving: a resident set (e.g. an SVM's support vectors) kept on the device

@@ -18,6 +18,7 @@ SOURCES = [
     "dense_mfma.hip",
     "plan.cpp",
     "api.cpp",
+    "batch.cpp",
 ]
 
 CFLAGS = [

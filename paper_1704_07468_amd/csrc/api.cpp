@@ -1,6 +1,7 @@
 // C ABI of the library: context, Gram, stage entry points.
 #include <algorithm>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 
@@ -22,6 +23,16 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
         ctx->dense_tau = (int)v;
     } else if (!strcmp(name, "profile")) {
         ctx->prof_on = v != 0;
+    } else if (!strcmp(name, "pool_mb")) {
+        if (v < 16) { set_error("pool_mb must be >= 16"); return GAKCO_EINVAL; }
+        ctx->pool_cap = (size_t)v << 20;
+    } else if (!strncmp(name, "tau_b", 5)) {
+        int b = 0, g = 0;
+        if (sscanf(name, "tau_b%d_g%d", &b, &g) != 2 || b < 1 || g < 1 || v < 0) {
+            set_error("bad class parameter '%s'", name);
+            return GAKCO_EINVAL;
+        }
+        ctx->class_tau[b * 100 + g] = (int)v;
     } else if (!strcmp(name, "bucket_avg")) {
         if (v < 16 || v > kSortCap) { set_error("bucket_avg must be in 16..%d", kSortCap); return GAKCO_EINVAL; }
         ctx->bucket_avg = (int)v;
@@ -234,6 +245,20 @@ gakco_status gakco_mask_groups(gakco_ctx *ctx, const int8_t *seqs, const int32_t
         grp_off[ng] = (int32_t)ne;
     }
     *n_groups_out = ng;
+    return GAKCO_OK;
+}
+
+gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *value)
+{
+    clear_error();
+    if (!ctx || !name || !value) { set_error("bad arguments"); return GAKCO_EINVAL; }
+    if (!strcmp(name, "dense_rows")) *value = ctx->last_dense_rows;
+    else if (!strcmp(name, "chunks")) *value = ctx->last_chunks;
+    else if (!strcmp(name, "dense_tau")) *value = ctx->dense_tau;
+    else if (!strcmp(name, "bucket_avg")) *value = ctx->bucket_avg;
+    else if (!strcmp(name, "arena_bytes")) *value = (int64_t)ctx->arena_cap;
+    else if (!strcmp(name, "dense_bytes")) *value = (int64_t)ctx->dense_cap;
+    else { set_error("unknown statistic '%s'", name); return GAKCO_EINVAL; }
     return GAKCO_OK;
 }
 

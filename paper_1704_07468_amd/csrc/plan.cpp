@@ -1,12 +1,19 @@
 // Planning and launch sequence of Gram jobs (host side).
+//
+// A plan covers one or more jobs.  Every job's position sets ("masks") are
+// ordered job by job, level by level; consecutive masks are grouped into
+// chunks whose partition and sort buffers fit one reusable pool, and each
+// chunk runs count -> scan -> scatter -> sort -> row accumulation before the
+// next one reuses the pool.  The int8 matrix-core products, the diagonal and
+// the epilogue run once at the end.  Everything the kernels read from the
+// host (job and mask descriptors, offsets, coefficient tables, block
+// prefixes) travels in one descriptor blob with one copy.
 #include "plan.h"
 
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-
-#include "launch.h"
 
 namespace gk {
 
@@ -114,7 +121,6 @@ gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one,
         set_error("N=%d with %u g-mers in one sequence exceeds the 32-bit run entry", N, maxng);
         return GAKCO_EUNSUPPORTED;
     }
-    // masks
     jp.masks.clear();
     if (removed_one) {
         for (int i = 0; i < m_one; ++i)
@@ -161,20 +167,30 @@ gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one,
     return GAKCO_OK;
 }
 
-static size_t mask_bytes(uint32_t T, int B)
+// Device buffers of one mask inside the pool: bucket offsets and cursors,
+// the bucketed (composite, index) pairs and their ping-pong copies, the run
+// entries and the per-g-mer info.
+struct MaskBuf {
+    size_t boff, bcur, comp, idx, comp2, idx2, E, info, size;
+};
+static MaskBuf mask_buf(uint32_t T, int B)
 {
     Layout l;
     const size_t nb = (size_t)1 << B;
-    l.take((nb + 1) * 4);  // boff
-    l.take(nb * 4);        // bcur
-    l.take((size_t)T * 8); // comp
-    l.take((size_t)T * 4); // idx
-    l.take((size_t)T * 8); // comp2
-    l.take((size_t)T * 4); // idx2
-    l.take((size_t)T * 4); // E
-    l.take((size_t)T * 8); // info
-    return l.size;
+    MaskBuf m{};
+    m.boff = l.take((nb + 1) * 4);
+    m.bcur = l.take(nb * 4);
+    m.comp = l.take((size_t)T * 8);
+    m.idx = l.take((size_t)T * 4);
+    m.comp2 = l.take((size_t)T * 8);
+    m.idx2 = l.take((size_t)T * 4);
+    m.E = l.take((size_t)T * 4);
+    m.info = l.take((size_t)T * 8);
+    m.size = l.size;
+    return m;
 }
+
+static int job_tau(const gakco_ctx *ctx, const JobPlan &jp) { return jp.tau >= 0 ? jp.tau : ctx->dense_tau; }
 
 gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
 {
@@ -183,45 +199,50 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.output_bytes = 0;
     p.dense_bytes = 0;
     p.n_dense = 0;
-    p.maxB = 0;
     p.maxM = 0;
-    size_t nmask = 0, nb_total = 0;
+    p.pool_bytes = 0;
+    p.chunks.clear();
+    size_t nmask = 0;
+    p.nflags = p.jobs.size();
     for (auto &jp : p.jobs) {
         const size_t N = (size_t)jp.N, M1 = (size_t)jp.M + 1;
-        jp.o_seqoff = L.take((N + 1) * 8);
-        jp.o_gstart = L.take((N + 1) * 4);
         if (!jp.key_override) {
             jp.o_key = L.take((size_t)jp.T * 8);
             jp.o_sid = L.take((size_t)jp.T * 4);
         }
-        if (jp.want_kernel) {
-            jp.own_C = !jp.Cm_out && !jp.Nm_out;
-            if (jp.own_C) jp.o_C = L.take(M1 * N * N * 8);
-            jp.o_Kd = L.take(N * 8);
-            jp.o_coef = L.take(M1 * M1 * 8);
-            jp.o_hco = L.take(M1 * 8);
-            p.output_bytes += N * N * 8 * ((jp.K_out ? 1 : 0) + (jp.Nm_out ? M1 : 0) + (jp.Cm_out ? M1 : 0));
-            p.maxM = std::max(p.maxM, jp.M);
-        }
-        // int8 matrix-core path: per level a sequence-major count matrix in
-        // the context's dense buffer, capacity bounded by the number of groups
-        // that can have tau distinct sequences
-        jp.dcap.assign((size_t)jp.M + 1, 0);
-        jp.o_dense.assign((size_t)jp.M + 1, 0);
-        jp.o_P.assign((size_t)jp.M + 1, 0);
+        jp.mask_first = (int)nmask;
+        nmask += jp.masks.size();
+        jp.lev_base = p.nflags - p.jobs.size();
+        p.nflags += M1;
+        jp.dcap.assign(M1, 0);
+        jp.o_dense.assign(M1, 0);
+        jp.o_P.assign(M1, 0);
         jp.Ntile = (jp.N + dense_tile() - 1) / dense_tile() * dense_tile();
-        if (jp.want_kernel && ctx->dense_tau > 0 && !jp.masks.empty()) {
+        if (!jp.want_kernel) continue;
+        if ((size_t)jp.Npad * 4 > ctx->lds_max) {
+            set_error("N=%d needs %d bytes of LDS per row; %zu available", jp.N, jp.Npad * 4, ctx->lds_max);
+            return GAKCO_EUNSUPPORTED;
+        }
+        jp.own_C = !jp.Cm_out && !jp.Nm_out;
+        if (jp.own_C) jp.o_C = L.take(M1 * N * N * 8);
+        jp.o_Kd = L.take(N * 8);
+        p.output_bytes += N * N * 8 * ((jp.K_out ? 1 : 0) + (jp.Nm_out ? M1 : 0) + (jp.Cm_out ? M1 : 0));
+        p.maxM = std::max(p.maxM, jp.M);
+        // int8 matrix-core path: per level a sequence-major count matrix in
+        // the context's dense buffer, its capacity bounded by how many groups
+        // can have tau distinct sequences; rows are split over dS blocks per
+        // output tile so that about 1024 blocks run, a split holding at most
+        // 65536 rows so that its int32 partial sums stay exact
+        const int tau = job_tau(ctx, jp);
+        if (tau > 0 && !jp.masks.empty()) {
             const size_t limit = std::min<size_t>(ctx->budget / 8, 8ull << 30);
-            std::vector<double> want((size_t)jp.M + 1, 0.0);
+            std::vector<double> want(M1, 0.0);
             double tot = 0;
             for (int m = 0; m <= jp.M; ++m) {
-                want[(size_t)m] = (double)binom64(jp.g, m) * ((double)jp.T / ctx->dense_tau + 1.0);
+                want[(size_t)m] = (double)binom64(jp.g, m) * ((double)jp.T / tau + 1.0);
                 tot += want[(size_t)m] * jp.Ntile;
             }
             const double scale = tot > (double)limit ? (double)limit / tot : 1.0;
-            // rows of a level are split over dS blocks per output tile so
-            // that about 1024 blocks run; a split holds at most 65536 rows so
-            // its int32 partial sums stay exact
             const int ntile = jp.Ntile / dense_tile();
             const int tiles = ntile * (ntile + 1) / 2;
             jp.dS = std::max(1, std::min(8, (1024 + tiles - 1) / tiles));
@@ -238,92 +259,111 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 p.n_dense += 1;
             }
         }
-        jp.o_mask.resize(jp.masks.size());
-        for (size_t i = 0; i < jp.masks.size(); ++i) {
-            const int B = jp.level_B[(size_t)jp.masks[i].level];
-            jp.o_mask[i] = L.take(mask_bytes(jp.T, B));
-            nb_total += (size_t)1 << B;
-            p.maxB = std::max(p.maxB, B);
-        }
-        nmask += jp.masks.size();
     }
-    // flags (err per job) and the bucket counters of every mask, contiguous
-    // so that one fill clears them
-    p.mw.resize(nmask);
-    size_t nlev_total = 0;
-    for (auto &jp : p.jobs) nlev_total += (size_t)jp.M + 1;
-    p.o_flags = L.take((p.jobs.size() + nlev_total) * 4);  // error flags, then dense row counters
-    p.o_bcnt = L.take(nb_total * 4);
+    p.mw.assign(nmask, MaskWork{});
+    p.o_flags = L.take(p.nflags * 4);
+    // chunks: greedy runs of masks whose buffers fit the pool
+    const size_t fixed = L.size + (16u << 20);  // + descriptor headroom
+    const size_t reserved = fixed + p.dense_bytes + p.output_bytes;
+    if (reserved >= ctx->budget) {
+        set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB",
+                  fixed / 1e9, p.dense_bytes / 1e9, p.output_bytes / 1e9, ctx->budget / 1e9);
+        return GAKCO_EBUDGET;
+    }
+    const size_t pool_limit = std::min(ctx->budget - reserved, ctx->pool_cap);
+    {
+        Chunk cur;
+        Layout pl;
+        size_t nbc = 0;
+        auto close = [&]() {
+            if (!cur.nmask) return;
+            cur.nbcnt = nbc;
+            cur.o_bcnt = pl.take(nbc * 4);
+            p.pool_bytes = std::max(p.pool_bytes, pl.size);
+            p.chunks.push_back(cur);
+            cur = Chunk{};
+            pl = Layout{};
+            nbc = 0;
+        };
+        int gi = 0;
+        for (auto &jp : p.jobs) {
+            for (size_t i = 0; i < jp.masks.size(); ++i, ++gi) {
+                const int B = jp.level_B[(size_t)jp.masks[i].level];
+                const MaskBuf mb = mask_buf(jp.T, B);
+                const size_t need = mb.size + ((size_t)4 << B) + 512;
+                if (need > pool_limit) {
+                    set_error("one position set needs %.3f GB of buffers; %.3f GB of the HBM budget are left",
+                              need / 1e9, pool_limit / 1e9);
+                    return GAKCO_EBUDGET;
+                }
+                if (cur.nmask && pl.size + need + nbc * 4 + 512 > pool_limit) close();
+                if (!cur.nmask) cur.mfirst = gi;
+                cur.o_mask.push_back(pl.take(mb.size));
+                cur.nmask += 1;
+                cur.maxB = std::max(cur.maxB, B);
+                nbc += (size_t)1 << B;
+            }
+        }
+        close();
+    }
+    // accumulation works of each chunk: one per (job, level) present in it,
+    // the levels with the most masks first
+    for (auto &c : p.chunks) {
+        for (size_t j = 0; j < p.jobs.size(); ++j) {
+            auto &jp = p.jobs[j];
+            if (!jp.want_kernel) continue;
+            const int a = std::max(c.mfirst, jp.mask_first);
+            const int b = std::min(c.mfirst + c.nmask, jp.mask_first + (int)jp.masks.size());
+            for (int lev = jp.M; lev >= 0; --lev) {
+                int first = -1, cnt = 0;
+                for (int gi = a; gi < b; ++gi)
+                    if (jp.masks[(size_t)(gi - jp.mask_first)].level == lev) {
+                        if (first < 0) first = gi;
+                        ++cnt;
+                    }
+                if (!cnt) continue;
+                AccWork w{};
+                w.job = (int)j;
+                w.mfirst = first;
+                w.nmask = cnt;
+                w.lev0 = lev;
+                w.nlev = 1;
+                w.Npad = jp.Npad;
+                c.aw.push_back(w);
+                c.acc_lds = std::max(c.acc_lds, (size_t)jp.Npad * 4);
+            }
+        }
+        c.nacc = (int)c.aw.size();
+    }
     // descriptor blob
     Layout d;
-    p.d_jobs = d.take(sizeof(JobDev) * p.jobs.size(), 64);
-    p.d_masks = d.take(sizeof(MaskWork) * nmask, 64);
-    // accumulate works: level groups that fit the LDS budget
-    p.aw.clear();
-    p.acc_groups.clear();
-    p.acc_lds.clear();
-    std::vector<std::vector<AccWork>> per_group;
-    int mfirst_global = 0;
-    for (size_t j = 0; j < p.jobs.size(); ++j) {
-        auto &jp = p.jobs[j];
-        jp.mask_first = mfirst_global;
-        mfirst_global += (int)jp.masks.size();
-        if (!jp.want_kernel) continue;
-        const size_t row_bytes = (size_t)jp.Npad * 4;
-        if (row_bytes > ctx->lds_max) {
-            set_error("N=%d needs %zu bytes of LDS per row; %zu available", jp.N, row_bytes, ctx->lds_max);
-            return GAKCO_EUNSUPPORTED;
-        }
-        // one block per (level, row); the levels with the most masks first
-        for (int lev = jp.M; lev >= 0; --lev) {
-            int first = -1, cnt = 0;
-            for (size_t i = 0; i < jp.masks.size(); ++i)
-                if (jp.masks[i].level == lev) {
-                    if (first < 0) first = (int)i;
-                    ++cnt;
-                }
-            if (!cnt) continue;
-            AccWork a{};
-            a.job = (int)j;
-            a.mfirst = jp.mask_first + first;
-            a.nmask = cnt;
-            a.lev0 = lev;
-            a.nlev = 1;
-            a.Npad = jp.Npad;
-            if (per_group.empty()) per_group.emplace_back();
-            per_group[0].push_back(a);
-        }
-    }
-    p.acc_prefix.clear();
-    for (auto &grp : per_group) {
-        const int first = (int)p.aw.size();
-        size_t lds = 0;
-        std::vector<uint32_t> pre(1, 0);
-        for (auto &a : grp) {
-            p.aw.push_back(a);
-            lds = std::max(lds, (size_t)a.nlev * (size_t)a.Npad * 4);
-            pre.push_back(pre.back() + (uint32_t)p.jobs[(size_t)a.job].N);
-        }
-        p.acc_groups.emplace_back(first, (int)grp.size());
-        p.acc_lds.push_back(lds);
-        p.acc_prefix.push_back(pre);
-    }
-    p.d_acc = d.take(sizeof(AccWork) * std::max<size_t>(1, p.aw.size()), 64);
-    p.d_dense = d.take(dense_work_size() * std::max(1, p.n_dense), 64);
+    const size_t nj = p.jobs.size();
+    p.d_jobs = d.take(sizeof(JobDev) * nj, 64);
+    p.d_masks = d.take(sizeof(MaskWork) * std::max<size_t>(1, nmask), 64);
+    p.d_dense = d.take(dense_work_size() * (size_t)std::max(1, p.n_dense), 64);
     p.d_pdense = d.take(((size_t)p.n_dense + 1) * 4, 64);
     p.d_pdtile = d.take(((size_t)p.n_dense + 1) * 4, 64);
-    const size_t nj = p.jobs.size();
     p.d_pv = d.take((nj + 1) * 4, 64);
     p.d_px = d.take((nj + 1) * 4, 64);
-    p.d_pt = d.take((nmask + 1) * 4, 64);
-    p.d_masks_cls = d.take(sizeof(MaskWork) * std::max<size_t>(1, nmask), 64);
-    p.d_pbw = d.take((nmask + 1) * 4, 64);
-    p.d_pbn = d.take((nmask + 1) * 4, 64);
     p.d_pd = d.take((nj + 1) * 4, 64);
     p.d_pf = d.take((nj + 1) * 4, 64);
-    p.d_pacc.clear();
-    for (auto &pre : p.acc_prefix) p.d_pacc.push_back(d.take(pre.size() * 4, 64));
+    for (auto &jp : p.jobs) {
+        const size_t M1 = (size_t)jp.M + 1;
+        jp.o_seqoff = d.take(((size_t)jp.N + 1) * 8, 64);
+        jp.o_gstart = d.take(((size_t)jp.N + 1) * 4, 64);
+        jp.o_coef = d.take(M1 * M1 * 8, 64);
+        jp.o_hco = d.take(M1 * 8, 64);
+    }
+    for (auto &c : p.chunks) {
+        c.d_pt = d.take(((size_t)c.nmask + 1) * 4, 64);
+        c.d_cls = d.take(sizeof(MaskWork) * (size_t)c.nmask, 64);
+        c.d_pbw = d.take(((size_t)c.nmask + 1) * 4, 64);
+        c.d_pbn = d.take(((size_t)c.nmask + 1) * 4, 64);
+        c.d_acc = d.take(sizeof(AccWork) * (size_t)std::max(1, c.nacc), 64);
+        c.d_pacc = d.take(((size_t)c.nacc + 1) * 4, 64);
+    }
     p.desc_bytes = d.size;
+    p.o_pool = L.take(p.pool_bytes);
     p.o_desc = L.take(p.desc_bytes);
     if (L.size + p.dense_bytes + p.output_bytes > ctx->budget) {
         set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB",
@@ -348,6 +388,15 @@ static gakco_status reserve_arena(gakco_ctx *ctx, size_t bytes)
     return GAKCO_OK;
 }
 
+static uint32_t uniform_of(const std::vector<uint32_t> &pre)
+{
+    if (pre.size() < 2) return 0;
+    const uint32_t u = pre[1] - pre[0];
+    for (size_t i = 1; i < pre.size(); ++i)
+        if (pre[i] - pre[i - 1] != u) return 0;
+    return u;
+}
+
 gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
     GK_TRY(reserve_arena(ctx, p.lay.size));
@@ -368,31 +417,43 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     }
     char *base = (char *)ctx->arena;
     p.base = base;
-    const size_t o_flags = p.o_flags, o_bcnt = p.o_bcnt;
+    char *dev_desc = base + p.o_desc;
+    char *pool = base + p.o_pool;
+    uint32_t *flags = reinterpret_cast<uint32_t *>(base + p.o_flags);
     p.desc_host.assign(p.desc_bytes, 0);
     char *blob = p.desc_host.data();
+    auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
     JobDev *jd = reinterpret_cast<JobDev *>(blob + p.d_jobs);
-    std::vector<uint32_t> pv(1, 0), px(1, 0), pt(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0);
-    size_t mi = 0, bc = 0, lev_base = 0;
+    std::vector<uint32_t> pv(1, 0), px(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0);
     int di = 0;
     for (size_t j = 0; j < p.jobs.size(); ++j) {
         auto &jp = p.jobs[j];
+        const int M1 = jp.M + 1;
+        // host tables into the blob
+        memcpy(blob + jp.o_seqoff, jp.seq_off.data(), jp.seq_off.size() * 8);
+        memcpy(blob + jp.o_gstart, jp.gstart.data(), jp.gstart.size() * 4);
+        int64_t *coef = reinterpret_cast<int64_t *>(blob + jp.o_coef);
+        int64_t *hco = reinterpret_cast<int64_t *>(blob + jp.o_hco);
+        for (int m = 0; m < M1; ++m) {
+            hco[m] = binom64(jp.g - m, jp.k);                                                 // Eq. 6
+            for (int q = 0; q < m; ++q) coef[(size_t)m * M1 + q] = binom64(jp.g - q, m - q);  // Eq. 9
+        }
         JobDev &J = jp.dev;
         J = JobDev{};
         J.seqs = jp.seqs;
-        J.seq_off = reinterpret_cast<const int64_t *>(base + jp.o_seqoff);
-        J.gstart = reinterpret_cast<const uint32_t *>(base + jp.o_gstart);
+        J.seq_off = reinterpret_cast<const int64_t *>(dev_desc + jp.o_seqoff);
+        J.gstart = reinterpret_cast<const uint32_t *>(dev_desc + jp.o_gstart);
         J.N = jp.N; J.sigma = jp.sigma; J.g = jp.g; J.k = jp.k; J.M = jp.M; J.b = jp.b; J.sb = jp.sb;
         J.T = jp.T;
         J.nsym = jp.nsym;
         J.key = jp.key_override ? jp.key_override : reinterpret_cast<uint64_t *>(base + jp.o_key);
         J.sid = jp.sid_override ? jp.sid_override : reinterpret_cast<uint32_t *>(base + jp.o_sid);
-        J.err = reinterpret_cast<int32_t *>(base + o_flags) + j;
+        J.err = reinterpret_cast<int32_t *>(flags + j);
         if (jp.want_kernel) {
             J.C = jp.own_C ? reinterpret_cast<int64_t *>(base + jp.o_C) : (jp.Cm_out ? jp.Cm_out : jp.Nm_out);
             J.Kd = reinterpret_cast<int64_t *>(base + jp.o_Kd);
-            J.coef = reinterpret_cast<const int64_t *>(base + jp.o_coef);
-            J.hco = reinterpret_cast<const int64_t *>(base + jp.o_hco);
+            J.coef = reinterpret_cast<const int64_t *>(dev_desc + jp.o_coef);
+            J.hco = reinterpret_cast<const int64_t *>(dev_desc + jp.o_hco);
             J.K_out = jp.K_out;
             J.Nm_out = jp.Nm_out;
             J.Cm_out = jp.Cm_out;
@@ -409,112 +470,100 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             for (int m = 0; m <= jp.M; ++m) {
                 if (!jp.dcap[(size_t)m]) continue;
                 dense_work_fill(blob + p.d_dense + dense_work_size() * (size_t)di, ctx->dense_buf + jp.o_dense[(size_t)m],
-                                reinterpret_cast<uint32_t *>(base + o_flags) + p.jobs.size() + lev_base + m,
-                                jp.dcap[(size_t)m], jp.dcap[(size_t)m], jp.N, ntile, jp.dS,
-                                J.C + (size_t)m * jp.N * jp.N, reinterpret_cast<int32_t *>(base + jp.o_P[(size_t)m]));
+                                flags + p.jobs.size() + jp.lev_base + m, jp.dcap[(size_t)m], jp.dcap[(size_t)m], jp.N,
+                                ntile, jp.dS, J.C + (size_t)m * jp.N * jp.N,
+                                reinterpret_cast<int32_t *>(base + jp.o_P[(size_t)m]));
                 pdn.push_back(pdn.back() + tiles * (uint32_t)jp.dS);
                 pdt.push_back(pdt.back() + tiles);
                 ++di;
             }
         }
-        for (size_t i = 0; i < jp.masks.size(); ++i, ++mi) {
-            MaskWork &W = p.mw[mi];
+    }
+    // mask works, chunk by chunk (each chunk's buffers at the start of the pool)
+    size_t j = 0;
+    for (auto &c : p.chunks) {
+        size_t bc = 0;
+        std::vector<uint32_t> pt(1, 0), pbw(1, 0), pbn(1, 0);
+        std::vector<MaskWork> cls;
+        for (int q = 0; q < c.nmask; ++q) {
+            const int gi = c.mfirst + q;
+            while (gi >= p.jobs[j].mask_first + (int)p.jobs[j].masks.size()) ++j;
+            auto &jp = p.jobs[j];
+            const MaskDesc &md = jp.masks[(size_t)(gi - jp.mask_first)];
+            MaskWork &W = p.mw[(size_t)gi];
             W = MaskWork{};
-            W.md = jp.masks[i];
+            W.md = md;
             W.job = (int)j;
             W.T = jp.T;
-            const int m = W.md.level;
+            const int m = md.level;
             W.w = (jp.g - m) * jp.b;
             W.B = jp.level_B[(size_t)m];
             W.hb = W.w - W.B;
             W.sb = jp.sb;
             W.cb = W.hb + W.sb;
-            W.key = J.key;
-            W.sid = J.sid;
+            W.key = jp.dev.key;
+            W.sid = jp.dev.sid;
             const size_t nb = (size_t)1 << W.B;
-            W.bcnt = reinterpret_cast<uint32_t *>(base + o_bcnt) + bc;
+            W.bcnt = reinterpret_cast<uint32_t *>(pool + c.o_bcnt) + bc;
             bc += nb;
-            Layout l;
-            char *mb = base + jp.o_mask[i];
-            W.boff = reinterpret_cast<uint32_t *>(mb + l.take((nb + 1) * 4));
-            W.bcur = reinterpret_cast<uint32_t *>(mb + l.take(nb * 4));
-            W.comp = reinterpret_cast<uint64_t *>(mb + l.take((size_t)jp.T * 8));
-            W.idx = reinterpret_cast<uint32_t *>(mb + l.take((size_t)jp.T * 4));
-            W.comp2 = reinterpret_cast<uint64_t *>(mb + l.take((size_t)jp.T * 8));
-            W.idx2 = reinterpret_cast<uint32_t *>(mb + l.take((size_t)jp.T * 4));
-            W.E = reinterpret_cast<uint32_t *>(mb + l.take((size_t)jp.T * 4));
-            W.info = reinterpret_cast<uint2 *>(mb + l.take((size_t)jp.T * 8));
-            W.D = nullptr;
-            W.dcount = nullptr;
-            W.dcap = 0;
-            W.dstride = 0;
-            W.tau = 0;
-            if (jp.want_kernel && (size_t)m < jp.dcap.size() && jp.dcap[(size_t)m]) {
+            const MaskBuf mb = mask_buf(jp.T, W.B);
+            char *mbp = pool + c.o_mask[(size_t)q];
+            W.boff = reinterpret_cast<uint32_t *>(mbp + mb.boff);
+            W.bcur = reinterpret_cast<uint32_t *>(mbp + mb.bcur);
+            W.comp = reinterpret_cast<uint64_t *>(mbp + mb.comp);
+            W.idx = reinterpret_cast<uint32_t *>(mbp + mb.idx);
+            W.comp2 = reinterpret_cast<uint64_t *>(mbp + mb.comp2);
+            W.idx2 = reinterpret_cast<uint32_t *>(mbp + mb.idx2);
+            W.E = reinterpret_cast<uint32_t *>(mbp + mb.E);
+            W.info = reinterpret_cast<uint2 *>(mbp + mb.info);
+            if (jp.want_kernel && jp.dcap[(size_t)m]) {
                 W.D = ctx->dense_buf + jp.o_dense[(size_t)m];
-                W.dcount = reinterpret_cast<uint32_t *>(base + o_flags) + p.jobs.size() + lev_base + m;
+                W.dcount = flags + p.jobs.size() + jp.lev_base + m;
                 W.dcap = jp.dcap[(size_t)m];
                 W.dstride = jp.dcap[(size_t)m];
-                W.tau = ctx->dense_tau;
+                W.tau = job_tau(ctx, jp);
             }
             pt.push_back(pt.back() + (jp.T + kTile - 1) / kTile);
         }
-        lev_base += (size_t)jp.M + 1;
+        // bucket-sort classes: 64-bit composites first
+        for (int q = 0; q < c.nmask; ++q) {
+            const MaskWork &W = p.mw[(size_t)(c.mfirst + q)];
+            if (W.cb > 32) { cls.push_back(W); pbw.push_back(pbw.back() + (1u << W.B)); }
+        }
+        c.nwide = (int)cls.size();
+        for (int q = 0; q < c.nmask; ++q) {
+            const MaskWork &W = p.mw[(size_t)(c.mfirst + q)];
+            if (W.cb <= 32) { cls.push_back(W); pbn.push_back(pbn.back() + (1u << W.B)); }
+        }
+        memcpy(blob + c.d_cls, cls.data(), sizeof(MaskWork) * cls.size());
+        c.uni_t = uniform_of(pt);
+        c.uni_bw = uniform_of(pbw);
+        c.uni_bn = uniform_of(pbn);
+        c.nb_t = pt.back();
+        c.nb_bw = pbw.back();
+        c.nb_bn = pbn.back();
+        put(c.d_pt, pt);
+        put(c.d_pbw, pbw);
+        put(c.d_pbn, pbn);
+        std::vector<uint32_t> pa(1, 0);
+        for (auto &w : c.aw) pa.push_back(pa.back() + (uint32_t)p.jobs[(size_t)w.job].N);
+        if (c.nacc) memcpy(blob + c.d_acc, c.aw.data(), sizeof(AccWork) * c.aw.size());
+        put(c.d_pacc, pa);
+        c.nb_acc = pa.back();
     }
     if (!p.mw.empty()) memcpy(blob + p.d_masks, p.mw.data(), sizeof(MaskWork) * p.mw.size());
-    if (!p.aw.empty()) memcpy(blob + p.d_acc, p.aw.data(), sizeof(AccWork) * p.aw.size());
-    auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
-    // bucket-sort classes: 64-bit composites first
-    std::vector<MaskWork> cls;
-    std::vector<uint32_t> pbw(1, 0), pbn(1, 0);
-    for (auto &W : p.mw)
-        if (W.cb > 32) { cls.push_back(W); pbw.push_back(pbw.back() + (1u << W.B)); }
-    p.nwide = (int)cls.size();
-    for (auto &W : p.mw)
-        if (W.cb <= 32) { cls.push_back(W); pbn.push_back(pbn.back() + (1u << W.B)); }
-    if (!cls.empty()) memcpy(blob + p.d_masks_cls, cls.data(), sizeof(MaskWork) * cls.size());
-    auto uniform = [](const std::vector<uint32_t> &pre) -> uint32_t {
-        if (pre.size() < 2) return 0;
-        const uint32_t u = pre[1] - pre[0];
-        for (size_t i = 1; i < pre.size(); ++i)
-            if (pre[i] - pre[i - 1] != u) return 0;
-        return u;
-    };
-    p.uni_t = uniform(pt);
-    p.uni_bw = uniform(pbw);
-    p.uni_bn = uniform(pbn);
-    p.nb_bw = pbw.back();
-    p.nb_bn = pbn.back();
-    put(p.d_pv, pv); put(p.d_px, px); put(p.d_pt, pt); put(p.d_pbw, pbw); put(p.d_pbn, pbn); put(p.d_pd, pd); put(p.d_pf, pf);
-    for (size_t i = 0; i < p.acc_prefix.size(); ++i) put(p.d_pacc[i], p.acc_prefix[i]);
-    put(p.d_pdense, pdn);
-    put(p.d_pdtile, pdt);
-    p.nb_dense = pdn.back();
-    p.nb_dtile = pdt.back();
-    p.nb_v = pv.back(); p.nb_x = px.back(); p.nb_t = pt.back(); p.nb_d = pd.back(); p.nb_f = pf.back();
+    put(p.d_pv, pv); put(p.d_px, px); put(p.d_pd, pd); put(p.d_pf, pf);
+    put(p.d_pdense, pdn); put(p.d_pdtile, pdt);
+    p.nb_v = pv.back(); p.nb_x = px.back(); p.nb_d = pd.back(); p.nb_f = pf.back();
+    p.nb_dense = pdn.back(); p.nb_dtile = pdt.back();
     return GAKCO_OK;
 }
 
 gakco_status plan_upload(Plan &p, hipStream_t st)
 {
-    char *base = p.base;
-    for (auto &jp : p.jobs) {
-        GK_HIP(hipMemcpyAsync(base + jp.o_seqoff, jp.seq_off.data(), jp.seq_off.size() * 8, hipMemcpyHostToDevice, st));
-        GK_HIP(hipMemcpyAsync(base + jp.o_gstart, jp.gstart.data(), jp.gstart.size() * 4, hipMemcpyHostToDevice, st));
-        if (jp.want_kernel) {
-            const int M1 = jp.M + 1;
-            std::vector<int64_t> coef((size_t)M1 * M1, 0), hco((size_t)M1, 0);
-            for (int m = 0; m < M1; ++m) {
-                hco[(size_t)m] = binom64(jp.g - m, jp.k);           // Eq. 6
-                for (int j = 0; j < m; ++j) coef[(size_t)m * M1 + j] = binom64(jp.g - j, m - j);  // Eq. 9
-            }
-            GK_HIP(hipMemcpyAsync(base + jp.o_coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, st));
-            GK_HIP(hipMemcpyAsync(base + jp.o_hco, hco.data(), hco.size() * 8, hipMemcpyHostToDevice, st));
-            // the copies above read pageable host memory that dies with this
-            // scope: wait for them
-            GK_HIP(hipStreamSynchronize(st));
-        }
-    }
-    GK_HIP(hipMemcpyAsync(base + p.o_desc, p.desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice, st));
+    // the blob lives as long as the plan; the call that owns the plan waits
+    // for the stream before the plan goes away
+    GK_HIP(hipMemcpyAsync(p.base + p.o_desc, p.desc_host.data(), p.desc_bytes, hipMemcpyHostToDevice, st));
     return GAKCO_OK;
 }
 
@@ -559,53 +608,35 @@ gakco_status prof_collect(gakco_ctx *ctx)
     return GAKCO_OK;
 }
 
-// Runs `launch` between two profiler events of phase `ph`.
-#define GK_PHASE(ph, launch)                         \
-    do {                                             \
-        size_t _slot = 0;                            \
-        GK_TRY(prof_begin(ctx, st, &_slot));         \
-        GK_HIP(launch);                              \
-        GK_TRY(prof_end(ctx, st, (ph), _slot));      \
-    } while (0)
-
 gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
     char *d = p.base + p.o_desc;
     const JobDev *jobs = reinterpret_cast<const JobDev *>(d + p.d_jobs);
     const MaskWork *masks = reinterpret_cast<const MaskWork *>(d + p.d_masks);
-    const AccWork *acc = reinterpret_cast<const AccWork *>(d + p.d_acc);
     auto P = [&](size_t off) { return reinterpret_cast<const uint32_t *>(d + off); };
-    const int nj = (int)p.jobs.size(), nm = (int)p.mw.size();
-    // clear flags and bucket counters (one contiguous region)
-    const size_t o_flags = p.o_flags, o_bcnt = p.o_bcnt;
-    size_t nbc = 0;
-    for (auto &W : p.mw) nbc += (size_t)1 << W.B;
-    size_t nflags = (size_t)nj;
-    for (auto &jp : p.jobs) nflags += (size_t)jp.M + 1;
-    GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_flags), nflags, 0u, st));
-    GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + o_bcnt), nbc, 0u, st));
+    const int nj = (int)p.jobs.size();
+    GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_flags), p.nflags, 0u, st));
     for (auto &jp : p.jobs)
         if (jp.want_kernel)
             GK_PHASE(PH_FILL, launch_fill_u64(reinterpret_cast<uint64_t *>(jp.dev.C), (size_t)(jp.M + 1) * jp.N * jp.N, 0ull, st));
     GK_PHASE(PH_VALIDATE, launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
     GK_PHASE(PH_EXTRACT, launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
-    if (nm) {
-        const MaskWork *cls = reinterpret_cast<const MaskWork *>(d + p.d_masks_cls);
-        GK_PHASE(PH_BCOUNT, launch_bucket_count(masks, P(p.d_pt), nm, p.uni_t, p.nb_t, p.maxB, st));
-        GK_PHASE(PH_BSCAN, launch_bucket_scan(masks, nm, st));
-        GK_PHASE(PH_BSCATTER, launch_bucket_scatter(masks, P(p.d_pt), nm, p.uni_t, p.nb_t, p.maxB, st));
-        GK_PHASE(PH_BSORT, launch_bucket_sort(cls, P(p.d_pbw), p.nwide, p.uni_bw, p.nb_bw, true, st));
-        GK_PHASE(PH_BSORT, launch_bucket_sort(cls + p.nwide, P(p.d_pbn), nm - p.nwide, p.uni_bn, p.nb_bn, false, st));
-    }
-    for (size_t gi = 0; gi < p.acc_groups.size(); ++gi) {
-        const auto &grp = p.acc_groups[gi];
-        GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, acc + grp.first, P(p.d_pacc[gi]), grp.second,
-                                             p.acc_prefix[gi].back(), p.acc_lds[gi], st));
+    for (auto &c : p.chunks) {
+        const MaskWork *cm = masks + c.mfirst;
+        const MaskWork *cls = reinterpret_cast<const MaskWork *>(d + c.d_cls);
+        GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt), c.nbcnt, 0u, st));
+        GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
+        GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, st));
+        GK_PHASE(PH_BSCATTER, launch_bucket_scatter(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
+        GK_PHASE(PH_BSORT, launch_bucket_sort(cls, P(c.d_pbw), c.nwide, c.uni_bw, c.nb_bw, true, st));
+        GK_PHASE(PH_BSORT, launch_bucket_sort(cls + c.nwide, P(c.d_pbn), c.nmask - c.nwide, c.uni_bn, c.nb_bn, false, st));
+        if (c.nacc)
+            GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc),
+                                                 c.nacc, c.nb_acc, c.acc_lds, st));
     }
     if (p.n_dense) {
         const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
-        ctx->dense_dirty = true;
         GK_PHASE(PH_DENSE, launch_dense(dw, P(p.d_pdense), p.n_dense, p.nb_dense, P(p.d_pdtile), p.nb_dtile, st));
         GK_PHASE(PH_DENSE, launch_dense_clear(dw, p.n_dense, st));
         ctx->dense_dirty = false;
@@ -614,23 +645,28 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         GK_PHASE(PH_DIAG, launch_diag(jobs, P(p.d_pd), nj, p.nb_d, p.maxM, st));
         GK_PHASE(PH_FINALIZE, launch_finalize(jobs, P(p.d_pf), nj, p.nb_f, p.maxM, st));
     }
+    ctx->last_chunks = (int64_t)p.chunks.size();
     return GAKCO_OK;
 }
 
 gakco_status plan_check_errors(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
-    std::vector<int32_t> flags(p.jobs.size(), 0);
+    std::vector<int32_t> flags(p.nflags, 0);
     GK_HIP(hipMemcpyAsync(flags.data(), p.base + p.o_flags, flags.size() * 4, hipMemcpyDeviceToHost, st));
     GK_HIP(hipStreamSynchronize(st));
     GK_TRY(prof_collect(ctx));
+    ctx->last_dense_rows = 0;
+    for (size_t i = p.jobs.size(); i < flags.size(); ++i) ctx->last_dense_rows += (uint32_t)flags[i];
     gakco_status first = GAKCO_OK;
-    for (size_t j = 0; j < flags.size(); ++j) {
+    for (size_t j = 0; j < p.jobs.size(); ++j) {
         if (flags[j] & 1) {
             p.jobs[j].status = GAKCO_ERANGE;
             if (first == GAKCO_OK) {
                 set_error("job %zu: a symbol code lies outside [0, sigma=%d)", j, p.jobs[j].sigma);
                 first = GAKCO_ERANGE;
             }
+        } else {
+            p.jobs[j].status = GAKCO_OK;
         }
     }
     return first;

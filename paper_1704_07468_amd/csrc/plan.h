@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -17,23 +18,30 @@ enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTE
 
 struct gakco_ctx {
     int device = 0;
+    size_t budget = 0;
+    int dense_tau = 0;       // 0 = int8 matrix-core path off
+    int bucket_avg = 512;    // target g-mers per hash bucket
+    size_t pool_cap = 16ull << 30;  // per-chunk partition/sort buffers
+    void *arena = nullptr;
+    size_t arena_cap = 0;
+    size_t lds_max = 0;      // dynamic LDS available to the row accumulation
+    // count matrices of the int8 matrix-core path: kept all-zero between
+    // calls (each call clears the rows it used)
+    int8_t *dense_buf = nullptr;
+    size_t dense_cap = 0;
+    bool dense_dirty = false;
+    // event profiler
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_pending;  // (phase, first of two events)
     double prof_ms[PH_COUNT] = {};
     int64_t prof_n[PH_COUNT] = {};
-    size_t budget = 0;
-    int dense_tau = 0;     // 0 = int8 matrix-core path off
-    int bucket_avg = 512;  // target g-mers per hash bucket
-    void *arena = nullptr;
-    size_t arena_cap = 0;
-    size_t lds_max = 0;    // dynamic LDS available to the row accumulation
-    // count matrices of the int8 matrix-core path: kept all-zero between
-    // calls (each call clears the rows it used)
-    int8_t *dense_buf = nullptr;
-    size_t dense_cap = 0;
-    bool dense_dirty = false;
+    // autotuned int8 path threshold per job class (symbol bits * 100 + g)
+    std::map<int, int> class_tau;
+    // statistics of the last call
+    int64_t last_dense_rows = 0;
+    int64_t last_chunks = 0;
 };
 
 namespace gk {
@@ -82,6 +90,7 @@ struct JobPlan {
     int64_t *Nm_out = nullptr;
     int64_t *Cm_out = nullptr;
     bool want_kernel = true;  // run accumulation + epilogue (false: partition only)
+    int tau = -1;             // per-job int8 path threshold (-1: the context's)
     // host-side shape
     std::vector<int32_t> lens;
     int M = 0, b = 0, sb = 0;
@@ -91,10 +100,8 @@ struct JobPlan {
     std::vector<int64_t> seq_off;
     std::vector<MaskDesc> masks;
     std::vector<int> level_B;  // bucket bits per level
-    // layout offsets
-    size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_err = 0, o_C = 0, o_Kd = 0, o_coef = 0,
-           o_hco = 0;
-    std::vector<size_t> o_mask;  // per mask: base of its buffers
+    // layout offsets (arena)
+    size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_C = 0, o_Kd = 0, o_coef = 0, o_hco = 0;
     std::vector<uint32_t> dcap;  // per level dense row capacity (0 = level has no dense path)
     std::vector<size_t> o_dense; // per level offset in the context's dense buffer
     std::vector<size_t> o_P;     // per level partial tiles of the split rows
@@ -106,40 +113,42 @@ struct JobPlan {
     uint32_t *sid_override = nullptr;
     // device view
     JobDev dev{};
-    int mask_first = 0;
+    int mask_first = 0;  // index of its first mask in Plan::mw
+    size_t lev_base = 0; // index of its first dense row counter
     int status = GAKCO_OK;
+};
+
+// A run of consecutive masks whose partition/sort buffers share the pool.
+struct Chunk {
+    int mfirst = 0, nmask = 0;
+    std::vector<size_t> o_mask;  // pool offset of each mask's buffers
+    size_t o_bcnt = 0, nbcnt = 0;
+    int maxB = 0;
+    // descriptor blob offsets
+    size_t d_pt = 0, d_cls = 0, d_pbw = 0, d_pbn = 0, d_acc = 0, d_pacc = 0;
+    uint32_t nb_t = 0, uni_t = 0, nb_bw = 0, nb_bn = 0, uni_bw = 0, uni_bn = 0, nb_acc = 0;
+    int nwide = 0, nacc = 0;
+    size_t acc_lds = 0;
+    std::vector<AccWork> aw;
 };
 
 // The whole plan of one call (one or more jobs).
 struct Plan {
     std::vector<JobPlan> jobs;
+    std::vector<Chunk> chunks;
     Layout lay;
     size_t o_desc = 0, desc_bytes = 0;
-    size_t o_flags = 0, o_bcnt = 0;  // per-job error flags; bucket counters of every mask
+    size_t o_flags = 0;  // per-job error flags, then the dense row counters
+    size_t nflags = 0;
+    size_t o_pool = 0, pool_bytes = 0;
     std::vector<char> desc_host;  // staged descriptor blob
-    // descriptor offsets inside the blob
-    size_t d_jobs = 0, d_masks = 0, d_acc = 0;
-    size_t d_pv = 0, d_px = 0, d_pt = 0, d_pd = 0, d_pf = 0;
-    uint32_t nb_v = 0, nb_x = 0, nb_t = 0, nb_d = 0, nb_f = 0;
-    // bucket sort: the mask works again, 64-bit-composite masks first, then
-    // 32-bit ones; per class a block prefix (or a uniform blocks-per-mask)
-    size_t d_masks_cls = 0, d_pbw = 0, d_pbn = 0;
-    uint32_t nb_bw = 0, nb_bn = 0, uni_t = 0, uni_bw = 0, uni_bn = 0;
-    int nwide = 0;
-    int maxB = 0, maxM = 0;
+    size_t d_jobs = 0, d_masks = 0, d_dense = 0, d_pdense = 0, d_pdtile = 0;
+    size_t d_pv = 0, d_px = 0, d_pd = 0, d_pf = 0;
+    uint32_t nb_v = 0, nb_x = 0, nb_d = 0, nb_f = 0, nb_dense = 0, nb_dtile = 0;
+    int n_dense = 0, maxM = 0;
+    size_t dense_bytes = 0, output_bytes = 0;
     std::vector<MaskWork> mw;
-    std::vector<AccWork> aw;
-    std::vector<size_t> acc_lds;      // dynamic LDS of each accumulate launch group
-    std::vector<std::pair<int, int>> acc_groups;  // [first, count) of aw per launch
-    std::vector<std::vector<uint32_t>> acc_prefix;
-    std::vector<size_t> d_pacc;
-    // dense path
-    size_t d_dense = 0, d_pdense = 0, d_pdtile = 0;
-    uint32_t nb_dense = 0, nb_dtile = 0;
-    int n_dense = 0;
-    size_t dense_bytes = 0;
-    char *base = nullptr;             // arena base
-    size_t output_bytes = 0;
+    char *base = nullptr;  // arena base
 };
 
 gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one, int m_one);
@@ -157,5 +166,14 @@ gakco_status prof_begin(gakco_ctx *ctx, hipStream_t st, size_t *slot);
 gakco_status prof_end(gakco_ctx *ctx, hipStream_t st, int phase, size_t slot);
 gakco_status prof_collect(gakco_ctx *ctx);
 const char *phase_name(int phase);
+
+// Runs `launch` between two profiler events of phase `ph`.
+#define GK_PHASE(ph, launch)                         \
+    do {                                             \
+        size_t _slot = 0;                            \
+        GK_TRY(prof_begin(ctx, st, &_slot));         \
+        GK_HIP(launch);                              \
+        GK_TRY(prof_end(ctx, st, (ph), _slot));      \
+    } while (0)
 
 }  // namespace gk

@@ -74,6 +74,8 @@ def lib():
                 "gakco_server_cancel": ([P, ctypes.c_uint64], i32),
                 "gakco_server_poll": ([P, P, i32, P, i32], i32),
                 "gakco_server_destroy": ([P], i32),
+                "gakco_ctx_stat": ([P, ctypes.c_char_p, P], i32),
+                "gakco_autotune": ([P, P, i32, i32, P, ctypes.c_char_p, sz], i32),
                 "gakco_profile_phases": ([], i32),
                 "gakco_profile_get": ([P, i32, P, P, P], i32),
                 "gakco_profile_reset": ([P], None),
@@ -146,6 +148,51 @@ class Context:
     def profile_reset(self):
         lib().gakco_profile_reset(self._h)
 
+    def stat(self, name: str) -> int:
+        v = ctypes.c_int64()
+        _check(lib().gakco_ctx_stat(self._h, name.encode(), ctypes.byref(v)))
+        return v.value
+
+    # ------------------------------------------------------------- batches --
+    def _jobs(self, jobs):
+        """jobs: list of dicts with seqs, lens (device tensors), sigma, g, k and
+        optional K / Nm output tensors; missing outputs are allocated."""
+        arr = (Job * len(jobs))()
+        status = (ctypes.c_int32 * len(jobs))()
+        keep = []
+        for i, j in enumerate(jobs):
+            seqs, lens = _dev_inputs(j["seqs"], j["lens"], self.device)
+            N, M = int(lens.numel()), j["g"] - j["k"]
+            if "K" not in j:
+                j["K"] = torch.empty((N, N), dtype=torch.float64, device=self.device)
+            if "Nm" not in j:
+                j["Nm"] = torch.empty((M + 1, N, N), dtype=torch.int64, device=self.device)
+            j["_seqs"], j["_lens"] = seqs, lens
+            keep += [seqs, lens]
+            arr[i] = Job(seqs.data_ptr(), lens.data_ptr(), N, j["sigma"], j["g"], j["k"],
+                         j["K"].data_ptr() if j["K"] is not None else None,
+                         j["Nm"].data_ptr() if j["Nm"] is not None else None,
+                         ctypes.addressof(status) + 4 * i)
+        return arr, status, keep
+
+    def gram_batch(self, jobs):
+        """Run every job in shared launches; returns the per-job statuses."""
+        arr, status, _keep = self._jobs(jobs)
+        rc = lib().gakco_gram_batch(self._h, arr, len(jobs), _stream(self.device))
+        if rc != OK and rc != ERANGE:
+            _check(rc)
+        return list(status)
+
+    def batch_plan(self, jobs):
+        return BatchPlan(self, jobs)
+
+    def autotune(self, jobs, reps: int = 2) -> str:
+        arr, _status, _keep = self._jobs(jobs)
+        buf = ctypes.create_string_buffer(4096)
+        _check(lib().gakco_autotune(self._h, arr, len(jobs), reps, _stream(self.device), buf, 4096))
+        return buf.value.decode()
+
+
     # ---------------------------------------------------------------- Gram --
     def gram(self, seqs, lens, sigma: int, g: int, k: int, want_K: bool = True, want_Nm: bool = True,
              want_Cm: bool = False, out: dict | None = None):
@@ -202,6 +249,35 @@ class Context:
             a, b = grp_off[q], grp_off[q + 1]
             out.append((int(grp_rep[q]), list(zip(ent_sid[a:b].tolist(), ent_cnt[a:b].tolist()))))
         return out
+
+
+class BatchPlan:
+    """A batch whose launch sequence is captured once into a hipGraph."""
+
+    def __init__(self, ctx: Context, jobs):
+        self.ctx = ctx
+        self.jobs = jobs
+        self._arr, self._status, self._keep = ctx._jobs(jobs)
+        h = ctypes.c_void_p()
+        _check(lib().gakco_batch_plan_create(ctx._h, self._arr, len(jobs), _stream(ctx.device), ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        rc = lib().gakco_batch_run(self._h, _stream(self.ctx.device))
+        if rc != OK and rc != ERANGE:
+            _check(rc)
+        return list(self._status)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gakco_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:
