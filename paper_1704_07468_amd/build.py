@@ -19,6 +19,8 @@ SOURCES = [
     "plan.cpp",
     "api.cpp",
     "batch.cpp",
+    "rows.hip",
+    "serve.cpp",
 ]
 
 CFLAGS = [

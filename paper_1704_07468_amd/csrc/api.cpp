@@ -16,6 +16,8 @@ hipError_t init_kernel_attributes(size_t acc_lds);
 
 using namespace gk;
 
+void rows_scratch_release(const gakco_ctx *ctx);
+
 static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
 {
     if (!strcmp(name, "dense_tau")) {
@@ -102,6 +104,7 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
 void gakco_ctx_destroy(gakco_ctx *ctx)
 {
     if (!ctx) return;
+    rows_scratch_release(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->dense_buf) {
         (void)hipSetDevice(ctx->device);

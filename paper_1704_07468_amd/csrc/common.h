@@ -73,6 +73,10 @@ struct MaskWork {
     uint32_t dcap;     // row capacity
     uint32_t dstride;  // bytes per sequence
     int32_t tau;       // min distinct sequences of a dense group (0 = off)
+    // resident tables (serving): per bucket its groups in hash-rest order
+    uint4 *gtab;       // [T] (hash rest lo, hi, first entry, end entry) at bucket offset + group (nullable)
+    uint32_t *bgrp;    // [2^B] groups per bucket
+    uint32_t *diag;    // [N] sum over runs of count^2 per sequence, this level (nullable)
 };
 
 // Row accumulation work: rows of one job over a range of masks.
@@ -267,9 +271,13 @@ __device__ __forceinline__ uint32_t last_le(UP a, uint32_t n, uint32_t v)
 // rpos, gsr, gaux: scratch of n entries each.  Runs and groups are found in
 // rounds of 1024 elements, 4 consecutive ones per thread, with one block scan
 // per round for each.
+// With W.gtab set, the bucket's groups are also listed (hash rest, first
+// entry, end entry) at gtab[ebase + group] and their number at
+// bgrp[bucket]; with W.diag set, every run adds count^2 to its sequence's
+// diagonal counter (the self-pairs of Algorithm 1's countAndUpdate).
 template <typename KP, typename VP, typename UP>
 __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos, UP gsr, UP gaux,
-                                              const MaskWork &W, uint32_t ebase, uint32_t *wsum)
+                                              const MaskWork &W, uint32_t ebase, uint32_t *wsum, uint32_t bucket)
 {
     const int tid = threadIdx.x;
     const int sb = W.sb;
@@ -343,6 +351,22 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
     }
     for (uint32_t i = tid; i < n; i += kThreads)
         if (i > 0 && fk[i] == fk[i - 1]) W.info[fv[i]] = make_uint2(0u, 0u);
+    if (W.gtab) {
+        for (uint32_t gi = tid; gi < G; gi += kThreads) {
+            const uint32_t r0 = gsr[gi];
+            const uint32_t r1 = (gi + 1 < G) ? gsr[gi + 1] : R;
+            const uint64_t hr = (uint64_t)fk[rpos[r0]] >> sb;
+            W.gtab[ebase + gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ebase + r0, ebase + r1);
+        }
+        if (tid == 0) W.bgrp[bucket] = G;
+    }
+    if (W.diag) {
+        for (uint32_t r = tid; r < R; r += kThreads) {
+            const uint32_t p = rpos[r];
+            const uint32_t cnt = ((r + 1 < R) ? rpos[r + 1] : n) - p;
+            atomicAdd(&W.diag[(uint32_t)((uint64_t)fk[p] & sidmask)], cnt * cnt);
+        }
+    }
 }
 
 // Block -> (item, block within item): arithmetic when every item has the

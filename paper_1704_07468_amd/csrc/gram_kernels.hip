@@ -177,6 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__rest
     if (bucket >= (1u << W.B)) return;
     const uint32_t base = W.boff[bucket];
     const uint32_t n = W.boff[bucket + 1] - base;
+    if (n == 0 && !BIG && W.gtab && threadIdx.x == 0) W.bgrp[bucket] = 0;
     if (n == 0 || (!BIG && n > (uint32_t)kSmallCap) || (BIG && n <= (uint32_t)kSmallCap)) return;
     K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
     if (n <= (uint32_t)CAP) {
@@ -192,8 +193,8 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__rest
         uint32_t *fv = which ? vB : vA;
         uint32_t *fr = reinterpret_cast<uint32_t *>(which ? kA : kB);
         uint32_t *fx = which ? vA : vB;
-        if (W64) block_segment(fk, fv, n, fr, fr + CAP, fx, W, base, ss.wsum);
-        else block_segment(fk, fv, n, fr, fx, xs, W, base, ss.wsum);
+        if (W64) block_segment(fk, fv, n, fr, fr + CAP, fx, W, base, ss.wsum, bucket);
+        else block_segment(fk, fv, n, fr, fx, xs, W, base, ss.wsum, bucket);
     } else {
         int which = 0;
         block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which);
@@ -204,8 +205,8 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__rest
         uint32_t *fx = (which ? W.idx : W.idx2) + base;
         // scratch: this bucket's slice of the free composite array (2n
         // words), or for 32-bit composites its slice of each half
-        if (W64) block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum);
-        else block_segment(fk, fv, n, fr + base, fr + (size_t)W.T + base, fx, W, base, ss.wsum);
+        if (W64) block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket);
+        else block_segment(fk, fv, n, fr + base, fr + (size_t)W.T + base, fx, W, base, ss.wsum, bucket);
     }
 }
 

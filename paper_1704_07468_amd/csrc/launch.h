@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 namespace gk {
+struct MaskDesc;
 struct JobDev;
 struct MaskWork;
 struct AccWork;
@@ -33,5 +34,16 @@ int dense_kchunk();
 uint32_t dense_split_rows();
 void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt, int S,
                      int64_t *C, int32_t *P);
+size_t res_mask_size();
+void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, const uint32_t *boff, const uint32_t *bgrp,
+                   const uint32_t *E, const uint4 *gtab);
+hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab,
+                       const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C, hipStream_t st);
+hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef, const int64_t *hco, int64_t *Kd,
+                               hipStream_t st);
+hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,
+                                const int64_t *Kd_sv, const int64_t *Kd_q, const double *alpha, double bias, double *K_rows,
+                                int64_t *Nm_rows, double *decision, hipStream_t st);
+hipError_t init_rows_attributes(size_t lds);
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
 }  // namespace gk

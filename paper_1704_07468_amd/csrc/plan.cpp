@@ -516,6 +516,14 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             W.idx2 = reinterpret_cast<uint32_t *>(mbp + mb.idx2);
             W.E = reinterpret_cast<uint32_t *>(mbp + mb.E);
             W.info = reinterpret_cast<uint2 *>(mbp + mb.info);
+            const size_t mi = (size_t)(gi - jp.mask_first);
+            if (!jp.ext_boff.empty()) {
+                W.boff = jp.ext_boff[mi];
+                W.bgrp = jp.ext_bgrp[mi];
+                W.E = jp.ext_E[mi];
+                W.gtab = jp.ext_gtab[mi];
+            }
+            if (!jp.ext_diag.empty()) W.diag = jp.ext_diag[(size_t)m];
             if (jp.want_kernel && jp.dcap[(size_t)m]) {
                 W.D = ctx->dense_buf + jp.o_dense[(size_t)m];
                 W.dcount = flags + p.jobs.size() + jp.lev_base + m;

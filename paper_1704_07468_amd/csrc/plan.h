@@ -111,6 +111,12 @@ struct JobPlan {
     bool own_C = false;
     uint64_t *key_override = nullptr;  // write g-mers to caller buffers (stage entry point)
     uint32_t *sid_override = nullptr;
+    // serving: caller-owned per-mask tables that outlive the call (bucket
+    // offsets, groups per bucket, run entries, group tables) and per-level
+    // diagonal counters (zeroed by the caller)
+    std::vector<uint32_t *> ext_boff, ext_bgrp, ext_E;
+    std::vector<uint4 *> ext_gtab;
+    std::vector<uint32_t *> ext_diag;
     // device view
     JobDev dev{};
     int mask_first = 0;  // index of its first mask in Plan::mw

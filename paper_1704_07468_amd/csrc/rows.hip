@@ -1,0 +1,234 @@
+// gfx950 kernels of the serving path: kernel rows of query sequences against
+// a resident set kept as per-position-set group tables.
+//
+// For a query q, a level m and one of its position sets, every g-mer of q is
+// reduced, hashed into the resident table's bucket, and its group (the
+// resident sequences holding the same reduced g-mer, with counts) found by a
+// binary search of the bucket's hash-ordered group list.  Each entry
+// (sequence sv, count c) of the group adds c to row[sv]: summed over the
+// g-mers of q this is count_q * count_sv per reduced g-mer, i.e. the q-by-sv
+// entries of Algorithm 1's countAndUpdate.  Rows of C_m then go through
+// Eq. 9, Eq. 7, the cosine normalisation and Eq. 1's decision value.
+#include "common.h"
+#include "launch.h"
+
+namespace gk {
+
+struct ResMask {
+    MaskDesc md;
+    int32_t w, B, hb, sb;
+    const uint32_t *boff;  // [2^B + 1] first entry of each bucket
+    const uint32_t *bgrp;  // [2^B] groups per bucket
+    const uint32_t *E;     // run entries: sequence | count << sb
+    const uint4 *gtab;     // groups (hash rest lo, hi, first entry, end entry)
+};
+
+struct RowsArgs {
+    const uint64_t *qkey;      // query g-mers, packed
+    const uint32_t *qgstart;   // [nq + 1]
+    int32_t nq, M, nsv, slab;  // SVs per block (one LDS row slab)
+    int32_t nslab;
+    const ResMask *rm;
+    const int32_t *lev_first;  // first mask of each level
+    const int32_t *lev_count;
+    uint32_t *C;               // [M+1][nq][nsv]
+};
+
+__device__ __forceinline__ void wave_sync_rows()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// First index in E[a, b) whose sequence id is >= s (entries sequence-sorted).
+__device__ __forceinline__ uint32_t lower_sid(const uint32_t *E, uint32_t a, uint32_t b, uint32_t s, uint32_t sidmask)
+{
+    while (a < b) {
+        const uint32_t mid = (a + b) >> 1;
+        if ((E[mid] & sidmask) < s) a = mid + 1; else b = mid;
+    }
+    return a;
+}
+
+// One block per (level, query, SV slab), heavy levels first.
+__global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
+{
+    extern __shared__ uint32_t acc[];
+    __shared__ uint32_t pre[kWaves][64];
+    __shared__ uint64_t iptr[kWaves][64];
+    const int per_level = A.nq * A.nslab;
+    const int level = A.M - (int)(blockIdx.x / per_level);
+    const int rem = (int)(blockIdx.x % per_level);
+    const int q = rem / A.nslab, sl = rem % A.nslab;
+    const int s0 = sl * A.slab, s1 = min(A.nsv, s0 + A.slab);
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < s1 - s0; i += kThreads) acc[i] = 0;
+    __syncthreads();
+    const uint32_t t0 = A.qgstart[q];
+    const uint32_t ng = A.qgstart[q + 1] - t0;
+    const uint32_t nmask = (uint32_t)A.lev_count[level];
+    const uint32_t total = ng * nmask;
+    const ResMask *rm = A.rm + A.lev_first[level];
+    const int sb = rm[0].sb;
+    const uint32_t sidmask = (uint32_t)bits_mask(sb);
+    for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
+        const uint32_t it = c0 + lane;
+        uint32_t len = 0;
+        if (it < total) {
+            const uint32_t s = it / ng;
+            const ResMask &R = rm[s];
+            const uint64_t h = mix_w(compact_key(A.qkey[t0 + (it - s * ng)], R.md), R.w);
+            const uint32_t b = (uint32_t)(R.hb >= 64 ? 0 : (h >> R.hb));
+            const uint64_t hr = h & bits_mask(R.hb);
+            uint32_t lo = R.boff[b], hi = lo + R.bgrp[b];
+            while (lo < hi) {  // first group with hash rest >= hr
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint4 gm = R.gtab[mid];
+                if ((((uint64_t)gm.y << 32) | gm.x) < hr) lo = mid + 1; else hi = mid;
+            }
+            if (lo < R.boff[b] + R.bgrp[b]) {
+                const uint4 gm = R.gtab[lo];
+                if ((((uint64_t)gm.y << 32) | gm.x) == hr) {
+                    uint32_t e0 = gm.z, e1 = gm.w;
+                    if (A.nslab > 1) {
+                        e0 = lower_sid(R.E, e0, e1, (uint32_t)s0, sidmask);
+                        e1 = lower_sid(R.E, e0, e1, (uint32_t)s1, sidmask);
+                    }
+                    len = e1 - e0;
+                    iptr[wid][lane] = reinterpret_cast<uint64_t>(R.E + e0);
+                }
+            }
+        }
+        const uint32_t inc = wave_incl_scan(len);
+        const uint32_t work = __shfl(inc, 63, 64);
+        pre[wid][lane] = inc - len;
+        wave_sync_rows();
+        for (uint32_t w = lane; w < work; w += 64) {
+            const uint32_t i = last_le(pre[wid], 64u, w);
+            const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[wid][i])[w - pre[wid][i]];
+            atomicAdd(&acc[(ent & sidmask) - (uint32_t)s0], ent >> sb);
+        }
+        wave_sync_rows();
+    }
+    __syncthreads();
+    uint32_t *crow = A.C + ((size_t)level * A.nq + q) * A.nsv;
+    for (int sv = s0 + tid; sv < s1; sv += kThreads) crow[sv] = acc[sv - s0];
+}
+
+// K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.
+__global__ __launch_bounds__(kThreads) void k_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef,
+                                                           const int64_t *hco, int64_t *Kd)
+{
+    const int x = blockIdx.x * kThreads + threadIdx.x;
+    if (x >= n) return;
+    int64_t nv[65];
+    int64_t kx = 0;
+    for (int m = 0; m <= M; ++m) {
+        int64_t v = diag[(size_t)m * n + x];
+        for (int j = 0; j < m; ++j) v -= coef[m * (M + 1) + j] * nv[j];
+        nv[m] = v;
+        kx += hco[m] * v;
+    }
+    Kd[x] = kx;
+}
+
+struct RowsFinArgs {
+    const uint32_t *C;
+    int32_t nq, nsv, M;
+    const int64_t *coef, *hco;
+    const int64_t *Kd_sv, *Kd_q;
+    const double *alpha;
+    double bias;
+    double *K_rows;
+    int64_t *Nm_rows;
+    double *decision;
+};
+
+// One block per query: Eq. 9 and Eq. 7 per entry, the normalisation with
+// K(sv,sv) and K(q,q), and f(q) = b + sum_i alpha_i K-hat(sv_i, q) (Eq. 1).
+// Every thread sums its entries in ascending order and the block combines
+// the thread sums in a fixed tree, so a query's value does not depend on the
+// other queries of its batch.
+template <int MM>
+__global__ __launch_bounds__(kThreads) void k_rows_finalize(RowsFinArgs A)
+{
+    __shared__ double red[kThreads];
+    __shared__ int64_t coef[MM * MM], hco[MM];
+    const int q = blockIdx.x, tid = threadIdx.x, M = A.M;
+    for (int i = tid; i < (M + 1) * (M + 1); i += kThreads) coef[(i / (M + 1)) * MM + (i % (M + 1))] = A.coef[i];
+    for (int i = tid; i <= M; i += kThreads) hco[i] = A.hco[i];
+    __syncthreads();
+    const int64_t kq = A.Kd_q[q];
+    double part = 0.0;
+    for (int sv = tid; sv < A.nsv; sv += kThreads) {
+        int64_t nv[MM];
+        int64_t K = 0;
+        for (int m = 0; m <= M; ++m) {
+            int64_t v = A.C[((size_t)m * A.nq + q) * A.nsv + sv];
+            for (int j = 0; j < m; ++j) v -= coef[m * MM + j] * nv[j];
+            nv[m] = v;
+            K += hco[m] * v;
+            if (A.Nm_rows) A.Nm_rows[((size_t)m * A.nq + q) * A.nsv + sv] = v;
+        }
+        const int64_t ks = A.Kd_sv[sv];
+        const double kh = (kq == 0 || ks == 0) ? 0.0 : (double)K / sqrt((double)ks * (double)kq);
+        if (A.K_rows) A.K_rows[(size_t)q * A.nsv + sv] = kh;
+        if (A.alpha) part += A.alpha[sv] * kh;
+    }
+    red[tid] = part;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0 && A.decision) A.decision[q] = A.bias + red[0];
+}
+
+size_t res_mask_size() { return sizeof(ResMask); }
+
+void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, const uint32_t *boff, const uint32_t *bgrp,
+                   const uint32_t *E, const uint4 *gtab)
+{
+    ResMask r{md, w, B, hb, sb, boff, bgrp, E, gtab};
+    *reinterpret_cast<ResMask *>(dst) = r;
+}
+
+hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab,
+                       const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C, hipStream_t st)
+{
+    if (nq <= 0) return hipSuccess;
+    RowsArgs a{qkey, qgstart, nq, M, nsv, slab, (nsv + slab - 1) / slab, reinterpret_cast<const ResMask *>(rm),
+               lev_first, lev_count, C};
+    const unsigned nb = (unsigned)(nq * (M + 1) * a.nslab);
+    hipLaunchKernelGGL(k_rows_accumulate, dim3(nb), dim3(kThreads), (size_t)slab * 4, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef, const int64_t *hco, int64_t *Kd,
+                               hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kdiag_counts, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, diag, n, M, coef, hco, Kd);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,
+                                const int64_t *Kd_sv, const int64_t *Kd_q, const double *alpha, double bias, double *K_rows,
+                                int64_t *Nm_rows, double *decision, hipStream_t st)
+{
+    if (nq <= 0) return hipSuccess;
+    RowsFinArgs a{C, nq, nsv, M, coef, hco, Kd_sv, Kd_q, alpha, bias, K_rows, Nm_rows, decision};
+    if (M < 8) hipLaunchKernelGGL(k_rows_finalize<8>, dim3(nq), dim3(kThreads), 0, st, a);
+    else if (M < 16) hipLaunchKernelGGL(k_rows_finalize<16>, dim3(nq), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_rows_finalize<65>, dim3(nq), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t init_rows_attributes(size_t lds)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_accumulate), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+}  // namespace gk

@@ -280,5 +280,105 @@ class BatchPlan:
             pass
 
 
+class Resident:
+    """A resident sequence set (e.g. support vectors) kept as device tables."""
+
+    def __init__(self, ctx: Context, seqs, lens, sigma: int, g: int, k: int, alpha=None, bias: float = 0.0):
+        import numpy as np
+        self.ctx = ctx
+        seqs, lens = _dev_inputs(seqs, lens, ctx.device)
+        self.n_sv, self.sigma, self.g, self.k = int(lens.numel()), sigma, g, k
+        a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().gakco_resident_create(ctx._h, _ptr(seqs), _ptr(lens), self.n_sv, sigma, g, k,
+                                           a.ctypes.data_as(ctypes.c_void_p) if a is not None else None,
+                                           float(bias), ctypes.byref(h)))
+        self._h = h
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().gakco_resident_info(self._h, None, None, None, None, ctypes.byref(b)))
+        return b.value
+
+    def rows(self, q_seqs, q_lens, want_nm: bool = False, ctx: Context | None = None):
+        """K-hat rows [n_q, n_sv] f64, decision values [n_q] f64, N_m rows if asked."""
+        ctx = ctx or self.ctx
+        q_seqs, q_lens = _dev_inputs(q_seqs, q_lens, ctx.device)
+        n_q, M = int(q_lens.numel()), self.g - self.k
+        K = torch.empty((n_q, self.n_sv), dtype=torch.float64, device=ctx.device)
+        dec = torch.empty(n_q, dtype=torch.float64, device=ctx.device)
+        Nm = torch.empty((M + 1, n_q, self.n_sv), dtype=torch.int64, device=ctx.device) if want_nm else None
+        _check(lib().gakco_rows(ctx._h, self._h, _ptr(q_seqs), _ptr(q_lens), n_q, _ptr(K), _ptr(Nm), _ptr(dec),
+                                _stream(ctx.device)))
+        out = {"K": K, "decision": dec}
+        if want_nm:
+            out["Nm"] = Nm
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gakco_resident_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over a resident set (host queries)."""
+
+    def __init__(self, resident: Resident, max_batch: int = 256, n_streams: int = 2, hbm_budget: int = 0, device: int = 0):
+        self.res = resident
+        h = ctypes.c_void_p()
+        _check(lib().gakco_server_create(resident._h, device, max_batch, n_streams, hbm_budget, ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, q, tag: int):
+        import numpy as np
+        q = np.ascontiguousarray(q, dtype=np.int8)
+        _check(lib().gakco_server_submit(self._h, q.ctypes.data_as(ctypes.c_void_p) if q.size else None,
+                                         int(q.size), int(tag)))
+
+    def cancel(self, tag: int) -> bool:
+        rc = lib().gakco_server_cancel(self._h, int(tag))
+        if rc == EAGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self, max_results: int = 64, wait_us: int = 1000):
+        import numpy as np
+        arr = (Result * max_results)()
+        n = ctypes.c_int32()
+        rc = lib().gakco_server_poll(self._h, arr, max_results, ctypes.byref(n), wait_us)
+        if rc not in (OK, EAGAIN):
+            _check(rc)
+        out = []
+        for i in range(n.value):
+            r = arr[i]
+            row = None
+            if r.K_row:
+                row = np.ctypeslib.as_array(ctypes.cast(r.K_row, ctypes.POINTER(ctypes.c_double)),
+                                            shape=(self.res.n_sv,)).copy()
+            out.append({"tag": r.tag, "status": r.status, "decision": r.decision, "K_row": row,
+                        "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done,
+                        "batch_size": r.batch_size})
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gakco_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def version() -> str:
     return lib().gakco_version().decode()
