@@ -154,12 +154,70 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
 }
 
 // ---------------------------------------------------- bucket sort+segment --
-// One block per (mask, bucket): radix-sort the bucket by (hash rest,
-// sequence) -- in LDS when it holds at most CAP g-mers, else in global
-// memory -- then segment it into groups and runs.  K is the composite word
-// (32 or 64 bits).  The small variant takes buckets of 1..kSmallCap g-mers,
-// the big one the rest.
+// Buckets are radix-sorted by (hash rest, sequence) and segmented into
+// groups and runs by one of three kernels, by size: a wave per bucket of at
+// most kWaveCap g-mers (four buckets per block, no block barrier), a block
+// per bucket of at most kSmallCap, and a block per larger bucket sorted in a
+// large LDS buffer or, beyond it, in global memory.  K is the composite word
+// (32 or 64 bits).
+constexpr int kWaveCap = 512;
 constexpr int kSmallCap = 1024;
+
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_bucket_sort_wave(const MaskWork *__restrict__ items,
+                                                               const uint32_t *__restrict__ bprefix, int nitems,
+                                                               uint32_t uniform, uint32_t nbuckets)
+{
+    __shared__ K kA[kWaves][kWaveCap], kB[kWaves][kWaveCap];
+    __shared__ uint32_t vA[kWaves][kWaveCap], vB[kWaves][kWaveCap], aux[kWaves][kWaveCap];
+    __shared__ uint32_t hist[kWaves][256];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t task = blockIdx.x * kWaves + wid;
+    if (task >= nbuckets) return;
+    int it;
+    uint32_t bucket;
+    map_block(bprefix, nitems, uniform, task, it, bucket);
+    const MaskWork &W = items[it];
+    if (bucket >= (1u << W.B)) return;
+    const uint32_t base = W.boff[bucket];
+    const uint32_t n = W.boff[bucket + 1] - base;
+    if (n == 0) {
+        if (W.gtab && lane == 0) W.bgrp[bucket] = 0;
+        return;
+    }
+    if (n > (uint32_t)kWaveCap) return;
+    const K *gc = reinterpret_cast<const K *>(W.comp);
+    {
+        // all loads in flight before the first LDS store
+        constexpr int PER = kWaveCap / 64;
+        K kr[PER];
+        uint32_t vr[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t i = q * 64 + lane;
+            if (i < n) {
+                kr[q] = gc[base + i];
+                vr[q] = W.idx[base + i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t i = q * 64 + lane;
+            if (i < n) {
+                kA[wid][i] = kr[q];
+                vA[wid][i] = vr[q];
+            }
+        }
+    }
+    wave_sync();
+    int which = 0;
+    wave_radix_sort<K>(kA[wid], vA[wid], kB[wid], vB[wid], n, W.cb, hist[wid], which);
+    const K *fk = which ? kB[wid] : kA[wid];
+    const uint32_t *fv = which ? vB[wid] : vA[wid];
+    uint32_t *rpos = reinterpret_cast<uint32_t *>(which ? kA[wid] : kB[wid]);
+    uint32_t *gsr = which ? vA[wid] : vB[wid];
+    wave_segment<K>(fk, fv, n, rpos, gsr, aux[wid], W, base, bucket);
+}
 
 template <typename K, int CAP, bool BIG>
 __global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
@@ -177,13 +235,29 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__rest
     if (bucket >= (1u << W.B)) return;
     const uint32_t base = W.boff[bucket];
     const uint32_t n = W.boff[bucket + 1] - base;
-    if (n == 0 && !BIG && W.gtab && threadIdx.x == 0) W.bgrp[bucket] = 0;
-    if (n == 0 || (!BIG && n > (uint32_t)kSmallCap) || (BIG && n <= (uint32_t)kSmallCap)) return;
+    if (n <= (uint32_t)kWaveCap || (!BIG && n > (uint32_t)kSmallCap) || (BIG && n <= (uint32_t)kSmallCap)) return;
     K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
     if (n <= (uint32_t)CAP) {
-        for (uint32_t i = threadIdx.x; i < n; i += kThreads) {
-            kA[i] = gc[base + i];
-            vA[i] = W.idx[base + i];
+        for (uint32_t c0 = 0; c0 < n; c0 += kThreads * 8) {
+            // eight loads per thread in flight before the LDS stores
+            K kr[8];
+            uint32_t vr[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t i = c0 + q * kThreads + threadIdx.x;
+                if (i < n) {
+                    kr[q] = gc[base + i];
+                    vr[q] = W.idx[base + i];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t i = c0 + q * kThreads + threadIdx.x;
+                if (i < n) {
+                    kA[i] = kr[q];
+                    vA[i] = vr[q];
+                }
+            }
         }
         __syncthreads();
         int which = 0;
@@ -219,13 +293,6 @@ __global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__rest
 // Each wave consumes its own chunks of 64 (mask, g-mer) items; a wave scan of
 // their run lengths spreads the chunk's updates evenly over the lanes, so the
 // loop has no block barrier.  The row is then added into the int64 C_m.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
                                                          const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
 {
@@ -269,7 +336,21 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         const uint32_t work = __shfl(inc, 63, 64);
         pre[wid][lane] = inc - len;
         wave_sync();
-        for (uint32_t w = lane; w < work; w += 64) {
+        // four independent updates per lane in flight: their searches and
+        // entry loads overlap before the LDS atomics
+        uint32_t w = lane;
+        for (; w + 192 < work; w += 256) {
+            uint32_t i[4], ent[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) i[u] = last_le(pre[wid], 64u, w + 64 * u);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                ent[u] = reinterpret_cast<const uint32_t *>(iptr[wid][i[u]])[w + 64 * u - pre[wid][i[u]]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                atomicAdd(&acc[ioff[wid][i[u]] + (ent[u] & sidmask)], icx[wid][i[u]] * (ent[u] >> sb));
+        }
+        for (; w < work; w += 64) {
             const uint32_t i = last_le(pre[wid], 64u, w);
             const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[wid][i])[w - pre[wid][i]];
             atomicAdd(&acc[ioff[wid][i] + (ent & sidmask)], icx[wid][i] * (ent >> sb));
@@ -329,6 +410,9 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     for (int i = tid; i <= M; i += kThreads) hco[i] = Jb.hco[i];
     __syncthreads();
     const int c = tid & 31;
+    // level loops are unrolled over the compile-time bound so the per-level
+    // values stay in registers
+    constexpr int UNR = MM <= 16 ? MM : 1;
     int64_t nv[4][MM];
     int64_t kv[4];
     bool valid[4];
@@ -339,16 +423,21 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
         valid[q] = (x < N) && (y < N) && (I < Jt || r <= c);
         kv[q] = 0;
         if (valid[q]) {
-            for (int m = 0; m <= M; ++m) {
-                int64_t v = Jb.C[((size_t)m * N + x) * N + y];
-                for (int jj = 0; jj < m; ++jj) v -= coef[m * MM + jj] * nv[q][jj];
+#pragma unroll UNR
+            for (int m = 0; m < MM; ++m) {
+                int64_t v = 0;
+                if (m <= M) {
+                    v = Jb.C[((size_t)m * N + x) * N + y];
+#pragma unroll UNR
+                    for (int jj = 0; jj < m; ++jj) v -= coef[m * MM + jj] * nv[q][jj];
+                    kv[q] += hco[m] * v;
+                }
                 nv[q][m] = v;
-                kv[q] += hco[m] * v;
             }
         }
     }
     __syncthreads();  // every read of C precedes any write (C may alias Nm_out)
-    auto emit = [&](int64_t *out, auto value_of) {
+    auto emit = [&](int64_t *out, auto value_of) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = (tid >> 5) + 8 * q;
@@ -368,13 +457,19 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
         __syncthreads();
     };
     if (Jb.Nm_out) {
-        for (int m = 0; m <= M; ++m)
-            emit(Jb.Nm_out + (size_t)m * N * N, [&](int q) { return nv[q][m]; });
+#pragma unroll UNR
+        for (int m = 0; m < MM; ++m) {
+            if (m > M) continue;
+            emit(Jb.Nm_out + (size_t)m * N * N, [&](int q) __attribute__((always_inline)) { return nv[q][m]; });
+        }
     }
     if (Jb.Cm_out) {
-        for (int m = 0; m <= M; ++m) {
-            emit(Jb.Cm_out + (size_t)m * N * N, [&](int q) {
+#pragma unroll UNR
+        for (int m = 0; m < MM; ++m) {
+            if (m > M) continue;
+            emit(Jb.Cm_out + (size_t)m * N * N, [&](int q) __attribute__((always_inline)) {
                 int64_t v = nv[q][m];
+#pragma unroll UNR
                 for (int jj = 0; jj < m; ++jj) v += coef[m * MM + jj] * nv[q][jj];
                 return v;
             });
@@ -447,10 +542,13 @@ hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, in
                               bool wide, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
+    const unsigned nw = (nblocks + kWaves - 1) / kWaves;  // nblocks = buckets of all items
     if (wide) {
+        hipLaunchKernelGGL((k_bucket_sort_wave<uint64_t>), dim3(nw), dim3(kThreads), 0, st, items, bprefix, nitems, uniform, nblocks);
         hipLaunchKernelGGL((k_bucket_sort<uint64_t, kSmallCap, false>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
         hipLaunchKernelGGL((k_bucket_sort<uint64_t, 4096, true>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
     } else {
+        hipLaunchKernelGGL((k_bucket_sort_wave<uint32_t>), dim3(nw), dim3(kThreads), 0, st, items, bprefix, nitems, uniform, nblocks);
         hipLaunchKernelGGL((k_bucket_sort<uint32_t, kSmallCap, false>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
         hipLaunchKernelGGL((k_bucket_sort<uint32_t, 6144, true>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
     }
