@@ -15,6 +15,7 @@ ARCH = "gfx950"
 
 SOURCES = [
     "gram_kernels.hip",
+    "bucket_sort.hip",
     "dense_mfma.hip",
     "plan.cpp",
     "api.cpp",

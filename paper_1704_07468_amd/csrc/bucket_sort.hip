@@ -1,0 +1,774 @@
+// Per-bucket sort and segmentation of the partitioned g-mers (Section 2.2,
+// step 3: for every reduced g-mer, the sequences that hold it and how often).
+//
+// A bucket holds the g-mers whose hashed reduced key shares its top B bits.
+// Sorting it by the composite word (hash rest, then sequence id) puts equal
+// reduced g-mers next to each other ("groups") and, inside a group, equal
+// sequences next to each other ("runs").  The scan kernel files every
+// non-empty bucket into a size class; then
+//   * a bucket of at most 1024 g-mers (512 with 64-bit composites) is sorted
+//     by one wave, 64 * EL elements held in registers (EL per lane), by a
+//     bitonic network whose exchanges are lane permutes (DPP, ds_swizzle,
+//     ds_bpermute) or register swaps;
+//   * a bucket of at most 16384 g-mers (8192 with 64-bit composites) is
+//     sorted by one block of 16 waves the same way, with the exchanges
+//     between waves going through LDS;
+//   * a larger bucket is radix-sorted by a block in global memory.
+// The sorted bucket goes to LDS and is segmented with ballot bitmaps of run
+// and group starts: prefix popcounts give each run its entry index and each
+// group its extent.
+#include "common.h"
+#include "launch.h"
+
+namespace gk {
+
+// ------------------------------------------------------------- classes --
+// Composite words of at most 32 bits are sorted packed with the g-mer index
+// as one 64-bit word (composite high); wider ones as (composite, index).
+__device__ __forceinline__ int ceil_log2_u(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
+
+__device__ __forceinline__ int bucket_class(uint32_t n, bool pk)
+{
+    if (n == 0) return -1;
+    if (n <= (pk ? kSortWaveMaxPk : kSortWaveMaxWide)) {
+        const int e = max(0, ceil_log2_u(n) - 6);  // log2 of elements per lane
+        return pk ? e : 5 + e;                      // packed 0..4, wide 5..8
+    }
+    if (n <= (pk ? kSortBlockMaxPk : kSortBlockMaxWide)) {
+        const int e = ceil_log2_u(n) - 10;          // packed 1..4, wide 0..3
+        return kSortClassWave + (pk ? e - 1 : 4 + e);
+    }
+    return kSortClassWave + kSortClassBlock + (pk ? 0 : 1);
+}
+
+// ---------------------------------------------------------- bucket scan --
+// Exclusive scan of the bucket counts of one mask (one block per mask), and
+// the filing of its non-empty buckets into the size-class lists.
+__global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__restrict__ items, SortLists L)
+{
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t ccnt[kSortClasses], cbase[kSortClasses];
+    const int q = blockIdx.x;
+    const MaskWork &W = items[q];
+    const uint32_t nb = 1u << W.B;
+    const uint32_t per = (nb + kThreads - 1) / kThreads;
+    const uint32_t b0 = threadIdx.x * per;
+    uint32_t loc = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < nb) loc += W.bcnt[b0 + i];
+    uint32_t tot;
+    uint32_t run = block_excl_scan(loc, wsum, &tot);
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < nb) {
+            W.boff[b0 + i] = run;
+            W.bcur[b0 + i] = run;
+            run += W.bcnt[b0 + i];
+        }
+    if (threadIdx.x == 0) W.boff[nb] = tot;
+    if (threadIdx.x < kSortClasses) ccnt[threadIdx.x] = 0;
+    __syncthreads();
+    const bool pk = W.cb <= 32;
+    for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
+        const int c = bucket_class(W.bcnt[b], pk);
+        if (c >= 0) atomicAdd(&ccnt[c], 1u);
+        else if (W.gtab) W.bgrp[b] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x < kSortClasses) {
+        const uint32_t c = ccnt[threadIdx.x];
+        cbase[threadIdx.x] = c ? atomicAdd(&L.cnt[threadIdx.x], c) : 0u;
+        ccnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
+        const int c = bucket_class(W.bcnt[b], pk);
+        if (c >= 0) {
+            const uint32_t pos = cbase[c] + atomicAdd(&ccnt[c], 1u);
+            if (pos < L.cap) L.list[(size_t)c * L.cap + pos] = ((uint32_t)q << 12) | b;
+        }
+    }
+}
+
+// ------------------------------------------------------ bitonic network --
+// Value of lane (lane ^ J) of the wave.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x)
+{
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (J << 10));  // bitmask mode: xor J
+    else return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32) << 2), (int)x);
+}
+template <int J>
+__device__ __forceinline__ uint64_t lane_xor64(uint64_t x)
+{
+    return ((uint64_t)lane_xor<J>((uint32_t)(x >> 32)) << 32) | lane_xor<J>((uint32_t)x);
+}
+
+// Element order: packed words compare as integers; wide ones by composite,
+// then g-mer index.  Real elements are pairwise distinct (distinct indices)
+// and the padding (all ones, index 0xFFFFFFFF, which no g-mer has) is
+// strictly above them, so an exchange needs one comparison: with y_lt =
+// (partner < own), the partner is taken when y_lt != keep_max.
+template <bool PK>
+__device__ __forceinline__ bool el_less(uint64_t ak, uint32_t av, uint64_t bk, uint32_t bv)
+{
+    if constexpr (PK) return ak < bk;
+    else return (ak < bk) | ((ak == bk) & (av < bv));
+}
+
+// Exchange with the lane at distance J < 64.  keep_max: this lane keeps the
+// larger element of its pair (the high end of an ascending pair or the low
+// end of a descending one).
+template <bool PK, int J>
+__device__ __forceinline__ void exchange_lanes(uint64_t &key, uint32_t &val, bool keep_max)
+{
+    const uint64_t yk = lane_xor64<J>(key);
+    uint32_t yv = 0;
+    if constexpr (!PK) yv = lane_xor<J>(val);
+    const bool take = el_less<PK>(yk, yv, key, val) != keep_max;
+    key = take ? yk : key;
+    if constexpr (!PK) val = take ? yv : val;
+}
+
+// Stage of distance J < 64 for every register e; element index i = ibase +
+// 64 e + lane; a pair is ascending when bit k of i is 0 -- a bit of the lane
+// when k < 64, else a bit of ibase + 64 e, the same for the whole wave.
+template <bool PK, int EL, int J>
+__device__ __forceinline__ void stage_lanes(uint64_t (&key)[EL], uint32_t (&val)[EL], uint32_t ibase, uint32_t k)
+{
+    const int lane = __lane_id();
+    const bool upper = (lane & J) != 0;
+    if (k < 64) {
+        const bool keep_max = upper == ((lane & (int)k) == 0);
+#pragma unroll
+        for (int e = 0; e < EL; ++e) exchange_lanes<PK, J>(key[e], val[e], keep_max);
+    } else {
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+            const bool asc = ((ibase + (uint32_t)(e * 64)) & k) == 0;  // wave-uniform
+            exchange_lanes<PK, J>(key[e], val[e], upper == asc);
+        }
+    }
+}
+
+// Stage of distance 64 D: registers e and e | D of the same lane.
+template <bool PK, int EL, int D>
+__device__ __forceinline__ void stage_regs(uint64_t (&key)[EL], uint32_t (&val)[EL], uint32_t ibase, uint32_t k)
+{
+    if constexpr (D < EL) {
+#pragma unroll
+        for (int e = 0; e < EL; ++e) {
+            if ((e & D) == 0) {
+                const int e2 = e | D;
+                const bool asc = ((ibase + (uint32_t)(e * 64)) & k) == 0;  // wave-uniform
+                const bool sw = el_less<PK>(key[e2], val[e2], key[e], val[e]) == asc;
+                const uint64_t ka = key[e], kb = key[e2];
+                key[e] = sw ? kb : ka;
+                key[e2] = sw ? ka : kb;
+                if constexpr (!PK) {
+                    const uint32_t va = val[e], vb = val[e2];
+                    val[e] = sw ? vb : va;
+                    val[e2] = sw ? va : vb;
+                }
+            }
+        }
+    }
+}
+
+// Stage of distance j >= 64 EL: between waves of a block, through LDS.
+template <bool PK, int EL>
+__device__ __forceinline__ void stage_lds(uint64_t (&key)[EL], uint32_t (&val)[EL], uint64_t *kb, uint32_t *vb,
+                                          uint32_t ibase, uint32_t k, uint32_t j)
+{
+    const int lane = __lane_id();
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
+        kb[i] = key[e];
+        if constexpr (!PK) vb[i] = val[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
+        const uint64_t yk = kb[i ^ j];
+        uint32_t yv = 0;
+        if constexpr (!PK) yv = vb[i ^ j];
+        const bool keep_max = ((i & j) != 0) == ((i & k) == 0);
+        const bool take = el_less<PK>(yk, yv, key[e], val[e]) != keep_max;
+        key[e] = take ? yk : key[e];
+        if constexpr (!PK) val[e] = take ? yv : val[e];
+    }
+}
+
+// Bitonic sort of NW * 64 * EL elements, ascending in i; wave `wave` of the
+// NW holds elements [wave * 64 EL, (wave + 1) * 64 EL).
+template <bool PK, int EL, int NW>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&key)[EL], uint32_t (&val)[EL], uint64_t *kb, uint32_t *vb, int wave)
+{
+    constexpr uint32_t WSPAN = 64u * EL;
+    constexpr uint32_t NP = WSPAN * NW;
+    const uint32_t ibase = (uint32_t)wave * WSPAN;
+    for (uint32_t k = 2; k <= NP; k <<= 1) {
+        if constexpr (NW > 1)
+            for (uint32_t j = k >> 1; j >= WSPAN; j >>= 1) stage_lds<PK, EL>(key, val, kb, vb, ibase, k, j);
+        for (uint32_t j = min(k >> 1, WSPAN >> 1); j >= 64; j >>= 1) {
+            switch (j >> 6) {
+            case 1: stage_regs<PK, EL, 1>(key, val, ibase, k); break;
+            case 2: stage_regs<PK, EL, 2>(key, val, ibase, k); break;
+            case 4: stage_regs<PK, EL, 4>(key, val, ibase, k); break;
+            case 8: stage_regs<PK, EL, 8>(key, val, ibase, k); break;
+            default: break;
+            }
+        }
+        if (k > 32) stage_lanes<PK, EL, 32>(key, val, ibase, k);
+        if (k > 16) stage_lanes<PK, EL, 16>(key, val, ibase, k);
+        if (k > 8) stage_lanes<PK, EL, 8>(key, val, ibase, k);
+        if (k > 4) stage_lanes<PK, EL, 4>(key, val, ibase, k);
+        if (k > 2) stage_lanes<PK, EL, 2>(key, val, ibase, k);
+        stage_lanes<PK, EL, 1>(key, val, ibase, k);
+    }
+}
+
+// ----------------------------------------------------------- segmentation --
+// One 64-bit word per 64 sorted positions: run starts (rbm), group starts
+// (gbm) and starts of candidate groups for the count matrix (cbm), with their
+// exclusive prefix popcounts, the position of the next run / group start at
+// or after each word and of the last group start before it (n, resp. none,
+// when there is none); slot: one word per candidate group.
+template <int NWORDS, int NSLOT>
+struct SegLds {
+    uint64_t rbm[NWORDS], gbm[NWORDS], cbm[NWORDS];
+    uint32_t rpre[NWORDS + 1], gpre[NWORDS + 1], cpre[NWORDS + 1];
+    uint32_t nextr[NWORDS + 1], nextg[NWORDS + 1], prevg[NWORDS + 1];
+    uint32_t slot[NSLOT];
+};
+
+template <int NW>
+__device__ __forceinline__ void seg_sync()
+{
+    if constexpr (NW > 1) __syncthreads();
+    else wave_sync();
+}
+
+__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t x)
+{
+    const int l = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_down(x, d, 64);
+        if (l + d < 64) x = min(x, y);
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_prefix_max(int x)
+{
+    const int l = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (l >= d) x = max(x, y);
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t first_bit(int w, uint64_t m) { return (uint32_t)(w * 64 + __ffsll((long long)m) - 1); }
+__device__ __forceinline__ int last_bit(int w, uint64_t m) { return w * 64 + 63 - (int)__clzll((long long)m); }
+
+// One wave: prefix popcounts of rbm and gbm, next run / group starts and the
+// last group start before each word, over nwords words.
+template <int NWORDS, int NSLOT>
+__device__ __forceinline__ void scan_words(SegLds<NWORDS, NSLOT> &S, int nwords, uint32_t n)
+{
+    constexpr int PER = (NWORDS + 63) / 64;
+    const int lane = __lane_id();
+    uint32_t rc = 0, gc = 0, fr = n, fg = n;
+    int lg = -1;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int w = lane * PER + p;
+        if (w < nwords && S.gbm[w]) lg = last_bit(w, S.gbm[w]);
+    }
+#pragma unroll
+    for (int p = PER - 1; p >= 0; --p) {
+        const int w = lane * PER + p;
+        if (w < nwords) {
+            const uint64_t r = S.rbm[w], g = S.gbm[w];
+            rc += __popcll(r);
+            gc += __popcll(g);
+            if (r) fr = first_bit(w, r);
+            if (g) fg = first_bit(w, g);
+        }
+    }
+    const uint32_t ri = wave_incl_scan(rc), gi = wave_incl_scan(gc);
+    uint32_t rx = ri - rc, gx = gi - gc;
+    const uint32_t sr = wave_suffix_min(fr), sg = wave_suffix_min(fg);
+    uint32_t ar = __shfl_down(sr, 1, 64), ag = __shfl_down(sg, 1, 64);
+    if (lane == 63) ar = ag = n;
+    int pg = __shfl_up(wave_prefix_max(lg), 1, 64);
+    if (lane == 0) pg = -1;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int w = lane * PER + p;
+        if (w < nwords) {
+            S.rpre[w] = rx;
+            S.gpre[w] = gx;
+            S.prevg[w] = (uint32_t)pg;
+            rx += __popcll(S.rbm[w]);
+            gx += __popcll(S.gbm[w]);
+            if (S.gbm[w]) pg = last_bit(w, S.gbm[w]);
+        }
+    }
+#pragma unroll
+    for (int p = PER - 1; p >= 0; --p) {
+        const int w = lane * PER + p;
+        if (w < nwords) {
+            const uint64_t r = S.rbm[w], g = S.gbm[w];
+            if (r) ar = first_bit(w, r);
+            if (g) ag = first_bit(w, g);
+            S.nextr[w] = ar;
+            S.nextg[w] = ag;
+        }
+    }
+    const uint32_t R = __shfl(ri, 63, 64), G = __shfl(gi, 63, 64);
+    if (lane == 0) {
+        S.rpre[nwords] = R;
+        S.gpre[nwords] = G;
+        S.nextr[nwords] = n;
+        S.nextg[nwords] = n;
+    }
+}
+
+// One wave: exclusive prefix popcounts of cbm, the total at cpre[nwords].
+template <int NWORDS, int NSLOT>
+__device__ __forceinline__ void scan_cand(SegLds<NWORDS, NSLOT> &S, int nwords)
+{
+    constexpr int PER = (NWORDS + 63) / 64;
+    const int lane = __lane_id();
+    uint32_t cc = 0;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int w = lane * PER + p;
+        if (w < nwords) cc += __popcll(S.cbm[w]);
+    }
+    const uint32_t ci = wave_incl_scan(cc);
+    uint32_t cx = ci - cc;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int w = lane * PER + p;
+        if (w < nwords) {
+            S.cpre[w] = cx;
+            cx += __popcll(S.cbm[w]);
+        }
+    }
+    const uint32_t C = __shfl(ci, 63, 64);
+    if (lane == 0) S.cpre[nwords] = C;
+}
+
+struct RunAt {
+    uint32_t r;    // run index in the bucket
+    uint32_t cnt;  // g-mers in the run
+    uint32_t len;  // runs from this one to the group end
+    uint32_t gi;   // group index in the bucket
+    uint32_t gs;   // position of the group's first g-mer
+};
+
+// The run starting at sorted position i (word w = i / 64, bit b = i % 64).
+template <int NWORDS, int NSLOT>
+__device__ __forceinline__ RunAt run_at(const SegLds<NWORDS, NSLOT> &S, int w, int b, uint32_t i, uint32_t n, uint32_t R)
+{
+    const uint64_t rb = S.rbm[w], gb = S.gbm[w];
+    const uint64_t le = (b == 63) ? ~0ull : ((2ull << b) - 1ull);
+    const uint64_t gt = ~le;
+    RunAt a;
+    a.r = S.rpre[w] + (uint32_t)__popcll(rb & (le >> 1));
+    const uint64_t mr = rb & gt, mg = gb & gt, ml = gb & le;
+    const uint32_t end = mr ? first_bit(w, mr) : S.nextr[w + 1];
+    const uint32_t gend = mg ? first_bit(w, mg) : S.nextg[w + 1];
+    a.cnt = end - i;
+    uint32_t rend = R;
+    if (gend < n) {
+        const int gw = (int)(gend >> 6);
+        rend = S.rpre[gw] + (uint32_t)__popcll(S.rbm[gw] & ((1ull << (gend & 63)) - 1ull));
+    }
+    a.len = rend - a.r;
+    a.gi = S.gpre[w] + (uint32_t)__popcll(ml) - 1u;
+    a.gs = ml ? (uint32_t)last_bit(w, ml) : S.prevg[w];
+    return a;
+}
+
+__device__ __forceinline__ bool bit_at(const uint64_t *bm, uint32_t i) { return (bm[i >> 6] >> (i & 63)) & 1ull; }
+
+// Candidate slot of the group starting at position gs (a set bit of cbm).
+template <int NWORDS, int NSLOT>
+__device__ __forceinline__ uint32_t cand_slot(const SegLds<NWORDS, NSLOT> &S, uint32_t gs)
+{
+    const int cw = (int)(gs >> 6);
+    return S.cpre[cw] + (uint32_t)__popcll(S.cbm[cw] & ((1ull << (gs & 63)) - 1ull));
+}
+
+// Runs and groups of one sorted bucket in LDS (kb: packed words or
+// composites, vb: indices of wide ones), segmented by NW waves.  Writes one
+// run entry (sequence | count << sb) per run at E[base + run], so each
+// group's entries are contiguous and sequence-sorted; per g-mer its info --
+// for the first g-mer of a run (entry index, runs to the group end | count <<
+// (sb+1)), for the others (0, 0).  Groups with at least tau runs and every
+// count <= 127 become rows of the int8 count matrix instead (info length 0),
+// as far as NSLOT candidate groups per bucket (otherwise all of the bucket's
+// groups stay on the exact sparse path).  With gtab, lists the groups (hash
+// rest, first entry, end entry); with diag, adds count^2 per run to its
+// sequence's diagonal counter.
+template <bool PK, int NW, int NWORDS, int NSLOT>
+__device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint32_t base, uint32_t n, const uint64_t *kb,
+                                        const uint32_t *vb, SegLds<NWORDS, NSLOT> &S)
+{
+    constexpr int NT = NW * 64;
+    const int lane = __lane_id();
+    const int wave = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
+    const int tid = wave * 64 + lane;
+    const int sb = W.sb;
+    const uint64_t sidmask = bits_mask(sb);
+    const int nwords = (int)((n + 63) >> 6);
+    auto comp_at = [&](uint32_t i) -> uint64_t { return PK ? (kb[i] >> 32) : kb[i]; };
+#pragma unroll 1
+    for (int w = wave; w < nwords; w += NW) {
+        const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
+        bool rs = false, gs = false;
+        if (i < n) {
+            if (i == 0) {
+                rs = gs = true;
+            } else {
+                const uint64_t c = comp_at(i), p = comp_at(i - 1);
+                rs = c != p;
+                gs = (c >> sb) != (p >> sb);
+            }
+        }
+        const uint64_t rb = __ballot(rs), gb = __ballot(gs);
+        if (lane == 0) {
+            S.rbm[w] = rb;
+            S.gbm[w] = gb;
+        }
+    }
+    seg_sync<NW>();
+    if (wave == 0) scan_words<NWORDS, NSLOT>(S, nwords, n);
+    seg_sync<NW>();
+    const uint32_t R = S.rpre[nwords], G = S.gpre[nwords];
+    // count-matrix candidates: groups with at least tau runs
+    bool dense = false;
+    if (W.tau > 0 && W.D != nullptr) {
+#pragma unroll 1
+        for (int w = wave; w < nwords; w += NW) {
+            const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
+            bool c = false;
+            if (i < n && bit_at(S.gbm, i)) c = run_at<NWORDS, NSLOT>(S, w, lane, i, n, R).len >= (uint32_t)W.tau;
+            const uint64_t cb = __ballot(c);
+            if (lane == 0) S.cbm[w] = cb;
+        }
+        seg_sync<NW>();
+        if (wave == 0) scan_cand<NWORDS, NSLOT>(S, nwords);
+        seg_sync<NW>();
+        const uint32_t ncand = S.cpre[nwords];
+        dense = ncand > 0 && ncand <= (uint32_t)NSLOT;
+        if (dense) {
+            for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) S.slot[s] = 0;
+            seg_sync<NW>();
+            // largest count of each candidate group
+#pragma unroll 1
+            for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
+                if (bit_at(S.rbm, i)) {
+                    const RunAt a = run_at<NWORDS, NSLOT>(S, (int)(i >> 6), (int)(i & 63), i, n, R);
+                    if (a.gs < n && bit_at(S.cbm, a.gs)) atomicMax(&S.slot[cand_slot(S, a.gs)], a.cnt);
+                }
+            }
+            seg_sync<NW>();
+            // candidates whose counts all fit int8 take a count-matrix row
+            for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) {
+                uint32_t row = 0xFFFFFFFFu;
+                if (S.slot[s] <= 127u) {
+                    row = atomicAdd(W.dcount, 1u);
+                    if (row >= W.dcap) row = 0xFFFFFFFFu;
+                }
+                S.slot[s] = row;
+            }
+            seg_sync<NW>();
+        }
+    }
+#pragma unroll 1
+    for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
+        const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
+        if (!bit_at(S.rbm, i)) {
+            if (idx < W.T) W.info[idx] = make_uint2(0u, 0u);
+            continue;
+        }
+        const RunAt a = run_at<NWORDS, NSLOT>(S, (int)(i >> 6), (int)(i & 63), i, n, R);
+        const uint64_t c = comp_at(i);
+        const uint32_t sid = (uint32_t)(c & sidmask);
+        const uint32_t ei = base + a.r;
+        W.E[ei] = sid | (a.cnt << sb);
+        uint32_t y = a.len | (a.cnt << (sb + 1));
+        if (dense && a.gs < n && bit_at(S.cbm, a.gs)) {
+            const uint32_t row = S.slot[cand_slot(S, a.gs)];
+            if (row != 0xFFFFFFFFu) {
+                if (sid < (uint32_t)W.N && row < W.dcap) W.D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)a.cnt;
+                y = 0;
+            }
+        }
+        if (idx < W.T) W.info[idx] = make_uint2(ei, y);
+        if (W.diag && sid < (uint32_t)W.N) atomicAdd(&W.diag[sid], a.cnt * a.cnt);
+        if (W.gtab && a.gs == i) {
+            const uint64_t hr = c >> sb;
+            W.gtab[base + a.gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ei, ei + a.len);
+        }
+    }
+    if (W.gtab && tid == 0) W.bgrp[bucket] = G;
+}
+
+// Load a bucket's (composite, index) pairs into registers, padding with the
+// largest element.
+template <bool PK, int EL>
+__device__ __forceinline__ void load_bucket(const MaskWork &W, uint32_t base, uint32_t n, uint32_t ibase, uint64_t (&key)[EL],
+                                            uint32_t (&val)[EL])
+{
+    const int lane = __lane_id();
+    const uint32_t *c32 = reinterpret_cast<const uint32_t *>(W.comp);
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
+        key[e] = ~0ull;
+        val[e] = 0xFFFFFFFFu;
+        if (i < n) {
+            const uint32_t x = W.idx[base + i];
+            if constexpr (PK) key[e] = ((uint64_t)c32[base + i] << 32) | x;
+            else key[e] = W.comp[base + i];
+            val[e] = x;
+        }
+    }
+}
+
+// Store the sorted elements held in registers to LDS.
+template <bool PK, int EL>
+__device__ __forceinline__ void store_sorted(const uint64_t (&key)[EL], const uint32_t (&val)[EL], uint32_t ibase, uint32_t n,
+                                             uint64_t *kb, uint32_t *vb)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int e = 0; e < EL; ++e) {
+        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
+        if (i < n) {
+            kb[i] = key[e];
+            if constexpr (!PK) vb[i] = val[e];
+        }
+    }
+}
+
+// ------------------------------------------------------ wave kernel --
+constexpr int kWaveWords = kSortWaveMaxPk / 64;
+constexpr int kWaveSlots = 256;
+
+struct WaveLds {
+    uint64_t kb[kSortWaveMaxPk];  // packed: 1024 words; wide: 512 words, then 512 indices
+    SegLds<kWaveWords, kWaveSlots> S;
+};
+
+template <bool PK, int EL>
+__device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, WaveLds &lds)
+{
+    const uint32_t base = W.boff[bucket];
+    const uint32_t n = W.boff[bucket + 1] - base;
+    if (n == 0 || n > 64u * EL) return;
+    uint32_t *vb = reinterpret_cast<uint32_t *>(lds.kb + kSortWaveMaxWide);
+    {
+        uint64_t key[EL];
+        uint32_t val[EL];
+        load_bucket<PK, EL>(W, base, n, 0, key, val);
+        bitonic_sort<PK, EL, 1>(key, val, nullptr, nullptr, 0);
+        store_sorted<PK, EL>(key, val, 0, n, lds.kb, vb);
+    }
+    wave_sync();
+    segment<PK, 1, kWaveWords, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S);
+    wave_sync();
+}
+
+// Each wave takes the buckets of the wave classes in a fixed stride over
+// their concatenation, largest class first.
+__global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
+{
+    __shared__ WaveLds lds[kWaves];
+    // packed 1024, wide 512, packed 512, wide 256, ..., packed 64 (class ids)
+    constexpr int order[kSortClassWave] = {4, 8, 3, 7, 2, 6, 1, 5, 0};
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
+    const uint32_t gw = blockIdx.x * kWaves + wid, nw = gridDim.x * kWaves;
+    uint32_t cum[kSortClassWave + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int s = 0; s < kSortClassWave; ++s) cum[s + 1] = cum[s] + min(L.cnt[order[s]], L.cap);
+    for (uint32_t t = gw; t < cum[kSortClassWave]; t += nw) {
+        int s = 0;
+#pragma unroll
+        for (int q = 1; q < kSortClassWave; ++q) s += (t >= cum[q]) ? 1 : 0;
+        uint32_t off = 0;
+        int c = 0;
+#pragma unroll
+        for (int q = 0; q < kSortClassWave; ++q) {
+            off = (q == s) ? cum[q] : off;
+            c = (q == s) ? order[q] : c;
+        }
+        const uint32_t ent = L.list[(size_t)c * L.cap + (t - off)];
+        const MaskWork &W = items[ent >> 12];
+        const uint32_t bucket = ent & 4095u;
+        if (bucket >= (1u << W.B)) continue;
+        switch (c) {
+        case 0: wave_bucket<true, 1>(W, bucket, lds[wid]); break;
+        case 1: wave_bucket<true, 2>(W, bucket, lds[wid]); break;
+        case 2: wave_bucket<true, 4>(W, bucket, lds[wid]); break;
+        case 3: wave_bucket<true, 8>(W, bucket, lds[wid]); break;
+        case 4: wave_bucket<true, 16>(W, bucket, lds[wid]); break;
+        case 5: wave_bucket<false, 1>(W, bucket, lds[wid]); break;
+        case 6: wave_bucket<false, 2>(W, bucket, lds[wid]); break;
+        case 7: wave_bucket<false, 4>(W, bucket, lds[wid]); break;
+        default: wave_bucket<false, 8>(W, bucket, lds[wid]); break;
+        }
+    }
+}
+
+// ------------------------------------------------------ block kernel --
+constexpr int kSortBlockThreads = 1024;
+constexpr int kSortBlockWaves = kSortBlockThreads / 64;
+constexpr int kBlockWords = kSortBlockMaxPk / 64;
+constexpr int kBlockSlots = 1024;
+
+struct BlockLds {
+    uint64_t buf[kSortBlockMaxPk];  // exchange buffer, then the sorted bucket
+    SegLds<kBlockWords, kBlockSlots> S;
+};
+
+template <bool PK, int EL>
+__device__ __forceinline__ void block_bucket(const MaskWork &W, uint32_t bucket, BlockLds &lds)
+{
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t base = W.boff[bucket];
+    const uint32_t n = W.boff[bucket + 1] - base;
+    // n is uniform over the block: every thread returns or none
+    if (n == 0 || n > (uint32_t)kSortBlockThreads * EL) return;
+    uint32_t *vb = reinterpret_cast<uint32_t *>(lds.buf + kSortBlockMaxWide);
+    {
+        uint64_t key[EL];
+        uint32_t val[EL];
+        const uint32_t ibase = (uint32_t)wave * 64u * EL;
+        load_bucket<PK, EL>(W, base, n, ibase, key, val);
+        bitonic_sort<PK, EL, kSortBlockWaves>(key, val, lds.buf, vb, wave);
+        __syncthreads();  // the last exchange reads are done
+        store_sorted<PK, EL>(key, val, ibase, n, lds.buf, vb);
+    }
+    __syncthreads();
+    segment<PK, kSortBlockWaves, kBlockWords, kBlockSlots>(W, bucket, base, n, lds.buf, vb, lds.S);
+}
+
+// Blocks take buckets of the block classes from a shared ticket counter,
+// largest class first.
+__global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork *__restrict__ items, SortLists L)
+{
+    __shared__ BlockLds lds;
+    __shared__ uint32_t ticket;
+    // packed 16384, wide 8192, packed 8192, wide 4096, packed 4096, wide
+    // 2048, packed 2048, wide 1024 (class offsets within the block classes)
+    constexpr int order[kSortClassBlock] = {3, 7, 2, 6, 1, 5, 0, 4};
+    uint32_t cum[kSortClassBlock + 1];
+    cum[0] = 0;
+#pragma unroll
+    for (int s = 0; s < kSortClassBlock; ++s) cum[s + 1] = cum[s] + min(L.cnt[kSortClassWave + order[s]], L.cap);
+    const uint32_t total = cum[kSortClassBlock];
+    while (true) {
+        if (threadIdx.x == 0) ticket = atomicAdd(&L.cnt[kSortTicketBlock], 1u);
+        __syncthreads();
+        const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);  // block-uniform
+        __syncthreads();
+        if (t >= total) break;
+        int s = 0;
+#pragma unroll
+        for (int q = 1; q < kSortClassBlock; ++q) s += (t >= cum[q]) ? 1 : 0;
+        uint32_t off = 0;
+        int oc = 0;
+#pragma unroll
+        for (int q = 0; q < kSortClassBlock; ++q) {
+            off = (q == s) ? cum[q] : off;
+            oc = (q == s) ? order[q] : oc;
+        }
+        const uint32_t ent = L.list[(size_t)(kSortClassWave + oc) * L.cap + (t - off)];
+        const MaskWork &W = items[ent >> 12];
+        const uint32_t bucket = ent & 4095u;
+        if (bucket >= (1u << W.B)) continue;
+        switch (oc) {
+        case 0: block_bucket<true, 2>(W, bucket, lds); break;
+        case 1: block_bucket<true, 4>(W, bucket, lds); break;
+        case 2: block_bucket<true, 8>(W, bucket, lds); break;
+        case 3: block_bucket<true, 16>(W, bucket, lds); break;
+        case 4: block_bucket<false, 1>(W, bucket, lds); break;
+        case 5: block_bucket<false, 2>(W, bucket, lds); break;
+        case 6: block_bucket<false, 4>(W, bucket, lds); break;
+        default: block_bucket<false, 8>(W, bucket, lds); break;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------- global kernel --
+// Buckets beyond the block classes: LSD radix sort in the bucket's own
+// global-memory slice (ping-pong with the second composite array), then the
+// block-wide segmentation with scratch taken from the free slices.
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_sort_global(const MaskWork *__restrict__ items, SortLists L, int cls)
+{
+    constexpr bool W64 = sizeof(K) == 8;
+    __shared__ SortScratch ss;
+    const uint32_t cnt = min(L.cnt[cls], L.cap);
+    for (uint32_t t = blockIdx.x; t < cnt; t += gridDim.x) {
+        const uint32_t ent = L.list[(size_t)cls * L.cap + t];
+        const MaskWork &W = items[ent >> 12];
+        const uint32_t bucket = ent & 4095u;
+        if (bucket >= (1u << W.B)) continue;
+        const uint32_t base = W.boff[bucket];
+        const uint32_t n = W.boff[bucket + 1] - base;
+        K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
+        int which = 0;
+        block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which);
+        __syncthreads();
+        K *fk = (which ? gc2 : gc) + base;
+        uint32_t *fv = (which ? W.idx2 : W.idx) + base;
+        uint32_t *fr = reinterpret_cast<uint32_t *>(which ? gc : gc2);
+        uint32_t *fx = (which ? W.idx : W.idx2) + base;
+        // scratch: this bucket's slice of the free composite array (2n
+        // words), or for 32-bit composites its slice of each half
+        if (W64) block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket);
+        else block_segment(fk, fv, n, fr + base, fr + (size_t)W.T + base, fx, W, base, ss.wsum, bucket);
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------- launchers --
+hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hipStream_t st)
+{
+    if (!nitems) return hipSuccess;
+    hipLaunchKernelGGL(k_bucket_scan, dim3(nitems), dim3(kThreads), 0, st, items, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_sort(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
+{
+    if (g.wave_blocks)
+        hipLaunchKernelGGL(k_sort_wave, dim3(g.wave_blocks), dim3(kThreads), 0, st, items, L);
+    if (g.block_blocks)
+        hipLaunchKernelGGL(k_sort_block, dim3(g.block_blocks), dim3(kSortBlockThreads), 0, st, items, L);
+    if (g.global_blocks_pk)
+        hipLaunchKernelGGL(k_sort_global<uint32_t>, dim3(g.global_blocks_pk), dim3(kThreads), 0, st, items, L,
+                           kSortClassWave + kSortClassBlock);
+    if (g.global_blocks_wide)
+        hipLaunchKernelGGL(k_sort_global<uint64_t>, dim3(g.global_blocks_wide), dim3(kThreads), 0, st, items, L,
+                           kSortClassWave + kSortClassBlock + 1);
+    return hipGetLastError();
+}
+
+}  // namespace gk

@@ -12,7 +12,27 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kMaxRuns = 33;     // kept positions form at most min(g-m, m+1) <= 33 runs (g <= 64)
 constexpr int kTile = 4096;      // g-mers per block in the partition kernels
 constexpr int kMaxBucketBits = 12;
-constexpr int kSortCap = 2048;   // bucket size sorted entirely in LDS
+
+// Bucket size classes of the per-bucket sort: nine wave classes (packed
+// composites 64..1024 g-mers, wide ones 64..512), eight block classes (packed
+// 2048..16384, wide 1024..8192) and two global-memory classes (packed, wide).
+constexpr uint32_t kSortWaveMaxPk = 1024;
+constexpr uint32_t kSortWaveMaxWide = 512;
+constexpr uint32_t kSortBlockMaxPk = 16384;
+constexpr uint32_t kSortBlockMaxWide = 8192;
+constexpr int kSortClassWave = 9;
+constexpr int kSortClassBlock = 8;
+constexpr int kSortClasses = kSortClassWave + kSortClassBlock + 2;
+constexpr int kSortTicketBlock = kSortClasses;  // counter slot of the block kernel's work tickets
+constexpr int kSortCounters = 32;               // counter words per chunk
+
+// Per-class lists of (mask << 12 | bucket) entries, cap entries per class,
+// and their counters.
+struct SortLists {
+    uint32_t *cnt;   // [kSortCounters] zeroed before the scan
+    uint32_t *list;  // [kSortClasses][cap]
+    uint32_t cap;
+};
 
 // One set of removed positions ("mask"), as the runs of kept symbol fields:
 // reduced = OR_r ((key >> src[r]) & (2^wid[r]-1)) << dst[r].  The kept
@@ -51,6 +71,7 @@ struct MaskWork {
     MaskDesc md;
     int32_t job;
     uint32_t T;
+    int32_t N;   // sequences of the job
     int32_t w;   // bits of the reduced key
     int32_t B;   // bucket bits (top bits of the hashed reduced key)
     int32_t hb;  // remaining hash bits, w - B
@@ -378,148 +399,6 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Stable LSD radix sort by the low `bits` bits, 8 per pass, on one wave.
-// Per pass: a digit histogram (LDS atomics), a wave scan of it into digit
-// bases, then groups of 64 elements ranked by ballots; the lowest lane of
-// each digit's ballot mask advances that digit's base with one LDS atomic and
-// shares the old value by shuffle.
-template <typename K>
-__device__ __forceinline__ void wave_radix_sort(K *k0, uint32_t *v0, K *k1, uint32_t *v1, uint32_t n, int bits,
-                                                uint32_t *hist, int &which)
-{
-    const int lane = __lane_id();
-    const uint64_t lt = lanemask_lt();
-    for (int shift = 0; shift < bits; shift += 8) {
-        K *sk = which ? k1 : k0;
-        uint32_t *sv = which ? v1 : v0;
-        K *dk = which ? k0 : k1;
-        uint32_t *dv = which ? v0 : v1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) hist[lane * 4 + q] = 0;
-        wave_sync();
-        for (uint32_t i = lane; i < n; i += 64) atomicAdd(&hist[(uint32_t)(sk[i] >> shift) & 255u], 1u);
-        wave_sync();
-        uint32_t c[4], loc = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            c[q] = hist[lane * 4 + q];
-            loc += c[q];
-        }
-        const bool single = __ballot(c[0] == n || c[1] == n || c[2] == n || c[3] == n) != 0;
-        if (single) continue;  // one digit only: order unchanged
-        uint32_t run = wave_incl_scan(loc) - loc;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            hist[lane * 4 + q] = run;
-            run += c[q];
-        }
-        wave_sync();
-        for (uint32_t r0 = 0; r0 < n; r0 += 64) {
-            const uint32_t i = r0 + lane;
-            const bool ok = i < n;
-            const K kk = ok ? sk[i] : (K)0;
-            const uint32_t vv = ok ? sv[i] : 0u;
-            const uint32_t d = ok ? ((uint32_t)(kk >> shift) & 255u) : 256u;
-            uint64_t peers = __ballot(ok);
-#pragma unroll
-            for (int bb = 0; bb < 8; ++bb) {
-                const uint64_t m = __ballot((d >> bb) & 1u);
-                peers &= ((d >> bb) & 1u) ? m : ~m;
-            }
-            const uint32_t rank = __popcll(peers & lt);
-            uint32_t old = 0;
-            if (ok && rank == 0) old = atomicAdd(&hist[d], (uint32_t)__popcll(peers));
-            old = __shfl(old, peers ? (__ffsll((long long)peers) - 1) : lane, 64);
-            if (ok) {
-                dk[old + rank] = kk;
-                dv[old + rank] = vv;
-            }
-        }
-        wave_sync();
-        which ^= 1;
-    }
-}
-
-// block_segment's work for one bucket on one wave (see there); run and
-// group indices come from ballots instead of block scans.
-template <typename K>
-__device__ __forceinline__ void wave_segment(const K *fk, const uint32_t *fv, uint32_t n, uint32_t *rpos, uint32_t *gsr,
-                                             uint32_t *gaux, const MaskWork &W, uint32_t ebase, uint32_t bucket)
-{
-    const int lane = __lane_id();
-    const uint64_t lt = lanemask_lt();
-    const int sb = W.sb;
-    const uint64_t sidmask = bits_mask(sb);
-    uint32_t R = 0, G = 0;
-    for (uint32_t r0 = 0; r0 < n; r0 += 64) {
-        const uint32_t i = r0 + lane;
-        bool rs = false, gs = false;
-        if (i < n) {
-            const uint64_t cur = (uint64_t)fk[i];
-            const uint64_t prev = i ? (uint64_t)fk[i - 1] : ~cur;
-            rs = cur != prev;
-            gs = (i == 0) || ((cur >> sb) != (prev >> sb));
-        }
-        const uint64_t br = __ballot(rs), bg = __ballot(gs);
-        const uint32_t ri = R + __popcll(br & lt);
-        if (gs) gsr[G + __popcll(bg & lt)] = ri;
-        if (rs) rpos[ri] = i;
-        R += __popcll(br);
-        G += __popcll(bg);
-    }
-    wave_sync();
-    const bool dense_on = (W.tau > 0) && (W.D != nullptr);
-    if (dense_on) {
-        for (uint32_t gi = lane; gi < G; gi += 64) gaux[gi] = 0;
-        wave_sync();
-        for (uint32_t r = lane; r < R; r += 64) {
-            const uint32_t pe = (r + 1 < R) ? rpos[r + 1] : n;
-            atomicMax(&gaux[last_le(gsr, G, r)], pe - rpos[r]);
-        }
-        wave_sync();
-        for (uint32_t gi = lane; gi < G; gi += 64) {
-            const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
-            uint32_t row = 0xFFFFFFFFu;
-            if (re - gsr[gi] >= (uint32_t)W.tau && gaux[gi] <= 127u) {
-                row = atomicAdd(W.dcount, 1u);
-                if (row >= W.dcap) row = 0xFFFFFFFFu;
-            }
-            gaux[gi] = row;
-        }
-        wave_sync();
-    }
-    for (uint32_t r = lane; r < R; r += 64) {
-        const uint32_t p = rpos[r];
-        const uint32_t cnt = ((r + 1 < R) ? rpos[r + 1] : n) - p;
-        const uint32_t sid = (uint32_t)((uint64_t)fk[p] & sidmask);
-        const uint32_t gi = last_le(gsr, G, r);
-        const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
-        const uint32_t e = ebase + r;
-        W.E[e] = sid | (cnt << sb);
-        uint32_t len = re - r;
-        if (dense_on) {
-            const uint32_t row = gaux[gi];
-            if (row != 0xFFFFFFFFu) {
-                W.D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)cnt;
-                len = 0;
-            }
-        }
-        W.info[fv[p]] = make_uint2(e, len ? (len | (cnt << (sb + 1))) : 0u);
-        if (W.diag) atomicAdd(&W.diag[sid], cnt * cnt);
-    }
-    for (uint32_t i = lane; i < n; i += 64)
-        if (i > 0 && fk[i] == fk[i - 1]) W.info[fv[i]] = make_uint2(0u, 0u);
-    if (W.gtab) {
-        for (uint32_t gi = lane; gi < G; gi += 64) {
-            const uint32_t r0 = gsr[gi];
-            const uint32_t r1 = (gi + 1 < G) ? gsr[gi + 1] : R;
-            const uint64_t hr = (uint64_t)fk[rpos[r0]] >> sb;
-            W.gtab[ebase + gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ebase + r0, ebase + r1);
-        }
-        if (lane == 0) W.bgrp[bucket] = G;
-    }
 }
 
 // Block -> (item, block within item): arithmetic when every item has the

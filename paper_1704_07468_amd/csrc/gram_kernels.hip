@@ -80,29 +80,6 @@ __global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__res
         if (hist[i]) atomicAdd(&W.bcnt[i], hist[i]);
 }
 
-// ---------------------------------------------------------- bucket scan --
-// Exclusive scan of the bucket counts of one mask (one block per mask).
-__global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__restrict__ items)
-{
-    __shared__ uint32_t wsum[kWaves];
-    const MaskWork &W = items[blockIdx.x];
-    const uint32_t nb = 1u << W.B;
-    const uint32_t per = (nb + kThreads - 1) / kThreads;
-    const uint32_t b0 = threadIdx.x * per;
-    uint32_t loc = 0;
-    for (uint32_t i = 0; i < per; ++i)
-        if (b0 + i < nb) loc += W.bcnt[b0 + i];
-    uint32_t tot;
-    uint32_t run = block_excl_scan(loc, wsum, &tot);
-    for (uint32_t i = 0; i < per; ++i)
-        if (b0 + i < nb) {
-            W.boff[b0 + i] = run;
-            W.bcur[b0 + i] = run;
-            run += W.bcnt[b0 + i];
-        }
-    if (threadIdx.x == 0) W.boff[nb] = tot;
-}
-
 // ------------------------------------------------------- bucket scatter --
 // Place (composite, g-mer index) of every g-mer into its bucket; composites
 // of at most 32 bits are stored as 32-bit words.  The order inside a bucket
@@ -150,137 +127,6 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
             else W.comp[pos] = cp[q];
             W.idx[pos] = t0 + q * kThreads + threadIdx.x;
         }
-    }
-}
-
-// ---------------------------------------------------- bucket sort+segment --
-// Buckets are radix-sorted by (hash rest, sequence) and segmented into
-// groups and runs by one of three kernels, by size: a wave per bucket of at
-// most kWaveCap g-mers (four buckets per block, no block barrier), a block
-// per bucket of at most kSmallCap, and a block per larger bucket sorted in a
-// large LDS buffer or, beyond it, in global memory.  K is the composite word
-// (32 or 64 bits).
-constexpr int kWaveCap = 512;
-constexpr int kSmallCap = 1024;
-
-template <typename K>
-__global__ __launch_bounds__(kThreads) void k_bucket_sort_wave(const MaskWork *__restrict__ items,
-                                                               const uint32_t *__restrict__ bprefix, int nitems,
-                                                               uint32_t uniform, uint32_t nbuckets)
-{
-    __shared__ K kA[kWaves][kWaveCap], kB[kWaves][kWaveCap];
-    __shared__ uint32_t vA[kWaves][kWaveCap], vB[kWaves][kWaveCap], aux[kWaves][kWaveCap];
-    __shared__ uint32_t hist[kWaves][256];
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t task = blockIdx.x * kWaves + wid;
-    if (task >= nbuckets) return;
-    int it;
-    uint32_t bucket;
-    map_block(bprefix, nitems, uniform, task, it, bucket);
-    const MaskWork &W = items[it];
-    if (bucket >= (1u << W.B)) return;
-    const uint32_t base = W.boff[bucket];
-    const uint32_t n = W.boff[bucket + 1] - base;
-    if (n == 0) {
-        if (W.gtab && lane == 0) W.bgrp[bucket] = 0;
-        return;
-    }
-    if (n > (uint32_t)kWaveCap) return;
-    const K *gc = reinterpret_cast<const K *>(W.comp);
-    {
-        // all loads in flight before the first LDS store
-        constexpr int PER = kWaveCap / 64;
-        K kr[PER];
-        uint32_t vr[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const uint32_t i = q * 64 + lane;
-            if (i < n) {
-                kr[q] = gc[base + i];
-                vr[q] = W.idx[base + i];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const uint32_t i = q * 64 + lane;
-            if (i < n) {
-                kA[wid][i] = kr[q];
-                vA[wid][i] = vr[q];
-            }
-        }
-    }
-    wave_sync();
-    int which = 0;
-    wave_radix_sort<K>(kA[wid], vA[wid], kB[wid], vB[wid], n, W.cb, hist[wid], which);
-    const K *fk = which ? kB[wid] : kA[wid];
-    const uint32_t *fv = which ? vB[wid] : vA[wid];
-    uint32_t *rpos = reinterpret_cast<uint32_t *>(which ? kA[wid] : kB[wid]);
-    uint32_t *gsr = which ? vA[wid] : vB[wid];
-    wave_segment<K>(fk, fv, n, rpos, gsr, aux[wid], W, base, bucket);
-}
-
-template <typename K, int CAP, bool BIG>
-__global__ __launch_bounds__(kThreads) void k_bucket_sort(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
-                                                          int nitems, uint32_t uniform)
-{
-    constexpr bool W64 = sizeof(K) == 8;
-    __shared__ K kA[CAP], kB[CAP];
-    __shared__ uint32_t vA[CAP], vB[CAP];
-    __shared__ uint32_t xs[W64 ? 1 : CAP];
-    __shared__ SortScratch ss;
-    int it;
-    uint32_t bucket;
-    map_block(bprefix, nitems, uniform, blockIdx.x, it, bucket);
-    const MaskWork &W = items[it];
-    if (bucket >= (1u << W.B)) return;
-    const uint32_t base = W.boff[bucket];
-    const uint32_t n = W.boff[bucket + 1] - base;
-    if (n <= (uint32_t)kWaveCap || (!BIG && n > (uint32_t)kSmallCap) || (BIG && n <= (uint32_t)kSmallCap)) return;
-    K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
-    if (n <= (uint32_t)CAP) {
-        for (uint32_t c0 = 0; c0 < n; c0 += kThreads * 8) {
-            // eight loads per thread in flight before the LDS stores
-            K kr[8];
-            uint32_t vr[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint32_t i = c0 + q * kThreads + threadIdx.x;
-                if (i < n) {
-                    kr[q] = gc[base + i];
-                    vr[q] = W.idx[base + i];
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint32_t i = c0 + q * kThreads + threadIdx.x;
-                if (i < n) {
-                    kA[i] = kr[q];
-                    vA[i] = vr[q];
-                }
-            }
-        }
-        __syncthreads();
-        int which = 0;
-        block_radix_sort<K>(kA, vA, kB, vB, n, W.cb, ss, which);
-        __syncthreads();
-        K *fk = which ? kB : kA;
-        uint32_t *fv = which ? vB : vA;
-        uint32_t *fr = reinterpret_cast<uint32_t *>(which ? kA : kB);
-        uint32_t *fx = which ? vA : vB;
-        if (W64) block_segment(fk, fv, n, fr, fr + CAP, fx, W, base, ss.wsum, bucket);
-        else block_segment(fk, fv, n, fr, fx, xs, W, base, ss.wsum, bucket);
-    } else {
-        int which = 0;
-        block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which);
-        __syncthreads();
-        K *fk = (which ? gc2 : gc) + base;
-        uint32_t *fv = (which ? W.idx2 : W.idx) + base;
-        uint32_t *fr = reinterpret_cast<uint32_t *>(which ? gc : gc2);
-        uint32_t *fx = (which ? W.idx : W.idx2) + base;
-        // scratch: this bucket's slice of the free composite array (2n
-        // words), or for 32-bit composites its slice of each half
-        if (W64) block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket);
-        else block_segment(fk, fv, n, fr + base, fr + (size_t)W.T + base, fx, W, base, ss.wsum, bucket);
     }
 }
 
@@ -524,34 +370,11 @@ hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, i
     hipLaunchKernelGGL(k_bucket_count, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
     return hipGetLastError();
 }
-hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st)
-{
-    if (!nitems) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_scan, dim3(nitems), dim3(kThreads), 0, st, items);
-    return hipGetLastError();
-}
 hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
                                  int maxB, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
-    return hipGetLastError();
-}
-// Items [0, nitems) of `items` share the composite width (wide: 64-bit).
-hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
-                              bool wide, hipStream_t st)
-{
-    if (!nblocks) return hipSuccess;
-    const unsigned nw = (nblocks + kWaves - 1) / kWaves;  // nblocks = buckets of all items
-    if (wide) {
-        hipLaunchKernelGGL((k_bucket_sort_wave<uint64_t>), dim3(nw), dim3(kThreads), 0, st, items, bprefix, nitems, uniform, nblocks);
-        hipLaunchKernelGGL((k_bucket_sort<uint64_t, kSmallCap, false>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
-        hipLaunchKernelGGL((k_bucket_sort<uint64_t, 4096, true>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
-    } else {
-        hipLaunchKernelGGL((k_bucket_sort_wave<uint32_t>), dim3(nw), dim3(kThreads), 0, st, items, bprefix, nitems, uniform, nblocks);
-        hipLaunchKernelGGL((k_bucket_sort<uint32_t, kSmallCap, false>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
-        hipLaunchKernelGGL((k_bucket_sort<uint32_t, 6144, true>), dim3(nblocks), dim3(kThreads), 0, st, items, bprefix, nitems, uniform);
-    }
     return hipGetLastError();
 }
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,

@@ -17,11 +17,15 @@ hipError_t launch_validate(const JobDev *jobs, const uint32_t *bprefix, int njob
 hipError_t launch_extract(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, hipStream_t st);
 hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
                                int maxB, hipStream_t st);
-hipError_t launch_bucket_scan(const MaskWork *items, int nitems, hipStream_t st);
+struct SortLists;
+// Grid sizes of the per-bucket sort kernels (0 = not launched).
+struct SortGrid {
+    uint32_t wave_blocks = 0, block_blocks = 0, global_blocks_pk = 0, global_blocks_wide = 0;
+};
+hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hipStream_t st);
 hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
                                  int maxB, hipStream_t st);
-hipError_t launch_bucket_sort(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
-                              bool wide, hipStream_t st);
+hipError_t launch_bucket_sort(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
                              uint32_t nblocks, size_t lds_bytes, hipStream_t st);
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);

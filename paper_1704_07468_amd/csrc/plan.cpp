@@ -277,8 +277,10 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         size_t nbc = 0;
         auto close = [&]() {
             if (!cur.nmask) return;
-            cur.nbcnt = nbc;
-            cur.o_bcnt = pl.take(nbc * 4);
+            cur.nbuck = nbc;
+            cur.nbcnt = nbc + kSortCounters;
+            cur.o_bcnt = pl.take(cur.nbcnt * 4);
+            cur.o_lists = pl.take((size_t)kSortClasses * nbc * 4);
             p.pool_bytes = std::max(p.pool_bytes, pl.size);
             p.chunks.push_back(cur);
             cur = Chunk{};
@@ -290,13 +292,13 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
             for (size_t i = 0; i < jp.masks.size(); ++i, ++gi) {
                 const int B = jp.level_B[(size_t)jp.masks[i].level];
                 const MaskBuf mb = mask_buf(jp.T, B);
-                const size_t need = mb.size + ((size_t)4 << B) + 512;
+                const size_t need = mb.size + ((size_t)4 << B) * (1 + kSortClasses) + 512;
                 if (need > pool_limit) {
                     set_error("one position set needs %.3f GB of buffers; %.3f GB of the HBM budget are left",
                               need / 1e9, pool_limit / 1e9);
                     return GAKCO_EBUDGET;
                 }
-                if (cur.nmask && pl.size + need + nbc * 4 + 512 > pool_limit) close();
+                if (cur.nmask && pl.size + need + nbc * 4 * (1 + kSortClasses) + 4 * kSortCounters + 512 > pool_limit) close();
                 if (!cur.nmask) cur.mfirst = gi;
                 cur.o_mask.push_back(pl.take(mb.size));
                 cur.nmask += 1;
@@ -356,9 +358,6 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     }
     for (auto &c : p.chunks) {
         c.d_pt = d.take(((size_t)c.nmask + 1) * 4, 64);
-        c.d_cls = d.take(sizeof(MaskWork) * (size_t)c.nmask, 64);
-        c.d_pbw = d.take(((size_t)c.nmask + 1) * 4, 64);
-        c.d_pbn = d.take(((size_t)c.nmask + 1) * 4, 64);
         c.d_acc = d.take(sizeof(AccWork) * (size_t)std::max(1, c.nacc), 64);
         c.d_pacc = d.take(((size_t)c.nacc + 1) * 4, 64);
     }
@@ -483,8 +482,8 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     size_t j = 0;
     for (auto &c : p.chunks) {
         size_t bc = 0;
-        std::vector<uint32_t> pt(1, 0), pbw(1, 0), pbn(1, 0);
-        std::vector<MaskWork> cls;
+        std::vector<uint32_t> pt(1, 0);
+        uint64_t bound_block = 0, bound_gpk = 0, bound_gwide = 0;
         for (int q = 0; q < c.nmask; ++q) {
             const int gi = c.mfirst + q;
             while (gi >= p.jobs[j].mask_first + (int)p.jobs[j].masks.size()) ++j;
@@ -495,6 +494,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             W.md = md;
             W.job = (int)j;
             W.T = jp.T;
+            W.N = jp.N;
             const int m = md.level;
             W.w = (jp.g - m) * jp.b;
             W.B = jp.level_B[(size_t)m];
@@ -533,26 +533,21 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             }
             pt.push_back(pt.back() + (jp.T + kTile - 1) / kTile);
         }
-        // bucket-sort classes: 64-bit composites first
+        // grids of the per-bucket sort: at most T / (class minimum) buckets
+        // of a mask fall in the block and global classes
         for (int q = 0; q < c.nmask; ++q) {
             const MaskWork &W = p.mw[(size_t)(c.mfirst + q)];
-            if (W.cb > 32) { cls.push_back(W); pbw.push_back(pbw.back() + (1u << W.B)); }
+            bound_block += W.T / ((W.cb <= 32 ? kSortWaveMaxPk : kSortWaveMaxWide) + 1);
+            if (W.cb <= 32) bound_gpk += W.T / (kSortBlockMaxPk + 1);
+            else bound_gwide += W.T / (kSortBlockMaxWide + 1);
         }
-        c.nwide = (int)cls.size();
-        for (int q = 0; q < c.nmask; ++q) {
-            const MaskWork &W = p.mw[(size_t)(c.mfirst + q)];
-            if (W.cb <= 32) { cls.push_back(W); pbn.push_back(pbn.back() + (1u << W.B)); }
-        }
-        memcpy(blob + c.d_cls, cls.data(), sizeof(MaskWork) * cls.size());
+        c.sgrid.wave_blocks = (uint32_t)std::min<size_t>((c.nbuck + kWaves - 1) / kWaves, 2048);
+        c.sgrid.block_blocks = (uint32_t)std::min<uint64_t>(bound_block, 256);
+        c.sgrid.global_blocks_pk = (uint32_t)std::min<uint64_t>(bound_gpk, 128);
+        c.sgrid.global_blocks_wide = (uint32_t)std::min<uint64_t>(bound_gwide, 128);
         c.uni_t = uniform_of(pt);
-        c.uni_bw = uniform_of(pbw);
-        c.uni_bn = uniform_of(pbn);
         c.nb_t = pt.back();
-        c.nb_bw = pbw.back();
-        c.nb_bn = pbn.back();
         put(c.d_pt, pt);
-        put(c.d_pbw, pbw);
-        put(c.d_pbn, pbn);
         std::vector<uint32_t> pa(1, 0);
         for (auto &w : c.aw) pa.push_back(pa.back() + (uint32_t)p.jobs[(size_t)w.job].N);
         if (c.nacc) memcpy(blob + c.d_acc, c.aw.data(), sizeof(AccWork) * c.aw.size());
@@ -632,13 +627,13 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
     for (auto &c : p.chunks) {
         const MaskWork *cm = masks + c.mfirst;
-        const MaskWork *cls = reinterpret_cast<const MaskWork *>(d + c.d_cls);
+        uint32_t *bcnt = reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt);
+        const SortLists L{bcnt + c.nbuck, reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_lists), (uint32_t)c.nbuck};
         GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt), c.nbcnt, 0u, st));
         GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
-        GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, st));
+        GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, L, st));
         GK_PHASE(PH_BSCATTER, launch_bucket_scatter(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
-        GK_PHASE(PH_BSORT, launch_bucket_sort(cls, P(c.d_pbw), c.nwide, c.uni_bw, c.nb_bw, true, st));
-        GK_PHASE(PH_BSORT, launch_bucket_sort(cls + c.nwide, P(c.d_pbn), c.nmask - c.nwide, c.uni_bn, c.nb_bn, false, st));
+        GK_PHASE(PH_BSORT, launch_bucket_sort(cm, L, c.sgrid, st));
         if (c.nacc)
             GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc),
                                                  c.nacc, c.nb_acc, c.acc_lds, st));

@@ -128,12 +128,15 @@ struct JobPlan {
 struct Chunk {
     int mfirst = 0, nmask = 0;
     std::vector<size_t> o_mask;  // pool offset of each mask's buffers
-    size_t o_bcnt = 0, nbcnt = 0;
+    size_t o_bcnt = 0, nbcnt = 0;  // bucket counts of every mask, then the sort counters
+    size_t nbuck = 0;              // buckets of all masks
+    size_t o_lists = 0;            // sort class lists, nbuck entries per class
     int maxB = 0;
+    SortGrid sgrid;
     // descriptor blob offsets
-    size_t d_pt = 0, d_cls = 0, d_pbw = 0, d_pbn = 0, d_acc = 0, d_pacc = 0;
-    uint32_t nb_t = 0, uni_t = 0, nb_bw = 0, nb_bn = 0, uni_bw = 0, uni_bn = 0, nb_acc = 0;
-    int nwide = 0, nacc = 0;
+    size_t d_pt = 0, d_acc = 0, d_pacc = 0;
+    uint32_t nb_t = 0, uni_t = 0, nb_acc = 0;
+    int nacc = 0;
     size_t acc_lds = 0;
     std::vector<AccWork> aw;
 };
