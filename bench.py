@@ -4,17 +4,30 @@ Workload: the protein Gram configuration -- N=3312 sequences over Sigma=20,
 lengths U{50..500}, Zipf(1.1) symbol composition, g=7, k=4 (M=3) -- computed
 in full: N_m for m=0..3 (int64, exact) and the FP64 cosine-normalised K.
 One step = one gakco_gram call over device-resident inputs into preallocated
-device outputs (extraction, every position set's partition sort and
-segmentation, row accumulation, inclusion-exclusion, K, normalisation).
+device outputs (validation, extraction, every position set's partition, sort
+and segmentation, row accumulation, int8 matrix-core products,
+inclusion-exclusion, K and normalisation).
 
-Prints ONE JSON line.  `roofline` describes the dominant kernel, timed live
-with HIP events on the library's stream; `cpu_baseline` times the CPU oracle
-on a bounded sub-Gram of the same workload.
+Prints ONE JSON line:
+  value / ms_per_step  from the timed steps (no profiler attached);
+  roofline             the dominant kernel of separate profiled steps (HIP
+                       events around each launch on the library's stream),
+                       its algorithmic bytes per launch over its mean launch
+                       time, and the HBM traffic measured by rocprofv3 PMC
+                       runs when those were taken from the current sources;
+  cpu_baseline         the CPU oracle timed on a sub-Gram of the workload;
+  serving              continuous-batching rows of the serving workload
+                       (resident 20000 DNA support sequences, g=10, k=6) under
+                       Poisson arrivals: p50/p99 latency and rows/s, beside
+                       the plain path (one gakco_rows call per query);
+  batched              the 64-job batched workload replayed from its captured
+                       hipGraph, beside the same jobs run one by one.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -23,6 +36,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_protein_gram.json")
+
+# profiler phase -> kernel name as rocprofv3 reports it
+PHASE_KERNEL = {
+    "fill": "k_fill_u64", "validate": "k_validate", "extract": "k_extract", "bucket_count": "k_bucket_count",
+    "bucket_scan": "k_bucket_scan", "bucket_scatter": "k_bucket_scatter", "sort_wave": "k_sort_wave",
+    "sort_block": "k_sort_block", "sort_global": "k_sort_global", "accumulate": "k_accumulate",
+    "dense_syrk": "k_dense_syrk", "dense_reduce": "k_dense_reduce", "dense_clear": "k_dense_clear",
+    "diag": "k_diag", "finalize": "k_finalize",
+}
 
 
 def parse():
@@ -30,53 +53,207 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=5, help="profiled steps for the per-kernel times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=900, help="sequences in the oracle's sub-Gram")
-    ap.add_argument("--profile-phases", action="store_true", help="print the per-phase table to stderr")
+    ap.add_argument("--cpu-sample", type=int, default=2400, help="sequences in the oracle's sub-Gram")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-queries", type=int, default=600)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB elementwise copy (scale for PMC byte counters)")
+    ap.add_argument("--profile-phases", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--dense-tau", type=int, default=None, help="override the int8 matrix-core threshold")
     ap.add_argument("--bucket-avg", type=int, default=None, help="override the partition bucket size")
     return ap.parse_args()
 
 
-def algorithmic_bytes(d, masks_per_level):
-    """HBM bytes each phase must move at minimum, per Gram call."""
-    N, T, M = d.N, int(sum(max(0, int(l) - d.g + 1) for l in d.lens)), d.M
-    nmask = sum(masks_per_level)
+def algorithmic(d, masks, prof_stats, dense_rows, ntile):
+    """Per-call algorithmic bytes (or int8 ops) of each kernel: what the
+    method must move, not what a kernel happens to move."""
+    N, M = d.N, d.M
+    T = int(sum(max(0, int(l) - d.g + 1) for l in d.lens))
+    S = sum(masks)
+    nsym = int(sum(int(l) for l in d.lens))
+    tri = N * (N + 1) // 2
+    # every (mask, g-mer) passes one sort kernel: packed (4-byte composite)
+    # or wide (8-byte); the partition writes that composite and the index
+    pk_all = sum(prof_stats.get(k, 0) for k in ("wave", "block", "global"))
+    wide_all = sum(prof_stats.get(k + "_wide", 0) for k in ("wave", "block", "global"))
+    scatter = 16 * T * S + 4 * pk_all + 8 * wide_all
+    sortb = {}
+    for kind in ("wave", "block", "global"):
+        pk, wide = prof_stats.get(kind, 0), prof_stats.get(kind + "_wide", 0)
+        # read the composite and index, write the g-mer's info (run entries,
+        # at most one 4-byte word per g-mer, are not counted)
+        sortb["sort_" + kind] = pk * (4 + 4 + 8) + wide * (8 + 4 + 8)
     return {
-        # read composite + index (12 B), write run entry (4 B) and g-mer info (8 B)
-        "bucket_sort": 24 * T * nmask,
-        # read packed key + sid (12 B), write composite + index (12 B)
-        "bucket_scatter": 24 * T * nmask,
-        "bucket_count": 8 * T * nmask,
-        # read the g-mer info of each row (8 B per g-mer and mask); add the
-        # upper triangle of every C_m (8 B read + 8 B write per entry)
-        "accumulate": 8 * T * nmask + (M + 1) * (N * (N + 1) // 2) * 16,
-        # read C_m upper triangle, write N_m (both triangles) and K
-        "finalize": (M + 1) * (N * (N + 1) // 2) * 8 + (M + 1) * N * N * 8 + N * N * 8,
-        "fill": (M + 1) * N * N * 8,
+        "extract": nsym + 12 * T,
+        "bucket_count": 8 * T * S,
+        "bucket_scatter": scatter,
+        **sortb,
+        # every (mask, g-mer) info read once; every upper-triangle entry of
+        # every C_m read and written once
+        "accumulate": 8 * T * S + 16 * (M + 1) * tri,
+        # each count-matrix row read once (bytes); ops below
+        "dense_syrk": ntile * dense_rows,
+        "finalize": 8 * (M + 1) * tri + 8 * (M + 1) * N * N + 8 * N * N,
+        "fill": 8 * (M + 1) * N * N,
     }, T
 
 
+def traffic_for(kernel):
+    """Measured HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE,
+    scaled by the copy kernel's counters), or None when the stored counters
+    were taken from other sources."""
+    try:
+        from paper_1704_07468_amd.profiling import source_sha
+        t = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if t.get("source_sha") != source_sha():
+        return None
+    k = t["kernels"].get(kernel)
+    c = t["copy"]
+    if not k or k.get("write_kib") is None or not c.get("fetch_kib") or not c.get("write_kib"):
+        return None
+    f_scale = c["bytes_read"] / (c["fetch_kib"] * 1024.0)
+    w_scale = c["bytes_written"] / (c["write_kib"] * 1024.0)
+    return k["fetch_kib"] * 1024.0 * f_scale + k["write_kib"] * 1024.0 * w_scale
+
+
+def note(msg):
+    print("[bench %7.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+T_START = time.perf_counter()
+
+
 def cpu_baseline(d, n_sample):
-    import numpy as np
     from oracle import oracle as orc
+    n_sample = min(n_sample, d.N)
     sub = d.subset(range(n_sample))
     threads = d.M + 1  # the paper's parallel version: one thread per m
     t0 = time.perf_counter()
     orc.kernel(sub.seqs, sub.lens, sub.g, sub.k, threads=threads, want_c=False)
     dt = time.perf_counter() - t0
     return {"value": n_sample * n_sample / dt, "unit": "kernel entries/s", "cores": threads, "kind": "oracle",
-            "sample": "oracle (Alg. 1, one thread per m) on the first %d of the %d protein sequences: "
-                      "%dx%d sub-Gram in %.2f s" % (n_sample, d.N, n_sample, n_sample, dt)}
+            "sample": "oracle (Algorithm 1, one thread per m) on the first %d of the %d protein sequences: "
+                      "%dx%d sub-Gram (N_m and K) in %.2f s" % (n_sample, d.N, n_sample, n_sample, dt)}
+
+
+def serving_leg(gakco, wl, n_q):
+    import numpy as np
+    s = wl.serving_resident()
+    ctx = gakco.Context(0)
+    res = gakco.Resident(ctx, s.sv.seqs, s.sv.lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias)
+    try:
+        q_seqs, q_lens = wl.serving_queries(n_q)
+        qoff = np.concatenate([[0], np.cumsum(q_lens)])
+        queries = [q_seqs[qoff[i]:qoff[i + 1]] for i in range(n_q)]
+        import torch
+        dev_q = [(torch.as_tensor(q).cuda(), torch.as_tensor(np.array([len(q)], dtype=np.int32)).cuda()) for q in queries]
+        note("serving: resident set built")
+        # plain: one rows call per query, no overlap
+        res.rows(*dev_q[0])
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for q, l in dev_q:
+            a = time.perf_counter()
+            res.rows(q, l)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - a)
+        plain_wall = time.perf_counter() - t0
+        plain_rate = n_q / plain_wall
+        note("serving: plain path %d queries in %.1f s" % (n_q, plain_wall))
+        # continuous batching under Poisson arrivals at 90% of the plain rate
+        # and at 3x it (queries arriving while others are on the device)
+        out = {"workload": "resident N_sv=20000 DNA l=200, g=10, k=6 (M=4); %d queries l~U{50..1000}" % n_q,
+               "unit": "ms", "plain": {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                                       "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                                       "rows_per_s": n_q * s.sv.N / plain_wall}}
+        for label, rate in (("load_0.9x_plain", 0.9 * plain_rate), ("load_3x_plain", 3.0 * plain_rate)):
+            srv = gakco.Server(res, max_batch=256, n_streams=2)
+            try:
+                arr = wl.poisson_arrivals(n_q, rate)
+                done = {}
+                t0 = time.perf_counter()
+                i = 0
+                while len(done) < n_q:
+                    now = time.perf_counter() - t0
+                    while i < n_q and arr[i] <= now:
+                        srv.submit(queries[i], i)
+                        i += 1
+                    for r in srv.poll(256, 200 if i < n_q else 20000):
+                        done[r["tag"]] = r
+                wall = time.perf_counter() - t0
+                note("serving: %s %d queries in %.1f s" % (label, n_q, wall))
+                lat_s = [done[t]["t_done"] - done[t]["t_submit"] for t in range(n_q)]
+                out[label] = {"offered_qps": rate, "p50_ms": 1e3 * float(np.percentile(lat_s, 50)),
+                              "p99_ms": 1e3 * float(np.percentile(lat_s, 99)),
+                              "rows_per_s": n_q * s.sv.N / wall,
+                              "mean_batch": float(np.mean([done[t]["batch_size"] for t in range(n_q)])),
+                              "all_ok": all(done[t]["status"] == 0 for t in range(n_q))}
+            finally:
+                srv.close()
+        return out
+    finally:
+        res.close()
+        ctx.close()
+
+
+def batched_leg(gakco, wl):
+    import torch
+    jobs_in = wl.batched()
+    ctx = gakco.Context(0)
+    try:
+        def mk():
+            return [{"seqs": j.seqs, "lens": j.lens, "sigma": j.sigma, "g": j.g, "k": j.k} for j in jobs_in]
+        entries = sum(j.N * j.N for j in jobs_in)
+        # plain: one gakco_gram per job, outputs preallocated
+        plain = mk()
+        dev = [(torch.as_tensor(j["seqs"]).cuda(), torch.as_tensor(j["lens"]).cuda()) for j in plain]
+        outs = [(torch.empty((j.N, j.N), dtype=torch.float64, device="cuda"),
+                 torch.empty((j.M + 1, j.N, j.N), dtype=torch.int64, device="cuda")) for j in jobs_in]
+        def run_plain():
+            for j, (s, l), (K, Nm) in zip(jobs_in, dev, outs):
+                ctx.gram_into(s, l, j.N, j.sigma, j.g, j.k, K=K, Nm=Nm)
+        run_plain()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_plain()
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        note("batched: plain serial %.1f ms" % (1e3 * t_plain))
+        bjobs = mk()
+        plan = ctx.batch_plan(bjobs)
+        try:
+            plan.run()
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st = plan.run()
+            torch.cuda.synchronize()
+            t_graph = (time.perf_counter() - t0) / reps
+            same = all(torch.equal(b["Nm"], Nm) and torch.equal(b["K"], K) for b, (K, Nm) in zip(bjobs, outs))
+        finally:
+            plan.close()
+        return {"workload": "64 jobs N~U{100..2000}, Sigma in {4,20,36}, l~U{50..600}, g in [6,10], k in [3,g-2]",
+                "unit": "kernel entries/s", "entries": entries,
+                "graph_replay": {"ms": 1e3 * t_graph, "value": entries / t_graph},
+                "plain_serial": {"ms": 1e3 * t_plain, "value": entries / t_plain},
+                "identical_results": bool(same), "status_ok": all(x == 0 for x in st)}
+    finally:
+        ctx.close()
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+        print("bench.py measures one GPU: this library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_1704_07468_amd import gakco, workloads as wl
 
@@ -99,35 +276,71 @@ def main():
     for _ in range(args.warmup):
         ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
     torch.cuda.synchronize()
-    ctx.set_param("profile", 1)
-    ctx.profile_reset()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile()
     ms = (t1 - t0) * 1000.0 / args.steps
     value = N * N / (ms / 1000.0)
 
-    import math
+    # per-kernel launch times from separate profiled steps
+    ctx.set_param("profile", 1)
+    ctx.profile_reset()
+    P = max(1, args.profile_steps)
+    for _ in range(P):
+        ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
+    torch.cuda.synchronize()
+    prof = ctx.profile()
+    sstat = {k: ctx.stat("sort_gmers_" + k) / P for k in ("wave", "wave_wide", "block", "block_wide", "global", "global_wide")}
+    dense_rows = ctx.stat("dense_rows")
+    ctx.set_param("profile", 0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
     masks = [math.comb(d.g, m) for m in range(M + 1)]
-    alg, T = algorithmic_bytes(d, masks)
-    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    dom_ms, dom_n = prof[dom]
-    per_launch_ms = dom_ms / max(1, dom_n)
-    launches_per_step = max(1, dom_n // args.steps)
-    alg_bytes_launch = alg.get(dom, 0) / launches_per_step
-    achieved = alg_bytes_launch / (per_launch_ms / 1000.0) / 1e9 if per_launch_ms > 0 else 0.0
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "launch_ms": round(per_launch_ms, 4)}
+    ntile = -(-N // 128) * 128
+    alg, T = algorithmic(d, masks, sstat, dense_rows, ntile)
+    kern = {}
+    for ph, (tot_ms, n) in prof.items():
+        if n:
+            kern[ph] = {"ms_per_step": tot_ms / P, "launches_per_step": n / P, "mean_launch_ms": tot_ms / n}
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    dk = kern[dom]
+    launch_s = dk["mean_launch_ms"] / 1000.0
+    if dom == "dense_syrk":
+        ops = ntile * ntile * dense_rows / dk["launches_per_step"]  # 2 ops per MAC over the upper triangle
+        roof = {"bound": "mfma", "kernel": PHASE_KERNEL[dom], "achieved": round(ops / launch_s / 1e12, 2),
+                "peak": 5000.0, "unit": "TOP/s", "frac": round(ops / launch_s / 1e12 / 5000.0, 4), "traffic": None}
+    else:
+        per_launch = alg.get(dom, 0) / dk["launches_per_step"]
+        achieved = per_launch / launch_s / 1e9
+        tr = traffic_for(PHASE_KERNEL.get(dom, dom))
+        roof = {"bound": "hbm", "kernel": PHASE_KERNEL.get(dom, dom), "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if tr is None else round(tr),
+                "algorithmic_bytes": round(per_launch), "mean_launch_ms": round(dk["mean_launch_ms"], 4)}
     if args.profile_phases:
-        for k_, (t_, n_) in sorted(prof.items(), key=lambda kv: -kv[1][0]):
-            if n_:
-                print("%-16s %9.3f ms/step  %6d launches" % (k_, t_ / args.steps, n_), file=sys.stderr)
+        for k_, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+            a = alg.get(k_)
+            gbs = "" if not a else "%8.1f GB/s algorithmic" % (a / (v["ms_per_step"] / 1e3) / 1e9)
+            print("%-15s %8.3f ms/step %5.1f launches/step %s" % (k_, v["ms_per_step"], v["launches_per_step"], gbs),
+                  file=sys.stderr)
+    ctx.close()
+
+    note("gram: %.3f ms/step" % ms)
     cpu = None if args.no_cpu_baseline else cpu_baseline(d, args.cpu_sample)
+    if cpu:
+        note("cpu baseline: " + cpu["sample"])
+    batched = None if args.no_batched else batched_leg(gakco, wl)
+    if batched:
+        note("batched: graph %.1f ms" % batched["graph_replay"]["ms"])
+    serving = None if args.no_serving else serving_leg(gakco, wl, args.serving_queries)
     line = {
         "metric": "kernel entries/sec (Gram + query rows) bit-exact; serving p50/p99 latency vs plain",
         "value": value, "unit": "kernel entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -138,7 +351,9 @@ def main():
                    "N": N, "sigma": d.sigma, "g": d.g, "k": d.k, "T_gmers": T, "position_sets": sum(masks)},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "phases_ms_per_step": {k_: round(t_ / args.steps, 4) for k_, (t_, n_) in prof.items() if n_},
+        "serving": serving,
+        "batched": batched,
+        "kernels_ms_per_step": {k_: round(v["ms_per_step"], 4) for k_, v in kern.items()},
     }
     print(json.dumps(line))
 

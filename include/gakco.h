@@ -87,13 +87,20 @@ void gakco_ctx_destroy(gakco_ctx *ctx);
 gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value);
 /* Read a value about the context or its last Gram call: "dense_rows" (groups
  * summed by the int8 matrix-core path), "chunks" (position-set chunks),
- * "dense_tau", "bucket_avg", "arena_bytes", "dense_bytes". */
+ * "dense_tau", "bucket_avg", "arena_bytes", "dense_bytes"; with the profiler
+ * on, "sort_gmers_<kind>" for kind in wave, wave_wide, block, block_wide,
+ * global, global_wide: g-mers (summed over position sets) whose bucket was
+ * sorted by that kernel, packed or 64-bit composites, since the last profile
+ * reset (synchronises the device). */
 gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *value);
 
 /* Event profiler (enable with the "profile" parameter): per launch phase of
  * the calls made on this context, the summed device time between HIP events
- * recorded on the call's stream around the phase's launches, and the number
- * of timed launches.  Phases are numbered 0 .. gakco_profile_phases()-1. */
+ * recorded on the call's stream around the phase's launch, and the number of
+ * timed launches.  Every phase is one kernel (launched at most once per
+ * position-set chunk; "sort_global" once per composite width), so its mean
+ * time is that kernel's launch duration.
+ * Phases are numbered 0 .. gakco_profile_phases()-1. */
 int32_t gakco_profile_phases(void);
 gakco_status gakco_profile_get(const gakco_ctx *ctx, int32_t phase, const char **name, double *total_ms,
                                int64_t *launches);
@@ -194,9 +201,10 @@ gakco_status gakco_autotune(gakco_ctx *ctx, const gakco_job *jobs_host, int32_t 
  * gakco_rows: for n_q queries (device q_seqs/q_lens), K_rows [n_q][n_sv]
  * receives the normalised kernel rows K-hat(q, sv_i); Nm_rows (nullable)
  * [g-k+1][n_q][n_sv] the exact mismatch profiles; decision (nullable) [n_q]
- * f(q) = b + sum_i alpha_i K-hat(sv_i, q) (Eq. 1), summed in ascending i with
- * a fixed per-query order so that a query's result does not depend on the
- * other queries of the batch.
+ * f(q) = b + sum_i alpha_i K-hat(sv_i, q) (Eq. 1), summed in a fixed
+ * per-query order (chunks of 2048 consecutive i, each summed by a fixed
+ * tree, then the chunk sums in ascending order) so that a query's result does
+ * not depend on the other queries of the batch.
  * ------------------------------------------------------------------------ */
 typedef struct gakco_resident gakco_resident;
 gakco_status gakco_resident_create(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens,

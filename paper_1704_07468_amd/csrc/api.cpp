@@ -25,6 +25,11 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
         ctx->dense_tau = (int)v;
     } else if (!strcmp(name, "profile")) {
         ctx->prof_on = v != 0;
+        if (ctx->prof_on && !ctx->prof_stat) {
+            GK_HIP(hipSetDevice(ctx->device));
+            GK_HIP(hipMalloc(&ctx->prof_stat, 8 * sizeof(unsigned long long)));
+            GK_HIP(hipMemset(ctx->prof_stat, 0, 8 * sizeof(unsigned long long)));
+        }
     } else if (!strcmp(name, "pool_mb")) {
         if (v < 16) { set_error("pool_mb must be >= 16"); return GAKCO_EINVAL; }
         ctx->pool_cap = (size_t)v << 20;
@@ -106,6 +111,11 @@ void gakco_ctx_destroy(gakco_ctx *ctx)
     if (!ctx) return;
     rows_scratch_release(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->prof_stat) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->prof_stat);
+    }
     if (ctx->dense_buf) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
@@ -261,6 +271,23 @@ gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *val
     else if (!strcmp(name, "bucket_avg")) *value = ctx->bucket_avg;
     else if (!strcmp(name, "arena_bytes")) *value = (int64_t)ctx->arena_cap;
     else if (!strcmp(name, "dense_bytes")) *value = (int64_t)ctx->dense_cap;
+    else if (!strncmp(name, "sort_gmers_", 11)) {
+        // g-mers handled by each sort kernel since the last profile reset
+        static const char *kinds[6] = {"wave", "wave_wide", "block", "block_wide", "global", "global_wide"};
+        int k = -1;
+        for (int i = 0; i < 6; ++i)
+            if (!strcmp(name + 11, kinds[i])) k = i;
+        if (k < 0) { set_error("unknown statistic '%s'", name); return GAKCO_EINVAL; }
+        unsigned long long v = 0;
+        if (ctx->prof_stat) {
+            if (hipSetDevice(ctx->device) != hipSuccess ||
+                hipMemcpy(&v, ctx->prof_stat + k, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) {
+                set_error("reading the profiling counters failed");
+                return GAKCO_EHIP;
+            }
+        }
+        *value = (int64_t)v;
+    }
     else { set_error("unknown statistic '%s'", name); return GAKCO_EINVAL; }
     return GAKCO_OK;
 }
@@ -285,6 +312,8 @@ void gakco_profile_reset(gakco_ctx *ctx)
         ctx->prof_ms[i] = 0;
         ctx->prof_n[i] = 0;
     }
+    if (ctx->prof_stat && hipSetDevice(ctx->device) == hipSuccess)
+        (void)hipMemset(ctx->prof_stat, 0, 8 * sizeof(unsigned long long));
 }
 
 }  // extern "C"

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
 {
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t ccnt[kSortClasses], cbase[kSortClasses];
+    __shared__ uint32_t gsum[6];
     const int q = blockIdx.x;
     const MaskWork &W = items[q];
     const uint32_t nb = 1u << W.B;
@@ -66,14 +67,24 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
         }
     if (threadIdx.x == 0) W.boff[nb] = tot;
     if (threadIdx.x < kSortClasses) ccnt[threadIdx.x] = 0;
+    if (threadIdx.x < 6) gsum[threadIdx.x] = 0;
     __syncthreads();
     const bool pk = W.cb <= 32;
     for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        const int c = bucket_class(W.bcnt[b], pk);
-        if (c >= 0) atomicAdd(&ccnt[c], 1u);
-        else if (W.gtab) W.bgrp[b] = 0;
+        const uint32_t n = W.bcnt[b];
+        const int c = bucket_class(n, pk);
+        if (c >= 0) {
+            atomicAdd(&ccnt[c], 1u);
+            if (L.stat) {
+                const int kind = c < kSortClassWave ? 0 : (c < kSortClassWave + kSortClassBlock ? 1 : 2);
+                atomicAdd(&gsum[kind * 2 + (pk ? 0 : 1)], n);
+            }
+        } else if (W.gtab) {
+            W.bgrp[b] = 0;
+        }
     }
     __syncthreads();
+    if (L.stat && threadIdx.x < 6 && gsum[threadIdx.x]) atomicAdd(&L.stat[threadIdx.x], (unsigned long long)gsum[threadIdx.x]);
     if (threadIdx.x < kSortClasses) {
         const uint32_t c = ccnt[threadIdx.x];
         cbase[threadIdx.x] = c ? atomicAdd(&L.cnt[threadIdx.x], c) : 0u;
@@ -756,12 +767,21 @@ hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hi
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_sort(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
+hipError_t launch_sort_wave(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
 {
-    if (g.wave_blocks)
-        hipLaunchKernelGGL(k_sort_wave, dim3(g.wave_blocks), dim3(kThreads), 0, st, items, L);
+    if (g.wave_blocks) hipLaunchKernelGGL(k_sort_wave, dim3(g.wave_blocks), dim3(kThreads), 0, st, items, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_block(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
+{
     if (g.block_blocks)
         hipLaunchKernelGGL(k_sort_block, dim3(g.block_blocks), dim3(kSortBlockThreads), 0, st, items, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_global(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
+{
     if (g.global_blocks_pk)
         hipLaunchKernelGGL(k_sort_global<uint32_t>, dim3(g.global_blocks_pk), dim3(kThreads), 0, st, items, L,
                            kSortClassWave + kSortClassBlock);

@@ -32,6 +32,7 @@ struct SortLists {
     uint32_t *cnt;   // [kSortCounters] zeroed before the scan
     uint32_t *list;  // [kSortClasses][cap]
     uint32_t cap;
+    unsigned long long *stat;  // nullable: g-mers per kernel (wave, block, global) x (packed, wide)
 };
 
 // One set of removed positions ("mask"), as the runs of kept symbol fields:

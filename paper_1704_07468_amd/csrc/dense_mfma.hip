@@ -176,13 +176,16 @@ __global__ __launch_bounds__(kThreads) void k_dense_clear(const DenseWork *__res
     (void)nwork;
 }
 
-hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks,
-                        const uint32_t *tprefix, uint32_t ntiles, hipStream_t st)
+hipError_t launch_dense_syrk(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
     hipLaunchKernelGGL(k_dense_syrk, dim3(nblocks), dim3(kThreads), 0, st, dw, bprefix, nwork);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_reduce(const DenseWork *dw, const uint32_t *tprefix, int nwork, uint32_t ntiles, hipStream_t st)
+{
+    if (!ntiles) return hipSuccess;
     hipLaunchKernelGGL(k_dense_reduce, dim3(ntiles), dim3(kThreads), 0, st, dw, tprefix, nwork);
     return hipGetLastError();
 }

@@ -25,12 +25,14 @@ struct SortGrid {
 hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hipStream_t st);
 hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
                                  int maxB, hipStream_t st);
-hipError_t launch_bucket_sort(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
+hipError_t launch_sort_wave(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
+hipError_t launch_sort_block(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
+hipError_t launch_sort_global(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
                              uint32_t nblocks, size_t lds_bytes, hipStream_t st);
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
-hipError_t launch_dense(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks,
-                        const uint32_t *tprefix, uint32_t ntiles, hipStream_t st);
+hipError_t launch_dense_syrk(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st);
+hipError_t launch_dense_reduce(const DenseWork *dw, const uint32_t *tprefix, int nwork, uint32_t ntiles, hipStream_t st);
 hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st);
 size_t dense_work_size();
 int dense_tile();
@@ -41,13 +43,15 @@ void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap,
 size_t res_mask_size();
 void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, const uint32_t *boff, const uint32_t *bgrp,
                    const uint32_t *E, const uint4 *gtab);
-hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab,
-                       const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C, hipStream_t st);
+hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
+                       int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
+                       hipStream_t st);
 hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef, const int64_t *hco, int64_t *Kd,
                                hipStream_t st);
 hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,
                                 const int64_t *Kd_sv, const int64_t *Kd_q, const double *alpha, double bias, double *K_rows,
-                                int64_t *Nm_rows, double *decision, hipStream_t st);
+                                int64_t *Nm_rows, double *decision, double *partial, hipStream_t st);
+size_t rows_partial_count(int nq, int nsv);
 hipError_t init_rows_attributes(size_t lds);
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
 }  // namespace gk

@@ -571,8 +571,9 @@ gakco_status plan_upload(Plan &p, hipStream_t st)
 }
 
 static const char *kPhaseNames[PH_COUNT] = {"fill", "validate", "extract", "bucket_count", "bucket_scan",
-                                            "bucket_scatter", "bucket_sort", "accumulate", "dense_mfma",
-                                            "diag", "finalize", "rows"};
+                                            "bucket_scatter", "sort_wave", "sort_block", "sort_global",
+                                            "accumulate", "dense_syrk", "dense_reduce", "dense_clear",
+                                            "diag", "finalize", "rows_kdiag", "rows", "rows_finalize"};
 const char *phase_name(int phase) { return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : ""; }
 
 gakco_status prof_begin(gakco_ctx *ctx, hipStream_t st, size_t *slot)
@@ -628,20 +629,24 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     for (auto &c : p.chunks) {
         const MaskWork *cm = masks + c.mfirst;
         uint32_t *bcnt = reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt);
-        const SortLists L{bcnt + c.nbuck, reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_lists), (uint32_t)c.nbuck};
+        const SortLists L{bcnt + c.nbuck, reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_lists), (uint32_t)c.nbuck,
+                          ctx->prof_on ? ctx->prof_stat : nullptr};
         GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt), c.nbcnt, 0u, st));
         GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
         GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, L, st));
         GK_PHASE(PH_BSCATTER, launch_bucket_scatter(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
-        GK_PHASE(PH_BSORT, launch_bucket_sort(cm, L, c.sgrid, st));
+        GK_PHASE(PH_SORT_WAVE, launch_sort_wave(cm, L, c.sgrid, st));
+        GK_PHASE(PH_SORT_BLOCK, launch_sort_block(cm, L, c.sgrid, st));
+        GK_PHASE(PH_SORT_GLOBAL, launch_sort_global(cm, L, c.sgrid, st));
         if (c.nacc)
             GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc),
                                                  c.nacc, c.nb_acc, c.acc_lds, st));
     }
     if (p.n_dense) {
         const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
-        GK_PHASE(PH_DENSE, launch_dense(dw, P(p.d_pdense), p.n_dense, p.nb_dense, P(p.d_pdtile), p.nb_dtile, st));
-        GK_PHASE(PH_DENSE, launch_dense_clear(dw, p.n_dense, st));
+        GK_PHASE(PH_DENSE_SYRK, launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));
+        GK_PHASE(PH_DENSE_REDUCE, launch_dense_reduce(dw, P(p.d_pdtile), p.n_dense, p.nb_dtile, st));
+        GK_PHASE(PH_DENSE_CLEAR, launch_dense_clear(dw, p.n_dense, st));
         ctx->dense_dirty = false;
     }
     if (p.nb_d) {

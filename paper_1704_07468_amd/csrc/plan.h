@@ -13,8 +13,10 @@
 #include "launch.h"
 
 // Phases timed by the optional event profiler (hipEvents around launches).
-enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_BSORT, PH_ACCUM, PH_DENSE,
-               PH_DIAG, PH_FINALIZE, PH_ROWS, PH_COUNT };
+// Each phase is one kernel launch (or none) per chunk of a call.
+enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_SORT_WAVE, PH_SORT_BLOCK,
+               PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_REDUCE, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
+               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_COUNT };
 
 struct gakco_ctx {
     int device = 0;
@@ -32,6 +34,7 @@ struct gakco_ctx {
     bool dense_dirty = false;
     // event profiler
     bool prof_on = false;
+    unsigned long long *prof_stat = nullptr;  // device: g-mers per sort kernel class (profiling only)
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_pending;  // (phase, first of two events)

@@ -27,11 +27,11 @@ struct RowsArgs {
     const uint64_t *qkey;      // query g-mers, packed
     const uint32_t *qgstart;   // [nq + 1]
     int32_t nq, M, nsv, slab;  // SVs per block (one LDS row slab)
-    int32_t nslab;
+    int32_t nslab, mchunk;     // SV slabs; position sets per block
     const ResMask *rm;
     const int32_t *lev_first;  // first mask of each level
     const int32_t *lev_count;
-    uint32_t *C;               // [M+1][nq][nsv]
+    uint32_t *C;               // [M+1][nq][nsv], zeroed; blocks add their partial rows
 };
 
 __device__ __forceinline__ void wave_sync_rows()
@@ -51,25 +51,40 @@ __device__ __forceinline__ uint32_t lower_sid(const uint32_t *E, uint32_t a, uin
     return a;
 }
 
-// One block per (level, query, SV slab), heavy levels first.
+// One block per (level, chunk of the level's position sets, query, SV slab),
+// heavy levels first: the block's partial row lives in LDS and is added into
+// C at the end (integer additions, so the sum does not depend on the order).
 __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
 {
     extern __shared__ uint32_t acc[];
     __shared__ uint32_t pre[kWaves][64];
     __shared__ uint64_t iptr[kWaves][64];
-    const int per_level = A.nq * A.nslab;
-    const int level = A.M - (int)(blockIdx.x / per_level);
-    const int rem = (int)(blockIdx.x % per_level);
+    const int per_item = A.nq * A.nslab;
+    int idx = (int)(blockIdx.x / per_item);
+    const int rem = (int)(blockIdx.x % per_item);
     const int q = rem / A.nslab, sl = rem % A.nslab;
+    // item -> (level, first position set of the chunk, position sets)
+    int level = 0, m0 = 0, mc = 0;
+    for (int l = A.M; l >= 0; --l) {
+        const int cnt = A.lev_count[l];
+        const int nch = (cnt + A.mchunk - 1) / A.mchunk;
+        if (idx < nch) {
+            level = l;
+            m0 = idx * A.mchunk;
+            mc = min(A.mchunk, cnt - m0);
+            break;
+        }
+        idx -= nch;
+    }
+    if (mc <= 0) return;
     const int s0 = sl * A.slab, s1 = min(A.nsv, s0 + A.slab);
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     for (int i = tid; i < s1 - s0; i += kThreads) acc[i] = 0;
     __syncthreads();
     const uint32_t t0 = A.qgstart[q];
     const uint32_t ng = A.qgstart[q + 1] - t0;
-    const uint32_t nmask = (uint32_t)A.lev_count[level];
-    const uint32_t total = ng * nmask;
-    const ResMask *rm = A.rm + A.lev_first[level];
+    const uint32_t total = ng * (uint32_t)mc;
+    const ResMask *rm = A.rm + A.lev_first[level] + m0;
     const int sb = rm[0].sb;
     const uint32_t sidmask = (uint32_t)bits_mask(sb);
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
@@ -113,7 +128,10 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     }
     __syncthreads();
     uint32_t *crow = A.C + ((size_t)level * A.nq + q) * A.nsv;
-    for (int sv = s0 + tid; sv < s1; sv += kThreads) crow[sv] = acc[sv - s0];
+    for (int sv = s0 + tid; sv < s1; sv += kThreads) {
+        const uint32_t v = acc[sv - s0];
+        if (v) atomicAdd(&crow[sv], v);
+    }
 }
 
 // K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.
@@ -143,33 +161,43 @@ struct RowsFinArgs {
     double *K_rows;
     int64_t *Nm_rows;
     double *decision;
+    double *partial;  // [nq][nchunk] decision sums per SV chunk
+    int32_t chunk, nchunk;
 };
 
-// One block per query: Eq. 9 and Eq. 7 per entry, the normalisation with
-// K(sv,sv) and K(q,q), and f(q) = b + sum_i alpha_i K-hat(sv_i, q) (Eq. 1).
-// Every thread sums its entries in ascending order and the block combines
-// the thread sums in a fixed tree, so a query's value does not depend on the
-// other queries of its batch.
+constexpr int kRowsChunk = 2048;  // SVs per epilogue block
+
+// One block per (query, chunk of SVs): Eq. 9 and Eq. 7 per entry, the
+// normalisation with K(sv,sv) and K(q,q), and the chunk's part of Eq. 1's
+// sum_i alpha_i K-hat(sv_i, q): every thread sums its entries in ascending
+// order and the block combines the thread sums in a fixed tree.
 template <int MM>
 __global__ __launch_bounds__(kThreads) void k_rows_finalize(RowsFinArgs A)
 {
     __shared__ double red[kThreads];
     __shared__ int64_t coef[MM * MM], hco[MM];
-    const int q = blockIdx.x, tid = threadIdx.x, M = A.M;
+    const int q = blockIdx.x / A.nchunk, ch = blockIdx.x % A.nchunk, tid = threadIdx.x, M = A.M;
+    const int s0 = ch * A.chunk, s1 = min(A.nsv, s0 + A.chunk);
     for (int i = tid; i < (M + 1) * (M + 1); i += kThreads) coef[(i / (M + 1)) * MM + (i % (M + 1))] = A.coef[i];
     for (int i = tid; i <= M; i += kThreads) hco[i] = A.hco[i];
     __syncthreads();
+    constexpr int UNR = MM <= 16 ? MM : 1;
     const int64_t kq = A.Kd_q[q];
     double part = 0.0;
-    for (int sv = tid; sv < A.nsv; sv += kThreads) {
+    for (int sv = s0 + tid; sv < s1; sv += kThreads) {
         int64_t nv[MM];
         int64_t K = 0;
-        for (int m = 0; m <= M; ++m) {
-            int64_t v = A.C[((size_t)m * A.nq + q) * A.nsv + sv];
-            for (int j = 0; j < m; ++j) v -= coef[m * MM + j] * nv[j];
+#pragma unroll UNR
+        for (int m = 0; m < MM; ++m) {
+            int64_t v = 0;
+            if (m <= M) {
+                v = A.C[((size_t)m * A.nq + q) * A.nsv + sv];
+#pragma unroll UNR
+                for (int j = 0; j < m; ++j) v -= coef[m * MM + j] * nv[j];
+                K += hco[m] * v;
+                if (A.Nm_rows) A.Nm_rows[((size_t)m * A.nq + q) * A.nsv + sv] = v;
+            }
             nv[m] = v;
-            K += hco[m] * v;
-            if (A.Nm_rows) A.Nm_rows[((size_t)m * A.nq + q) * A.nsv + sv] = v;
         }
         const int64_t ks = A.Kd_sv[sv];
         const double kh = (kq == 0 || ks == 0) ? 0.0 : (double)K / sqrt((double)ks * (double)kq);
@@ -182,7 +210,17 @@ __global__ __launch_bounds__(kThreads) void k_rows_finalize(RowsFinArgs A)
         if (tid < s) red[tid] += red[tid + s];
         __syncthreads();
     }
-    if (tid == 0 && A.decision) A.decision[q] = A.bias + red[0];
+    if (tid == 0) A.partial[(size_t)q * A.nchunk + ch] = red[0];
+}
+
+// f(q) = b + the chunk sums in ascending chunk order (one thread per query).
+__global__ __launch_bounds__(kThreads) void k_rows_decision(RowsFinArgs A)
+{
+    const int q = blockIdx.x * kThreads + threadIdx.x;
+    if (q >= A.nq) return;
+    double f = 0.0;
+    for (int c = 0; c < A.nchunk; ++c) f += A.partial[(size_t)q * A.nchunk + c];
+    A.decision[q] = A.bias + f;
 }
 
 size_t res_mask_size() { return sizeof(ResMask); }
@@ -194,13 +232,14 @@ void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, 
     *reinterpret_cast<ResMask *>(dst) = r;
 }
 
-hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab,
-                       const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C, hipStream_t st)
+hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
+                       int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
+                       hipStream_t st)
 {
     if (nq <= 0) return hipSuccess;
-    RowsArgs a{qkey, qgstart, nq, M, nsv, slab, (nsv + slab - 1) / slab, reinterpret_cast<const ResMask *>(rm),
+    RowsArgs a{qkey, qgstart, nq, M, nsv, slab, (nsv + slab - 1) / slab, mchunk, reinterpret_cast<const ResMask *>(rm),
                lev_first, lev_count, C};
-    const unsigned nb = (unsigned)(nq * (M + 1) * a.nslab);
+    const unsigned nb = (unsigned)((size_t)nq * nitems * a.nslab);
     hipLaunchKernelGGL(k_rows_accumulate, dim3(nb), dim3(kThreads), (size_t)slab * 4, st, a);
     return hipGetLastError();
 }
@@ -213,15 +252,20 @@ hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t
     return hipGetLastError();
 }
 
+size_t rows_partial_count(int nq, int nsv) { return (size_t)nq * (size_t)((nsv + kRowsChunk - 1) / kRowsChunk); }
+
 hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,
                                 const int64_t *Kd_sv, const int64_t *Kd_q, const double *alpha, double bias, double *K_rows,
-                                int64_t *Nm_rows, double *decision, hipStream_t st)
+                                int64_t *Nm_rows, double *decision, double *partial, hipStream_t st)
 {
     if (nq <= 0) return hipSuccess;
-    RowsFinArgs a{C, nq, nsv, M, coef, hco, Kd_sv, Kd_q, alpha, bias, K_rows, Nm_rows, decision};
-    if (M < 8) hipLaunchKernelGGL(k_rows_finalize<8>, dim3(nq), dim3(kThreads), 0, st, a);
-    else if (M < 16) hipLaunchKernelGGL(k_rows_finalize<16>, dim3(nq), dim3(kThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_rows_finalize<65>, dim3(nq), dim3(kThreads), 0, st, a);
+    const int nchunk = (nsv + kRowsChunk - 1) / kRowsChunk;
+    RowsFinArgs a{C, nq, nsv, M, coef, hco, Kd_sv, Kd_q, alpha, bias, K_rows, Nm_rows, decision, partial, kRowsChunk, nchunk};
+    const dim3 grid((unsigned)(nq * nchunk));
+    if (M < 8) hipLaunchKernelGGL(k_rows_finalize<8>, grid, dim3(kThreads), 0, st, a);
+    else if (M < 16) hipLaunchKernelGGL(k_rows_finalize<16>, grid, dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_rows_finalize<65>, grid, dim3(kThreads), 0, st, a);
+    if (decision) hipLaunchKernelGGL(k_rows_decision, dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
 

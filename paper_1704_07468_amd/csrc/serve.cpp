@@ -111,6 +111,7 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     const size_t o_diag = l.take((size_t)M1 * n_q * 4);
     const size_t o_kq = l.take((size_t)n_q * 8);
     const size_t o_C = l.take((size_t)M1 * n_q * R->n_sv * 4);
+    const size_t o_part = l.take(rows_partial_count(n_q, R->n_sv) * 8);
     char *scr = nullptr;
     GK_TRY(rows_scratch(ctx, l.size, &scr));
     uint32_t *diag = reinterpret_cast<uint32_t *>(scr + o_diag);
@@ -122,12 +123,19 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     GK_TRY(plan_launch(ctx, p, st));
     int64_t *Kq = reinterpret_cast<int64_t *>(scr + o_kq);
     uint32_t *C = reinterpret_cast<uint32_t *>(scr + o_C);
-    GK_PHASE(PH_ROWS, launch_kdiag_counts(diag, n_q, R->M, R->coef, R->hco, Kq, st));
-    const int slab = (int)std::min<size_t>((size_t)R->n_sv, ctx->lds_max / 4);
-    GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, R->rm, R->lev_first, R->lev_count,
-                                  C, st));
-    GK_PHASE(PH_ROWS, launch_rows_finalize(C, n_q, R->n_sv, R->M, R->coef, R->hco, R->Kd, Kq, R->alpha, R->bias, K_rows,
-                                           Nm_rows, decision, st));
+    GK_PHASE(PH_ROWS_KDIAG, launch_kdiag_counts(diag, n_q, R->M, R->coef, R->hco, Kq, st));
+    // grid: (level, chunk of position sets) x query x SV slab, sized so that
+    // even one query spreads over the whole device
+    const int slab = (int)std::min<size_t>((size_t)R->n_sv, 4096);
+    const int mchunk = n_q < 16 ? 8 : 32;
+    int nitems = 0;
+    for (int m = 0; m <= R->M; ++m) nitems += (int)((binom64(R->g, m) + mchunk - 1) / mchunk);
+    GK_HIP(launch_fill_u32(C, (size_t)M1 * n_q * R->n_sv, 0u, st));
+    GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,
+                                  R->lev_count, C, st));
+    GK_PHASE(PH_ROWS_FINALIZE, launch_rows_finalize(C, n_q, R->n_sv, R->M, R->coef, R->hco, R->Kd, Kq, R->alpha, R->bias, K_rows,
+                                           Nm_rows, decision,
+                                                           reinterpret_cast<double *>(scr + o_part), st));
     return plan_check_errors(ctx, p, st);
 }
 
