@@ -52,7 +52,9 @@ def short_name(name: str) -> str:
 def stats(csv_path: str, out_path: str, cmd: str, top: int = 20) -> None:
     rows = list(csv.DictReader(open(csv_path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    lines = ["# rocprofv3 kernel statistics", "# command: " + cmd, "",
+    lines = ["# rocprofv3 kernel statistics", "# command: " + cmd,
+             "# summarised by: python3 -m paper_1704_07468_amd.profiling stats <dir>/<host>/<pid>/run_kernel_stats.csv "
+             "<out> --cmd '<command>'", "",
              "%-44s %7s %12s %12s %7s" % ("kernel", "calls", "mean_us", "total_ms", "pct")]
     for r in rows[:top]:
         lines.append("%-44s %7s %12.1f %12.3f %7.2f" % (
@@ -88,6 +90,8 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, copy_bytes: int, cmd:
         kernels[short_name(k)] = {"fetch_kib": fetch[k], "write_kib": write.get(k)}
     out = {
         "command": cmd,
+        "summarised_by": "python3 -m paper_1704_07468_amd.profiling traffic <fetch counter_collection.csv> "
+                         "<write counter_collection.csv> <out> --copy-bytes 1073741824 --cmd '<command>'",
         "source_sha": source_sha(),
         "units": "KiB per dispatch, mean over dispatches",
         "copy": {"kernel": short_name(copy), "bytes_read": copy_bytes, "bytes_written": copy_bytes,

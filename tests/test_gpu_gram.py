@@ -108,7 +108,7 @@ def test_gram_fig2_example(gk):
 
 
 @pytest.mark.parametrize("case", ["k_eq_g", "k_zero", "single_seq", "short_seqs", "sigma1", "gb64",
-                                  "many_buckets", "heavy_keys"])
+                                  "many_buckets", "heavy_keys", "global_packed", "global_wide"])
 def test_gram_edge_cases(gk, case):
     rng = np.random.default_rng(99)
     if case == "k_eq_g":
@@ -128,10 +128,55 @@ def test_gram_edge_cases(gk, case):
         d = wl.GramInput("gb64", seqs, lens, 16, 16, 14)
     elif case == "many_buckets":
         d = wl.protein(N=500, lmin=50, lmax=200, g=7, k=5)
-    elif case == "heavy_keys":  # small key space: buckets far above the LDS capacity
+    elif case == "heavy_keys":  # small key space: buckets of single keys
         seqs, lens = wl.random_small(rng, 120, 100, 400, 2)
         d = wl.GramInput("heavy", seqs, lens, 2, 8, 5)
+    elif case == "global_packed":  # 2-bit reduced keys: buckets beyond the block sort (> 16384)
+        seqs, lens = wl.random_small(rng, 600, 480, 500, 2)
+        d = wl.GramInput("global_packed", seqs, lens, 2, 4, 2)
+    elif case == "global_wide":  # one hot 48-bit key: a bucket of 64-bit composites beyond 8192
+        lens = np.full(60, 500, dtype=np.int32)
+        seqs = np.where(rng.random(int(lens.sum())) < 0.95, 0, rng.integers(1, 36, int(lens.sum()))).astype(np.int8)
+        d = wl.GramInput("global_wide", seqs, lens, 36, 8, 6)
     run_and_compare(gk, d)
+
+
+def test_gram_sort_classes_reached():
+    """The edge cases above reach every sort kernel: the profiler's per-class
+    g-mer counters see the wave, block and global-memory sorts, for 32- and
+    64-bit composites."""
+    from paper_1704_07468_amd import gakco
+    rng = np.random.default_rng(99)
+    ctx = gakco.Context(0)
+    try:
+        ctx.set_param("profile", 1)
+        seen = {}
+        seqs, lens = wl.random_small(rng, 600, 480, 500, 2)
+        lens_w = np.full(60, 500, dtype=np.int32)
+        seqs_w = np.where(rng.random(int(lens_w.sum())) < 0.95, 0,
+                          rng.integers(1, 36, int(lens_w.sum()))).astype(np.int8)
+        for name, (sq, ln, sig, g, k) in {"packed": (seqs, lens, 2, 4, 2), "wide": (seqs_w, lens_w, 36, 8, 6),
+                                          "protein": (wl.protein(N=400).seqs, wl.protein(N=400).lens, 20, 7, 4)}.items():
+            ctx.profile_reset()
+            ctx.gram(sq, ln, sig, g, k)
+            seen[name] = {c: ctx.stat("sort_gmers_" + c) for c in
+                          ("wave", "wave_wide", "block", "block_wide", "global", "global_wide")}
+            print(name, seen[name], flush=True)
+        assert seen["packed"]["global"] > 0
+        assert seen["wide"]["global_wide"] > 0
+        assert seen["protein"]["wave"] > 0 and seen["protein"]["wave_wide"] > 0 and seen["protein"]["block"] > 0
+    finally:
+        ctx.close()
+    # larger buckets put the 64-bit composites of m=0 into the block sort (the
+    # results of this geometry are checked in test_gram_tuning_invariance)
+    c2 = gakco.Context(0, tune={"bucket_avg": 2000})
+    try:
+        c2.set_param("profile", 1)
+        d = wl.protein(N=200, lmin=50, lmax=300)
+        c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+        assert c2.stat("sort_gmers_block_wide") > 0
+    finally:
+        c2.close()
 
 
 def test_gram_symbol_out_of_range(gk):
