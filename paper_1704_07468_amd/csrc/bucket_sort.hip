@@ -385,6 +385,7 @@ struct RunAt {
     uint32_t len;  // runs from this one to the group end
     uint32_t gi;   // group index in the bucket
     uint32_t gs;   // position of the group's first g-mer
+    uint32_t gend; // position after the group's last g-mer
 };
 
 // The run starting at sorted position i (word w = i / 64, bit b = i % 64).
@@ -408,6 +409,7 @@ __device__ __forceinline__ RunAt run_at(const SegLds<NWORDS, NSLOT> &S, int w, i
     a.len = rend - a.r;
     a.gi = S.gpre[w] + (uint32_t)__popcll(ml) - 1u;
     a.gs = ml ? (uint32_t)last_bit(w, ml) : S.prevg[w];
+    a.gend = gend;
     return a;
 }
 
@@ -426,7 +428,8 @@ __device__ __forceinline__ uint32_t cand_slot(const SegLds<NWORDS, NSLOT> &S, ui
 // run entry (sequence | count << sb) per run at E[base + run], so each
 // group's entries are contiguous and sequence-sorted; per g-mer its info --
 // for the first g-mer of a run (entry index, runs to the group end | count <<
-// (sb+1)), for the others (0, 0).  Groups with at least tau runs and every
+// (sb+1)), for the others (0, 0); with W.inl a run two entries from its group
+// end carries that last entry (sequence | count << sb) instead of its index.  Groups with at least tau runs and every
 // count <= 127 become rows of the int8 count matrix instead (info length 0),
 // as far as NSLOT candidate groups per bucket (otherwise all of the bucket's
 // groups stay on the exact sparse path).  With gtab, lists the groups (hash
@@ -527,7 +530,12 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
                 y = 0;
             }
         }
-        if (idx < W.T) W.info[idx] = make_uint2(ei, y);
+        uint32_t x = ei;
+        if (W.inl && y != 0 && a.len == 2) {  // the group's last run, inline
+            const uint32_t nx = i + a.cnt;
+            x = (uint32_t)(comp_at(nx) & sidmask) | ((a.gend - nx) << sb);
+        }
+        if (idx < W.T) W.info[idx] = make_uint2(x, y);
         if (W.diag && sid < (uint32_t)W.N) atomicAdd(&W.diag[sid], a.cnt * a.cnt);
         if (W.gtab && a.gs == i) {
             const uint64_t hr = c >> sb;

@@ -95,6 +95,8 @@ struct MaskWork {
     uint32_t dcap;     // row capacity
     uint32_t dstride;  // bytes per sequence
     int32_t tau;       // min distinct sequences of a dense group (0 = off)
+    int32_t inl;       // 1: a run two entries from its group end carries the
+                       // last entry in its info instead of its own index
     // resident tables (serving): per bucket its groups in hash-rest order
     uint4 *gtab;       // [T] (hash rest lo, hi, first entry, end entry) at bucket offset + group (nullable)
     uint32_t *bgrp;    // [2^B] groups per bucket
@@ -368,8 +370,14 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
                 len = 0;
             }
         }
+        uint32_t x = e;
+        if (W.inl && len == 2) {  // the group's last run, inline
+            const uint32_t p1 = rpos[r + 1];
+            const uint32_t c1 = ((r + 2 < R) ? rpos[r + 2] : n) - p1;
+            x = (uint32_t)((uint64_t)fk[p1] & sidmask) | (c1 << sb);
+        }
         // y: entries to the group end in the low sb+1 bits, the run count above
-        W.info[fv[p]] = make_uint2(e, len ? (len | (cnt << (sb + 1))) : 0u);
+        W.info[fv[p]] = make_uint2(x, len ? (len | (cnt << (sb + 1))) : 0u);
     }
     for (uint32_t i = tid; i < n; i += kThreads)
         if (i > 0 && fk[i] == fk[i - 1]) W.info[fv[i]] = make_uint2(0u, 0u);

@@ -136,9 +136,12 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
 // its group), the entries from X's own to the group end -- exactly the
 // sequences Y >= X of the group, since entries are sequence-sorted -- add
 // count_X * count_Y to row[Y] (Algorithm 1 countAndUpdate, upper triangle).
-// Each wave consumes its own chunks of 64 (mask, g-mer) items; a wave scan of
-// their run lengths spreads the chunk's updates evenly over the lanes, so the
-// loop has no block barrier.  The row is then added into the int64 C_m.
+// X's own entry is count_X^2 on the diagonal, summed in registers; a run with
+// one more entry carries it in its info; longer tails are read from the run
+// entries.  Each wave consumes its own chunks of 64 (mask, g-mer) items; a
+// wave scan of their tail lengths spreads the chunk's updates evenly over the
+// lanes, so the loop has no block barrier.  The row is then added into the
+// int64 C_m.
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
                                                          const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
 {
@@ -163,6 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
     __syncthreads();
     const uint32_t total = (uint32_t)A.nmask * ng;
+    uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t q = c0 + lane;
         uint32_t len = 0;
@@ -171,11 +175,20 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             const uint32_t t = t0 + (q - s * ng);
             const MaskWork &W = items[A.mfirst + s];
             const uint2 inf = W.info[t];
-            len = inf.y & lmask;
-            if (len) {
-                iptr[wid][lane] = reinterpret_cast<uint64_t>(W.E + inf.x);
-                icx[wid][lane] = inf.y >> (sb + 1);
-                ioff[wid][lane] = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
+            const uint32_t tail = inf.y & lmask;  // entries from X's own to the group end
+            if (tail) {
+                const uint32_t cx = inf.y >> (sb + 1);
+                const uint32_t off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
+                if (A.nlev == 1) dsum += cx * cx;
+                else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
+                if (tail == 2) {
+                    atomicAdd(&acc[off + (inf.x & sidmask)], cx * (inf.x >> sb));
+                } else if (tail > 2) {
+                    len = tail - 1;
+                    iptr[wid][lane] = reinterpret_cast<uint64_t>(W.E + inf.x + 1);
+                    icx[wid][lane] = cx;
+                    ioff[wid][lane] = off;
+                }
             }
         }
         const uint32_t inc = wave_incl_scan(len);
@@ -202,6 +215,10 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             atomicAdd(&acc[ioff[wid][i] + (ent & sidmask)], icx[wid][i] * (ent >> sb));
         }
         wave_sync();
+    }
+    if (A.nlev == 1) {
+        const uint32_t d = wave_incl_scan(dsum);
+        if (lane == 63 && d) atomicAdd(&acc[X], d);
     }
     __syncthreads();
     for (int l = 0; l < A.nlev; ++l) {

@@ -524,6 +524,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
                 W.gtab = jp.ext_gtab[mi];
             }
             if (!jp.ext_diag.empty()) W.diag = jp.ext_diag[(size_t)m];
+            W.inl = jp.want_kernel ? 1 : 0;
             if (jp.want_kernel && jp.dcap[(size_t)m]) {
                 W.D = ctx->dense_buf + jp.o_dense[(size_t)m];
                 W.dcount = flags + p.jobs.size() + jp.lev_base + m;
