@@ -43,7 +43,7 @@ PHASE_KERNEL = {
     "fill": "k_fill_u64", "validate": "k_validate", "extract": "k_extract", "bucket_count": "k_bucket_count",
     "bucket_scan": "k_bucket_scan", "bucket_scatter": "k_bucket_scatter", "sort_wave": "k_sort_wave",
     "sort_block": "k_sort_block", "sort_global": "k_sort_global", "accumulate": "k_accumulate",
-    "dense_syrk": "k_dense_syrk", "dense_reduce": "k_dense_reduce", "dense_clear": "k_dense_clear",
+    "dense_syrk": "k_dense_syrk", "dense_clear": "k_dense_clear",
     "diag": "k_diag", "finalize": "k_finalize",
 }
 

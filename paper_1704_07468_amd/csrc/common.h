@@ -47,6 +47,23 @@ struct MaskDesc {
     uint8_t rdst[kMaxRuns];
 };
 
+// int8 matrix-core path geometry: 128 x 128 output tiles, rows staged 64 at
+// a time, a row split holding at most 65536 rows (65536 * 127^2 < 2^31 keeps
+// its int32 partial sums exact).
+constexpr int kDenseTile = 128;
+constexpr int kDenseK = 64;
+constexpr uint32_t kDenseSplitRows = 65536;
+constexpr int kDenseMaxSplits = 8;  // row splits per output tile
+
+// Per level of a job: the split partial tiles of its count-matrix products
+// (P == nullptr when the level has none), added by the epilogue.
+struct DenseRef {
+    const int32_t *P;        // [upper tiles][S][128 * 128]
+    const uint32_t *count;   // rows used (device counter)
+    uint32_t cap;            // row capacity
+    int32_t S, ntile;        // row splits; tiles per edge
+};
+
 // Per-dataset ("job") state.
 struct JobDev {
     const int8_t *seqs;      // concatenated symbol codes
@@ -62,6 +79,7 @@ struct JobDev {
     int64_t *Kd;             // [N] unnormalised K diagonal
     const int64_t *coef;     // [(M+1)*(M+1)] C(g-j, m-j) at [m*(M+1)+j]
     const int64_t *hco;      // [M+1] C(g-m, k)
+    const DenseRef *dref;    // [M+1] int8-path partials per level
     double *K_out;
     int64_t *Nm_out;
     int64_t *Cm_out;
@@ -110,6 +128,7 @@ struct AccWork {
     int32_t nmask;
     int32_t lev0, nlev;
     int32_t Npad;    // LDS row stride
+    int32_t first;   // 1: first work of its (job, level): store the row, else add
 };
 
 // --------------------------------------------------------------------------
@@ -138,6 +157,44 @@ __device__ __forceinline__ uint64_t compact_key(uint64_t key, const MaskDesc &md
     for (int i = 0; i < md.nrun; ++i)
         r |= ((key >> md.rsrc[i]) & bits_mask(md.rwid[i])) << md.rdst[i];
     return r;
+}
+
+// Rows [r0, r1) of split s of S when R rows are used (splits of whole
+// 64-row steps).
+__device__ __forceinline__ void split_range(uint32_t R, int S, int s, uint32_t &r0, uint32_t &r1)
+{
+    const uint32_t per = ((R + S - 1) / S + kDenseK - 1) / kDenseK * kDenseK;
+    r0 = min(R, per * (uint32_t)s);
+    r1 = min(R, r0 + per);
+}
+
+// Splits of a level that hold rows (they come first).
+__device__ __forceinline__ int dense_splits_used(const DenseRef &D)
+{
+    if (!D.P) return 0;
+    const uint32_t R = min(*D.count, D.cap);
+    int ns = 0;
+    for (int s = 0; s < D.S; ++s) {
+        uint32_t r0, r1;
+        split_range(R, D.S, s, r0, r1);
+        if (r0 < r1) ns = s + 1;
+    }
+    return ns;
+}
+
+// The int8-path part of C_m[x][y] (x <= y): the sum of the used splits'
+// partial tiles.
+__device__ __forceinline__ int64_t dense_part(const DenseRef &D, int ns, int x, int y)
+{
+    const int I = x / kDenseTile, Jt = y / kDenseTile;
+    const int f = I * D.ntile - (I * (I - 1)) / 2 + (Jt - I);
+    const size_t e = (size_t)(x % kDenseTile) * kDenseTile + (size_t)(y % kDenseTile);
+    const int32_t *p = D.P + (size_t)f * D.S * (kDenseTile * kDenseTile) + e;
+    int64_t v = 0;
+#pragma unroll
+    for (int s = 0; s < kDenseMaxSplits; ++s)  // independent loads, issued together
+        if (s < ns) v += p[(size_t)s * (kDenseTile * kDenseTile)];
+    return v;
 }
 
 // Index i with prefix[i] <= v < prefix[i+1]; prefix has n+1 entries.

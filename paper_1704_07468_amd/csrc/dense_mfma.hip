@@ -6,8 +6,8 @@
 // group's contribution to C_m is the outer product of that row with itself
 // and the contribution of all of them is D_m^T D_m.  Counts are <= 127, so
 // int8 operands with int32 accumulation are exact for up to
-// 2^31 / 127^2 = 133144 rows; partial sums are added into the int64 C_m every
-// 65536 rows.  D is stored sequence-major (Dt[X][r]) so every MFMA operand
+// 2^31 / 127^2 = 133144 rows; each split of at most 65536 rows keeps its
+// exact int32 partial tile, and the epilogue adds the splits into C_m.  D is stored sequence-major (Dt[X][r]) so every MFMA operand
 // is 16 contiguous bytes along r.  Only tiles on or above the diagonal are
 // computed; the epilogue mirrors the upper triangle.
 #include "common.h"
@@ -18,10 +18,10 @@ namespace gk {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kDTile = 128;           // output tile edge
-constexpr int kDK = 64;               // rows (k) staged per LDS buffer
+constexpr int kDTile = kDenseTile;    // output tile edge
+constexpr int kDK = kDenseK;          // rows (k) staged per LDS buffer
 constexpr int kDRow = kDK + 16;       // padded LDS row: 80 bytes keeps 16-byte reads conflict-free
-constexpr uint32_t kDSplitRows = 65536;  // rows per split: int32 partials stay exact
+constexpr uint32_t kDSplitRows = kDenseSplitRows;
 
 struct DenseWork {
     int8_t *Dt;              // [Npad][stride] counts, zero beyond the used rows
@@ -29,17 +29,8 @@ struct DenseWork {
     uint32_t cap;            // row capacity (<= S * kDSplitRows)
     uint32_t stride;         // bytes per sequence (multiple of kDK, >= cap)
     int32_t N, nt, S;        // sequences, tiles per edge, row splits
-    int64_t *C;              // C_m [N][N]
     int32_t *P;              // partial tiles [nt*(nt+1)/2][S][128*128]
 };
-
-// Rows [r0, r1) of split s when R rows are used.
-__device__ __forceinline__ void split_range(uint32_t R, int S, int s, uint32_t &r0, uint32_t &r1)
-{
-    const uint32_t per = ((R + S - 1) / S + kDK - 1) / kDK * kDK;
-    r0 = min(R, per * (uint32_t)s);
-    r1 = min(R, r0 + per);
-}
 
 __device__ __forceinline__ void tile_of(int f, int nt, int &I, int &J)
 {
@@ -58,7 +49,7 @@ __device__ __forceinline__ void tile_of(int f, int nt, int &I, int &J)
 // of the tile) and B (columns) operand slabs of 64 rows are staged through
 // double-buffered LDS with coalesced 16-byte loads; each wave computes a
 // 64x64 quarter as 2x2 MFMA tiles.  The exact int32 partial tile is stored
-// for the reduction.
+// for the epilogue, which adds the splits into C_m.
 __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__restrict__ dw, const uint32_t *__restrict__ bprefix,
                                                          int nwork)
 {
@@ -134,34 +125,6 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
     put(acc11, wx * 64 + 32, wy * 64 + 32);
 }
 
-// C_m[x][y] += sum over the non-empty splits of the partial tiles (x <= y).
-__global__ __launch_bounds__(kThreads) void k_dense_reduce(const DenseWork *__restrict__ dw, const uint32_t *__restrict__ tprefix,
-                                                           int nwork)
-{
-    const int wi = find_item(tprefix, nwork, blockIdx.x);
-    const DenseWork &W = dw[wi];
-    const uint32_t R = min(*W.count, W.cap);
-    if (R == 0) return;
-    const int f = (int)(blockIdx.x - tprefix[wi]);
-    int I, J;
-    tile_of(f, W.nt, I, J);
-    int ns = 0;
-    for (int s = 0; s < W.S; ++s) {
-        uint32_t r0, r1;
-        split_range(R, W.S, s, r0, r1);
-        if (r0 < r1) ns = s + 1;
-    }
-    const int N = W.N;
-    const int32_t *P = W.P + (size_t)f * W.S * (kDTile * kDTile);
-    for (int e = threadIdx.x; e < kDTile * kDTile; e += kThreads) {
-        const int x = I * kDTile + e / kDTile, y = J * kDTile + e % kDTile;
-        if (x >= N || y >= N || x > y) continue;
-        int64_t sum = 0;
-        for (int s = 0; s < ns; ++s) sum += P[(size_t)s * (kDTile * kDTile) + e];
-        if (sum) W.C[(size_t)x * N + y] += sum;
-    }
-}
-
 // Restore the zero invariant of Dt: clear the used rows of every sequence.
 __global__ __launch_bounds__(kThreads) void k_dense_clear(const DenseWork *__restrict__ dw, int nwork)
 {
@@ -183,12 +146,7 @@ hipError_t launch_dense_syrk(const DenseWork *dw, const uint32_t *bprefix, int n
     return hipGetLastError();
 }
 
-hipError_t launch_dense_reduce(const DenseWork *dw, const uint32_t *tprefix, int nwork, uint32_t ntiles, hipStream_t st)
-{
-    if (!ntiles) return hipSuccess;
-    hipLaunchKernelGGL(k_dense_reduce, dim3(ntiles), dim3(kThreads), 0, st, dw, tprefix, nwork);
-    return hipGetLastError();
-}
+
 
 hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st)
 {
@@ -203,9 +161,9 @@ int dense_kchunk() { return kDK; }
 uint32_t dense_split_rows() { return kDSplitRows; }
 
 void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt, int S,
-                     int64_t *C, int32_t *P)
+                     int32_t *P)
 {
-    DenseWork w{Dt, count, cap, stride, N, nt, S, C, P};
+    DenseWork w{Dt, count, cap, stride, N, nt, S, P};
     *reinterpret_cast<DenseWork *>(dst) = w;
 }
 

@@ -161,7 +161,14 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     const uint32_t lmask = (uint32_t)bits_mask(sb + 1);
     const uint32_t t0 = J.gstart[X];
     const uint32_t ng = J.gstart[X + 1] - t0;
-    if (ng == 0 || A.nmask == 0) return;  // nothing to add: the row stays 0
+    if (ng == 0 || A.nmask == 0) {  // nothing to add: a stored row is 0
+        if (A.first)
+            for (int l = 0; l < A.nlev; ++l) {
+                int64_t *crow = J.C + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
+                for (int Y = X + tid; Y < N; Y += kThreads) crow[Y] = 0;
+            }
+        return;
+    }
     const int npad = A.Npad;
     for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
     __syncthreads();
@@ -224,9 +231,13 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     for (int l = 0; l < A.nlev; ++l) {
         int64_t *crow = J.C + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
         const uint32_t *arow = acc + l * npad;
-        for (int Y = X + tid; Y < N; Y += kThreads) {
-            const uint32_t v = arow[Y];
-            if (v) crow[Y] += (int64_t)v;
+        if (A.first) {
+            for (int Y = X + tid; Y < N; Y += kThreads) crow[Y] = (int64_t)arow[Y];
+        } else {
+            for (int Y = X + tid; Y < N; Y += kThreads) {
+                const uint32_t v = arow[Y];
+                if (v) crow[Y] += (int64_t)v;
+            }
         }
     }
 }
@@ -245,6 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(const JobDev *__restrict__ jo
     int64_t kx = 0;
     for (int m = 0; m <= M; ++m) {
         int64_t v = J.C[((size_t)m * N + X) * N + X];
+        if (J.dref && J.dref[m].P) v += dense_part(J.dref[m], dense_splits_used(J.dref[m]), X, X);
         for (int jj = 0; jj < m; ++jj) v -= J.coef[m * (M + 1) + jj] * nv[jj];
         nv[m] = v;
         kx += J.hco[m] * v;
@@ -261,6 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     __shared__ int64_t coef[MM * MM];
     __shared__ int64_t hco[MM];
     __shared__ int64_t tile[32][33];
+    __shared__ int nsplit[MM];
     const int j = find_item(bprefix, njobs, blockIdx.x);
     const JobDev &Jb = jobs[j];
     const int N = Jb.N, M = Jb.M;
@@ -270,7 +283,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     if (I > Jt) return;
     const int tid = threadIdx.x;
     for (int i = tid; i < (M + 1) * (M + 1); i += kThreads) coef[(i / (M + 1)) * MM + (i % (M + 1))] = Jb.coef[i];
-    for (int i = tid; i <= M; i += kThreads) hco[i] = Jb.hco[i];
+    for (int i = tid; i <= M; i += kThreads) {
+        hco[i] = Jb.hco[i];
+        nsplit[i] = (Jb.dref && Jb.dref[i].P) ? dense_splits_used(Jb.dref[i]) : 0;
+    }
     __syncthreads();
     const int c = tid & 31;
     // level loops are unrolled over the compile-time bound so the per-level
@@ -291,6 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
                 int64_t v = 0;
                 if (m <= M) {
                     v = Jb.C[((size_t)m * N + x) * N + y];
+                if (nsplit[m]) v += dense_part(Jb.dref[m], nsplit[m], x, y);
 #pragma unroll UNR
                     for (int jj = 0; jj < m; ++jj) v -= coef[m * MM + jj] * nv[q][jj];
                     kv[q] += hco[m] * v;

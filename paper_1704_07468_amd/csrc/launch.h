@@ -32,14 +32,13 @@ hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const Ac
                              uint32_t nblocks, size_t lds_bytes, hipStream_t st);
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
 hipError_t launch_dense_syrk(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st);
-hipError_t launch_dense_reduce(const DenseWork *dw, const uint32_t *tprefix, int nwork, uint32_t ntiles, hipStream_t st);
 hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st);
 size_t dense_work_size();
 int dense_tile();
 int dense_kchunk();
 uint32_t dense_split_rows();
 void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap, uint32_t stride, int N, int nt, int S,
-                     int64_t *C, int32_t *P);
+                     int32_t *P);
 size_t res_mask_size();
 void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, const uint32_t *boff, const uint32_t *bgrp,
                    const uint32_t *E, const uint4 *gtab);

@@ -245,7 +245,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
             const double scale = tot > (double)limit ? (double)limit / tot : 1.0;
             const int ntile = jp.Ntile / dense_tile();
             const int tiles = ntile * (ntile + 1) / 2;
-            jp.dS = std::max(1, std::min(8, (1024 + tiles - 1) / tiles));
+            jp.dS = std::max(1, std::min(kDenseMaxSplits, (1024 + tiles - 1) / tiles));
             const uint64_t kc = (uint64_t)dense_kchunk();
             for (int m = 0; m <= jp.M; ++m) {
                 uint64_t c = (uint64_t)(want[(size_t)m] * scale);
@@ -309,7 +309,10 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         close();
     }
     // accumulation works of each chunk: one per (job, level) present in it,
-    // the levels with the most masks first
+    // the levels with the most masks first; the first work of a (job, level)
+    // stores its rows, later ones add to them
+    std::vector<std::vector<char>> stored(p.jobs.size());
+    for (size_t j = 0; j < p.jobs.size(); ++j) stored[j].assign((size_t)p.jobs[j].M + 1, 0);
     for (auto &c : p.chunks) {
         for (size_t j = 0; j < p.jobs.size(); ++j) {
             auto &jp = p.jobs[j];
@@ -331,6 +334,8 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 w.lev0 = lev;
                 w.nlev = 1;
                 w.Npad = jp.Npad;
+                w.first = stored[j][(size_t)lev] ? 0 : 1;
+                stored[j][(size_t)lev] = 1;
                 c.aw.push_back(w);
                 c.acc_lds = std::max(c.acc_lds, (size_t)jp.Npad * 4);
             }
@@ -355,6 +360,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         jp.o_gstart = d.take(((size_t)jp.N + 1) * 4, 64);
         jp.o_coef = d.take(M1 * M1 * 8, 64);
         jp.o_hco = d.take(M1 * 8, 64);
+        jp.o_dref = d.take(M1 * sizeof(DenseRef), 64);
     }
     for (auto &c : p.chunks) {
         c.d_pt = d.take(((size_t)c.nmask + 1) * 4, 64);
@@ -437,6 +443,17 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             hco[m] = binom64(jp.g - m, jp.k);                                                 // Eq. 6
             for (int q = 0; q < m; ++q) coef[(size_t)m * M1 + q] = binom64(jp.g - q, m - q);  // Eq. 9
         }
+        DenseRef *dref = reinterpret_cast<DenseRef *>(blob + jp.o_dref);
+        for (int m = 0; m < M1; ++m) {
+            dref[m] = DenseRef{};
+            if (jp.want_kernel && jp.dcap[(size_t)m]) {
+                dref[m].P = reinterpret_cast<const int32_t *>(p.base + jp.o_P[(size_t)m]);
+                dref[m].count = reinterpret_cast<const uint32_t *>(p.base + p.o_flags) + p.jobs.size() + jp.lev_base + m;
+                dref[m].cap = jp.dcap[(size_t)m];
+                dref[m].S = jp.dS;
+                dref[m].ntile = jp.Ntile / dense_tile();
+            }
+        }
         JobDev &J = jp.dev;
         J = JobDev{};
         J.seqs = jp.seqs;
@@ -453,6 +470,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             J.Kd = reinterpret_cast<int64_t *>(base + jp.o_Kd);
             J.coef = reinterpret_cast<const int64_t *>(dev_desc + jp.o_coef);
             J.hco = reinterpret_cast<const int64_t *>(dev_desc + jp.o_hco);
+            J.dref = reinterpret_cast<const DenseRef *>(dev_desc + jp.o_dref);
             J.K_out = jp.K_out;
             J.Nm_out = jp.Nm_out;
             J.Cm_out = jp.Cm_out;
@@ -470,8 +488,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
                 if (!jp.dcap[(size_t)m]) continue;
                 dense_work_fill(blob + p.d_dense + dense_work_size() * (size_t)di, ctx->dense_buf + jp.o_dense[(size_t)m],
                                 flags + p.jobs.size() + jp.lev_base + m, jp.dcap[(size_t)m], jp.dcap[(size_t)m], jp.N,
-                                ntile, jp.dS, J.C + (size_t)m * jp.N * jp.N,
-                                reinterpret_cast<int32_t *>(base + jp.o_P[(size_t)m]));
+                                ntile, jp.dS, reinterpret_cast<int32_t *>(base + jp.o_P[(size_t)m]));
                 pdn.push_back(pdn.back() + tiles * (uint32_t)jp.dS);
                 pdt.push_back(pdt.back() + tiles);
                 ++di;
@@ -573,7 +590,7 @@ gakco_status plan_upload(Plan &p, hipStream_t st)
 
 static const char *kPhaseNames[PH_COUNT] = {"fill", "validate", "extract", "bucket_count", "bucket_scan",
                                             "bucket_scatter", "sort_wave", "sort_block", "sort_global",
-                                            "accumulate", "dense_syrk", "dense_reduce", "dense_clear",
+                                            "accumulate", "dense_syrk", "dense_clear",
                                             "diag", "finalize", "rows_kdiag", "rows", "rows_finalize"};
 const char *phase_name(int phase) { return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : ""; }
 
@@ -620,10 +637,9 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     const MaskWork *masks = reinterpret_cast<const MaskWork *>(d + p.d_masks);
     auto P = [&](size_t off) { return reinterpret_cast<const uint32_t *>(d + off); };
     const int nj = (int)p.jobs.size();
+    // (C_m needs no clearing: the first accumulation work of every level
+    // stores its rows)
     GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_flags), p.nflags, 0u, st));
-    for (auto &jp : p.jobs)
-        if (jp.want_kernel)
-            GK_PHASE(PH_FILL, launch_fill_u64(reinterpret_cast<uint64_t *>(jp.dev.C), (size_t)(jp.M + 1) * jp.N * jp.N, 0ull, st));
     GK_PHASE(PH_VALIDATE, launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
     GK_PHASE(PH_EXTRACT, launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
@@ -646,7 +662,6 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     if (p.n_dense) {
         const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
         GK_PHASE(PH_DENSE_SYRK, launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));
-        GK_PHASE(PH_DENSE_REDUCE, launch_dense_reduce(dw, P(p.d_pdtile), p.n_dense, p.nb_dtile, st));
         GK_PHASE(PH_DENSE_CLEAR, launch_dense_clear(dw, p.n_dense, st));
         ctx->dense_dirty = false;
     }

@@ -15,7 +15,7 @@
 // Phases timed by the optional event profiler (hipEvents around launches).
 // Each phase is one kernel launch (or none) per chunk of a call.
 enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_SORT_WAVE, PH_SORT_BLOCK,
-               PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_REDUCE, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
+               PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
                PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_COUNT };
 
 struct gakco_ctx {
@@ -104,7 +104,7 @@ struct JobPlan {
     std::vector<MaskDesc> masks;
     std::vector<int> level_B;  // bucket bits per level
     // layout offsets (arena)
-    size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_C = 0, o_Kd = 0, o_coef = 0, o_hco = 0;
+    size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_C = 0, o_Kd = 0, o_coef = 0, o_hco = 0, o_dref = 0;
     std::vector<uint32_t> dcap;  // per level dense row capacity (0 = level has no dense path)
     std::vector<size_t> o_dense; // per level offset in the context's dense buffer
     std::vector<size_t> o_P;     // per level partial tiles of the split rows
