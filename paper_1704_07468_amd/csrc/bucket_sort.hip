@@ -552,17 +552,14 @@ __device__ __forceinline__ void load_bucket(const MaskWork &W, uint32_t base, ui
                                             uint32_t (&val)[EL])
 {
     const int lane = __lane_id();
-    const uint32_t *c32 = reinterpret_cast<const uint32_t *>(W.comp);
 #pragma unroll
     for (int e = 0; e < EL; ++e) {
         const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
         key[e] = ~0ull;
         val[e] = 0xFFFFFFFFu;
         if (i < n) {
-            const uint32_t x = W.idx[base + i];
-            if constexpr (PK) key[e] = ((uint64_t)c32[base + i] << 32) | x;
-            else key[e] = W.comp[base + i];
-            val[e] = x;
+            key[e] = W.comp[base + i];  // packed: composite << 32 | index
+            if constexpr (!PK) val[e] = W.idx[base + i];
         }
     }
 }
@@ -736,12 +733,13 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
 
 // ----------------------------------------------------- global kernel --
 // Buckets beyond the block classes: LSD radix sort in the bucket's own
-// global-memory slice (ping-pong with the second composite array), then the
-// block-wide segmentation with scratch taken from the free slices.
-template <typename K>
+// global-memory slice (ping-pong with the second composite array) -- packed
+// words by their composite half, wide composites with their index array --
+// then the block-wide segmentation with scratch taken from the free slices.
+template <bool PK>
 __global__ __launch_bounds__(kThreads) void k_sort_global(const MaskWork *__restrict__ items, SortLists L, int cls)
 {
-    constexpr bool W64 = sizeof(K) == 8;
+    using K = uint64_t;
     __shared__ SortScratch ss;
     const uint32_t cnt = min(L.cnt[cls], L.cap);
     for (uint32_t t = blockIdx.x; t < cnt; t += gridDim.x) {
@@ -753,16 +751,15 @@ __global__ __launch_bounds__(kThreads) void k_sort_global(const MaskWork *__rest
         const uint32_t n = W.boff[bucket + 1] - base;
         K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
         int which = 0;
-        block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which);
+        // packed words carry their index: the index arrays ride along unused
+        block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which, PK ? 32 : 0);
         __syncthreads();
         K *fk = (which ? gc2 : gc) + base;
         uint32_t *fv = (which ? W.idx2 : W.idx) + base;
         uint32_t *fr = reinterpret_cast<uint32_t *>(which ? gc : gc2);
         uint32_t *fx = (which ? W.idx : W.idx2) + base;
-        // scratch: this bucket's slice of the free composite array (2n
-        // words), or for 32-bit composites its slice of each half
-        if (W64) block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket);
-        else block_segment(fk, fv, n, fr + base, fr + (size_t)W.T + base, fx, W, base, ss.wsum, bucket);
+        // scratch: this bucket's slice of the free composite array (2n words)
+        block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket, PK ? 32 : 0);
         __syncthreads();
     }
 }
@@ -791,10 +788,10 @@ hipError_t launch_sort_block(const MaskWork *items, SortLists L, const SortGrid 
 hipError_t launch_sort_global(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
 {
     if (g.global_blocks_pk)
-        hipLaunchKernelGGL(k_sort_global<uint32_t>, dim3(g.global_blocks_pk), dim3(kThreads), 0, st, items, L,
+        hipLaunchKernelGGL(k_sort_global<true>, dim3(g.global_blocks_pk), dim3(kThreads), 0, st, items, L,
                            kSortClassWave + kSortClassBlock);
     if (g.global_blocks_wide)
-        hipLaunchKernelGGL(k_sort_global<uint64_t>, dim3(g.global_blocks_wide), dim3(kThreads), 0, st, items, L,
+        hipLaunchKernelGGL(k_sort_global<false>, dim3(g.global_blocks_wide), dim3(kThreads), 0, st, items, L,
                            kSortClassWave + kSortClassBlock + 1);
     return hipGetLastError();
 }

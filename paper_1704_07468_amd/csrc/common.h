@@ -101,8 +101,9 @@ struct MaskWork {
     uint32_t *bcnt;   // [2^B]
     uint32_t *boff;   // [2^B + 1]
     uint32_t *bcur;   // [2^B]
-    uint64_t *comp;   // [T] composite (hash rest, sequence) of each bucketed g-mer
-    uint32_t *idx;    // [T] its g-mer index
+    uint64_t *comp;   // [T] composite (hash rest, sequence) of each bucketed g-mer; when it
+                      // fits 32 bits, packed with its g-mer index: composite << 32 | index
+    uint32_t *idx;    // [T] g-mer index of a wide composite
     uint64_t *comp2;  // [T] ping-pong buffers for buckets sorted in global memory
     uint32_t *idx2;   // [T]
     uint32_t *E;      // [T] run entries: sequence | count << sb, grouped, sequence-sorted
@@ -248,8 +249,8 @@ struct SortScratch {
 
 constexpr int kE = 4;  // elements per thread per round of the radix passes and the segmentation
 
-// Stable LSD radix sort of n (key, value) pairs by the low `bits` bits of the
-// key, 8 bits per pass, ping-ponging between (k0,v0) and (k1,v1).  A pass is
+// Stable LSD radix sort of n (key, value) pairs by key bits [shift0,
+// shift0 + bits), 8 bits per pass, ping-ponging between (k0,v0) and (k1,v1).  A pass is
 // an LDS digit histogram, a block scan of it, and rounds of 1024 elements: in
 // each round every wave ranks 4 consecutive groups of 64 elements by digit
 // with ballots -- the lanes holding the same digit form a ballot mask, a
@@ -260,11 +261,11 @@ constexpr int kE = 4;  // elements per thread per round of the radix passes and 
 // skipped.  `which` says where the data is on entry (0: k0/v0) and is updated.
 template <typename K, typename KP, typename VP>
 __device__ __forceinline__ void block_radix_sort(KP k0, VP v0, KP k1, VP v1, uint32_t n, int bits,
-                                                 SortScratch &s, int &which)
+                                                 SortScratch &s, int &which, int shift0 = 0)
 {
     const int tid = threadIdx.x, wid = tid >> 6, lane = __lane_id();
     const uint64_t lt = lanemask_lt();
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = shift0; shift < shift0 + bits; shift += 8) {
         KP sk = which ? k1 : k0;
         VP sv = which ? v1 : v0;
         KP dk = which ? k0 : k1;
@@ -358,8 +359,12 @@ __device__ __forceinline__ uint32_t last_le(UP a, uint32_t n, uint32_t v)
 // diagonal counter (the self-pairs of Algorithm 1's countAndUpdate).
 template <typename KP, typename VP, typename UP>
 __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos, UP gsr, UP gaux,
-                                              const MaskWork &W, uint32_t ebase, uint32_t *wsum, uint32_t bucket)
+                                              const MaskWork &W, uint32_t ebase, uint32_t *wsum, uint32_t bucket,
+                                              int cshift)
 {
+    // cshift = 32: fk holds packed words (composite << 32 | g-mer index)
+    auto comp = [&](uint32_t i) -> uint64_t { return (uint64_t)fk[i] >> cshift; };
+    auto gidx = [&](uint32_t i) -> uint32_t { return cshift ? (uint32_t)(uint64_t)fk[i] : (uint32_t)fv[i]; };
     const int tid = threadIdx.x;
     const int sb = W.sb;
     const uint64_t sidmask = bits_mask(sb);
@@ -367,12 +372,12 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
     for (uint32_t r0 = 0; r0 < n; r0 += kThreads * kE) {
         const uint32_t i0 = r0 + (uint32_t)tid * kE;
         uint32_t rsf = 0, gsf = 0;  // bit e: element i0+e starts a run / a group
-        uint64_t prev = (i0 > 0 && i0 <= n) ? (uint64_t)fk[i0 - 1] : 0ull;
+        uint64_t prev = (i0 > 0 && i0 <= n) ? comp(i0 - 1) : 0ull;
 #pragma unroll
         for (int e = 0; e < kE; ++e) {
             const uint32_t i = i0 + e;
             if (i < n) {
-                const uint64_t cur = (uint64_t)fk[i];
+                const uint64_t cur = comp(i);
                 if (i == 0 || cur != prev) rsf |= 1u << e;
                 if (i == 0 || (cur >> sb) != (prev >> sb)) gsf |= 1u << e;
                 prev = cur;
@@ -414,7 +419,7 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         const uint32_t p = rpos[r];
         const uint32_t pe = (r + 1 < R) ? rpos[r + 1] : n;
         const uint32_t cnt = pe - p;
-        const uint32_t sid = (uint32_t)((uint64_t)fk[p] & sidmask);
+        const uint32_t sid = (uint32_t)(comp(p) & sidmask);
         const uint32_t gi = last_le(gsr, G, r);
         const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
         const uint32_t e = ebase + r;
@@ -431,18 +436,18 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         if (W.inl && len == 2) {  // the group's last run, inline
             const uint32_t p1 = rpos[r + 1];
             const uint32_t c1 = ((r + 2 < R) ? rpos[r + 2] : n) - p1;
-            x = (uint32_t)((uint64_t)fk[p1] & sidmask) | (c1 << sb);
+            x = (uint32_t)(comp(p1) & sidmask) | (c1 << sb);
         }
         // y: entries to the group end in the low sb+1 bits, the run count above
-        W.info[fv[p]] = make_uint2(x, len ? (len | (cnt << (sb + 1))) : 0u);
+        W.info[gidx(p)] = make_uint2(x, len ? (len | (cnt << (sb + 1))) : 0u);
     }
     for (uint32_t i = tid; i < n; i += kThreads)
-        if (i > 0 && fk[i] == fk[i - 1]) W.info[fv[i]] = make_uint2(0u, 0u);
+        if (i > 0 && comp(i) == comp(i - 1)) W.info[gidx(i)] = make_uint2(0u, 0u);
     if (W.gtab) {
         for (uint32_t gi = tid; gi < G; gi += kThreads) {
             const uint32_t r0 = gsr[gi];
             const uint32_t r1 = (gi + 1 < G) ? gsr[gi + 1] : R;
-            const uint64_t hr = (uint64_t)fk[rpos[r0]] >> sb;
+            const uint64_t hr = comp(rpos[r0]) >> sb;
             W.gtab[ebase + gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ebase + r0, ebase + r1);
         }
         if (tid == 0) W.bgrp[bucket] = G;
@@ -451,7 +456,7 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         for (uint32_t r = tid; r < R; r += kThreads) {
             const uint32_t p = rpos[r];
             const uint32_t cnt = ((r + 1 < R) ? rpos[r + 1] : n) - p;
-            atomicAdd(&W.diag[(uint32_t)((uint64_t)fk[p] & sidmask)], cnt * cnt);
+            atomicAdd(&W.diag[(uint32_t)(comp(p) & sidmask)], cnt * cnt);
         }
     }
 }

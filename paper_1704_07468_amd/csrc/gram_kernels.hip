@@ -81,9 +81,10 @@ __global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__res
 }
 
 // ------------------------------------------------------- bucket scatter --
-// Place (composite, g-mer index) of every g-mer into its bucket; composites
-// of at most 32 bits are stored as 32-bit words.  The order inside a bucket
-// is arbitrary; the bucket sort restores it.
+// Place (composite, g-mer index) of every g-mer into its bucket: composites
+// of at most 32 bits as one packed word composite << 32 | index, wider ones
+// in the composite array with the index beside it.  The order inside a
+// bucket is arbitrary; the bucket sort restores it.
 __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
                                                              int nitems, uint32_t uniform)
 {
@@ -123,9 +124,13 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
     for (int q = 0; q < Q; ++q) {
         if (bk[q] != 0xFFFFFFFFu) {
             const uint32_t pos = hist[bk[q]] + rk[q];
-            if (narrow) reinterpret_cast<uint32_t *>(W.comp)[pos] = (uint32_t)cp[q];
-            else W.comp[pos] = cp[q];
-            W.idx[pos] = t0 + q * kThreads + threadIdx.x;
+            const uint32_t t = t0 + q * kThreads + threadIdx.x;
+            if (narrow) {
+                W.comp[pos] = (cp[q] << 32) | t;
+            } else {
+                W.comp[pos] = cp[q];
+                W.idx[pos] = t;
+            }
         }
     }
 }
