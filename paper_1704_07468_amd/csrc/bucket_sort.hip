@@ -424,24 +424,26 @@ __device__ __forceinline__ uint32_t cand_slot(const SegLds<NWORDS, NSLOT> &S, ui
 }
 
 // Runs and groups of one sorted bucket in LDS (kb: packed words or
-// composites, vb: indices of wide ones), segmented by NW waves.  Writes one
-// run entry (sequence | count << sb) per run at E[base + run], so each
-// group's entries are contiguous and sequence-sorted; per g-mer its info --
-// for the first g-mer of a run (entry index, runs to the group end | count <<
-// (sb+1)), for the others (0, 0); with W.inl a run two entries from its group
-// end carries that last entry (sequence | count << sb) instead of its index.  Groups with at least tau runs and every
-// count <= 127 become rows of the int8 count matrix instead (info length 0),
-// as far as NSLOT candidate groups per bucket (otherwise all of the bucket's
-// groups stay on the exact sparse path).  With gtab, lists the groups (hash
-// rest, first entry, end entry); with diag, adds count^2 per run to its
-// sequence's diagonal counter.
+// composites, vb: indices of wide ones), segmented by the NW waves of its
+// group (wave = the wave's index in the group).  Writes one run entry
+// (sequence | count << sb) per run at E[base + run], so each group's entries
+// are contiguous and sequence-sorted; per g-mer its info -- for the first
+// g-mer of a run (entry index, runs to the group end | count << (sb+1)), for
+// the others (0, 0); with W.inl a run two entries from its group end carries
+// that last entry (sequence | count << sb) instead of its index.  Groups with
+// at least tau runs and every count <= 127 become rows of the int8 count
+// matrix instead (info length 0), as far as NSLOT candidate groups per bucket
+// (otherwise all of the bucket's groups stay on the exact sparse path).  With
+// gtab, lists the groups (hash rest, first entry, end entry); with diag, adds
+// count^2 per run to its sequence's diagonal counter.  n = 0 does nothing but
+// takes part in the barriers: every barrier is reached by every wave of the
+// block, whatever its bucket.
 template <bool PK, int NW, int NWORDS, int NSLOT>
 __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint32_t base, uint32_t n, const uint64_t *kb,
-                                        const uint32_t *vb, SegLds<NWORDS, NSLOT> &S)
+                                        const uint32_t *vb, SegLds<NWORDS, NSLOT> &S, int wave)
 {
     constexpr int NT = NW * 64;
     const int lane = __lane_id();
-    const int wave = NW > 1 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     const int tid = wave * 64 + lane;
     const int sb = W.sb;
     const uint64_t sidmask = bits_mask(sb);
@@ -471,8 +473,8 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     seg_sync<NW>();
     const uint32_t R = S.rpre[nwords], G = S.gpre[nwords];
     // count-matrix candidates: groups with at least tau runs
-    bool dense = false;
-    if (W.tau > 0 && W.D != nullptr) {
+    const bool dense_on = n > 0 && W.tau > 0 && W.D != nullptr;
+    if (dense_on) {
 #pragma unroll 1
         for (int w = wave; w < nwords; w += NW) {
             const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
@@ -481,35 +483,36 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
             const uint64_t cb = __ballot(c);
             if (lane == 0) S.cbm[w] = cb;
         }
-        seg_sync<NW>();
-        if (wave == 0) scan_cand<NWORDS, NSLOT>(S, nwords);
-        seg_sync<NW>();
-        const uint32_t ncand = S.cpre[nwords];
-        dense = ncand > 0 && ncand <= (uint32_t)NSLOT;
-        if (dense) {
-            for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) S.slot[s] = 0;
-            seg_sync<NW>();
-            // largest count of each candidate group
+    }
+    seg_sync<NW>();
+    if (dense_on && wave == 0) scan_cand<NWORDS, NSLOT>(S, nwords);
+    seg_sync<NW>();
+    const uint32_t ncand = dense_on ? S.cpre[nwords] : 0u;
+    const bool dense = ncand > 0 && ncand <= (uint32_t)NSLOT;
+    if (dense)
+        for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) S.slot[s] = 0;
+    seg_sync<NW>();
+    if (dense) {  // largest count of each candidate group
 #pragma unroll 1
-            for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
-                if (bit_at(S.rbm, i)) {
-                    const RunAt a = run_at<NWORDS, NSLOT>(S, (int)(i >> 6), (int)(i & 63), i, n, R);
-                    if (a.gs < n && bit_at(S.cbm, a.gs)) atomicMax(&S.slot[cand_slot(S, a.gs)], a.cnt);
-                }
+        for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
+            if (bit_at(S.rbm, i)) {
+                const RunAt a = run_at<NWORDS, NSLOT>(S, (int)(i >> 6), (int)(i & 63), i, n, R);
+                if (a.gs < n && bit_at(S.cbm, a.gs)) atomicMax(&S.slot[cand_slot(S, a.gs)], a.cnt);
             }
-            seg_sync<NW>();
-            // candidates whose counts all fit int8 take a count-matrix row
-            for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) {
-                uint32_t row = 0xFFFFFFFFu;
-                if (S.slot[s] <= 127u) {
-                    row = atomicAdd(W.dcount, 1u);
-                    if (row >= W.dcap) row = 0xFFFFFFFFu;
-                }
-                S.slot[s] = row;
-            }
-            seg_sync<NW>();
         }
     }
+    seg_sync<NW>();
+    if (dense) {  // candidates whose counts all fit int8 take a count-matrix row
+        for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) {
+            uint32_t row = 0xFFFFFFFFu;
+            if (S.slot[s] <= 127u) {
+                row = atomicAdd(W.dcount, 1u);
+                if (row >= W.dcap) row = 0xFFFFFFFFu;
+            }
+            S.slot[s] = row;
+        }
+    }
+    seg_sync<NW>();
 #pragma unroll 1
     for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
         const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
@@ -542,7 +545,7 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
             W.gtab[base + a.gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ei, ei + a.len);
         }
     }
-    if (W.gtab && tid == 0) W.bgrp[bucket] = G;
+    if (W.gtab && n > 0 && tid == 0) W.bgrp[bucket] = G;
 }
 
 // Load a bucket's (composite, index) pairs into registers, padding with the
@@ -604,7 +607,7 @@ __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, 
         store_sorted<PK, EL>(key, val, 0, n, lds.kb, vb);
     }
     wave_sync();
-    segment<PK, 1, kWaveWords, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S);
+    segment<PK, 1, kWaveWords, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S, 0);
     wave_sync();
 }
 
@@ -651,51 +654,77 @@ __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restri
 }
 
 // ------------------------------------------------------ block kernel --
+// A 1024-thread block sorts G = 16 / NW buckets of one class side by side:
+// each group of NW waves holds one bucket, 64 * EL elements per wave (EL = 16
+// packed, 8 wide), so only the merges beyond one wave's share go through LDS.
+// All groups run the same network and reach the same barriers.
 constexpr int kSortBlockThreads = 1024;
 constexpr int kSortBlockWaves = kSortBlockThreads / 64;
-constexpr int kBlockWords = kSortBlockMaxPk / 64;
-constexpr int kBlockSlots = 1024;
+constexpr int kBlockSlots = 1024;  // count-matrix candidate slots per block
+
+template <int NWORDS, int NSLOT>
+constexpr size_t seg_bytes() { return sizeof(SegLds<NWORDS, NSLOT>); }
 
 struct BlockLds {
-    uint64_t buf[kSortBlockMaxPk];  // exchange buffer, then the sorted bucket
-    SegLds<kBlockWords, kBlockSlots> S;
+    uint64_t buf[kSortBlockMaxPk];  // exchange buffers, then the sorted buckets
+    // per-group segmentation scratch (largest: 8 groups of 32 words)
+    uint64_t seg[(8 * seg_bytes<32, kBlockSlots / 8>() + 7) / 8];
 };
 
-template <bool PK, int EL>
-__device__ __forceinline__ void block_bucket(const MaskWork &W, uint32_t bucket, BlockLds &lds)
+template <bool PK, int NW>
+__device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items, const uint32_t *ents, int nb, BlockLds &lds)
 {
+    constexpr int EL = PK ? 16 : 8;
+    constexpr int NP = NW * 64 * EL;
+    constexpr int G = kSortBlockWaves / NW;
+    constexpr int NWORDS = NP / 64;
+    constexpr int NSLOT = kBlockSlots / G;
+    using Seg = SegLds<NWORDS, NSLOT>;
+    static_assert(sizeof(Seg) * G <= sizeof(lds.seg), "segmentation scratch");
+    static_assert((PK ? 8 : 12) * NP * G <= (int)sizeof(lds.buf), "exchange buffers");
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const uint32_t base = W.boff[bucket];
-    const uint32_t n = W.boff[bucket + 1] - base;
-    // n is uniform over the block: every thread returns or none
-    if (n == 0 || n > (uint32_t)kSortBlockThreads * EL) return;
-    uint32_t *vb = reinterpret_cast<uint32_t *>(lds.buf + kSortBlockMaxWide);
+    const int gi = wave / NW, wg = wave % NW;
+    // this group's bucket (none: n = 0, the first bucket's mask stands in)
+    const uint32_t ent = ents[gi < nb ? gi : 0];
+    const MaskWork &W = items[ent >> 12];
+    const uint32_t bucket = ent & 4095u;
+    uint32_t base = 0, n = 0;
+    if (gi < nb && bucket < (1u << W.B)) {
+        base = W.boff[bucket];
+        n = min(W.boff[bucket + 1] - base, (uint32_t)NP);
+    }
+    uint64_t *kb = lds.buf + (size_t)gi * NP;
+    uint32_t *vb = reinterpret_cast<uint32_t *>(lds.buf + (size_t)G * NP) + (size_t)gi * NP;  // wide only
+    Seg &S = *reinterpret_cast<Seg *>(reinterpret_cast<char *>(lds.seg) + (size_t)gi * sizeof(Seg));
     {
         uint64_t key[EL];
         uint32_t val[EL];
-        const uint32_t ibase = (uint32_t)wave * 64u * EL;
+        const uint32_t ibase = (uint32_t)wg * 64u * EL;
         load_bucket<PK, EL>(W, base, n, ibase, key, val);
-        bitonic_sort<PK, EL, kSortBlockWaves>(key, val, lds.buf, vb, wave);
+        bitonic_sort<PK, EL, NW>(key, val, kb, vb, wg);
         __syncthreads();  // the last exchange reads are done
-        store_sorted<PK, EL>(key, val, ibase, n, lds.buf, vb);
+        store_sorted<PK, EL>(key, val, ibase, n, kb, vb);
     }
     __syncthreads();
-    segment<PK, kSortBlockWaves, kBlockWords, kBlockSlots>(W, bucket, base, n, lds.buf, vb, lds.S);
+    segment<PK, NW, NWORDS, NSLOT>(W, bucket, base, n, kb, vb, S, wg);
 }
 
-// Blocks take buckets of the block classes from a shared ticket counter,
-// largest class first.
+// Blocks take groups of buckets of one block class from a shared ticket
+// counter, largest class first.
 __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork *__restrict__ items, SortLists L)
 {
     __shared__ BlockLds lds;
     __shared__ uint32_t ticket;
-    // packed 16384, wide 8192, packed 8192, wide 4096, packed 4096, wide
-    // 2048, packed 2048, wide 1024 (class offsets within the block classes)
+    // class offsets within the block classes, largest first: packed 16384,
+    // wide 8192, packed 8192, wide 4096, packed 4096, wide 2048, packed 2048,
+    // wide 1024; buckets per block = 16 / waves per bucket
     constexpr int order[kSortClassBlock] = {3, 7, 2, 6, 1, 5, 0, 4};
+    constexpr int gsz[kSortClassBlock] = {1, 1, 2, 2, 4, 4, 8, 8};
     uint32_t cum[kSortClassBlock + 1];
     cum[0] = 0;
 #pragma unroll
-    for (int s = 0; s < kSortClassBlock; ++s) cum[s + 1] = cum[s] + min(L.cnt[kSortClassWave + order[s]], L.cap);
+    for (int s = 0; s < kSortClassBlock; ++s)
+        cum[s + 1] = cum[s] + (min(L.cnt[kSortClassWave + order[s]], L.cap) + gsz[s] - 1) / gsz[s];
     const uint32_t total = cum[kSortClassBlock];
     while (true) {
         if (threadIdx.x == 0) ticket = atomicAdd(&L.cnt[kSortTicketBlock], 1u);
@@ -707,25 +736,27 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
 #pragma unroll
         for (int q = 1; q < kSortClassBlock; ++q) s += (t >= cum[q]) ? 1 : 0;
         uint32_t off = 0;
-        int oc = 0;
+        int oc = 0, gs = 1;
 #pragma unroll
         for (int q = 0; q < kSortClassBlock; ++q) {
             off = (q == s) ? cum[q] : off;
             oc = (q == s) ? order[q] : oc;
+            gs = (q == s) ? gsz[q] : gs;
         }
-        const uint32_t ent = L.list[(size_t)(kSortClassWave + oc) * L.cap + (t - off)];
-        const MaskWork &W = items[ent >> 12];
-        const uint32_t bucket = ent & 4095u;
-        if (bucket >= (1u << W.B)) continue;
+        const int c = kSortClassWave + oc;
+        const uint32_t cnt = min(L.cnt[c], L.cap);
+        const uint32_t first = (t - off) * (uint32_t)gs;
+        const int nb = (int)min((uint32_t)gs, cnt - first);
+        const uint32_t *ents = L.list + (size_t)c * L.cap + first;
         switch (oc) {
-        case 0: block_bucket<true, 2>(W, bucket, lds); break;
-        case 1: block_bucket<true, 4>(W, bucket, lds); break;
-        case 2: block_bucket<true, 8>(W, bucket, lds); break;
-        case 3: block_bucket<true, 16>(W, bucket, lds); break;
-        case 4: block_bucket<false, 1>(W, bucket, lds); break;
-        case 5: block_bucket<false, 2>(W, bucket, lds); break;
-        case 6: block_bucket<false, 4>(W, bucket, lds); break;
-        default: block_bucket<false, 8>(W, bucket, lds); break;
+        case 0: block_buckets<true, 2>(items, ents, nb, lds); break;    // packed 2048
+        case 1: block_buckets<true, 4>(items, ents, nb, lds); break;    // packed 4096
+        case 2: block_buckets<true, 8>(items, ents, nb, lds); break;    // packed 8192
+        case 3: block_buckets<true, 16>(items, ents, nb, lds); break;   // packed 16384
+        case 4: block_buckets<false, 2>(items, ents, nb, lds); break;   // wide 1024
+        case 5: block_buckets<false, 4>(items, ents, nb, lds); break;   // wide 2048
+        case 6: block_buckets<false, 8>(items, ents, nb, lds); break;   // wide 4096
+        default: block_buckets<false, 16>(items, ents, nb, lds); break; // wide 8192
         }
         __syncthreads();
     }
