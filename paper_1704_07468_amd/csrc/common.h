@@ -160,11 +160,14 @@ __device__ __forceinline__ uint64_t compact_key(uint64_t key, const MaskDesc &md
     return r;
 }
 
-// Rows [r0, r1) of split s of S when R rows are used (splits of whole
-// 64-row steps).
+// Rows [r0, r1) of split s of at most S when R rows are used: whole 64-row
+// steps, at least kDenseMinSplitRows rows per split, so that a level with
+// few rows writes (and its epilogue reads) few partial tiles.
+constexpr uint32_t kDenseMinSplitRows = 8192;
 __device__ __forceinline__ void split_range(uint32_t R, int S, int s, uint32_t &r0, uint32_t &r1)
 {
-    const uint32_t per = ((R + S - 1) / S + kDenseK - 1) / kDenseK * kDenseK;
+    const uint32_t used = max(1u, min((uint32_t)S, (R + kDenseMinSplitRows - 1) / kDenseMinSplitRows));
+    const uint32_t per = ((R + used - 1) / used + kDenseK - 1) / kDenseK * kDenseK;
     r0 = min(R, per * (uint32_t)s);
     r1 = min(R, r0 + per);
 }
@@ -183,13 +186,20 @@ __device__ __forceinline__ int dense_splits_used(const DenseRef &D)
     return ns;
 }
 
+// Offset of element (x, y) (tile-local, 0..127) in a 128 x 128 partial tile
+// stored as sixteen contiguous 32 x 32 sub-tiles, the epilogue's tile.
+__device__ __forceinline__ uint32_t dense_tile_offset(int x, int y)
+{
+    return (uint32_t)(((x >> 5) * 4 + (y >> 5)) * 1024 + (x & 31) * 32 + (y & 31));
+}
+
 // The int8-path part of C_m[x][y] (x <= y): the sum of the used splits'
 // partial tiles.
 __device__ __forceinline__ int64_t dense_part(const DenseRef &D, int ns, int x, int y)
 {
     const int I = x / kDenseTile, Jt = y / kDenseTile;
     const int f = I * D.ntile - (I * (I - 1)) / 2 + (Jt - I);
-    const size_t e = (size_t)(x % kDenseTile) * kDenseTile + (size_t)(y % kDenseTile);
+    const size_t e = dense_tile_offset(x % kDenseTile, y % kDenseTile);
     const int32_t *p = D.P + (size_t)f * D.S * (kDenseTile * kDenseTile) + e;
     int64_t v = 0;
 #pragma unroll

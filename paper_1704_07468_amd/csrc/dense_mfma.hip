@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int xl = xb + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            P[xl * kDTile + yb + (lane & 31)] = acc[v];
+            P[dense_tile_offset(xl, yb + (lane & 31))] = acc[v];
         }
     };
     put(acc00, wx * 64, wy * 64);
