@@ -6,13 +6,13 @@
 // reduced g-mers next to each other ("groups") and, inside a group, equal
 // sequences next to each other ("runs").  The scan kernel files every
 // non-empty bucket into a size class; then
-//   * a bucket of at most 1024 g-mers (512 with 64-bit composites) is sorted
+//   * a bucket of at most 512 g-mers (256 with 64-bit composites) is sorted
 //     by one wave, 64 * EL elements held in registers (EL per lane), by a
-//     bitonic network whose exchanges are lane permutes (DPP, ds_swizzle,
-//     ds_bpermute) or register swaps;
+//     bitonic network whose exchanges are lane permutes (DPP row operations,
+//     row / half-wave swaps) or register swaps;
 //   * a bucket of at most 16384 g-mers (8192 with 64-bit composites) is
-//     sorted by one block of 16 waves the same way, with the exchanges
-//     between waves going through LDS;
+//     sorted the same way by 1, 2, .., 16 waves of a 1024-thread block, 1024
+//     (512) elements a wave, the exchanges between waves going through LDS;
 //   * a larger bucket is radix-sorted by a block in global memory.
 // The sorted bucket goes to LDS and is segmented with ballot bitmaps of run
 // and group starts: prefix popcounts give each run its entry index and each
@@ -32,11 +32,12 @@ __device__ __forceinline__ int bucket_class(uint32_t n, bool pk)
     if (n == 0) return -1;
     if (n <= (pk ? kSortWaveMaxPk : kSortWaveMaxWide)) {
         const int e = max(0, ceil_log2_u(n) - 6);  // log2 of elements per lane
-        return pk ? e : 5 + e;                      // packed 0..4, wide 5..8
+        return pk ? e : 4 + e;                      // packed 0..3, wide 4..6
     }
     if (n <= (pk ? kSortBlockMaxPk : kSortBlockMaxWide)) {
-        const int e = ceil_log2_u(n) - 10;          // packed 1..4, wide 0..3
-        return kSortClassWave + (pk ? e - 1 : 4 + e);
+        // log2 of waves per bucket (1024 packed / 512 wide elements a wave)
+        const int e = ceil_log2_u(n) - (pk ? 10 : 9);  // 0..4
+        return kSortClassWave + (pk ? e : 5 + e);
     }
     return kSortClassWave + kSortClassBlock + (pk ? 0 : 1);
 }
@@ -54,24 +55,26 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
     const uint32_t nb = 1u << W.B;
     const uint32_t per = (nb + kThreads - 1) / kThreads;
     const uint32_t b0 = threadIdx.x * per;
+    const gptr<uint32_t> bcnt = glb(W.bcnt), boff = glb(W.boff), bcur = glb(W.bcur);
+    const gptr<uint32_t> lcnt = glb(L.cnt), list = glb(L.list);
     uint32_t loc = 0;
     for (uint32_t i = 0; i < per; ++i)
-        if (b0 + i < nb) loc += W.bcnt[b0 + i];
+        if (b0 + i < nb) loc += bcnt[b0 + i];
     uint32_t tot;
     uint32_t run = block_excl_scan(loc, wsum, &tot);
     for (uint32_t i = 0; i < per; ++i)
         if (b0 + i < nb) {
-            W.boff[b0 + i] = run;
-            W.bcur[b0 + i] = run;
-            run += W.bcnt[b0 + i];
+            boff[b0 + i] = run;
+            bcur[b0 + i] = run;
+            run += bcnt[b0 + i];
         }
-    if (threadIdx.x == 0) W.boff[nb] = tot;
+    if (threadIdx.x == 0) boff[nb] = tot;
     if (threadIdx.x < kSortClasses) ccnt[threadIdx.x] = 0;
     if (threadIdx.x < 6) gsum[threadIdx.x] = 0;
     __syncthreads();
     const bool pk = W.cb <= 32;
     for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        const uint32_t n = W.bcnt[b];
+        const uint32_t n = bcnt[b];
         const int c = bucket_class(n, pk);
         if (c >= 0) {
             atomicAdd(&ccnt[c], 1u);
@@ -80,47 +83,65 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
                 atomicAdd(&gsum[kind * 2 + (pk ? 0 : 1)], n);
             }
         } else if (W.gtab) {
-            W.bgrp[b] = 0;
+            glb(W.bgrp)[b] = 0;
         }
     }
     __syncthreads();
-    if (L.stat && threadIdx.x < 6 && gsum[threadIdx.x]) atomicAdd(&L.stat[threadIdx.x], (unsigned long long)gsum[threadIdx.x]);
+    if (L.stat && threadIdx.x < 6 && gsum[threadIdx.x])
+        g_atomic_add(glb(L.stat) + threadIdx.x, (unsigned long long)gsum[threadIdx.x]);
     if (threadIdx.x < kSortClasses) {
         const uint32_t c = ccnt[threadIdx.x];
-        cbase[threadIdx.x] = c ? atomicAdd(&L.cnt[threadIdx.x], c) : 0u;
+        cbase[threadIdx.x] = c ? g_atomic_add(lcnt + threadIdx.x, c) : 0u;
         ccnt[threadIdx.x] = 0;
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
-        const int c = bucket_class(W.bcnt[b], pk);
+        const int c = bucket_class(bcnt[b], pk);
         if (c >= 0) {
             const uint32_t pos = cbase[c] + atomicAdd(&ccnt[c], 1u);
-            if (pos < L.cap) L.list[(size_t)c * L.cap + pos] = ((uint32_t)q << 12) | b;
+            if (pos < L.cap) list[(size_t)c * L.cap + pos] = ((uint32_t)q << 12) | b;
         }
     }
 }
 
 // ------------------------------------------------------ bitonic network --
-// Value of lane (lane ^ J) of the wave.
+// The two values of the pair {i, i ^ J} that lane i belongs to (J < 64), all
+// VALU: DPP quad permutes (J = 1, 2), DPP row rotations (J = 4: by 12 for the
+// lanes with bit 2 clear, by 4 for the others; J = 8: by 8), and the gfx950
+// row / half-wave swaps (J = 16, 32), which return the lower-index value
+// first.  Order within the pair does not matter to the caller.
 template <int J>
-__device__ __forceinline__ uint32_t lane_xor(uint32_t x)
+__device__ __forceinline__ void lane_pair(uint32_t x, uint32_t &a, uint32_t &b)
 {
-    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
-    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | (J << 10));  // bitmask mode: xor J
-    else return (uint32_t)__builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32) << 2), (int)x);
-}
-template <int J>
-__device__ __forceinline__ uint64_t lane_xor64(uint64_t x)
-{
-    return ((uint64_t)lane_xor<J>((uint32_t)(x >> 32)) << 32) | lane_xor<J>((uint32_t)x);
+    if constexpr (J == 1) {
+        a = x;
+        b = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    } else if constexpr (J == 2) {
+        a = x;
+        b = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    } else if constexpr (J == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x12C, 0xF, 0xF, false);  // row_ror:12
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x124, 0xF, 0xF, false);  // row_ror:4
+        a = x;
+        b = (__lane_id() & 4) ? dn : up;
+    } else if constexpr (J == 8) {
+        a = x;
+        b = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else if constexpr (J == 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        a = p[0];
+        b = p[1];
+    } else {
+        const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        a = p[0];
+        b = p[1];
+    }
 }
 
 // Element order: packed words compare as integers; wide ones by composite,
 // then g-mer index.  Real elements are pairwise distinct (distinct indices)
 // and the padding (all ones, index 0xFFFFFFFF, which no g-mer has) is
-// strictly above them, so an exchange needs one comparison: with y_lt =
-// (partner < own), the partner is taken when y_lt != keep_max.
+// strictly above them, so one comparison decides a pair.
 template <bool PK>
 __device__ __forceinline__ bool el_less(uint64_t ak, uint32_t av, uint64_t bk, uint32_t bv)
 {
@@ -128,18 +149,21 @@ __device__ __forceinline__ bool el_less(uint64_t ak, uint32_t av, uint64_t bk, u
     else return (ak < bk) | ((ak == bk) & (av < bv));
 }
 
-// Exchange with the lane at distance J < 64.  keep_max: this lane keeps the
+// Exchange within the pair at distance J < 64.  keep_max: this lane keeps the
 // larger element of its pair (the high end of an ascending pair or the low
 // end of a descending one).
 template <bool PK, int J>
 __device__ __forceinline__ void exchange_lanes(uint64_t &key, uint32_t &val, bool keep_max)
 {
-    const uint64_t yk = lane_xor64<J>(key);
-    uint32_t yv = 0;
-    if constexpr (!PK) yv = lane_xor<J>(val);
-    const bool take = el_less<PK>(yk, yv, key, val) != keep_max;
-    key = take ? yk : key;
-    if constexpr (!PK) val = take ? yv : val;
+    uint32_t ah, bh, al, bl;
+    lane_pair<J>((uint32_t)(key >> 32), ah, bh);
+    lane_pair<J>((uint32_t)key, al, bl);
+    const uint64_t ak = ((uint64_t)ah << 32) | al, bk = ((uint64_t)bh << 32) | bl;
+    uint32_t av = 0, bv = 0;
+    if constexpr (!PK) lane_pair<J>(val, av, bv);
+    const bool take_a = el_less<PK>(ak, av, bk, bv) != keep_max;
+    key = take_a ? ak : bk;
+    if constexpr (!PK) val = take_a ? av : bv;
 }
 
 // Stage of distance J < 64 for every register e; element index i = ibase +
@@ -415,6 +439,59 @@ __device__ __forceinline__ RunAt run_at(const SegLds<NWORDS, NSLOT> &S, int w, i
 
 __device__ __forceinline__ bool bit_at(const uint64_t *bm, uint32_t i) { return (bm[i >> 6] >> (i & 63)) & 1ull; }
 
+// The tables of word w, read once by the wave (w is wave-uniform) and kept
+// in scalar registers.
+struct WordAt {
+    uint64_t rb, gb;
+    uint32_t rpre, gpre, nextr1, nextg1, prevg;
+};
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x)
+{
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+}
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
+template <int NWORDS, int NSLOT>
+__device__ __forceinline__ WordAt word_at(const SegLds<NWORDS, NSLOT> &S, int w)
+{
+    WordAt u;
+    u.rb = uniform64(S.rbm[w]);
+    u.gb = uniform64(S.gbm[w]);
+    u.rpre = uniform32(S.rpre[w]);
+    u.gpre = uniform32(S.gpre[w]);
+    u.nextr1 = uniform32(S.nextr[w + 1]);
+    u.nextg1 = uniform32(S.nextg[w + 1]);
+    u.prevg = uniform32(S.prevg[w]);
+    return u;
+}
+
+// run_at with the word's tables already at hand.
+template <int NWORDS, int NSLOT>
+__device__ __forceinline__ RunAt run_at_w(const SegLds<NWORDS, NSLOT> &S, const WordAt &u, int w, int b, uint32_t i,
+                                          uint32_t n, uint32_t R)
+{
+    const uint64_t le = (b == 63) ? ~0ull : ((2ull << b) - 1ull);
+    const uint64_t gt = ~le;
+    RunAt a;
+    a.r = u.rpre + (uint32_t)__popcll(u.rb & (le >> 1));
+    const uint64_t mr = u.rb & gt, mg = u.gb & gt, ml = u.gb & le;
+    const uint32_t end = mr ? first_bit(w, mr) : u.nextr1;
+    const uint32_t gend = mg ? first_bit(w, mg) : u.nextg1;
+    a.cnt = end - i;
+    uint32_t rend = R;
+    if (gend < n) {
+        const int gw = (int)(gend >> 6);
+        rend = S.rpre[gw] + (uint32_t)__popcll(S.rbm[gw] & ((1ull << (gend & 63)) - 1ull));
+    }
+    a.len = rend - a.r;
+    a.gi = u.gpre + (uint32_t)__popcll(ml) - 1u;
+    a.gs = ml ? (uint32_t)last_bit(w, ml) : u.prevg;
+    a.gend = gend;
+    return a;
+}
+
 // Candidate slot of the group starting at position gs (a set bit of cbm).
 template <int NWORDS, int NSLOT>
 __device__ __forceinline__ uint32_t cand_slot(const SegLds<NWORDS, NSLOT> &S, uint32_t gs)
@@ -445,7 +522,18 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     constexpr int NT = NW * 64;
     const int lane = __lane_id();
     const int tid = wave * 64 + lane;
+    // the mask's fields, read once: stores through its pointers could
+    // otherwise alias the descriptor and force reloads after every store
     const int sb = W.sb;
+    const gptr<uint32_t> E = glb(W.E);
+    const gptr<uint2> info = glb(W.info);
+    const gptr<int8_t> D = glb(W.D);
+    const gptr<uint32_t> dcount = glb(W.dcount);
+    const gptr<uint32_t> diag = glb(W.diag);
+    const gptr<uint4> gtab = glb(W.gtab);
+    const gptr<uint32_t> bgrp = glb(W.bgrp);
+    const uint32_t T = W.T, Nseq = (uint32_t)W.N, dcap = W.dcap, dstride = W.dstride;
+    const int tau = W.tau, inl = W.inl;
     const uint64_t sidmask = bits_mask(sb);
     const int nwords = (int)((n + 63) >> 6);
     auto comp_at = [&](uint32_t i) -> uint64_t { return PK ? (kb[i] >> 32) : kb[i]; };
@@ -473,13 +561,14 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     seg_sync<NW>();
     const uint32_t R = S.rpre[nwords], G = S.gpre[nwords];
     // count-matrix candidates: groups with at least tau runs
-    const bool dense_on = n > 0 && W.tau > 0 && W.D != nullptr;
+    const bool dense_on = n > 0 && tau > 0 && D != nullptr;
     if (dense_on) {
-#pragma unroll 1
+#pragma unroll 2
         for (int w = wave; w < nwords; w += NW) {
             const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
+            const WordAt u = word_at(S, w);
             bool c = false;
-            if (i < n && bit_at(S.gbm, i)) c = run_at<NWORDS, NSLOT>(S, w, lane, i, n, R).len >= (uint32_t)W.tau;
+            if (i < n && ((u.gb >> lane) & 1ull)) c = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R).len >= (uint32_t)tau;
             const uint64_t cb = __ballot(c);
             if (lane == 0) S.cbm[w] = cb;
         }
@@ -493,10 +582,12 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
         for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) S.slot[s] = 0;
     seg_sync<NW>();
     if (dense) {  // largest count of each candidate group
-#pragma unroll 1
-        for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
-            if (bit_at(S.rbm, i)) {
-                const RunAt a = run_at<NWORDS, NSLOT>(S, (int)(i >> 6), (int)(i & 63), i, n, R);
+#pragma unroll 2
+        for (int w = wave; w < nwords; w += NW) {
+            const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
+            const WordAt u = word_at(S, w);
+            if (i < n && ((u.rb >> lane) & 1ull)) {
+                const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
                 if (a.gs < n && bit_at(S.cbm, a.gs)) atomicMax(&S.slot[cand_slot(S, a.gs)], a.cnt);
             }
         }
@@ -506,46 +597,49 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
         for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) {
             uint32_t row = 0xFFFFFFFFu;
             if (S.slot[s] <= 127u) {
-                row = atomicAdd(W.dcount, 1u);
-                if (row >= W.dcap) row = 0xFFFFFFFFu;
+                row = g_atomic_add(dcount, 1u);
+                if (row >= dcap) row = 0xFFFFFFFFu;
             }
             S.slot[s] = row;
         }
     }
     seg_sync<NW>();
-#pragma unroll 1
-    for (uint32_t i = (uint32_t)tid; i < n; i += NT) {
+#pragma unroll 2
+    for (int w = wave; w < nwords; w += NW) {
+        const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
+        const WordAt u = word_at(S, w);
+        if (i >= n) continue;
         const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
-        if (!bit_at(S.rbm, i)) {
-            if (idx < W.T) W.info[idx] = make_uint2(0u, 0u);
+        if (!((u.rb >> lane) & 1ull)) {
+            if (idx < T) st_u2(info, idx, 0u, 0u);
             continue;
         }
-        const RunAt a = run_at<NWORDS, NSLOT>(S, (int)(i >> 6), (int)(i & 63), i, n, R);
+        const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
         const uint64_t c = comp_at(i);
         const uint32_t sid = (uint32_t)(c & sidmask);
         const uint32_t ei = base + a.r;
-        W.E[ei] = sid | (a.cnt << sb);
+        E[ei] = sid | (a.cnt << sb);
         uint32_t y = a.len | (a.cnt << (sb + 1));
         if (dense && a.gs < n && bit_at(S.cbm, a.gs)) {
             const uint32_t row = S.slot[cand_slot(S, a.gs)];
             if (row != 0xFFFFFFFFu) {
-                if (sid < (uint32_t)W.N && row < W.dcap) W.D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)a.cnt;
+                if (sid < Nseq && row < dcap) D[(size_t)sid * (size_t)dstride + row] = (int8_t)a.cnt;
                 y = 0;
             }
         }
         uint32_t x = ei;
-        if (W.inl && y != 0 && a.len == 2) {  // the group's last run, inline
+        if (inl && y != 0 && a.len == 2) {  // the group's last run, inline
             const uint32_t nx = i + a.cnt;
             x = (uint32_t)(comp_at(nx) & sidmask) | ((a.gend - nx) << sb);
         }
-        if (idx < W.T) W.info[idx] = make_uint2(x, y);
-        if (W.diag && sid < (uint32_t)W.N) atomicAdd(&W.diag[sid], a.cnt * a.cnt);
-        if (W.gtab && a.gs == i) {
+        if (idx < T) st_u2(info, idx, x, y);
+        if (diag && sid < Nseq) g_atomic_add(diag + sid, a.cnt * a.cnt);
+        if (gtab && a.gs == i) {
             const uint64_t hr = c >> sb;
-            W.gtab[base + a.gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ei, ei + a.len);
+            st_u4(gtab, base + a.gi, (uint32_t)hr, (uint32_t)(hr >> 32), ei, ei + a.len);
         }
     }
-    if (W.gtab && n > 0 && tid == 0) W.bgrp[bucket] = G;
+    if (gtab && n > 0 && tid == 0) bgrp[bucket] = G;
 }
 
 // Load a bucket's (composite, index) pairs into registers, padding with the
@@ -555,14 +649,16 @@ __device__ __forceinline__ void load_bucket(const MaskWork &W, uint32_t base, ui
                                             uint32_t (&val)[EL])
 {
     const int lane = __lane_id();
+    const gptr<const uint64_t> comp = glb((const uint64_t *)W.comp);
+    const gptr<const uint32_t> gidx = glb((const uint32_t *)W.idx);
 #pragma unroll
     for (int e = 0; e < EL; ++e) {
         const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
         key[e] = ~0ull;
         val[e] = 0xFFFFFFFFu;
         if (i < n) {
-            key[e] = W.comp[base + i];  // packed: composite << 32 | index
-            if constexpr (!PK) val[e] = W.idx[base + i];
+            key[e] = comp[base + i];  // packed: composite << 32 | index
+            if constexpr (!PK) val[e] = gidx[base + i];
         }
     }
 }
@@ -585,18 +681,19 @@ __device__ __forceinline__ void store_sorted(const uint64_t (&key)[EL], const ui
 
 // ------------------------------------------------------ wave kernel --
 constexpr int kWaveWords = kSortWaveMaxPk / 64;
-constexpr int kWaveSlots = 256;
+constexpr int kWaveSlots = 128;
 
 struct WaveLds {
-    uint64_t kb[kSortWaveMaxPk];  // packed: 1024 words; wide: 512 words, then 512 indices
+    uint64_t kb[kSortWaveMaxPk];  // packed: 512 words; wide: 256 words, then 256 indices
     SegLds<kWaveWords, kWaveSlots> S;
 };
 
 template <bool PK, int EL>
 __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, WaveLds &lds)
 {
-    const uint32_t base = W.boff[bucket];
-    const uint32_t n = W.boff[bucket + 1] - base;
+    const gptr<const uint32_t> boff = glb((const uint32_t *)W.boff);
+    const uint32_t base = boff[bucket];
+    const uint32_t n = boff[bucket + 1] - base;
     if (n == 0 || n > 64u * EL) return;
     uint32_t *vb = reinterpret_cast<uint32_t *>(lds.kb + kSortWaveMaxWide);
     {
@@ -613,17 +710,18 @@ __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, 
 
 // Each wave takes the buckets of the wave classes in a fixed stride over
 // their concatenation, largest class first.
-__global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
 {
     __shared__ WaveLds lds[kWaves];
-    // packed 1024, wide 512, packed 512, wide 256, ..., packed 64 (class ids)
-    constexpr int order[kSortClassWave] = {4, 8, 3, 7, 2, 6, 1, 5, 0};
+    // packed 512, wide 256, packed 256, wide 128, ..., packed 64 (class ids)
+    constexpr int order[kSortClassWave] = {3, 6, 2, 5, 1, 4, 0};
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
     const uint32_t gw = blockIdx.x * kWaves + wid, nw = gridDim.x * kWaves;
     uint32_t cum[kSortClassWave + 1];
     cum[0] = 0;
+    const gptr<const uint32_t> lcnt = glb((const uint32_t *)L.cnt), list = glb((const uint32_t *)L.list);
 #pragma unroll
-    for (int s = 0; s < kSortClassWave; ++s) cum[s + 1] = cum[s] + min(L.cnt[order[s]], L.cap);
+    for (int s = 0; s < kSortClassWave; ++s) cum[s + 1] = cum[s] + min(lcnt[order[s]], L.cap);
     for (uint32_t t = gw; t < cum[kSortClassWave]; t += nw) {
         int s = 0;
 #pragma unroll
@@ -635,7 +733,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restri
             off = (q == s) ? cum[q] : off;
             c = (q == s) ? order[q] : c;
         }
-        const uint32_t ent = L.list[(size_t)c * L.cap + (t - off)];
+        const uint32_t ent = list[(size_t)c * L.cap + (t - off)];
         const MaskWork &W = items[ent >> 12];
         const uint32_t bucket = ent & 4095u;
         if (bucket >= (1u << W.B)) continue;
@@ -644,11 +742,9 @@ __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restri
         case 1: wave_bucket<true, 2>(W, bucket, lds[wid]); break;
         case 2: wave_bucket<true, 4>(W, bucket, lds[wid]); break;
         case 3: wave_bucket<true, 8>(W, bucket, lds[wid]); break;
-        case 4: wave_bucket<true, 16>(W, bucket, lds[wid]); break;
-        case 5: wave_bucket<false, 1>(W, bucket, lds[wid]); break;
-        case 6: wave_bucket<false, 2>(W, bucket, lds[wid]); break;
-        case 7: wave_bucket<false, 4>(W, bucket, lds[wid]); break;
-        default: wave_bucket<false, 8>(W, bucket, lds[wid]); break;
+        case 4: wave_bucket<false, 1>(W, bucket, lds[wid]); break;
+        case 5: wave_bucket<false, 2>(W, bucket, lds[wid]); break;
+        default: wave_bucket<false, 4>(W, bucket, lds[wid]); break;
         }
     }
 }
@@ -667,12 +763,12 @@ constexpr size_t seg_bytes() { return sizeof(SegLds<NWORDS, NSLOT>); }
 
 struct BlockLds {
     uint64_t buf[kSortBlockMaxPk];  // exchange buffers, then the sorted buckets
-    // per-group segmentation scratch (largest: 8 groups of 32 words)
-    uint64_t seg[(8 * seg_bytes<32, kBlockSlots / 8>() + 7) / 8];
+    // per-group segmentation scratch (largest: 16 groups of 16 words)
+    uint64_t seg[(16 * seg_bytes<16, kBlockSlots / 16>() + 7) / 8];
 };
 
 template <bool PK, int NW>
-__device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items, const uint32_t *ents, int nb, BlockLds &lds)
+__device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items, gptr<const uint32_t> ents, int nb, BlockLds &lds)
 {
     constexpr int EL = PK ? 16 : 8;
     constexpr int NP = NW * 64 * EL;
@@ -690,8 +786,9 @@ __device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items
     const uint32_t bucket = ent & 4095u;
     uint32_t base = 0, n = 0;
     if (gi < nb && bucket < (1u << W.B)) {
-        base = W.boff[bucket];
-        n = min(W.boff[bucket + 1] - base, (uint32_t)NP);
+        const gptr<const uint32_t> boff = glb((const uint32_t *)W.boff);
+        base = boff[bucket];
+        n = min(boff[bucket + 1] - base, (uint32_t)NP);
     }
     uint64_t *kb = lds.buf + (size_t)gi * NP;
     uint32_t *vb = reinterpret_cast<uint32_t *>(lds.buf + (size_t)G * NP) + (size_t)gi * NP;  // wide only
@@ -716,18 +813,19 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
     __shared__ BlockLds lds;
     __shared__ uint32_t ticket;
     // class offsets within the block classes, largest first: packed 16384,
-    // wide 8192, packed 8192, wide 4096, packed 4096, wide 2048, packed 2048,
-    // wide 1024; buckets per block = 16 / waves per bucket
-    constexpr int order[kSortClassBlock] = {3, 7, 2, 6, 1, 5, 0, 4};
-    constexpr int gsz[kSortClassBlock] = {1, 1, 2, 2, 4, 4, 8, 8};
+    // wide 8192, packed 8192, wide 4096, ..., packed 1024, wide 512; buckets
+    // per block = 16 / waves per bucket
+    constexpr int order[kSortClassBlock] = {4, 9, 3, 8, 2, 7, 1, 6, 0, 5};
+    constexpr int gsz[kSortClassBlock] = {1, 1, 2, 2, 4, 4, 8, 8, 16, 16};
     uint32_t cum[kSortClassBlock + 1];
     cum[0] = 0;
+    const gptr<uint32_t> lcnt = glb(L.cnt);
 #pragma unroll
     for (int s = 0; s < kSortClassBlock; ++s)
-        cum[s + 1] = cum[s] + (min(L.cnt[kSortClassWave + order[s]], L.cap) + gsz[s] - 1) / gsz[s];
+        cum[s + 1] = cum[s] + (min(lcnt[kSortClassWave + order[s]], L.cap) + gsz[s] - 1) / gsz[s];
     const uint32_t total = cum[kSortClassBlock];
     while (true) {
-        if (threadIdx.x == 0) ticket = atomicAdd(&L.cnt[kSortTicketBlock], 1u);
+        if (threadIdx.x == 0) ticket = g_atomic_add(lcnt + kSortTicketBlock, 1u);
         __syncthreads();
         const uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);  // block-uniform
         __syncthreads();
@@ -744,18 +842,20 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
             gs = (q == s) ? gsz[q] : gs;
         }
         const int c = kSortClassWave + oc;
-        const uint32_t cnt = min(L.cnt[c], L.cap);
+        const uint32_t cnt = min(lcnt[c], L.cap);
         const uint32_t first = (t - off) * (uint32_t)gs;
         const int nb = (int)min((uint32_t)gs, cnt - first);
-        const uint32_t *ents = L.list + (size_t)c * L.cap + first;
+        const gptr<const uint32_t> ents = glb((const uint32_t *)L.list) + (size_t)c * L.cap + first;
         switch (oc) {
-        case 0: block_buckets<true, 2>(items, ents, nb, lds); break;    // packed 2048
-        case 1: block_buckets<true, 4>(items, ents, nb, lds); break;    // packed 4096
-        case 2: block_buckets<true, 8>(items, ents, nb, lds); break;    // packed 8192
-        case 3: block_buckets<true, 16>(items, ents, nb, lds); break;   // packed 16384
-        case 4: block_buckets<false, 2>(items, ents, nb, lds); break;   // wide 1024
-        case 5: block_buckets<false, 4>(items, ents, nb, lds); break;   // wide 2048
-        case 6: block_buckets<false, 8>(items, ents, nb, lds); break;   // wide 4096
+        case 0: block_buckets<true, 1>(items, ents, nb, lds); break;    // packed 1024
+        case 1: block_buckets<true, 2>(items, ents, nb, lds); break;    // packed 2048
+        case 2: block_buckets<true, 4>(items, ents, nb, lds); break;    // packed 4096
+        case 3: block_buckets<true, 8>(items, ents, nb, lds); break;    // packed 8192
+        case 4: block_buckets<true, 16>(items, ents, nb, lds); break;   // packed 16384
+        case 5: block_buckets<false, 1>(items, ents, nb, lds); break;   // wide 512
+        case 6: block_buckets<false, 2>(items, ents, nb, lds); break;   // wide 1024
+        case 7: block_buckets<false, 4>(items, ents, nb, lds); break;   // wide 2048
+        case 8: block_buckets<false, 8>(items, ents, nb, lds); break;   // wide 4096
         default: block_buckets<false, 16>(items, ents, nb, lds); break; // wide 8192
         }
         __syncthreads();
@@ -772,23 +872,24 @@ __global__ __launch_bounds__(kThreads) void k_sort_global(const MaskWork *__rest
 {
     using K = uint64_t;
     __shared__ SortScratch ss;
-    const uint32_t cnt = min(L.cnt[cls], L.cap);
+    const uint32_t cnt = min(glb(L.cnt)[cls], L.cap);
     for (uint32_t t = blockIdx.x; t < cnt; t += gridDim.x) {
-        const uint32_t ent = L.list[(size_t)cls * L.cap + t];
+        const uint32_t ent = glb(L.list)[(size_t)cls * L.cap + t];
         const MaskWork &W = items[ent >> 12];
         const uint32_t bucket = ent & 4095u;
         if (bucket >= (1u << W.B)) continue;
-        const uint32_t base = W.boff[bucket];
-        const uint32_t n = W.boff[bucket + 1] - base;
-        K *gc = reinterpret_cast<K *>(W.comp), *gc2 = reinterpret_cast<K *>(W.comp2);
+        const uint32_t base = glb(W.boff)[bucket];
+        const uint32_t n = glb(W.boff)[bucket + 1] - base;
+        const gptr<K> gc = glb(reinterpret_cast<K *>(W.comp)), gc2 = glb(reinterpret_cast<K *>(W.comp2));
+        const gptr<uint32_t> ix = glb(W.idx), ix2 = glb(W.idx2);
         int which = 0;
         // packed words carry their index: the index arrays ride along unused
-        block_radix_sort<K>(gc + base, W.idx + base, gc2 + base, W.idx2 + base, n, W.cb, ss, which, PK ? 32 : 0);
+        block_radix_sort<K>(gc + base, ix + base, gc2 + base, ix2 + base, n, W.cb, ss, which, PK ? 32 : 0);
         __syncthreads();
-        K *fk = (which ? gc2 : gc) + base;
-        uint32_t *fv = (which ? W.idx2 : W.idx) + base;
-        uint32_t *fr = reinterpret_cast<uint32_t *>(which ? gc : gc2);
-        uint32_t *fx = (which ? W.idx : W.idx2) + base;
+        const gptr<K> fk = (which ? gc2 : gc) + base;
+        const gptr<uint32_t> fv = (which ? ix2 : ix) + base;
+        const gptr<uint32_t> fr = (gptr<uint32_t>)(which ? gc : gc2);
+        const gptr<uint32_t> fx = (which ? ix : ix2) + base;
         // scratch: this bucket's slice of the free composite array (2n words)
         block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket, PK ? 32 : 0);
         __syncthreads();

@@ -13,15 +13,15 @@ constexpr int kMaxRuns = 33;     // kept positions form at most min(g-m, m+1) <=
 constexpr int kTile = 4096;      // g-mers per block in the partition kernels
 constexpr int kMaxBucketBits = 12;
 
-// Bucket size classes of the per-bucket sort: nine wave classes (packed
-// composites 64..1024 g-mers, wide ones 64..512), eight block classes (packed
-// 2048..16384, wide 1024..8192) and two global-memory classes (packed, wide).
-constexpr uint32_t kSortWaveMaxPk = 1024;
-constexpr uint32_t kSortWaveMaxWide = 512;
+// Bucket size classes of the per-bucket sort: seven wave classes (packed
+// composites 64..512 g-mers, wide ones 64..256), ten block classes (packed
+// 1024..16384, wide 512..8192) and two global-memory classes (packed, wide).
+constexpr uint32_t kSortWaveMaxPk = 512;
+constexpr uint32_t kSortWaveMaxWide = 256;
 constexpr uint32_t kSortBlockMaxPk = 16384;
 constexpr uint32_t kSortBlockMaxWide = 8192;
-constexpr int kSortClassWave = 9;
-constexpr int kSortClassBlock = 8;
+constexpr int kSortClassWave = 7;
+constexpr int kSortClassBlock = 10;
 constexpr int kSortClasses = kSortClassWave + kSortClassBlock + 2;
 constexpr int kSortTicketBlock = kSortClasses;  // counter slot of the block kernel's work tickets
 constexpr int kSortCounters = 32;               // counter words per chunk
@@ -133,6 +133,36 @@ struct AccWork {
 };
 
 // --------------------------------------------------------------------------
+// Global-memory pointers.  Pointers read from descriptors are generic, and
+// generic (flat) accesses also count against the LDS counter, so every LDS
+// wait after them waits for the global access too; kernels that mix LDS work
+// with global accesses go through these.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> glb(T *p) { return (gptr<T>)p; }
+template <typename T>
+__device__ __forceinline__ T g_atomic_add(gptr<T> p, T v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// uint2 / uint4 records through global pointers (as plain words: the HIP
+// vector classes cannot be assigned in another address space)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_u2(gptr<uint2> p, size_t i, uint32_t x, uint32_t y)
+{
+    ((gptr<uint64_t>)p)[i] = ((uint64_t)y << 32) | x;
+}
+__device__ __forceinline__ uint2 ld_u2(gptr<const uint2> p, size_t i)
+{
+    const uint64_t v = ((gptr<const uint64_t>)p)[i];
+    return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+__device__ __forceinline__ void st_u4(gptr<uint4> p, size_t i, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    ((gptr<u32x4>)p)[i] = u32x4{a, b, c, d};
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
 __device__ __forceinline__ uint64_t bits_mask(int w) { return (w >= 64) ? ~0ull : ((1ull << w) - 1ull); }
@@ -375,6 +405,9 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
     // cshift = 32: fk holds packed words (composite << 32 | g-mer index)
     auto comp = [&](uint32_t i) -> uint64_t { return (uint64_t)fk[i] >> cshift; };
     auto gidx = [&](uint32_t i) -> uint32_t { return cshift ? (uint32_t)(uint64_t)fk[i] : (uint32_t)fv[i]; };
+    const gptr<uint32_t> E = glb(W.E);
+    const gptr<uint2> info = glb(W.info);
+    const gptr<int8_t> D = glb(W.D);
     const int tid = threadIdx.x;
     const int sb = W.sb;
     const uint64_t sidmask = bits_mask(sb);
@@ -411,14 +444,14 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         __syncthreads();
         for (uint32_t r = tid; r < R; r += kThreads) {
             const uint32_t pe = (r + 1 < R) ? rpos[r + 1] : n;
-            atomicMax(&gaux[last_le(gsr, G, r)], pe - rpos[r]);
+            __hip_atomic_fetch_max(&gaux[last_le(gsr, G, r)], pe - rpos[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         for (uint32_t gi = tid; gi < G; gi += kThreads) {
             const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
             uint32_t row = 0xFFFFFFFFu;
             if (re - gsr[gi] >= (uint32_t)W.tau && gaux[gi] <= 127u) {
-                row = atomicAdd(W.dcount, 1u);
+                row = g_atomic_add(glb(W.dcount), 1u);
                 if (row >= W.dcap) row = 0xFFFFFFFFu;
             }
             gaux[gi] = row;
@@ -433,12 +466,12 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         const uint32_t gi = last_le(gsr, G, r);
         const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
         const uint32_t e = ebase + r;
-        W.E[e] = sid | (cnt << sb);
+        E[e] = sid | (cnt << sb);
         uint32_t len = re - r;
         if (dense_on) {
             const uint32_t row = gaux[gi];
             if (row != 0xFFFFFFFFu) {
-                W.D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)cnt;
+                D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)cnt;
                 len = 0;
             }
         }
@@ -449,24 +482,24 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
             x = (uint32_t)(comp(p1) & sidmask) | (c1 << sb);
         }
         // y: entries to the group end in the low sb+1 bits, the run count above
-        W.info[gidx(p)] = make_uint2(x, len ? (len | (cnt << (sb + 1))) : 0u);
+        st_u2(info, gidx(p), x, len ? (len | (cnt << (sb + 1))) : 0u);
     }
     for (uint32_t i = tid; i < n; i += kThreads)
-        if (i > 0 && comp(i) == comp(i - 1)) W.info[gidx(i)] = make_uint2(0u, 0u);
+        if (i > 0 && comp(i) == comp(i - 1)) st_u2(info, gidx(i), 0u, 0u);
     if (W.gtab) {
         for (uint32_t gi = tid; gi < G; gi += kThreads) {
             const uint32_t r0 = gsr[gi];
             const uint32_t r1 = (gi + 1 < G) ? gsr[gi + 1] : R;
             const uint64_t hr = comp(rpos[r0]) >> sb;
-            W.gtab[ebase + gi] = make_uint4((uint32_t)hr, (uint32_t)(hr >> 32), ebase + r0, ebase + r1);
+            st_u4(glb(W.gtab), ebase + gi, (uint32_t)hr, (uint32_t)(hr >> 32), ebase + r0, ebase + r1);
         }
-        if (tid == 0) W.bgrp[bucket] = G;
+        if (tid == 0) glb(W.bgrp)[bucket] = G;
     }
     if (W.diag) {
         for (uint32_t r = tid; r < R; r += kThreads) {
             const uint32_t p = rpos[r];
             const uint32_t cnt = ((r + 1 < R) ? rpos[r + 1] : n) - p;
-            atomicAdd(&W.diag[(uint32_t)(comp(p) & sidmask)], cnt * cnt);
+            g_atomic_add(glb(W.diag) + (uint32_t)(comp(p) & sidmask), cnt * cnt);
         }
     }
 }

@@ -163,12 +163,13 @@ def test_gram_sort_classes_reached():
                           ("wave", "wave_wide", "block", "block_wide", "global", "global_wide")}
             print(name, seen[name], flush=True)
         assert seen["packed"]["global"] > 0
-        assert seen["wide"]["global_wide"] > 0
-        assert seen["protein"]["wave"] > 0 and seen["protein"]["wave_wide"] > 0 and seen["protein"]["block"] > 0
+        assert seen["wide"]["global_wide"] > 0 and seen["wide"]["wave_wide"] > 0
+        assert seen["protein"]["wave"] > 0 and seen["protein"]["block"] > 0 and seen["protein"]["block_wide"] > 0
     finally:
         ctx.close()
-    # larger buckets put the 64-bit composites of m=0 into the block sort (the
-    # results of this geometry are checked in test_gram_tuning_invariance)
+    # larger buckets put the 64-bit composites of m=0 into the multi-wave
+    # block classes (the results of this geometry are checked in
+    # test_gram_tuning_invariance)
     c2 = gakco.Context(0, tune={"bucket_avg": 2000})
     try:
         c2.set_param("profile", 1)
