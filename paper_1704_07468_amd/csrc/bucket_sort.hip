@@ -710,7 +710,7 @@ __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, 
 
 // Each wave takes the buckets of the wave classes in a fixed stride over
 // their concatenation, largest class first.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
+__global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
 {
     __shared__ WaveLds lds[kWaves];
     // packed 512, wide 256, packed 256, wide 128, ..., packed 64 (class ids)

@@ -230,7 +230,7 @@ __device__ __forceinline__ int64_t dense_part(const DenseRef &D, int ns, int x, 
     const int I = x / kDenseTile, Jt = y / kDenseTile;
     const int f = I * D.ntile - (I * (I - 1)) / 2 + (Jt - I);
     const size_t e = dense_tile_offset(x % kDenseTile, y % kDenseTile);
-    const int32_t *p = D.P + (size_t)f * D.S * (kDenseTile * kDenseTile) + e;
+    const gptr<const int32_t> p = glb((const int32_t *)D.P) + (size_t)f * D.S * (kDenseTile * kDenseTile) + e;
     int64_t v = 0;
 #pragma unroll
     for (int s = 0; s < kDenseMaxSplits; ++s)  // independent loads, issued together

@@ -69,15 +69,15 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
     const int wx = wave & 1, wy = wave >> 1;
     // staging: thread -> (row, 16-byte column) pairs of the 128 x 64 slabs
     const int lr = tid >> 2, lc = (tid & 3) * 16;  // rows lr and lr + 64
-    const int8_t *ga = W.Dt + (size_t)(I * kDTile + lr) * W.stride + lc;
-    const int8_t *gb = W.Dt + (size_t)(J * kDTile + lr) * W.stride + lc;
+    const gptr<const int8_t> ga = glb((const int8_t *)W.Dt) + (size_t)(I * kDTile + lr) * W.stride + lc;
+    const gptr<const int8_t> gb = glb((const int8_t *)W.Dt) + (size_t)(J * kDTile + lr) * W.stride + lc;
     const size_t s64 = (size_t)64 * W.stride;
     v4i pa0, pa1, pb0, pb1;
     auto gload = [&](uint32_t r) {
-        pa0 = *reinterpret_cast<const v4i *>(ga + r);
-        pa1 = *reinterpret_cast<const v4i *>(ga + s64 + r);
-        pb0 = *reinterpret_cast<const v4i *>(gb + r);
-        pb1 = *reinterpret_cast<const v4i *>(gb + s64 + r);
+        pa0 = *(gptr<const v4i>)(ga + r);
+        pa1 = *(gptr<const v4i>)(ga + s64 + r);
+        pb0 = *(gptr<const v4i>)(gb + r);
+        pb1 = *(gptr<const v4i>)(gb + s64 + r);
     };
     auto lstore = [&](int buf) {
         *reinterpret_cast<v4i *>(&sA[buf][lr][lc]) = pa0;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
             buf ^= 1;
         }
     }
-    int32_t *P = W.P + ((size_t)f * W.S + sp) * (kDTile * kDTile);
+    const gptr<int32_t> P = glb(W.P) + ((size_t)f * W.S + sp) * (kDTile * kDTile);
     auto put = [&](const v16i &acc, int xb, int yb) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_clear(const DenseWork *__res
     const size_t total = (size_t)W.N * nv;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (size_t)gridDim.x * kThreads) {
         const size_t x = i / nv, q = i - x * nv;
-        *reinterpret_cast<v4i *>(W.Dt + x * W.stride + q * 16) = v4i{0, 0, 0, 0};
+        *(gptr<v4i>)(glb(W.Dt) + x * W.stride + q * 16) = v4i{0, 0, 0, 0};
     }
     (void)nwork;
 }

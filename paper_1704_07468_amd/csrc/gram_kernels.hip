@@ -71,13 +71,13 @@ __global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__res
     for (int q = 0; q < kTile / kThreads; ++q) {
         const uint32_t t = t0 + q * kThreads + threadIdx.x;
         if (t < W.T) {
-            const uint64_t h = mix_w(compact_key(W.key[t], W.md), W.w);
+            const uint64_t h = mix_w(compact_key(glb(W.key)[t], W.md), W.w);
             atomicAdd(&hist[(uint32_t)(h >> W.hb)], 1u);
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += kThreads)
-        if (hist[i]) atomicAdd(&W.bcnt[i], hist[i]);
+        if (hist[i]) g_atomic_add(glb(W.bcnt) + i, hist[i]);
 }
 
 // ------------------------------------------------------- bucket scatter --
@@ -107,16 +107,16 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
         const uint32_t t = t0 + q * kThreads + threadIdx.x;
         bk[q] = 0xFFFFFFFFu;
         if (t < W.T) {
-            const uint64_t h = mix_w(compact_key(W.key[t], W.md), W.w);
+            const uint64_t h = mix_w(compact_key(glb(W.key)[t], W.md), W.w);
             bk[q] = (uint32_t)(h >> W.hb);
-            cp[q] = ((h & hmask) << W.sb) | (uint64_t)W.sid[t];
+            cp[q] = ((h & hmask) << W.sb) | (uint64_t)glb(W.sid)[t];
             rk[q] = atomicAdd(&hist[bk[q]], 1u);
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += kThreads) {
         const uint32_t c = hist[i];
-        if (c) hist[i] = atomicAdd(&W.bcur[i], c);
+        if (c) hist[i] = g_atomic_add(glb(W.bcur) + i, c);
     }
     __syncthreads();
     const bool narrow = W.cb <= 32;
@@ -126,10 +126,10 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
             const uint32_t pos = hist[bk[q]] + rk[q];
             const uint32_t t = t0 + q * kThreads + threadIdx.x;
             if (narrow) {
-                W.comp[pos] = (cp[q] << 32) | t;
+                glb(W.comp)[pos] = (cp[q] << 32) | t;
             } else {
-                W.comp[pos] = cp[q];
-                W.idx[pos] = t;
+                glb(W.comp)[pos] = cp[q];
+                glb(W.idx)[pos] = t;
             }
         }
     }
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     if (ng == 0 || A.nmask == 0) {  // nothing to add: a stored row is 0
         if (A.first)
             for (int l = 0; l < A.nlev; ++l) {
-                int64_t *crow = J.C + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
+                const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
                 for (int Y = X + tid; Y < N; Y += kThreads) crow[Y] = 0;
             }
         return;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             const uint32_t s = q / ng;
             const uint32_t t = t0 + (q - s * ng);
             const MaskWork &W = items[A.mfirst + s];
-            const uint2 inf = W.info[t];
+            const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
             const uint32_t tail = inf.y & lmask;  // entries from X's own to the group end
             if (tail) {
                 const uint32_t cx = inf.y >> (sb + 1);
@@ -216,14 +216,14 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             for (int u = 0; u < 4; ++u) i[u] = last_le(pre[wid], 64u, w + 64 * u);
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                ent[u] = reinterpret_cast<const uint32_t *>(iptr[wid][i[u]])[w + 64 * u - pre[wid][i[u]]];
+                ent[u] = ((gptr<const uint32_t>)iptr[wid][i[u]])[w + 64 * u - pre[wid][i[u]]];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 atomicAdd(&acc[ioff[wid][i[u]] + (ent[u] & sidmask)], icx[wid][i[u]] * (ent[u] >> sb));
         }
         for (; w < work; w += 64) {
             const uint32_t i = last_le(pre[wid], 64u, w);
-            const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[wid][i])[w - pre[wid][i]];
+            const uint32_t ent = ((gptr<const uint32_t>)iptr[wid][i])[w - pre[wid][i]];
             atomicAdd(&acc[ioff[wid][i] + (ent & sidmask)], icx[wid][i] * (ent >> sb));
         }
         wave_sync();
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     }
     __syncthreads();
     for (int l = 0; l < A.nlev; ++l) {
-        int64_t *crow = J.C + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
+        const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
         const uint32_t *arow = acc + l * npad;
         if (A.first) {
             for (int Y = X + tid; Y < N; Y += kThreads) crow[Y] = (int64_t)arow[Y];
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     __shared__ int64_t hco[MM];
     __shared__ int64_t tile[32][33];
     __shared__ int nsplit[MM];
+    __shared__ DenseRef dref[MM];
     const int j = find_item(bprefix, njobs, blockIdx.x);
     const JobDev &Jb = jobs[j];
     const int N = Jb.N, M = Jb.M;
@@ -291,6 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     for (int i = tid; i <= M; i += kThreads) {
         hco[i] = Jb.hco[i];
         nsplit[i] = (Jb.dref && Jb.dref[i].P) ? dense_splits_used(Jb.dref[i]) : 0;
+        if (nsplit[i]) dref[i] = Jb.dref[i];
     }
     __syncthreads();
     const int c = tid & 31;
@@ -311,8 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
             for (int m = 0; m < MM; ++m) {
                 int64_t v = 0;
                 if (m <= M) {
-                    v = Jb.C[((size_t)m * N + x) * N + y];
-                if (nsplit[m]) v += dense_part(Jb.dref[m], nsplit[m], x, y);
+                    v = glb(Jb.C)[((size_t)m * N + x) * N + y];
+                    if (nsplit[m]) v += dense_part(dref[m], nsplit[m], x, y);
 #pragma unroll UNR
                     for (int jj = 0; jj < m; ++jj) v -= coef[m * MM + jj] * nv[q][jj];
                     kv[q] += hco[m] * v;
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
         }
     }
     __syncthreads();  // every read of C precedes any write (C may alias Nm_out)
-    auto emit = [&](int64_t *out, auto value_of) __attribute__((always_inline)) {
+    auto emit = [&](gptr<int64_t> out, auto value_of) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = (tid >> 5) + 8 * q;
@@ -345,14 +347,14 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
 #pragma unroll UNR
         for (int m = 0; m < MM; ++m) {
             if (m > M) continue;
-            emit(Jb.Nm_out + (size_t)m * N * N, [&](int q) __attribute__((always_inline)) { return nv[q][m]; });
+            emit(glb(Jb.Nm_out) + (size_t)m * N * N, [&](int q) __attribute__((always_inline)) { return nv[q][m]; });
         }
     }
     if (Jb.Cm_out) {
 #pragma unroll UNR
         for (int m = 0; m < MM; ++m) {
             if (m > M) continue;
-            emit(Jb.Cm_out + (size_t)m * N * N, [&](int q) __attribute__((always_inline)) {
+            emit(glb(Jb.Cm_out) + (size_t)m * N * N, [&](int q) __attribute__((always_inline)) {
                 int64_t v = nv[q][m];
 #pragma unroll UNR
                 for (int jj = 0; jj < m; ++jj) v += coef[m * MM + jj] * nv[q][jj];
@@ -361,10 +363,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
         }
     }
     if (Jb.K_out) {
-        int64_t *kout = reinterpret_cast<int64_t *>(Jb.K_out);
+        const gptr<int64_t> kout = glb(reinterpret_cast<int64_t *>(Jb.K_out));
         emit(kout, [&](int q) {
             const int r = (tid >> 5) + 8 * q;
-            const int64_t kx = Jb.Kd[I * 32 + r], ky = Jb.Kd[Jt * 32 + c];
+            const int64_t kx = glb(Jb.Kd)[I * 32 + r], ky = glb(Jb.Kd)[Jt * 32 + c];
             const double kh = (kx == 0 || ky == 0) ? 0.0 : (double)kv[q] / sqrt((double)kx * (double)ky);
             return __double_as_longlong(kh);
         });
