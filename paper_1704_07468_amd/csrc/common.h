@@ -251,13 +251,24 @@ __device__ __forceinline__ int find_item(const uint32_t *prefix, int n, uint32_t
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
 {
-    const int l = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (l >= d) x += y;
-    }
-    return x;
+    // within each row of 16 lanes: shifted adds (row_shr:1, 2, 4, 8; a lane
+    // shifted in from outside the row adds 0)
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x111, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x112, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x114, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0u, x, 0x118, 0xF, 0xF, false);
+    // then the totals of the rows below
+    const uint32_t r0 = __builtin_amdgcn_readlane(x, 15);
+    const uint32_t r1 = r0 + __builtin_amdgcn_readlane(x, 31);
+    const uint32_t r2 = r1 + __builtin_amdgcn_readlane(x, 47);
+    const int row = __lane_id() >> 4;
+    return x + (row == 0 ? 0u : row == 1 ? r0 : row == 2 ? r1 : r2);
+}
+
+// Set bits of m below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Block-wide exclusive scan of one value per thread (kThreads threads).

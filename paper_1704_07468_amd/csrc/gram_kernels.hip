@@ -143,18 +143,19 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
 // count_X * count_Y to row[Y] (Algorithm 1 countAndUpdate, upper triangle).
 // X's own entry is count_X^2 on the diagonal, summed in registers; a run with
 // one more entry carries it in its info; longer tails are read from the run
-// entries.  Each wave consumes its own chunks of 64 (mask, g-mer) items; a
-// wave scan of their tail lengths spreads the chunk's updates evenly over the
-// lanes, so the loop has no block barrier.  The row is then added into the
-// int64 C_m.
+// entries.  Each wave consumes its own chunks of 64 (mask, g-mer) items; the
+// chunk's tails are laid end to end (a wave scan of their lengths) and the
+// lanes walk that sequence 256 updates at a time: a mark per tail start in
+// LDS, a ballot of the marks and a popcount below the lane give each update
+// its tail without a search.  The loop has no block barrier.  The row is
+// then added into the int64 C_m.
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
                                                          const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
 {
     extern __shared__ uint32_t acc[];
-    __shared__ uint32_t pre[kWaves][64];
-    __shared__ uint64_t iptr[kWaves][64];
-    __shared__ uint32_t icx[kWaves][64];
-    __shared__ uint32_t ioff[kWaves][64];
+    __shared__ uint64_t tbase[kWaves][64];  // per tail: entry address - 4 * its start in the sequence
+    __shared__ uint2 tfac[kWaves][64];      // per tail: (count_X, row offset of its level)
+    __shared__ uint8_t mark[kWaves][256];   // tail starts in the current window (zero between windows)
     const int a = find_item(bprefix, nacc, blockIdx.x);
     const AccWork &A = aw[a];
     const JobDev &J = jobs[A.job];
@@ -176,12 +177,15 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     }
     const int npad = A.Npad;
     for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
+    for (int i = lane; i < 256; i += 64) mark[wid][i] = 0;
     __syncthreads();
     const uint32_t total = (uint32_t)A.nmask * ng;
     uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t q = c0 + lane;
         uint32_t len = 0;
+        uint64_t ebase = 0;
+        uint32_t cx = 0, off = 0;
         if (q < total) {
             const uint32_t s = q / ng;
             const uint32_t t = t0 + (q - s * ng);
@@ -189,42 +193,60 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
             const uint32_t tail = inf.y & lmask;  // entries from X's own to the group end
             if (tail) {
-                const uint32_t cx = inf.y >> (sb + 1);
-                const uint32_t off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
+                cx = inf.y >> (sb + 1);
+                off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
                 if (A.nlev == 1) dsum += cx * cx;
                 else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
                 if (tail == 2) {
                     atomicAdd(&acc[off + (inf.x & sidmask)], cx * (inf.x >> sb));
                 } else if (tail > 2) {
                     len = tail - 1;
-                    iptr[wid][lane] = reinterpret_cast<uint64_t>(W.E + inf.x + 1);
-                    icx[wid][lane] = cx;
-                    ioff[wid][lane] = off;
+                    ebase = reinterpret_cast<uint64_t>(W.E + inf.x + 1);
                 }
             }
         }
         const uint32_t inc = wave_incl_scan(len);
-        const uint32_t work = __shfl(inc, 63, 64);
-        pre[wid][lane] = inc - len;
-        wave_sync();
-        // four independent updates per lane in flight: their searches and
-        // entry loads overlap before the LDS atomics
-        uint32_t w = lane;
-        for (; w + 192 < work; w += 256) {
-            uint32_t i[4], ent[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) i[u] = last_le(pre[wid], 64u, w + 64 * u);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                ent[u] = ((gptr<const uint32_t>)iptr[wid][i[u]])[w + 64 * u - pre[wid][i[u]]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                atomicAdd(&acc[ioff[wid][i[u]] + (ent[u] & sidmask)], icx[wid][i[u]] * (ent[u] >> sb));
+        const uint32_t work = __builtin_amdgcn_readlane(inc, 63);
+        if (work == 0) continue;  // wave-uniform
+        const uint32_t start = inc - len;  // this tail's first position in the sequence
+        const uint64_t nz = __ballot(len > 0);
+        if (len > 0) {  // tails in start order: k = nonempty tails below this lane
+            const uint32_t k = lanes_below(nz);
+            tbase[wid][k] = ebase - 4ull * start;
+            tfac[wid][k] = make_uint2(cx, off);
         }
-        for (; w < work; w += 64) {
-            const uint32_t i = last_le(pre[wid], 64u, w);
-            const uint32_t ent = ((gptr<const uint32_t>)iptr[wid][i])[w - pre[wid][i]];
-            atomicAdd(&acc[ioff[wid][i] + (ent & sidmask)], icx[wid][i] * (ent >> sb));
+        uint32_t done = 0;  // tails started before the window
+#pragma unroll 1
+        for (uint32_t w = 0; w < work; w += 256) {
+            const bool here = len > 0 && start >= w && start < w + 256;
+            if (here) mark[wid][start - w] = 1;
+            wave_sync();
+            uint64_t st[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
+            wave_sync();
+            if (here) mark[wid][start - w] = 0;
+            uint32_t k[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                k[u] = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
+                done += (uint32_t)__popcll(st[u]);
+            }
+            uint32_t ent[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t p = w + 64u * u + (uint32_t)lane;
+                ent[u] = 0;
+                if (p < work) ent[u] = *(gptr<const uint32_t>)(tbase[wid][k[u]] + 4ull * p);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t p = w + 64u * u + (uint32_t)lane;
+                if (p < work) {
+                    const uint2 f = tfac[wid][k[u]];
+                    atomicAdd(&acc[f.y + (ent[u] & sidmask)], f.x * (ent[u] >> sb));
+                }
+            }
         }
         wave_sync();
     }
