@@ -42,7 +42,7 @@ __device__ __forceinline__ void wave_sync_rows()
 }
 
 // First index in E[a, b) whose sequence id is >= s (entries sequence-sorted).
-__device__ __forceinline__ uint32_t lower_sid(const uint32_t *E, uint32_t a, uint32_t b, uint32_t s, uint32_t sidmask)
+__device__ __forceinline__ uint32_t lower_sid(gptr<const uint32_t> E, uint32_t a, uint32_t b, uint32_t s, uint32_t sidmask)
 {
     while (a < b) {
         const uint32_t mid = (a + b) >> 1;
@@ -57,8 +57,8 @@ __device__ __forceinline__ uint32_t lower_sid(const uint32_t *E, uint32_t a, uin
 __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
 {
     extern __shared__ uint32_t acc[];
-    __shared__ uint32_t pre[kWaves][64];
-    __shared__ uint64_t iptr[kWaves][64];
+    __shared__ uint64_t tbase[kWaves][64];  // per group range: entry address - 4 * its start in the sequence
+    __shared__ uint8_t mark[kWaves][256];   // range starts in the current window (zero between windows)
     const int per_item = A.nq * A.nslab;
     int idx = (int)(blockIdx.x / per_item);
     const int rem = (int)(blockIdx.x % per_item);
@@ -80,6 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     const int s0 = sl * A.slab, s1 = min(A.nsv, s0 + A.slab);
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     for (int i = tid; i < s1 - s0; i += kThreads) acc[i] = 0;
+    for (int i = lane; i < 256; i += 64) mark[wid][i] = 0;
     __syncthreads();
     const uint32_t t0 = A.qgstart[q];
     const uint32_t ng = A.qgstart[q + 1] - t0;
@@ -90,47 +91,75 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t it = c0 + lane;
         uint32_t len = 0;
+        uint64_t ebase = 0;
         if (it < total) {
             const uint32_t s = it / ng;
             const ResMask &R = rm[s];
-            const uint64_t h = mix_w(compact_key(A.qkey[t0 + (it - s * ng)], R.md), R.w);
+            const uint64_t h = mix_w(compact_key(glb(A.qkey)[t0 + (it - s * ng)], R.md), R.w);
             const uint32_t b = (uint32_t)(R.hb >= 64 ? 0 : (h >> R.hb));
             const uint64_t hr = h & bits_mask(R.hb);
-            uint32_t lo = R.boff[b], hi = lo + R.bgrp[b];
+            const gptr<const u32x4> gtab = (gptr<const u32x4>)glb(R.gtab);
+            const uint32_t g0 = glb(R.boff)[b], g1 = g0 + glb(R.bgrp)[b];
+            uint32_t lo = g0, hi = g1;
             while (lo < hi) {  // first group with hash rest >= hr
                 const uint32_t mid = (lo + hi) >> 1;
-                const uint4 gm = R.gtab[mid];
+                const u32x4 gm = gtab[mid];
                 if ((((uint64_t)gm.y << 32) | gm.x) < hr) lo = mid + 1; else hi = mid;
             }
-            if (lo < R.boff[b] + R.bgrp[b]) {
-                const uint4 gm = R.gtab[lo];
+            if (lo < g1) {
+                const u32x4 gm = gtab[lo];
                 if ((((uint64_t)gm.y << 32) | gm.x) == hr) {
                     uint32_t e0 = gm.z, e1 = gm.w;
                     if (A.nslab > 1) {
-                        e0 = lower_sid(R.E, e0, e1, (uint32_t)s0, sidmask);
-                        e1 = lower_sid(R.E, e0, e1, (uint32_t)s1, sidmask);
+                        e0 = lower_sid(glb(R.E), e0, e1, (uint32_t)s0, sidmask);
+                        e1 = lower_sid(glb(R.E), e0, e1, (uint32_t)s1, sidmask);
                     }
                     len = e1 - e0;
-                    iptr[wid][lane] = reinterpret_cast<uint64_t>(R.E + e0);
+                    ebase = reinterpret_cast<uint64_t>(R.E + e0);
                 }
             }
         }
+        // the chunk's entry ranges end to end, walked 256 updates at a time;
+        // each update finds its range from a ballot of the range-start marks
         const uint32_t inc = wave_incl_scan(len);
-        const uint32_t work = __shfl(inc, 63, 64);
-        pre[wid][lane] = inc - len;
-        wave_sync_rows();
-        for (uint32_t w = lane; w < work; w += 64) {
-            const uint32_t i = last_le(pre[wid], 64u, w);
-            const uint32_t ent = reinterpret_cast<const uint32_t *>(iptr[wid][i])[w - pre[wid][i]];
-            atomicAdd(&acc[(ent & sidmask) - (uint32_t)s0], ent >> sb);
+        const uint32_t work = __builtin_amdgcn_readlane(inc, 63);
+        if (work == 0) continue;  // wave-uniform
+        const uint32_t start = inc - len;
+        const uint64_t nz = __ballot(len > 0);
+        if (len > 0) tbase[wid][lanes_below(nz)] = ebase - 4ull * start;
+        uint32_t done = 0;  // ranges started before the window
+#pragma unroll 1
+        for (uint32_t w = 0; w < work; w += 256) {
+            const bool here = len > 0 && start >= w && start < w + 256;
+            if (here) mark[wid][start - w] = 1;
+            wave_sync_rows();
+            uint64_t st[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
+            wave_sync_rows();
+            if (here) mark[wid][start - w] = 0;
+            uint32_t ent[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t k = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
+                done += (uint32_t)__popcll(st[u]);
+                const uint32_t p = w + 64u * u + (uint32_t)lane;
+                ent[u] = 0;
+                if (p < work) ent[u] = *(gptr<const uint32_t>)(tbase[wid][k] + 4ull * p);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t p = w + 64u * u + (uint32_t)lane;
+                if (p < work) atomicAdd(&acc[(ent[u] & sidmask) - (uint32_t)s0], ent[u] >> sb);
+            }
         }
         wave_sync_rows();
     }
     __syncthreads();
-    uint32_t *crow = A.C + ((size_t)level * A.nq + q) * A.nsv;
+    const gptr<uint32_t> crow = glb(A.C) + ((size_t)level * A.nq + q) * A.nsv;
     for (int sv = s0 + tid; sv < s1; sv += kThreads) {
         const uint32_t v = acc[sv - s0];
-        if (v) atomicAdd(&crow[sv], v);
+        if (v) g_atomic_add(crow + sv, v);
     }
 }
 
