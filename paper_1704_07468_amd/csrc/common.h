@@ -528,6 +528,16 @@ __device__ __forceinline__ void wave_sync()
 
 // Block -> (item, block within item): arithmetic when every item has the
 // same number of blocks, else a search of the per-item block prefix.
+// Block b of a grid of nb blocks runs on XCD b % 8 (blocks are dealt round-
+// robin to the 8 XCDs).  xcd_order(b, nb) renumbers the blocks so that each
+// XCD runs one contiguous range of the work: blocks writing the same region
+// then share one L2, where their partial-line writes merge.
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nb)
+{
+    const uint32_t q = nb / 8, rem = nb % 8, x = b % 8;
+    return x * q + min(x, rem) + b / 8;
+}
+
 __device__ __forceinline__ void map_block(const uint32_t *prefix, int n, uint32_t uniform, uint32_t bid, int &item,
                                           uint32_t &sub)
 {

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
     extern __shared__ uint32_t hist[];
     int it;
     uint32_t tile;
-    map_block(bprefix, nitems, uniform, blockIdx.x, it, tile);
+    map_block(bprefix, nitems, uniform, xcd_order(blockIdx.x, gridDim.x), it, tile);
     const MaskWork &W = items[it];
     const uint32_t t0 = tile * kTile;
     if (t0 >= W.T) return;
