@@ -269,15 +269,18 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[EL], uint32_t (&val
 
 // ----------------------------------------------------------- segmentation --
 // One 64-bit word per 64 sorted positions: run starts (rbm), group starts
-// (gbm) and starts of candidate groups for the count matrix (cbm), with their
-// exclusive prefix popcounts, the position of the next run / group start at
-// or after each word and of the last group start before it (n, resp. none,
-// when there is none); slot: one word per candidate group.
+// (gbm), positions whose composite recurs 127 positions later, i.e. that lie
+// in a run of more than 127 g-mers (lbm), and starts of candidate groups for
+// the count matrix (cbm), with their exclusive prefix popcounts, the position
+// of the next run / group start at or after each word and of the last group
+// start before it (n, resp. none, when there is none); slot: one word per
+// candidate group.
 template <int NWORDS, int NSLOT>
 struct SegLds {
-    uint64_t rbm[NWORDS], gbm[NWORDS], cbm[NWORDS];
+    uint64_t rbm[NWORDS], gbm[NWORDS], lbm[NWORDS], cbm[NWORDS];
     uint32_t rpre[NWORDS + 1], gpre[NWORDS + 1], cpre[NWORDS + 1];
     uint32_t nextr[NWORDS + 1], nextg[NWORDS + 1], prevg[NWORDS + 1];
+    uint32_t inner;  // some full word holds no group start (lies inside one group)
     uint32_t slot[NSLOT];
 };
 
@@ -288,26 +291,45 @@ __device__ __forceinline__ void seg_sync()
     else wave_sync();
 }
 
-__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t x)
+// Wave-wide inclusive prefix max and suffix max of unsigned values (0 is the
+// identity): DPP shifts within rows of 16 lanes, then the row totals.
+__device__ __forceinline__ uint32_t wave_prefix_max_u(uint32_t x)
 {
-    const int l = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_down(x, d, 64);
-        if (l + d < 64) x = min(x, y);
-    }
-    return x;
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false));  // row_shr:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false));  // row_shr:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false));  // row_shr:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false));  // row_shr:8
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+    const uint32_t r1 = max(r0, (uint32_t)__builtin_amdgcn_readlane((int)x, 31));
+    const uint32_t r2 = max(r1, (uint32_t)__builtin_amdgcn_readlane((int)x, 47));
+    const int row = __lane_id() >> 4;
+    return max(x, row == 0 ? 0u : row == 1 ? r0 : row == 2 ? r1 : r2);
 }
-
-__device__ __forceinline__ int wave_prefix_max(int x)
+__device__ __forceinline__ uint32_t wave_suffix_max_u(uint32_t x)
 {
-    const int l = __lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (l >= d) x = max(x, y);
-    }
-    return x;
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x101, 0xF, 0xF, false));  // row_shl:1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x102, 0xF, 0xF, false));  // row_shl:2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x104, 0xF, 0xF, false));  // row_shl:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x108, 0xF, 0xF, false));  // row_shl:8
+    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+    const uint32_t r2 = max(r3, (uint32_t)__builtin_amdgcn_readlane((int)x, 32));
+    const uint32_t r1 = max(r2, (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+    const int row = __lane_id() >> 4;
+    return max(x, row == 3 ? 0u : row == 2 ? r3 : row == 1 ? r2 : r1);
+}
+__device__ __forceinline__ uint32_t wave_suffix_min(uint32_t x) { return ~wave_suffix_max_u(~x); }
+__device__ __forceinline__ int wave_prefix_max(int x)  // x >= -1
+{
+    return (int)wave_prefix_max_u((uint32_t)(x + 1)) - 1;
+}
+// The value of lane + 1 (lane 63: 0) and of lane - 1 (lane 0: 0).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, false);  // wave_shr:1
 }
 
 __device__ __forceinline__ uint32_t first_bit(int w, uint64_t m) { return (uint32_t)(w * 64 + __ffsll((long long)m) - 1); }
@@ -322,11 +344,14 @@ __device__ __forceinline__ void scan_words(SegLds<NWORDS, NSLOT> &S, int nwords,
     const int lane = __lane_id();
     uint32_t rc = 0, gc = 0, fr = n, fg = n;
     int lg = -1;
+    bool inner = false;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int w = lane * PER + p;
         if (w < nwords && S.gbm[w]) lg = last_bit(w, S.gbm[w]);
+        if (w < nwords && (uint32_t)(w + 1) * 64u <= n && !S.gbm[w]) inner = true;
     }
+    const bool any_inner = __ballot(inner) != 0;
 #pragma unroll
     for (int p = PER - 1; p >= 0; --p) {
         const int w = lane * PER + p;
@@ -341,9 +366,9 @@ __device__ __forceinline__ void scan_words(SegLds<NWORDS, NSLOT> &S, int nwords,
     const uint32_t ri = wave_incl_scan(rc), gi = wave_incl_scan(gc);
     uint32_t rx = ri - rc, gx = gi - gc;
     const uint32_t sr = wave_suffix_min(fr), sg = wave_suffix_min(fg);
-    uint32_t ar = __shfl_down(sr, 1, 64), ag = __shfl_down(sg, 1, 64);
+    uint32_t ar = from_next_lane(sr), ag = from_next_lane(sg);
     if (lane == 63) ar = ag = n;
-    int pg = __shfl_up(wave_prefix_max(lg), 1, 64);
+    int pg = (int)from_prev_lane((uint32_t)wave_prefix_max(lg));
     if (lane == 0) pg = -1;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
@@ -368,12 +393,13 @@ __device__ __forceinline__ void scan_words(SegLds<NWORDS, NSLOT> &S, int nwords,
             S.nextg[w] = ag;
         }
     }
-    const uint32_t R = __shfl(ri, 63, 64), G = __shfl(gi, 63, 64);
+    const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)ri, 63), G = (uint32_t)__builtin_amdgcn_readlane((int)gi, 63);
     if (lane == 0) {
         S.rpre[nwords] = R;
         S.gpre[nwords] = G;
         S.nextr[nwords] = n;
         S.nextg[nwords] = n;
+        S.inner = any_inner ? 1u : 0u;
     }
 }
 
@@ -399,7 +425,7 @@ __device__ __forceinline__ void scan_cand(SegLds<NWORDS, NSLOT> &S, int nwords)
             cx += __popcll(S.cbm[w]);
         }
     }
-    const uint32_t C = __shfl(ci, 63, 64);
+    const uint32_t C = (uint32_t)__builtin_amdgcn_readlane((int)ci, 63);
     if (lane == 0) S.cpre[nwords] = C;
 }
 
@@ -540,35 +566,64 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
 #pragma unroll 1
     for (int w = wave; w < nwords; w += NW) {
         const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
-        bool rs = false, gs = false;
+        bool rs = false, gs = false, lr = false;
         if (i < n) {
+            const uint64_t c = comp_at(i);
             if (i == 0) {
                 rs = gs = true;
             } else {
-                const uint64_t c = comp_at(i), p = comp_at(i - 1);
+                const uint64_t p = comp_at(i - 1);
                 rs = c != p;
                 gs = (c >> sb) != (p >> sb);
             }
+            lr = i + 127u < n && comp_at(i + 127u) == c;
         }
-        const uint64_t rb = __ballot(rs), gb = __ballot(gs);
+        const uint64_t rb = __ballot(rs), gb = __ballot(gs), lb = __ballot(lr);
         if (lane == 0) {
             S.rbm[w] = rb;
             S.gbm[w] = gb;
+            S.lbm[w] = lb;
         }
     }
     seg_sync<NW>();
     if (wave == 0) scan_words<NWORDS, NSLOT>(S, nwords, n);
     seg_sync<NW>();
     const uint32_t R = S.rpre[nwords], G = S.gpre[nwords];
-    // count-matrix candidates: groups with at least tau runs
-    const bool dense_on = n > 0 && tau > 0 && D != nullptr;
+    // count-matrix candidates: groups with at least tau runs, none of them
+    // longer than 127 g-mers.  Such a group spans at least tau positions;
+    // from 127 on, that covers one full word without a group start, so
+    // buckets without such a word are skipped.
+    const bool dense_on = n > 0 && tau > 0 && D != nullptr && R >= (uint32_t)tau && (tau < 127 || S.inner);
     if (dense_on) {
-#pragma unroll 2
+#pragma unroll 1
         for (int w = wave; w < nwords; w += NW) {
             const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
             const WordAt u = word_at(S, w);
             bool c = false;
-            if (i < n && ((u.gb >> lane) & 1ull)) c = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R).len >= (uint32_t)tau;
+            if (i < n && ((u.gb >> lane) & 1ull)) {
+                const uint64_t gt = lane == 63 ? 0ull : (~0ull << (lane + 1));
+                const uint64_t mg = u.gb & gt;
+                const uint32_t gend = mg ? first_bit(w, mg) : u.nextg1;
+                if (gend - i >= (uint32_t)tau) {  // long enough in positions: count its runs
+                    const uint32_t r0 = u.rpre + (uint32_t)__popcll(u.rb & ~(gt | (1ull << lane)));
+                    uint32_t r1 = R;
+                    if (gend < n) {
+                        const int gw = (int)(gend >> 6);
+                        r1 = S.rpre[gw] + (uint32_t)__popcll(S.rbm[gw] & ((1ull << (gend & 63)) - 1ull));
+                    }
+                    if (r1 - r0 >= (uint32_t)tau) {
+                        // no position of the group in a run longer than 127
+                        bool ok = true;
+                        for (int x = w; x <= (int)((gend - 1) >> 6) && ok; ++x) {
+                            uint64_t m = S.lbm[x];
+                            if (x == w) m &= ~0ull << lane;
+                            if (x == (int)((gend - 1) >> 6) && (gend & 63)) m &= (1ull << (gend & 63)) - 1ull;
+                            ok = m == 0;
+                        }
+                        c = ok;
+                    }
+                }
+            }
             const uint64_t cb = __ballot(c);
             if (lane == 0) S.cbm[w] = cb;
         }
@@ -578,28 +633,10 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     seg_sync<NW>();
     const uint32_t ncand = dense_on ? S.cpre[nwords] : 0u;
     const bool dense = ncand > 0 && ncand <= (uint32_t)NSLOT;
-    if (dense)
-        for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) S.slot[s] = 0;
-    seg_sync<NW>();
-    if (dense) {  // largest count of each candidate group
-#pragma unroll 2
-        for (int w = wave; w < nwords; w += NW) {
-            const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
-            const WordAt u = word_at(S, w);
-            if (i < n && ((u.rb >> lane) & 1ull)) {
-                const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
-                if (a.gs < n && bit_at(S.cbm, a.gs)) atomicMax(&S.slot[cand_slot(S, a.gs)], a.cnt);
-            }
-        }
-    }
-    seg_sync<NW>();
-    if (dense) {  // candidates whose counts all fit int8 take a count-matrix row
+    if (dense) {  // every candidate takes a count-matrix row while rows last
         for (uint32_t s = (uint32_t)tid; s < ncand; s += NT) {
-            uint32_t row = 0xFFFFFFFFu;
-            if (S.slot[s] <= 127u) {
-                row = g_atomic_add(dcount, 1u);
-                if (row >= dcap) row = 0xFFFFFFFFu;
-            }
+            uint32_t row = g_atomic_add(dcount, 1u);
+            if (row >= dcap) row = 0xFFFFFFFFu;
             S.slot[s] = row;
         }
     }
