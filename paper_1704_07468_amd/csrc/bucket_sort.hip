@@ -166,37 +166,35 @@ __device__ __forceinline__ void exchange_lanes(uint64_t &key, uint32_t &val, boo
     if constexpr (!PK) val = take_a ? av : bv;
 }
 
-// Stage of distance J < 64 for every register e; element index i = ibase +
-// 64 e + lane; a pair is ascending when bit k of i is 0 -- a bit of the lane
-// when k < 64, else a bit of ibase + 64 e, the same for the whole wave.
+// Elements are held blocked: lane l has elements i = ibase + EL l + e in its
+// registers e = 0..EL-1, so the stages of distance below EL are register
+// swaps and only the longer ones exchange between lanes.
+
+// Stage of element distance J EL (lane distance J < 64) for every register.
+// A pair is ascending when bit k of i is 0; k >= 2 J EL, so that bit belongs
+// to ibase + EL l, the same for all registers of the lane.
 template <bool PK, int EL, int J>
 __device__ __forceinline__ void stage_lanes(uint64_t (&key)[EL], uint32_t (&val)[EL], uint32_t ibase, uint32_t k)
 {
     const int lane = __lane_id();
     const bool upper = (lane & J) != 0;
-    if (k < 64) {
-        const bool keep_max = upper == ((lane & (int)k) == 0);
+    const bool asc = ((ibase + (uint32_t)(EL * lane)) & k) == 0;
+    const bool keep_max = upper == asc;
 #pragma unroll
-        for (int e = 0; e < EL; ++e) exchange_lanes<PK, J>(key[e], val[e], keep_max);
-    } else {
-#pragma unroll
-        for (int e = 0; e < EL; ++e) {
-            const bool asc = ((ibase + (uint32_t)(e * 64)) & k) == 0;  // wave-uniform
-            exchange_lanes<PK, J>(key[e], val[e], upper == asc);
-        }
-    }
+    for (int e = 0; e < EL; ++e) exchange_lanes<PK, J>(key[e], val[e], keep_max);
 }
 
-// Stage of distance 64 D: registers e and e | D of the same lane.
+// Stage of distance D < EL: registers e and e | D of the same lane.
 template <bool PK, int EL, int D>
 __device__ __forceinline__ void stage_regs(uint64_t (&key)[EL], uint32_t (&val)[EL], uint32_t ibase, uint32_t k)
 {
     if constexpr (D < EL) {
+        const uint32_t l0 = ibase + (uint32_t)(EL * __lane_id());
 #pragma unroll
         for (int e = 0; e < EL; ++e) {
             if ((e & D) == 0) {
                 const int e2 = e | D;
-                const bool asc = ((ibase + (uint32_t)(e * 64)) & k) == 0;  // wave-uniform
+                const bool asc = ((l0 + (uint32_t)e) & k) == 0;
                 const bool sw = el_less<PK>(key[e2], val[e2], key[e], val[e]) == asc;
                 const uint64_t ka = key[e], kb = key[e2];
                 key[e] = sw ? kb : ka;
@@ -216,18 +214,17 @@ template <bool PK, int EL>
 __device__ __forceinline__ void stage_lds(uint64_t (&key)[EL], uint32_t (&val)[EL], uint64_t *kb, uint32_t *vb,
                                           uint32_t ibase, uint32_t k, uint32_t j)
 {
-    const int lane = __lane_id();
+    const uint32_t l0 = ibase + (uint32_t)(EL * __lane_id());
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < EL; ++e) {
-        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
-        kb[i] = key[e];
-        if constexpr (!PK) vb[i] = val[e];
+        kb[l0 + e] = key[e];
+        if constexpr (!PK) vb[l0 + e] = val[e];
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < EL; ++e) {
-        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
+        const uint32_t i = l0 + (uint32_t)e;
         const uint64_t yk = kb[i ^ j];
         uint32_t yv = 0;
         if constexpr (!PK) yv = vb[i ^ j];
@@ -249,21 +246,18 @@ __device__ __forceinline__ void bitonic_sort(uint64_t (&key)[EL], uint32_t (&val
     for (uint32_t k = 2; k <= NP; k <<= 1) {
         if constexpr (NW > 1)
             for (uint32_t j = k >> 1; j >= WSPAN; j >>= 1) stage_lds<PK, EL>(key, val, kb, vb, ibase, k, j);
-        for (uint32_t j = min(k >> 1, WSPAN >> 1); j >= 64; j >>= 1) {
-            switch (j >> 6) {
-            case 1: stage_regs<PK, EL, 1>(key, val, ibase, k); break;
-            case 2: stage_regs<PK, EL, 2>(key, val, ibase, k); break;
-            case 4: stage_regs<PK, EL, 4>(key, val, ibase, k); break;
-            case 8: stage_regs<PK, EL, 8>(key, val, ibase, k); break;
-            default: break;
-            }
-        }
-        if (k > 32) stage_lanes<PK, EL, 32>(key, val, ibase, k);
-        if (k > 16) stage_lanes<PK, EL, 16>(key, val, ibase, k);
-        if (k > 8) stage_lanes<PK, EL, 8>(key, val, ibase, k);
-        if (k > 4) stage_lanes<PK, EL, 4>(key, val, ibase, k);
-        if (k > 2) stage_lanes<PK, EL, 2>(key, val, ibase, k);
-        stage_lanes<PK, EL, 1>(key, val, ibase, k);
+        // lane stages, element distances WSPAN / 2 .. EL
+        if (k > 32u * EL) stage_lanes<PK, EL, 32>(key, val, ibase, k);
+        if (k > 16u * EL) stage_lanes<PK, EL, 16>(key, val, ibase, k);
+        if (k > 8u * EL) stage_lanes<PK, EL, 8>(key, val, ibase, k);
+        if (k > 4u * EL) stage_lanes<PK, EL, 4>(key, val, ibase, k);
+        if (k > 2u * EL) stage_lanes<PK, EL, 2>(key, val, ibase, k);
+        if (k > 1u * EL) stage_lanes<PK, EL, 1>(key, val, ibase, k);
+        // register stages, distances EL / 2 .. 1
+        if (k > 8) stage_regs<PK, EL, 8>(key, val, ibase, k);
+        if (k > 4) stage_regs<PK, EL, 4>(key, val, ibase, k);
+        if (k > 2) stage_regs<PK, EL, 2>(key, val, ibase, k);
+        stage_regs<PK, EL, 1>(key, val, ibase, k);
     }
 }
 
@@ -680,7 +674,9 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
 }
 
 // Load a bucket's (composite, index) pairs into registers, padding with the
-// largest element.
+// largest element.  The loads are coalesced (register e of lane l takes
+// element ibase + 64 e + l); which slot holds which element does not matter
+// before the sort.
 template <bool PK, int EL>
 __device__ __forceinline__ void load_bucket(const MaskWork &W, uint32_t base, uint32_t n, uint32_t ibase, uint64_t (&key)[EL],
                                             uint32_t (&val)[EL])
@@ -700,7 +696,8 @@ __device__ __forceinline__ void load_bucket(const MaskWork &W, uint32_t base, ui
     }
 }
 
-// Store the sorted elements held in registers to LDS.
+// Store the sorted elements held in registers (blocked: i = ibase + EL lane
+// + e) to LDS.
 template <bool PK, int EL>
 __device__ __forceinline__ void store_sorted(const uint64_t (&key)[EL], const uint32_t (&val)[EL], uint32_t ibase, uint32_t n,
                                              uint64_t *kb, uint32_t *vb)
@@ -708,7 +705,7 @@ __device__ __forceinline__ void store_sorted(const uint64_t (&key)[EL], const ui
     const int lane = __lane_id();
 #pragma unroll
     for (int e = 0; e < EL; ++e) {
-        const uint32_t i = ibase + (uint32_t)(e * 64 + lane);
+        const uint32_t i = ibase + (uint32_t)(EL * lane + e);
         if (i < n) {
             kb[i] = key[e];
             if constexpr (!PK) vb[i] = val[e];
