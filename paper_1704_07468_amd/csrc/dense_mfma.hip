@@ -72,28 +72,25 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
     const gptr<const int8_t> ga = glb((const int8_t *)W.Dt) + (size_t)(I * kDTile + lr) * W.stride + lc;
     const gptr<const int8_t> gb = glb((const int8_t *)W.Dt) + (size_t)(J * kDTile + lr) * W.stride + lc;
     const size_t s64 = (size_t)64 * W.stride;
-    v4i pa0, pa1, pb0, pb1;
-    auto gload = [&](uint32_t r) {
-        pa0 = *(gptr<const v4i>)(ga + r);
-        pa1 = *(gptr<const v4i>)(ga + s64 + r);
-        pb0 = *(gptr<const v4i>)(gb + r);
-        pb1 = *(gptr<const v4i>)(gb + s64 + r);
+    // operand slabs of one 64-row step, in registers on their way to LDS
+    struct Slab {
+        v4i a0, a1, b0, b1;
     };
-    auto lstore = [&](int buf) {
-        *reinterpret_cast<v4i *>(&sA[buf][lr][lc]) = pa0;
-        *reinterpret_cast<v4i *>(&sA[buf][lr + 64][lc]) = pa1;
-        *reinterpret_cast<v4i *>(&sB[buf][lr][lc]) = pb0;
-        *reinterpret_cast<v4i *>(&sB[buf][lr + 64][lc]) = pb1;
+    auto gload = [&](uint32_t r, Slab &x) {
+        x.a0 = *(gptr<const v4i>)(ga + r);
+        x.a1 = *(gptr<const v4i>)(ga + s64 + r);
+        x.b0 = *(gptr<const v4i>)(gb + r);
+        x.b1 = *(gptr<const v4i>)(gb + s64 + r);
+    };
+    auto lstore = [&](int buf, const Slab &x) {
+        *reinterpret_cast<v4i *>(&sA[buf][lr][lc]) = x.a0;
+        *reinterpret_cast<v4i *>(&sA[buf][lr + 64][lc]) = x.a1;
+        *reinterpret_cast<v4i *>(&sB[buf][lr][lc]) = x.b0;
+        *reinterpret_cast<v4i *>(&sB[buf][lr + 64][lc]) = x.b1;
     };
     v16i acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
     const int fr = lane & 31, fk = 16 * (lane >> 5);
-    gload(r0);
-    lstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (uint32_t r = r0; r < r1; r += kDK) {
-        const bool more = r + kDK < r1;
-        if (more) gload(r + kDK);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < kDK; kk += 32) {
             const v4i a0 = *reinterpret_cast<const v4i *>(&sA[buf][wx * 64 + fr][kk + fk]);
@@ -105,11 +102,33 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
             acc10 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b0, acc10, 0, 0, 0);
             acc11 = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc11, 0, 0, 0);
         }
-        if (more) {
-            lstore(buf ^ 1);
-            __syncthreads();
-            buf ^= 1;
-        }
+    };
+    // Two steps of loads in flight: while step r is multiplied from LDS, the
+    // slabs of step r + 64 (already loaded) go to the other buffer and those
+    // of step r + 128 are loaded.  Loads past the split's last step re-read
+    // that step (rows up to a multiple of 64 past the used rows are zero and
+    // allocated), so no load is conditional.
+    const uint32_t last = r0 + (r1 - r0 - 1) / kDK * kDK;
+    Slab x0, x1;
+    gload(r0, x0);
+    gload(min(r0 + kDK, last), x1);
+    lstore(0, x0);
+    __syncthreads();
+    auto step = [&](uint32_t r, int buf, Slab &ld, const Slab &st) {
+        gload(min(r + 2 * kDK, last), ld);
+        compute(buf);
+        lstore(buf ^ 1, st);
+        __syncthreads();
+    };
+    uint32_t r = r0;
+#pragma unroll 1
+    while (true) {
+        step(r, 0, x0, x1);  // x1: step r + 64; x0 <- step r + 128
+        r += kDK;
+        if (r >= r1) break;
+        step(r, 1, x1, x0);
+        r += kDK;
+        if (r >= r1) break;
     }
     const gptr<int32_t> P = glb(W.P) + ((size_t)f * W.S + sp) * (kDTile * kDTile);
     auto put = [&](const v16i &acc, int xb, int yb) {
