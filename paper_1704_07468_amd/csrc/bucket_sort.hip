@@ -520,6 +520,23 @@ __device__ __forceinline__ uint32_t cand_slot(const SegLds<NWORDS, NSLOT> &S, ui
     return S.cpre[cw] + (uint32_t)__popcll(S.cbm[cw] & ((1ull << (gs & 63)) - 1ull));
 }
 
+// Adds each lane's diagonal term v (0: none) to counter q.  When every term
+// of the wave belongs to one sequence -- a single query, whose runs all have
+// sequence 0, or a group of runs of one sequence -- the wave adds their sum
+// once instead of contending on one address lane by lane.
+__device__ __forceinline__ void diag_add(gptr<uint32_t> diag, uint32_t nseq, uint32_t v, uint32_t q)
+{
+    const uint64_t act = __ballot(v != 0);
+    if (!act) return;
+    const uint32_t q0 = (uint32_t)__builtin_amdgcn_readlane((int)q, __ffsll((long long)act) - 1);
+    if (__ballot(v != 0 && q != q0) == 0) {
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
+        if (__lane_id() == 0 && q0 < nseq) g_atomic_add(diag + q0, tot);
+    } else if (v != 0 && q < nseq) {
+        g_atomic_add(diag + q, v);
+    }
+}
+
 // Runs and groups of one sorted bucket in LDS (kb: packed words or
 // composites, vb: indices of wide ones), segmented by the NW waves of its
 // group (wave = the wave's index in the group).  Writes one run entry
@@ -639,36 +656,40 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     for (int w = wave; w < nwords; w += NW) {
         const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
         const WordAt u = word_at(S, w);
-        if (i >= n) continue;
-        const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
-        if (!((u.rb >> lane) & 1ull)) {
-            if (idx < T) st_u2(info, idx, 0u, 0u);
-            continue;
-        }
-        const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
-        const uint64_t c = comp_at(i);
-        const uint32_t sid = (uint32_t)(c & sidmask);
-        const uint32_t ei = base + a.r;
-        E[ei] = sid | (a.cnt << sb);
-        uint32_t y = a.len | (a.cnt << (sb + 1));
-        if (dense && a.gs < n && bit_at(S.cbm, a.gs)) {
-            const uint32_t row = S.slot[cand_slot(S, a.gs)];
-            if (row != 0xFFFFFFFFu) {
-                if (sid < Nseq && row < dcap) D[(size_t)sid * (size_t)dstride + row] = (int8_t)a.cnt;
-                y = 0;
+        uint32_t dv = 0, dq = 0;  // this lane's diagonal term count^2 and its sequence
+        if (i < n) {
+            const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
+            if (!((u.rb >> lane) & 1ull)) {
+                if (idx < T) st_u2(info, idx, 0u, 0u);
+            } else {
+                const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
+                const uint64_t c = comp_at(i);
+                const uint32_t sid = (uint32_t)(c & sidmask);
+                const uint32_t ei = base + a.r;
+                E[ei] = sid | (a.cnt << sb);
+                uint32_t y = a.len | (a.cnt << (sb + 1));
+                if (dense && a.gs < n && bit_at(S.cbm, a.gs)) {
+                    const uint32_t row = S.slot[cand_slot(S, a.gs)];
+                    if (row != 0xFFFFFFFFu) {
+                        if (sid < Nseq && row < dcap) D[(size_t)sid * (size_t)dstride + row] = (int8_t)a.cnt;
+                        y = 0;
+                    }
+                }
+                uint32_t x = ei;
+                if (inl && y != 0 && a.len == 2) {  // the group's last run, inline
+                    const uint32_t nx = i + a.cnt;
+                    x = (uint32_t)(comp_at(nx) & sidmask) | ((a.gend - nx) << sb);
+                }
+                if (idx < T) st_u2(info, idx, x, y);
+                dv = a.cnt * a.cnt;
+                dq = sid;
+                if (gtab && a.gs == i) {
+                    const uint64_t hr = c >> sb;
+                    st_u4(gtab, base + a.gi, (uint32_t)hr, (uint32_t)(hr >> 32), ei, ei + a.len);
+                }
             }
         }
-        uint32_t x = ei;
-        if (inl && y != 0 && a.len == 2) {  // the group's last run, inline
-            const uint32_t nx = i + a.cnt;
-            x = (uint32_t)(comp_at(nx) & sidmask) | ((a.gend - nx) << sb);
-        }
-        if (idx < T) st_u2(info, idx, x, y);
-        if (diag && sid < Nseq) g_atomic_add(diag + sid, a.cnt * a.cnt);
-        if (gtab && a.gs == i) {
-            const uint64_t hr = c >> sb;
-            st_u4(gtab, base + a.gi, (uint32_t)hr, (uint32_t)(hr >> 32), ei, ei + a.len);
-        }
+        if (diag) diag_add(diag, Nseq, dv, dq);
     }
     if (gtab && n > 0 && tid == 0) bgrp[bucket] = G;
 }
