@@ -127,9 +127,18 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     // grid: (level, chunk of position sets) x query x SV slab, sized so that
     // even one query spreads over the whole device
     const int slab = (int)std::min<size_t>((size_t)R->n_sv, 4096);
-    const int mchunk = n_q < 16 ? 8 : 32;
-    int nitems = 0;
-    for (int m = 0; m <= R->M; ++m) nitems += (int)((binom64(R->g, m) + mchunk - 1) / mchunk);
+    const int nslab = (int)((R->n_sv + slab - 1) / slab);
+    // position sets per block: the most that still gives about 1024 blocks
+    // (fewer per block means more partial rows to add, more blocks more
+    // parallelism; a single query needs the latter)
+    auto items_for = [&](int mc) {
+        int n = 0;
+        for (int m = 0; m <= R->M; ++m) n += (int)((binom64(R->g, m) + mc - 1) / mc);
+        return n;
+    };
+    int mchunk = 32;
+    while (mchunk > 1 && (int64_t)items_for(mchunk) * n_q * nslab < 1024) mchunk /= 2;
+    const int nitems = items_for(mchunk);
     GK_HIP(launch_fill_u32(C, (size_t)M1 * n_q * R->n_sv, 0u, st));
     GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,
                                   R->lev_count, C, st));
