@@ -293,10 +293,13 @@ __global__ __launch_bounds__(kThreads) void k_diag(const JobDev *__restrict__ jo
 
 // One block per 32x32 tile (I <= J) of the upper triangle: inclusion-
 // exclusion (Eq. 9), K (Eq. 7) and the cosine normalisation for every entry
-// x <= y, written to (x, y) and, through an LDS transpose, to (y, x).
-template <int MM>
-__global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
+// x <= y, written to (x, y) and, through an LDS transpose, to (y, x).  QN
+// entries per thread (1024 / QN threads), so that the per-level values of
+// up to MM levels stay in registers.
+template <int MM, int QN>
+__global__ __launch_bounds__(1024 / QN) void k_finalize(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
 {
+    constexpr int FT = 1024 / QN, RS = FT / 32;  // threads; rows apart of a thread's entries
     __shared__ int64_t coef[MM * MM];
     __shared__ int64_t hco[MM];
     __shared__ int64_t tile[32][33];
@@ -310,8 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     const int I = flat / nt, Jt = flat % nt;
     if (I > Jt) return;
     const int tid = threadIdx.x;
-    for (int i = tid; i < (M + 1) * (M + 1); i += kThreads) coef[(i / (M + 1)) * MM + (i % (M + 1))] = Jb.coef[i];
-    for (int i = tid; i <= M; i += kThreads) {
+    for (int i = tid; i < (M + 1) * (M + 1); i += FT) coef[(i / (M + 1)) * MM + (i % (M + 1))] = Jb.coef[i];
+    for (int i = tid; i <= M; i += FT) {
         hco[i] = Jb.hco[i];
         nsplit[i] = (Jb.dref && Jb.dref[i].P) ? dense_splits_used(Jb.dref[i]) : 0;
         if (nsplit[i]) dref[i] = Jb.dref[i];
@@ -321,12 +324,12 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     // level loops are unrolled over the compile-time bound so the per-level
     // values stay in registers
     constexpr int UNR = MM <= 16 ? MM : 1;
-    int64_t nv[4][MM];
-    int64_t kv[4];
-    bool valid[4];
+    int64_t nv[QN][MM];
+    int64_t kv[QN];
+    bool valid[QN];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int r = (tid >> 5) + 8 * q;
+    for (int q = 0; q < QN; ++q) {
+        const int r = (tid >> 5) + RS * q;
         const int x = I * 32 + r, y = Jt * 32 + c;
         valid[q] = (x < N) && (y < N) && (I < Jt || r <= c);
         kv[q] = 0;
@@ -348,8 +351,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     __syncthreads();  // every read of C precedes any write (C may alias Nm_out)
     auto emit = [&](gptr<int64_t> out, auto value_of) __attribute__((always_inline)) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = (tid >> 5) + 8 * q;
+        for (int q = 0; q < QN; ++q) {
+            const int r = (tid >> 5) + RS * q;
             if (valid[q]) {
                 const int64_t v = value_of(q);
                 out[(size_t)(I * 32 + r) * N + (Jt * 32 + c)] = v;
@@ -358,8 +361,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = (tid >> 5) + 8 * q;
+        for (int q = 0; q < QN; ++q) {
+            const int r = (tid >> 5) + RS * q;
             const int sx = I * 32 + c, sy = Jt * 32 + r;  // source element (sx, sy), sx <= sy
             if (sx < N && sy < N && (I < Jt || c <= r)) out[(size_t)sy * N + sx] = tile[c][r];
         }
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const JobDev *__restrict_
     if (Jb.K_out) {
         const gptr<int64_t> kout = glb(reinterpret_cast<int64_t *>(Jb.K_out));
         emit(kout, [&](int q) {
-            const int r = (tid >> 5) + 8 * q;
+            const int r = (tid >> 5) + RS * q;
             const int64_t kx = glb(Jb.Kd)[I * 32 + r], ky = glb(Jb.Kd)[Jt * 32 + c];
             const double kh = (kx == 0 || ky == 0) ? 0.0 : (double)kv[q] / sqrt((double)kx * (double)ky);
             return __double_as_longlong(kh);
@@ -458,9 +461,9 @@ hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, u
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    if (maxM < 8) hipLaunchKernelGGL(k_finalize<8>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
-    else if (maxM < 16) hipLaunchKernelGGL(k_finalize<16>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
-    else hipLaunchKernelGGL(k_finalize<65>, dim3(nblocks), dim3(kThreads), 0, st, jobs, bprefix, njobs);
+    if (maxM < 8) hipLaunchKernelGGL((k_finalize<8, 2>), dim3(nblocks), dim3(512), 0, st, jobs, bprefix, njobs);
+    else if (maxM < 16) hipLaunchKernelGGL((k_finalize<16, 1>), dim3(nblocks), dim3(1024), 0, st, jobs, bprefix, njobs);
+    else hipLaunchKernelGGL((k_finalize<65, 4>), dim3(nblocks), dim3(256), 0, st, jobs, bprefix, njobs);
     return hipGetLastError();
 }
 
