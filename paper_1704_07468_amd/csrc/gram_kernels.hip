@@ -54,29 +54,30 @@ __global__ __launch_bounds__(kThreads) void k_extract(const JobDev *__restrict__
 }
 
 // --------------------------------------------------------- bucket count --
-// Histogram of bucket = top B bits of mix_w(reduced key) per mask.
-__global__ __launch_bounds__(kThreads) void k_bucket_count(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
-                                                           int nitems, uint32_t uniform)
+// Histogram of bucket = top B bits of mix_w(reduced key) per mask, over
+// tiles of kCountTile g-mers (larger than the scatter's: fewer global adds).
+__global__ __launch_bounds__(kCountThreads) void k_bucket_count(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
+                                                                int nitems, uint32_t uniform)
 {
     extern __shared__ uint32_t hist[];
     int it;
     uint32_t tile;
     map_block(bprefix, nitems, uniform, blockIdx.x, it, tile);
     const MaskWork &W = items[it];
-    const uint32_t t0 = tile * kTile;
+    const uint32_t t0 = tile * kCountTile;
     if (t0 >= W.T) return;
     const uint32_t nb = 1u << W.B;
-    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += kCountThreads) hist[i] = 0;
     __syncthreads();
-    for (int q = 0; q < kTile / kThreads; ++q) {
-        const uint32_t t = t0 + q * kThreads + threadIdx.x;
+    for (int q = 0; q < kCountTile / kCountThreads; ++q) {
+        const uint32_t t = t0 + q * kCountThreads + threadIdx.x;
         if (t < W.T) {
             const uint64_t h = mix_w(compact_key(glb(W.key)[t], W.md), W.w);
             atomicAdd(&hist[(uint32_t)(h >> W.hb)], 1u);
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += kThreads)
+    for (uint32_t i = threadIdx.x; i < nb; i += kCountThreads)
         if (hist[i]) g_atomic_add(glb(W.bcnt) + i, hist[i]);
 }
 
@@ -433,7 +434,7 @@ hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, i
                                int maxB, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_count, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
+    hipLaunchKernelGGL(k_bucket_count, dim3(nblocks), dim3(kCountThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
     return hipGetLastError();
 }
 hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,

@@ -364,6 +364,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     }
     for (auto &c : p.chunks) {
         c.d_pt = d.take(((size_t)c.nmask + 1) * 4, 64);
+        c.d_ptc = d.take(((size_t)c.nmask + 1) * 4, 64);
         c.d_acc = d.take(sizeof(AccWork) * (size_t)std::max(1, c.nacc), 64);
         c.d_pacc = d.take(((size_t)c.nacc + 1) * 4, 64);
     }
@@ -499,7 +500,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     size_t j = 0;
     for (auto &c : p.chunks) {
         size_t bc = 0;
-        std::vector<uint32_t> pt(1, 0);
+        std::vector<uint32_t> pt(1, 0), ptc(1, 0);
         uint64_t bound_block = 0, bound_gpk = 0, bound_gwide = 0;
         for (int q = 0; q < c.nmask; ++q) {
             const int gi = c.mfirst + q;
@@ -550,6 +551,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
                 W.tau = job_tau(ctx, jp);
             }
             pt.push_back(pt.back() + (jp.T + kTile - 1) / kTile);
+            ptc.push_back(ptc.back() + (jp.T + kCountTile - 1) / kCountTile);
         }
         // grids of the per-bucket sort: at most T / (class minimum) buckets
         // of a mask fall in the block and global classes
@@ -566,6 +568,9 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         c.uni_t = uniform_of(pt);
         c.nb_t = pt.back();
         put(c.d_pt, pt);
+        c.uni_tc = uniform_of(ptc);
+        c.nb_tc = ptc.back();
+        put(c.d_ptc, ptc);
         std::vector<uint32_t> pa(1, 0);
         for (auto &w : c.aw) pa.push_back(pa.back() + (uint32_t)p.jobs[(size_t)w.job].N);
         if (c.nacc) memcpy(blob + c.d_acc, c.aw.data(), sizeof(AccWork) * c.aw.size());
@@ -649,7 +654,7 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         const SortLists L{bcnt + c.nbuck, reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_lists), (uint32_t)c.nbuck,
                           ctx->prof_on ? ctx->prof_stat : nullptr};
         GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt), c.nbcnt, 0u, st));
-        GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
+        GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_ptc), c.nmask, c.uni_tc, c.nb_tc, c.maxB, st));
         GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, L, st));
         GK_PHASE(PH_BSCATTER, launch_bucket_scatter(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
         GK_PHASE(PH_SORT_WAVE, launch_sort_wave(cm, L, c.sgrid, st));

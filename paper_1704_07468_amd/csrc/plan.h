@@ -137,8 +137,8 @@ struct Chunk {
     int maxB = 0;
     SortGrid sgrid;
     // descriptor blob offsets
-    size_t d_pt = 0, d_acc = 0, d_pacc = 0;
-    uint32_t nb_t = 0, uni_t = 0, nb_acc = 0;
+    size_t d_pt = 0, d_ptc = 0, d_acc = 0, d_pacc = 0;
+    uint32_t nb_t = 0, uni_t = 0, nb_tc = 0, uni_tc = 0, nb_acc = 0;  // scatter / count tile grids
     int nacc = 0;
     size_t acc_lds = 0;
     std::vector<AccWork> aw;
