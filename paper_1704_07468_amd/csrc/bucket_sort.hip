@@ -520,21 +520,32 @@ __device__ __forceinline__ uint32_t cand_slot(const SegLds<NWORDS, NSLOT> &S, ui
     return S.cpre[cw] + (uint32_t)__popcll(S.cbm[cw] & ((1ull << (gs & 63)) - 1ull));
 }
 
-// Adds each lane's diagonal term v (0: none) to counter q.  When every term
-// of the wave belongs to one sequence -- a single query, whose runs all have
-// sequence 0, or a group of runs of one sequence -- the wave adds their sum
-// once instead of contending on one address lane by lane.
-__device__ __forceinline__ void diag_add(gptr<uint32_t> diag, uint32_t nseq, uint32_t v, uint32_t q)
+// Adds each lane's diagonal term v (0: none) to counter q.  The terms of a
+// wave often belong to few sequences (a query batch: every run has one of
+// few sequence ids), so that lane-by-lane atomics would contend on few
+// addresses: the wave sums the terms of one sequence at a time and adds each
+// sum once, for up to 16 sequences and while a sequence has more than one
+// term; the remaining terms go lane by lane.
+__device__ __forceinline__ void diag_add(gptr<uint32_t> diag, uint32_t nseq, uint32_t v, uint32_t q, uint32_t *dl,
+                                         uint32_t dofs)
 {
-    const uint64_t act = __ballot(v != 0);
-    if (!act) return;
-    const uint32_t q0 = (uint32_t)__builtin_amdgcn_readlane((int)q, __ffsll((long long)act) - 1);
-    if (__ballot(v != 0 && q != q0) == 0) {
-        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
-        if (__lane_id() == 0 && q0 < nseq) g_atomic_add(diag + q0, tot);
-    } else if (v != 0 && q < nseq) {
-        g_atomic_add(diag + q, v);
+    if (dl) {  // the block's LDS sums (few counters in all)
+        if (v != 0 && q < nseq) atomicAdd(&dl[dofs + q], v);
+        return;
     }
+    uint64_t act = __ballot(v != 0);
+#pragma unroll 1
+    for (int k = 0; k < 16 && act; ++k) {
+        const uint32_t q0 = (uint32_t)__builtin_amdgcn_readlane((int)q, __ffsll((long long)act) - 1);
+        const bool mine = v != 0 && q == q0;
+        const uint64_t mm = __ballot(mine);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(mine ? v : 0u), 63);
+        if (__lane_id() == 0 && q0 < nseq) g_atomic_add(diag + q0, tot);
+        if (mine) v = 0;
+        act = __ballot(v != 0);
+        if (__popcll(mm) == 1) break;  // sequences mostly distinct: the rest lane by lane
+    }
+    if (v != 0 && q < nseq) g_atomic_add(diag + q, v);
 }
 
 // Runs and groups of one sorted bucket in LDS (kb: packed words or
@@ -554,7 +565,8 @@ __device__ __forceinline__ void diag_add(gptr<uint32_t> diag, uint32_t nseq, uin
 // block, whatever its bucket.
 template <bool PK, int NW, int NWORDS, int NSLOT>
 __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint32_t base, uint32_t n, const uint64_t *kb,
-                                        const uint32_t *vb, SegLds<NWORDS, NSLOT> &S, int wave)
+                                        const uint32_t *vb, SegLds<NWORDS, NSLOT> &S, int wave, uint32_t *dl,
+                                        const uint32_t *diag0)
 {
     constexpr int NT = NW * 64;
     const int lane = __lane_id();
@@ -689,7 +701,7 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
                 }
             }
         }
-        if (diag) diag_add(diag, Nseq, dv, dq);
+        if (diag) diag_add(diag, Nseq, dv, dq, dl, (uint32_t)(W.diag - diag0));
     }
     if (gtab && n > 0 && tid == 0) bgrp[bucket] = G;
 }
@@ -744,7 +756,8 @@ struct WaveLds {
 };
 
 template <bool PK, int EL>
-__device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, WaveLds &lds)
+__device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, WaveLds &lds, uint32_t *dl,
+                                            const uint32_t *diag0)
 {
     const gptr<const uint32_t> boff = glb((const uint32_t *)W.boff);
     const uint32_t base = boff[bucket];
@@ -759,15 +772,35 @@ __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, 
         store_sorted<PK, EL>(key, val, 0, n, lds.kb, vb);
     }
     wave_sync();
-    segment<PK, 1, kWaveWords, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S, 0);
+    segment<PK, 1, kWaveWords, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S, 0, dl, diag0);
     wave_sync();
 }
 
 // Each wave takes the buckets of the wave classes in a fixed stride over
 // their concatenation, largest class first.
+// Zero / flush the block's LDS diagonal sums (L.ndiag words of dynamic LDS).
+template <int NT>
+__device__ __forceinline__ uint32_t *diag_lds_begin(const SortLists &L, uint32_t *dyn)
+{
+    if (!L.ndiag) return nullptr;
+    for (uint32_t i = threadIdx.x; i < L.ndiag; i += NT) dyn[i] = 0;
+    __syncthreads();
+    return dyn;
+}
+template <int NT>
+__device__ __forceinline__ void diag_lds_end(const SortLists &L, const uint32_t *dl)
+{
+    if (!dl) return;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < L.ndiag; i += NT)
+        if (dl[i]) g_atomic_add(glb(L.diag0) + i, dl[i]);
+}
+
 __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
 {
     __shared__ WaveLds lds[kWaves];
+    extern __shared__ uint32_t dyn_lds[];
+    uint32_t *dl = diag_lds_begin<kThreads>(L, dyn_lds);
     // packed 512, wide 256, packed 256, wide 128, ..., packed 64 (class ids)
     constexpr int order[kSortClassWave] = {3, 6, 2, 5, 1, 4, 0};
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
@@ -793,15 +826,16 @@ __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restri
         const uint32_t bucket = ent & 4095u;
         if (bucket >= (1u << W.B)) continue;
         switch (c) {
-        case 0: wave_bucket<true, 1>(W, bucket, lds[wid]); break;
-        case 1: wave_bucket<true, 2>(W, bucket, lds[wid]); break;
-        case 2: wave_bucket<true, 4>(W, bucket, lds[wid]); break;
-        case 3: wave_bucket<true, 8>(W, bucket, lds[wid]); break;
-        case 4: wave_bucket<false, 1>(W, bucket, lds[wid]); break;
-        case 5: wave_bucket<false, 2>(W, bucket, lds[wid]); break;
-        default: wave_bucket<false, 4>(W, bucket, lds[wid]); break;
+        case 0: wave_bucket<true, 1>(W, bucket, lds[wid], dl, L.diag0); break;
+        case 1: wave_bucket<true, 2>(W, bucket, lds[wid], dl, L.diag0); break;
+        case 2: wave_bucket<true, 4>(W, bucket, lds[wid], dl, L.diag0); break;
+        case 3: wave_bucket<true, 8>(W, bucket, lds[wid], dl, L.diag0); break;
+        case 4: wave_bucket<false, 1>(W, bucket, lds[wid], dl, L.diag0); break;
+        case 5: wave_bucket<false, 2>(W, bucket, lds[wid], dl, L.diag0); break;
+        default: wave_bucket<false, 4>(W, bucket, lds[wid], dl, L.diag0); break;
         }
     }
+    diag_lds_end<kThreads>(L, dl);
 }
 
 // ------------------------------------------------------ block kernel --
@@ -823,7 +857,8 @@ struct BlockLds {
 };
 
 template <bool PK, int NW>
-__device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items, gptr<const uint32_t> ents, int nb, BlockLds &lds)
+__device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items, gptr<const uint32_t> ents, int nb, BlockLds &lds,
+                                              uint32_t *dl, const uint32_t *diag0)
 {
     constexpr int EL = PK ? 16 : 8;
     constexpr int NP = NW * 64 * EL;
@@ -858,7 +893,7 @@ __device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items
         store_sorted<PK, EL>(key, val, ibase, n, kb, vb);
     }
     __syncthreads();
-    segment<PK, NW, NWORDS, NSLOT>(W, bucket, base, n, kb, vb, S, wg);
+    segment<PK, NW, NWORDS, NSLOT>(W, bucket, base, n, kb, vb, S, wg, dl, diag0);
 }
 
 // Blocks take groups of buckets of one block class from a shared ticket
@@ -867,6 +902,8 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
 {
     __shared__ BlockLds lds;
     __shared__ uint32_t ticket;
+    extern __shared__ uint32_t dyn_lds[];
+    uint32_t *dl = diag_lds_begin<kSortBlockThreads>(L, dyn_lds);
     // class offsets within the block classes, largest first: packed 16384,
     // wide 8192, packed 8192, wide 4096, ..., packed 1024, wide 512; buckets
     // per block = 16 / waves per bucket
@@ -902,19 +939,20 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
         const int nb = (int)min((uint32_t)gs, cnt - first);
         const gptr<const uint32_t> ents = glb((const uint32_t *)L.list) + (size_t)c * L.cap + first;
         switch (oc) {
-        case 0: block_buckets<true, 1>(items, ents, nb, lds); break;    // packed 1024
-        case 1: block_buckets<true, 2>(items, ents, nb, lds); break;    // packed 2048
-        case 2: block_buckets<true, 4>(items, ents, nb, lds); break;    // packed 4096
-        case 3: block_buckets<true, 8>(items, ents, nb, lds); break;    // packed 8192
-        case 4: block_buckets<true, 16>(items, ents, nb, lds); break;   // packed 16384
-        case 5: block_buckets<false, 1>(items, ents, nb, lds); break;   // wide 512
-        case 6: block_buckets<false, 2>(items, ents, nb, lds); break;   // wide 1024
-        case 7: block_buckets<false, 4>(items, ents, nb, lds); break;   // wide 2048
-        case 8: block_buckets<false, 8>(items, ents, nb, lds); break;   // wide 4096
-        default: block_buckets<false, 16>(items, ents, nb, lds); break; // wide 8192
+        case 0: block_buckets<true, 1>(items, ents, nb, lds, dl, L.diag0); break;    // packed 1024
+        case 1: block_buckets<true, 2>(items, ents, nb, lds, dl, L.diag0); break;    // packed 2048
+        case 2: block_buckets<true, 4>(items, ents, nb, lds, dl, L.diag0); break;    // packed 4096
+        case 3: block_buckets<true, 8>(items, ents, nb, lds, dl, L.diag0); break;    // packed 8192
+        case 4: block_buckets<true, 16>(items, ents, nb, lds, dl, L.diag0); break;   // packed 16384
+        case 5: block_buckets<false, 1>(items, ents, nb, lds, dl, L.diag0); break;   // wide 512
+        case 6: block_buckets<false, 2>(items, ents, nb, lds, dl, L.diag0); break;   // wide 1024
+        case 7: block_buckets<false, 4>(items, ents, nb, lds, dl, L.diag0); break;   // wide 2048
+        case 8: block_buckets<false, 8>(items, ents, nb, lds, dl, L.diag0); break;   // wide 4096
+        default: block_buckets<false, 16>(items, ents, nb, lds, dl, L.diag0); break; // wide 8192
         }
         __syncthreads();
     }
+    diag_lds_end<kSortBlockThreads>(L, dl);
 }
 
 // ----------------------------------------------------- global kernel --
@@ -961,14 +999,14 @@ hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hi
 
 hipError_t launch_sort_wave(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
 {
-    if (g.wave_blocks) hipLaunchKernelGGL(k_sort_wave, dim3(g.wave_blocks), dim3(kThreads), 0, st, items, L);
+    if (g.wave_blocks) hipLaunchKernelGGL(k_sort_wave, dim3(g.wave_blocks), dim3(kThreads), (size_t)L.ndiag * 4, st, items, L);
     return hipGetLastError();
 }
 
 hipError_t launch_sort_block(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
 {
     if (g.block_blocks)
-        hipLaunchKernelGGL(k_sort_block, dim3(g.block_blocks), dim3(kSortBlockThreads), 0, st, items, L);
+        hipLaunchKernelGGL(k_sort_block, dim3(g.block_blocks), dim3(kSortBlockThreads), (size_t)L.ndiag * 4, st, items, L);
     return hipGetLastError();
 }
 

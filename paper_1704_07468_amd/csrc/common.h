@@ -35,7 +35,13 @@ struct SortLists {
     uint32_t *list;  // [kSortClasses][cap]
     uint32_t cap;
     unsigned long long *stat;  // nullable: g-mers per kernel (wave, block, global) x (packed, wide)
+    // the diagonal counters of the chunk's masks when they form one array of
+    // at most kDiagLds words (a query batch): the sort kernels sum into LDS
+    // and add each block's sums once at its end (ndiag = 0: direct atomics)
+    uint32_t *diag0;
+    uint32_t ndiag;
 };
+constexpr uint32_t kDiagLds = 1024;
 
 // One set of removed positions ("mask"), as the runs of kept symbol fields:
 // reduced = OR_r ((key >> src[r]) & (2^wid[r]-1)) << dst[r].  The kept

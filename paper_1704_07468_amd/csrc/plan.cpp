@@ -651,8 +651,18 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     for (auto &c : p.chunks) {
         const MaskWork *cm = masks + c.mfirst;
         uint32_t *bcnt = reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt);
+        // one job's diagonal counters, [M+1][N] in one array: summed in LDS if small
+        uint32_t *diag0 = nullptr;
+        uint32_t ndiag = 0;
+        if (p.jobs.size() == 1 && !p.jobs[0].ext_diag.empty()) {
+            const size_t nd = (size_t)(p.jobs[0].M + 1) * (size_t)p.jobs[0].N;
+            if (nd <= kDiagLds) {
+                diag0 = p.jobs[0].ext_diag[0];
+                ndiag = (uint32_t)nd;
+            }
+        }
         const SortLists L{bcnt + c.nbuck, reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_lists), (uint32_t)c.nbuck,
-                          ctx->prof_on ? ctx->prof_stat : nullptr};
+                          ctx->prof_on ? ctx->prof_stat : nullptr, diag0, ndiag};
         GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt), c.nbcnt, 0u, st));
         GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_ptc), c.nmask, c.uni_tc, c.nb_tc, c.maxB, st));
         GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, L, st));
