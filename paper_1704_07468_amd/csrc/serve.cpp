@@ -124,21 +124,14 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     int64_t *Kq = reinterpret_cast<int64_t *>(scr + o_kq);
     uint32_t *C = reinterpret_cast<uint32_t *>(scr + o_C);
     GK_PHASE(PH_ROWS_KDIAG, launch_kdiag_counts(diag, n_q, R->M, R->coef, R->hco, Kq, st));
-    // grid: (level, chunk of position sets) x query x SV slab, sized so that
-    // even one query spreads over the whole device
+    // grid: (level, position set) x query x SV slab, so that even one query
+    // spreads over the whole device; one set per block measured faster at
+    // every batch size (1..160 queries) than chunks of several sets, whose
+    // partial rows are fewer but whose blocks run longer
     const int slab = (int)std::min<size_t>((size_t)R->n_sv, 4096);
-    const int nslab = (int)((R->n_sv + slab - 1) / slab);
-    // position sets per block: the most that still gives about 1024 blocks
-    // (fewer per block means more partial rows to add, more blocks more
-    // parallelism; a single query needs the latter)
-    auto items_for = [&](int mc) {
-        int n = 0;
-        for (int m = 0; m <= R->M; ++m) n += (int)((binom64(R->g, m) + mc - 1) / mc);
-        return n;
-    };
-    int mchunk = 32;
-    while (mchunk > 1 && (int64_t)items_for(mchunk) * n_q * nslab < 1024) mchunk /= 2;
-    const int nitems = items_for(mchunk);
+    const int mchunk = 1;
+    int nitems = 0;
+    for (int m = 0; m <= R->M; ++m) nitems += (int)binom64(R->g, m);
     GK_HIP(launch_fill_u32(C, (size_t)M1 * n_q * R->n_sv, 0u, st));
     GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,
                                   R->lev_count, C, st));
