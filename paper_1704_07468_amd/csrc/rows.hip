@@ -163,19 +163,27 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     }
 }
 
-// K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.
+// K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.  The
+// per-level values of up to MM levels stay in registers.
+template <int MM>
 __global__ __launch_bounds__(kThreads) void k_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef,
                                                            const int64_t *hco, int64_t *Kd)
 {
     const int x = blockIdx.x * kThreads + threadIdx.x;
     if (x >= n) return;
-    int64_t nv[65];
+    constexpr int UNR = MM <= 16 ? MM : 1;
+    int64_t nv[MM];
     int64_t kx = 0;
-    for (int m = 0; m <= M; ++m) {
-        int64_t v = diag[(size_t)m * n + x];
-        for (int j = 0; j < m; ++j) v -= coef[m * (M + 1) + j] * nv[j];
+#pragma unroll UNR
+    for (int m = 0; m < MM; ++m) {
+        int64_t v = 0;
+        if (m <= M) {
+            v = diag[(size_t)m * n + x];
+#pragma unroll UNR
+            for (int j = 0; j < m; ++j) v -= coef[m * (M + 1) + j] * nv[j];
+            kx += hco[m] * v;
+        }
         nv[m] = v;
-        kx += hco[m] * v;
     }
     Kd[x] = kx;
 }
@@ -277,7 +285,10 @@ hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t
                                hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_kdiag_counts, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, st, diag, n, M, coef, hco, Kd);
+    const dim3 grid((n + kThreads - 1) / kThreads);
+    if (M < 8) hipLaunchKernelGGL(k_kdiag_counts<8>, grid, dim3(kThreads), 0, st, diag, n, M, coef, hco, Kd);
+    else if (M < 16) hipLaunchKernelGGL(k_kdiag_counts<16>, grid, dim3(kThreads), 0, st, diag, n, M, coef, hco, Kd);
+    else hipLaunchKernelGGL(k_kdiag_counts<65>, grid, dim3(kThreads), 0, st, diag, n, M, coef, hco, Kd);
     return hipGetLastError();
 }
 
