@@ -102,6 +102,15 @@ gakco_status gakco_ctx_create(int device, size_t hbm_budget, const char *tune_js
         delete ctx;
         return GAKCO_EHIP;
     }
+    bool ok = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipEventCreateWithFlags(&ctx->fork_ev[i], hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        set_error("creating the side stream failed");
+        gakco_ctx_destroy(ctx);
+        return GAKCO_EHIP;
+    }
     *out = ctx;
     return GAKCO_OK;
 }
@@ -111,6 +120,15 @@ void gakco_ctx_destroy(gakco_ctx *ctx)
     if (!ctx) return;
     rows_scratch_release(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->side) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->fork_ev[i]) (void)hipEventDestroy(ctx->fork_ev[i]);
+        if (ctx->join_ev[i]) (void)hipEventDestroy(ctx->join_ev[i]);
+    }
     if (ctx->prof_stat) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();

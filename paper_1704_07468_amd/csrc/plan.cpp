@@ -648,7 +648,29 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     GK_PHASE(PH_VALIDATE, launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
     GK_PHASE(PH_EXTRACT, launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
+    // Independent kernels overlap on the side stream: the block sort beside
+    // the wave sort (different buckets), and, after the last chunk's sorts,
+    // the int8 products beside the last accumulation (different outputs).
+    // Not while profiling (per-kernel times) or while the stream is being
+    // captured into a graph.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    GK_HIP(hipStreamIsCapturing(st, &cap));
+    const bool dual = ctx->side && !ctx->prof_on && cap == hipStreamCaptureStatusNone;
+    auto fork = [&](int i) -> gakco_status {
+        GK_HIP(hipEventRecord(ctx->fork_ev[i], st));
+        GK_HIP(hipStreamWaitEvent(ctx->side, ctx->fork_ev[i], 0));
+        return GAKCO_OK;
+    };
+    auto join = [&](int i) -> gakco_status {
+        GK_HIP(hipEventRecord(ctx->join_ev[i], ctx->side));
+        GK_HIP(hipStreamWaitEvent(st, ctx->join_ev[i], 0));
+        return GAKCO_OK;
+    };
+    const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
+    bool dense_done = false;
+    size_t ci = 0;
     for (auto &c : p.chunks) {
+        const bool last = ++ci == p.chunks.size();
         const MaskWork *cm = masks + c.mfirst;
         uint32_t *bcnt = reinterpret_cast<uint32_t *>(p.base + p.o_pool + c.o_bcnt);
         // one job's diagonal counters, [M+1][N] in one array: summed in LDS if small
@@ -667,6 +689,24 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         GK_PHASE(PH_BCOUNT, launch_bucket_count(cm, P(c.d_ptc), c.nmask, c.uni_tc, c.nb_tc, c.maxB, st));
         GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, L, st));
         GK_PHASE(PH_BSCATTER, launch_bucket_scatter(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
+        if (dual) {
+            GK_TRY(fork(0));
+            GK_HIP(launch_sort_block(cm, L, c.sgrid, ctx->side));
+            GK_HIP(launch_sort_wave(cm, L, c.sgrid, st));
+            GK_HIP(launch_sort_global(cm, L, c.sgrid, st));
+            GK_TRY(join(0));
+            if (last && p.n_dense) {
+                GK_TRY(fork(1));
+                GK_HIP(launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, ctx->side));
+                GK_HIP(launch_dense_clear(dw, p.n_dense, ctx->side));
+                dense_done = true;
+            }
+            if (c.nacc)
+                GK_HIP(launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc), c.nacc,
+                                         c.nb_acc, c.acc_lds, st));
+            if (dense_done) GK_TRY(join(1));
+            continue;
+        }
         GK_PHASE(PH_SORT_WAVE, launch_sort_wave(cm, L, c.sgrid, st));
         GK_PHASE(PH_SORT_BLOCK, launch_sort_block(cm, L, c.sgrid, st));
         GK_PHASE(PH_SORT_GLOBAL, launch_sort_global(cm, L, c.sgrid, st));
@@ -674,12 +714,11 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
             GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc),
                                                  c.nacc, c.nb_acc, c.acc_lds, st));
     }
-    if (p.n_dense) {
-        const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
+    if (p.n_dense && !dense_done) {
         GK_PHASE(PH_DENSE_SYRK, launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));
         GK_PHASE(PH_DENSE_CLEAR, launch_dense_clear(dw, p.n_dense, st));
-        ctx->dense_dirty = false;
     }
+    if (p.n_dense) ctx->dense_dirty = false;
     if (p.nb_d) {
         GK_PHASE(PH_DIAG, launch_diag(jobs, P(p.d_pd), nj, p.nb_d, p.maxM, st));
         GK_PHASE(PH_FINALIZE, launch_finalize(jobs, P(p.d_pf), nj, p.nb_f, p.maxM, st));

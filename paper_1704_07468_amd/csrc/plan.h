@@ -42,6 +42,10 @@ struct gakco_ctx {
     int64_t prof_n[PH_COUNT] = {};
     // autotuned int8 path threshold per job class (symbol bits * 100 + g)
     std::map<int, int> class_tau;
+    // second stream (default priority) and fork/join events: the block sort
+    // runs beside the wave sort, the int8 products beside the accumulation
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev[2] = {nullptr, nullptr};
     // statistics of the last call
     int64_t last_dense_rows = 0;
     int64_t last_chunks = 0;
