@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--profile-phases", action="store_true", help="print the per-kernel table to stderr")
     ap.add_argument("--dense-tau", type=int, default=None, help="override the int8 matrix-core threshold")
     ap.add_argument("--bucket-avg", type=int, default=None, help="override the partition bucket size")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="all kernels on one stream (per-kernel traces without side-stream overlap)")
     return ap.parse_args()
 
 
@@ -272,6 +274,8 @@ def main():
         tune["dense_tau"] = args.dense_tau
     if args.bucket_avg is not None:
         tune["bucket_avg"] = args.bucket_avg
+    if args.no_overlap:
+        tune["overlap"] = 0
     ctx = gakco.Context(0, tune=tune or None)
     for _ in range(args.warmup):
         ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)

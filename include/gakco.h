@@ -75,6 +75,11 @@ const char *gakco_version(void);
  *   "profile"       1 = time every launch phase with HIP events (see
  *                   gakco_profile_get)
  *   "pool_mb"       cap of the buffer pool reused by chunks of position sets
+ *   "overlap"       1 (default) = run independent kernels of a Gram call
+ *                   side by side on a second stream of the context (the
+ *                   block sort beside the wave sort, the int8 products
+ *                   beside the accumulation); 0 = all on the caller's
+ *                   stream.  Never while profiling or under graph capture.
  *   "tau_b<B>_g<G>" dense_tau for jobs with B-bit symbols and this g (as
  *                   written by gakco_autotune)
  * Missing keys keep their defaults.  Not thread-safe: one context per host

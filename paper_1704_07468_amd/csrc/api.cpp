@@ -40,6 +40,8 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
             return GAKCO_EINVAL;
         }
         ctx->class_tau[b * 100 + g] = (int)v;
+    } else if (!strcmp(name, "overlap")) {
+        ctx->overlap = v != 0;
     } else if (!strcmp(name, "bucket_avg")) {
         if (v < 16 || v > 4096) { set_error("bucket_avg must be in 16..4096"); return GAKCO_EINVAL; }
         ctx->bucket_avg = (int)v;

@@ -651,11 +651,11 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     // Independent kernels overlap on the side stream: the block sort beside
     // the wave sort (different buckets), and, after the last chunk's sorts,
     // the int8 products beside the last accumulation (different outputs).
-    // Not while profiling (per-kernel times) or while the stream is being
-    // captured into a graph.
+    // Not while profiling (per-kernel times), with the "overlap" parameter
+    // 0, or while the stream is being captured into a graph.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     GK_HIP(hipStreamIsCapturing(st, &cap));
-    const bool dual = ctx->side && !ctx->prof_on && cap == hipStreamCaptureStatusNone;
+    const bool dual = ctx->side && ctx->overlap && !ctx->prof_on && cap == hipStreamCaptureStatusNone;
     auto fork = [&](int i) -> gakco_status {
         GK_HIP(hipEventRecord(ctx->fork_ev[i], st));
         GK_HIP(hipStreamWaitEvent(ctx->side, ctx->fork_ev[i], 0));

@@ -45,6 +45,7 @@ struct gakco_ctx {
     // second stream (default priority) and fork/join events: the block sort
     // runs beside the wave sort, the int8 products beside the accumulation
     hipStream_t side = nullptr;
+    bool overlap = true;
     hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev[2] = {nullptr, nullptr};
     // statistics of the last call
     int64_t last_dense_rows = 0;

@@ -203,15 +203,18 @@ def test_gram_invalid_args(gk):
 
 
 def test_gram_tuning_invariance(gk):
-    """Different bucket geometries give bit-identical integers (race check)."""
+    """Different bucket geometries, and the kernels on one stream or side by
+    side on two, give bit-identical integers (race check)."""
     from paper_1704_07468_amd import gakco
     d = wl.protein(N=200, lmin=50, lmax=300)
     base = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
-    for avg in (64, 2000):
-        c2 = gakco.Context(0, tune={"bucket_avg": avg})
-        r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
-        assert (r["Nm"] == base["Nm"]).all().item()
-        assert (r["K"] == base["K"]).all().item()
+    for tune in ({"bucket_avg": 64}, {"bucket_avg": 2000}, {"overlap": 0}, {"overlap": 1, "pool_mb": 16}):
+        print("tune:", tune, flush=True)
+        c2 = gakco.Context(0, tune=tune)
+        for _ in range(2):
+            r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
+            assert (r["Nm"] == base["Nm"]).all().item()
+            assert (r["K"] == base["K"]).all().item()
         c2.close()
 
 
