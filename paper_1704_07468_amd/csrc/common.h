@@ -201,7 +201,7 @@ __device__ __forceinline__ uint64_t compact_key(uint64_t key, const MaskDesc &md
 // Rows [r0, r1) of split s of at most S when R rows are used: whole 64-row
 // steps, at least kDenseMinSplitRows rows per split, so that a level with
 // few rows writes (and its epilogue reads) few partial tiles.
-constexpr uint32_t kDenseMinSplitRows = 8192;
+constexpr uint32_t kDenseMinSplitRows = 32768;
 __device__ __forceinline__ void split_range(uint32_t R, int S, int s, uint32_t &r0, uint32_t &r1)
 {
     const uint32_t used = max(1u, min((uint32_t)S, (R + kDenseMinSplitRows - 1) / kDenseMinSplitRows));
