@@ -80,7 +80,9 @@ struct JobDev {
     int32_t N, sigma, g, k, M, b, sb;  // sb = bits of a sequence id
     uint32_t T;              // number of g-mers
     int64_t nsym;            // total symbols
-    uint64_t *key;           // [T] packed g-mers, first symbol most significant
+    uint64_t *key;           // [T] packed g-mers, first symbol most significant; with
+                             // kshift > 0 the sequence id sits above them (key >> kshift)
+    int32_t kshift;          // g * b when g * b + sb <= 64 (and the keys are internal), else 0
     uint32_t *sid;           // [T] sequence of each g-mer
     int32_t *err;            // bit 0: a symbol outside [0, sigma)
     int64_t *C;              // [M+1][N][N] cumulative profiles (upper triangle accumulated)
@@ -124,6 +126,7 @@ struct MaskWork {
     int32_t tau;       // min distinct sequences of a dense group (0 = off)
     int32_t inl;       // 1: a run two entries from its group end carries the
                        // last entry in its info instead of its own index
+    int32_t kshift;    // > 0: each key carries its sequence id at this bit (the job's kshift)
     // resident tables (serving): per bucket its groups in hash-rest order
     uint4 *gtab;       // [T] (hash rest lo, hi, first entry, end entry) at bucket offset + group (nullable)
     uint32_t *bgrp;    // [2^B] groups per bucket

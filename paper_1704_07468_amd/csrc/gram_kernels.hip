@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kThreads) void k_extract(const JobDev *__restrict__
     const uint64_t fm = (1ull << J.b) - 1ull;
     uint64_t key = 0;
     for (int q = 0; q < J.g; ++q) key = (key << J.b) | ((uint64_t)(uint8_t)s[q] & fm);
-    J.key[t] = key;
+    J.key[t] = J.kshift ? key | ((uint64_t)X << J.kshift) : key;
     J.sid[t] = (uint32_t)X;
 }
 
@@ -108,9 +108,10 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
         const uint32_t t = t0 + q * kThreads + threadIdx.x;
         bk[q] = 0xFFFFFFFFu;
         if (t < W.T) {
-            const uint64_t h = mix_w(compact_key(glb(W.key)[t], W.md), W.w);
+            const uint64_t kv = glb(W.key)[t];
+            const uint64_t h = mix_w(compact_key(kv, W.md), W.w);
             bk[q] = (uint32_t)(h >> W.hb);
-            cp[q] = ((h & hmask) << W.sb) | (uint64_t)glb(W.sid)[t];
+            cp[q] = ((h & hmask) << W.sb) | (W.kshift ? (kv >> W.kshift) : (uint64_t)glb(W.sid)[t]);
             rk[q] = atomicAdd(&hist[bk[q]], 1u);
         }
     }

@@ -464,6 +464,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         J.T = jp.T;
         J.nsym = jp.nsym;
         J.key = jp.key_override ? jp.key_override : reinterpret_cast<uint64_t *>(base + jp.o_key);
+        J.kshift = (!jp.key_override && jp.g * jp.b < 64 && jp.g * jp.b + jp.sb <= 64) ? jp.g * jp.b : 0;
         J.sid = jp.sid_override ? jp.sid_override : reinterpret_cast<uint32_t *>(base + jp.o_sid);
         J.err = reinterpret_cast<int32_t *>(flags + j);
         if (jp.want_kernel) {
@@ -520,6 +521,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             W.sb = jp.sb;
             W.cb = W.hb + W.sb;
             W.key = jp.dev.key;
+            W.kshift = jp.dev.kshift;
             W.sid = jp.dev.sid;
             const size_t nb = (size_t)1 << W.B;
             W.bcnt = reinterpret_cast<uint32_t *>(pool + c.o_bcnt) + bc;
