@@ -227,7 +227,7 @@ gakco_status gakco_autotune(gakco_ctx *ctx, const gakco_job *jobs_host, int32_t 
         j.status_out = nullptr;
         classes[symbol_bits(j.sigma) * 100 + j.g].push_back(j);
     }
-    const int taus[] = {0, 32, 64, 128, 256, 512};
+    const int taus[] = {0, 32, 64, 128, 192, 256, 512};
     std::string js = "{";
     char buf[128];
     for (auto &kv : classes) {
