@@ -78,10 +78,14 @@ def algorithmic(d, masks, prof_stats, dense_rows, ntile):
     nsym = int(sum(int(l) for l in d.lens))
     tri = N * (N + 1) // 2
     # every (mask, g-mer) passes one sort kernel: packed (4-byte composite)
-    # or wide (8-byte); the partition writes that composite and the index
+    # or wide (8-byte); the partition reads the g-mer key (and the sequence
+    # id, unless it fits above the key) and writes that composite and the index
     pk_all = sum(prof_stats.get(k, 0) for k in ("wave", "block", "global"))
     wide_all = sum(prof_stats.get(k + "_wide", 0) for k in ("wave", "block", "global"))
-    scatter = 16 * T * S + 4 * pk_all + 8 * wide_all
+    b = max(1, (d.sigma - 1).bit_length())
+    sb = max(1, (N - 1).bit_length())
+    key_read = 8 if d.g * b + sb <= 64 else 12
+    scatter = key_read * T * S + 4 * pk_all + 8 * wide_all + 4 * (pk_all + wide_all)
     sortb = {}
     for kind in ("wave", "block", "global"):
         pk, wide = prof_stats.get(kind, 0), prof_stats.get(kind + "_wide", 0)
