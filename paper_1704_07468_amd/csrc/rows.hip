@@ -110,10 +110,10 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
                 const u32x4 gm = gtab[lo];
                 if ((((uint64_t)gm.y << 32) | gm.x) == hr) {
                     uint32_t e0 = gm.z, e1 = gm.w;
-                    if (A.nslab > 1) {
-                        e0 = lower_sid(glb(R.E), e0, e1, (uint32_t)s0, sidmask);
-                        e1 = lower_sid(glb(R.E), e0, e1, (uint32_t)s1, sidmask);
-                    }
+                    // the slab's part of the group (the first slab starts
+                    // at the group's start, the last ends at its end)
+                    if (s0 > 0) e0 = lower_sid(glb(R.E), e0, e1, (uint32_t)s0, sidmask);
+                    if (s1 < A.nsv) e1 = lower_sid(glb(R.E), e0, e1, (uint32_t)s1, sidmask);
                     len = e1 - e0;
                     ebase = reinterpret_cast<uint64_t>(R.E + e0);
                 }

@@ -127,8 +127,12 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     // grid: (level, position set) x query x SV slab, so that even one query
     // spreads over the whole device; one set per block measured faster at
     // every batch size (1..160 queries) than chunks of several sets, whose
-    // partial rows are fewer but whose blocks run longer
-    const int slab = (int)std::min<size_t>((size_t)R->n_sv, 4096);
+    // partial rows are fewer but whose blocks run longer.  Slabs of about a
+    // third of the SVs (4096..8192 of them: a 16..32 KB LDS row): an inner
+    // slab binary-searches its two edges in a group's entries, an outer one
+    // only one, and three slabs measured best for 20000 SVs
+    const size_t third = (R->n_sv + 2) / 3;
+    const int slab = (int)std::min<size_t>((size_t)R->n_sv, std::min<size_t>(8192, std::max<size_t>(4096, third)));
     const int mchunk = 1;
     int nitems = 0;
     for (int m = 0; m <= R->M; ++m) nitems += (int)binom64(R->g, m);
