@@ -41,9 +41,24 @@ __device__ __forceinline__ void wave_sync_rows()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// First index in E[a, b) whose sequence id is >= s (entries sequence-sorted).
-__device__ __forceinline__ uint32_t lower_sid(gptr<const uint32_t> E, uint32_t a, uint32_t b, uint32_t s, uint32_t sidmask)
+// First index in E[a, b) whose sequence id is >= s (entries sequence-sorted,
+// ids below nsv).  A long range is first narrowed around where s would fall
+// if its ids were spread evenly (two probes), then binary-searched.
+__device__ __forceinline__ uint32_t lower_sid(gptr<const uint32_t> E, uint32_t a, uint32_t b, uint32_t s, uint32_t sidmask,
+                                              uint32_t nsv)
 {
+    if (b - a > 32) {
+        constexpr uint32_t w = 8;
+        const uint32_t gs = a + (uint32_t)(((uint64_t)(b - a) * s) / nsv);
+        const uint32_t l = gs > a + w ? gs - w : a, r = min(b, gs + w);
+        if ((E[l] & sidmask) >= s) {
+            b = l + 1;  // the answer is at most l
+        } else {
+            a = l + 1;
+            if (r < b && (E[r - 1] & sidmask) < s) a = r;  // at least r
+            else b = r;                                      // in (l, r)
+        }
+    }
     while (a < b) {
         const uint32_t mid = (a + b) >> 1;
         if ((E[mid] & sidmask) < s) a = mid + 1; else b = mid;
@@ -112,8 +127,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
                     uint32_t e0 = gm.z, e1 = gm.w;
                     // the slab's part of the group (the first slab starts
                     // at the group's start, the last ends at its end)
-                    if (s0 > 0) e0 = lower_sid(glb(R.E), e0, e1, (uint32_t)s0, sidmask);
-                    if (s1 < A.nsv) e1 = lower_sid(glb(R.E), e0, e1, (uint32_t)s1, sidmask);
+                    if (s0 > 0) e0 = lower_sid(glb(R.E), e0, e1, (uint32_t)s0, sidmask, (uint32_t)A.nsv);
+                    if (s1 < A.nsv) e1 = lower_sid(glb(R.E), e0, e1, (uint32_t)s1, sidmask, (uint32_t)A.nsv);
                     len = e1 - e0;
                     ebase = reinterpret_cast<uint64_t>(R.E + e0);
                 }
