@@ -11,6 +11,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kMaxRuns = 33;     // kept positions form at most min(g-m, m+1) <= 33 runs (g <= 64)
 constexpr int kTile = 4096;      // g-mers per block in the partition scatter
+constexpr int kScatterThreads = 512;  // its threads: 8 g-mers each, 8 waves per SIMD
 constexpr int kCountTile = 16384;  // g-mers per 1024-thread block in the bucket count
 constexpr int kCountThreads = 1024;
 constexpr int kMaxBucketBits = 12;

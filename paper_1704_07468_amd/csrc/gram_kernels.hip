@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kCountThreads) void k_bucket_count(const MaskWork *
 // of at most 32 bits as one packed word composite << 32 | index, wider ones
 // in the composite array with the index beside it.  The order inside a
 // bucket is arbitrary; the bucket sort restores it.
-__global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
+__global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWork *__restrict__ items, const uint32_t *__restrict__ bprefix,
                                                              int nitems, uint32_t uniform)
 {
     extern __shared__ uint32_t hist[];
@@ -97,15 +97,15 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
     const uint32_t t0 = tile * kTile;
     if (t0 >= W.T) return;
     const uint32_t nb = 1u << W.B;
-    constexpr int Q = kTile / kThreads;
-    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) hist[i] = 0;
+    constexpr int Q = kTile / kScatterThreads;
+    for (uint32_t i = threadIdx.x; i < nb; i += kScatterThreads) hist[i] = 0;
     __syncthreads();
     uint32_t bk[Q], rk[Q];
     uint64_t cp[Q];
     const uint64_t hmask = bits_mask(W.hb);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const uint32_t t = t0 + q * kThreads + threadIdx.x;
+        const uint32_t t = t0 + q * kScatterThreads + threadIdx.x;
         bk[q] = 0xFFFFFFFFu;
         if (t < W.T) {
             const uint64_t kv = glb(W.key)[t];
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += kThreads) {
+    for (uint32_t i = threadIdx.x; i < nb; i += kScatterThreads) {
         const uint32_t c = hist[i];
         if (c) hist[i] = g_atomic_add(glb(W.bcur) + i, c);
     }
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scatter(const MaskWork *__r
     for (int q = 0; q < Q; ++q) {
         if (bk[q] != 0xFFFFFFFFu) {
             const uint32_t pos = hist[bk[q]] + rk[q];
-            const uint32_t t = t0 + q * kThreads + threadIdx.x;
+            const uint32_t t = t0 + q * kScatterThreads + threadIdx.x;
             if (narrow) {
                 glb(W.comp)[pos] = (cp[q] << 32) | t;
             } else {
@@ -442,7 +442,7 @@ hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix,
                                  int maxB, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(nblocks), dim3(kScatterThreads), (size_t)4u << maxB, st, items, bprefix, nitems, uniform);
     return hipGetLastError();
 }
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
