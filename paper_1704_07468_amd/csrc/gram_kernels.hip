@@ -147,17 +147,19 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
 // one more entry carries it in its info; longer tails are read from the run
 // entries.  Each wave consumes its own chunks of 64 (mask, g-mer) items; the
 // chunk's tails are laid end to end (a wave scan of their lengths) and the
-// lanes walk that sequence 256 updates at a time: a mark per tail start in
-// LDS, a ballot of the marks and a popcount below the lane give each update
-// its tail without a search.  The loop has no block barrier.  The row is
+// lanes walk that sequence kAccWindow updates at a time (eight gathers in
+// flight per lane): a mark per tail start in LDS, a ballot of the marks and
+// a popcount below the lane give each update its tail without a search.  The loop has no block barrier.  The row is
 // then added into the int64 C_m.
+constexpr int kAccWindow = 512;
+constexpr int kAccU = kAccWindow / 64;
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
                                                          const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
 {
     extern __shared__ uint32_t acc[];
     __shared__ uint64_t tbase[kWaves][64];  // per tail: entry address - 4 * its start in the sequence
     __shared__ uint2 tfac[kWaves][64];      // per tail: (count_X, row offset of its level)
-    __shared__ uint8_t mark[kWaves][256];   // tail starts in the current window (zero between windows)
+    __shared__ uint8_t mark[kWaves][kAccWindow];  // tail starts in the current window (zero between windows)
     const int a = find_item(bprefix, nacc, blockIdx.x);
     const AccWork &A = aw[a];
     const JobDev &J = jobs[A.job];
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     }
     const int npad = A.Npad;
     for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
-    for (int i = lane; i < 256; i += 64) mark[wid][i] = 0;
+    for (int i = lane; i < kAccWindow; i += 64) mark[wid][i] = 0;
     __syncthreads();
     const uint32_t total = (uint32_t)A.nmask * ng;
     uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
@@ -219,30 +221,30 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         }
         uint32_t done = 0;  // tails started before the window
 #pragma unroll 1
-        for (uint32_t w = 0; w < work; w += 256) {
-            const bool here = len > 0 && start >= w && start < w + 256;
+        for (uint32_t w = 0; w < work; w += kAccWindow) {
+            const bool here = len > 0 && start >= w && start < w + kAccWindow;
             if (here) mark[wid][start - w] = 1;
             wave_sync();
-            uint64_t st[4];
+            uint64_t st[kAccU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
+            for (int u = 0; u < kAccU; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
             wave_sync();
             if (here) mark[wid][start - w] = 0;
-            uint32_t k[4];
+            uint32_t k[kAccU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kAccU; ++u) {
                 k[u] = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
                 done += (uint32_t)__popcll(st[u]);
             }
-            uint32_t ent[4];
+            uint32_t ent[kAccU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kAccU; ++u) {
                 const uint32_t p = w + 64u * u + (uint32_t)lane;
                 ent[u] = 0;
                 if (p < work) ent[u] = *(gptr<const uint32_t>)(tbase[wid][k[u]] + 4ull * p);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kAccU; ++u) {
                 const uint32_t p = w + 64u * u + (uint32_t)lane;
                 if (p < work) {
                     const uint2 f = tfac[wid][k[u]];

@@ -69,11 +69,13 @@ __device__ __forceinline__ uint32_t lower_sid(gptr<const uint32_t> E, uint32_t a
 // One block per (level, chunk of the level's position sets, query, SV slab),
 // heavy levels first: the block's partial row lives in LDS and is added into
 // C at the end (integer additions, so the sum does not depend on the order).
+constexpr int kRowsWindow = 1024;  // updates per window: sixteen gathers in flight per lane
+constexpr int kRowsU = kRowsWindow / 64;
 __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
 {
     extern __shared__ uint32_t acc[];
     __shared__ uint64_t tbase[kWaves][64];  // per group range: entry address - 4 * its start in the sequence
-    __shared__ uint8_t mark[kWaves][256];   // range starts in the current window (zero between windows)
+    __shared__ uint8_t mark[kWaves][kRowsWindow];  // range starts in the current window (zero between windows)
     const int per_item = A.nq * A.nslab;
     int idx = (int)(blockIdx.x / per_item);
     const int rem = (int)(blockIdx.x % per_item);
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     const int s0 = sl * A.slab, s1 = min(A.nsv, s0 + A.slab);
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     for (int i = tid; i < s1 - s0; i += kThreads) acc[i] = 0;
-    for (int i = lane; i < 256; i += 64) mark[wid][i] = 0;
+    for (int i = lane; i < kRowsWindow; i += 64) mark[wid][i] = 0;
     __syncthreads();
     const uint32_t t0 = A.qgstart[q];
     const uint32_t ng = A.qgstart[q + 1] - t0;
@@ -134,8 +136,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
                 }
             }
         }
-        // the chunk's entry ranges end to end, walked 256 updates at a time;
-        // each update finds its range from a ballot of the range-start marks
+        // the chunk's entry ranges end to end, walked kRowsWindow updates at a
+        // time; each update finds its range from a ballot of the range-start marks
         const uint32_t inc = wave_incl_scan(len);
         const uint32_t work = __builtin_amdgcn_readlane(inc, 63);
         if (work == 0) continue;  // wave-uniform
@@ -144,18 +146,18 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
         if (len > 0) tbase[wid][lanes_below(nz)] = ebase - 4ull * start;
         uint32_t done = 0;  // ranges started before the window
 #pragma unroll 1
-        for (uint32_t w = 0; w < work; w += 256) {
-            const bool here = len > 0 && start >= w && start < w + 256;
+        for (uint32_t w = 0; w < work; w += kRowsWindow) {
+            const bool here = len > 0 && start >= w && start < w + kRowsWindow;
             if (here) mark[wid][start - w] = 1;
             wave_sync_rows();
-            uint64_t st[4];
+            uint64_t st[kRowsU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
+            for (int u = 0; u < kRowsU; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
             wave_sync_rows();
             if (here) mark[wid][start - w] = 0;
-            uint32_t ent[4];
+            uint32_t ent[kRowsU];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kRowsU; ++u) {
                 const uint32_t k = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
                 done += (uint32_t)__popcll(st[u]);
                 const uint32_t p = w + 64u * u + (uint32_t)lane;
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
                 if (p < work) ent[u] = *(gptr<const uint32_t>)(tbase[wid][k] + 4ull * p);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kRowsU; ++u) {
                 const uint32_t p = w + 64u * u + (uint32_t)lane;
                 if (p < work) atomicAdd(&acc[(ent[u] & sidmask) - (uint32_t)s0], ent[u] >> sb);
             }
