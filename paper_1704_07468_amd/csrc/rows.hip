@@ -155,14 +155,16 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
             for (int u = 0; u < kRowsU; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
             wave_sync_rows();
             if (here) mark[wid][start - w] = 0;
+            // A position past the end (last window only) has k = the last
+            // range, so clamping it to work - 1 re-reads that range's last
+            // entry: every load is valid and none waits on a branch.
             uint32_t ent[kRowsU];
 #pragma unroll
             for (int u = 0; u < kRowsU; ++u) {
                 const uint32_t k = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
                 done += (uint32_t)__popcll(st[u]);
-                const uint32_t p = w + 64u * u + (uint32_t)lane;
-                ent[u] = 0;
-                if (p < work) ent[u] = *(gptr<const uint32_t>)(tbase[wid][k] + 4ull * p);
+                const uint32_t p = min(w + 64u * u + (uint32_t)lane, work - 1u);
+                ent[u] = *(gptr<const uint32_t>)(tbase[wid][k] + 4ull * p);
             }
 #pragma unroll
             for (int u = 0; u < kRowsU; ++u) {
