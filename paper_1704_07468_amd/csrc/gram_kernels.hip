@@ -300,6 +300,20 @@ __global__ __launch_bounds__(kThreads) void k_diag(const JobDev *__restrict__ jo
 // x <= y, written to (x, y) and, through an LDS transpose, to (y, x).  QN
 // entries per thread (1024 / QN threads), so that the per-level values of
 // up to MM levels stay in registers.
+// Tile (I, J), I <= J, of the f-th upper tile in row-major order of an
+// nt x nt tile grid: row I starts at S(I) = I nt - I (I - 1) / 2.
+__device__ __forceinline__ void upper_tile(int f, int nt, int &I, int &J)
+{
+    const double b = 2.0 * nt + 1.0;
+    int i = (int)((b - sqrt(b * b - 8.0 * f)) * 0.5);
+    i = max(0, min(i, nt - 1));
+    auto S = [nt](int r) { return r * nt - r * (r - 1) / 2; };
+    while (i + 1 < nt && S(i + 1) <= f) ++i;
+    while (i > 0 && S(i) > f) --i;
+    I = i;
+    J = i + (f - S(i));
+}
+
 template <int MM, int QN>
 __global__ __launch_bounds__(1024 / QN) void k_finalize(const JobDev *__restrict__ jobs, const uint32_t *__restrict__ bprefix, int njobs)
 {
@@ -314,8 +328,8 @@ __global__ __launch_bounds__(1024 / QN) void k_finalize(const JobDev *__restrict
     const int N = Jb.N, M = Jb.M;
     const int nt = (N + 31) / 32;
     const int flat = (int)(blockIdx.x - bprefix[j]);
-    const int I = flat / nt, Jt = flat % nt;
-    if (I > Jt) return;
+    int I, Jt;
+    upper_tile(flat, nt, I, Jt);
     const int tid = threadIdx.x;
     for (int i = tid; i < (M + 1) * (M + 1); i += FT) coef[(i / (M + 1)) * MM + (i % (M + 1))] = Jb.coef[i];
     for (int i = tid; i <= M; i += FT) {
@@ -359,7 +373,7 @@ __global__ __launch_bounds__(1024 / QN) void k_finalize(const JobDev *__restrict
             const int r = (tid >> 5) + RS * q;
             if (valid[q]) {
                 const int64_t v = value_of(q);
-                out[(size_t)(I * 32 + r) * N + (Jt * 32 + c)] = v;
+                __builtin_nontemporal_store(v, &out[(size_t)(I * 32 + r) * N + (Jt * 32 + c)]);
                 tile[r][c] = v;
             }
         }
@@ -368,7 +382,7 @@ __global__ __launch_bounds__(1024 / QN) void k_finalize(const JobDev *__restrict
         for (int q = 0; q < QN; ++q) {
             const int r = (tid >> 5) + RS * q;
             const int sx = I * 32 + c, sy = Jt * 32 + r;  // source element (sx, sy), sx <= sy
-            if (sx < N && sy < N && (I < Jt || c <= r)) out[(size_t)sy * N + sx] = tile[c][r];
+            if (sx < N && sy < N && (I < Jt || c <= r)) __builtin_nontemporal_store(tile[c][r], &out[(size_t)sy * N + sx]);
         }
         __syncthreads();
     };

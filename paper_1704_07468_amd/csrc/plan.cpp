@@ -482,7 +482,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         px.push_back(px.back() + (jp.T + kThreads - 1) / kThreads);
         pd.push_back(pd.back() + (jp.want_kernel ? (uint32_t)((jp.N + kThreads - 1) / kThreads) : 0u));
         const uint32_t nt = (uint32_t)((jp.N + 31) / 32);
-        pf.push_back(pf.back() + (jp.want_kernel ? nt * nt : 0u));
+        pf.push_back(pf.back() + (jp.want_kernel ? nt * (nt + 1) / 2 : 0u));  // upper tiles
         if (jp.want_kernel) {
             const int ntile = jp.Ntile / dense_tile();
             const uint32_t tiles = (uint32_t)(ntile * (ntile + 1) / 2);
