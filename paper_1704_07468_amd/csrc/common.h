@@ -51,9 +51,10 @@ constexpr uint32_t kDiagLds = 1024;
 struct MaskDesc {
     int32_t level;  // m
     int32_t nrun;
-    uint8_t rsrc[kMaxRuns];
-    uint8_t rwid[kMaxRuns];
-    uint8_t rdst[kMaxRuns];
+    // run i: bits [src, src + wid) of the key go to [dst, dst + wid) of the
+    // reduced key; packed src | wid << 8 | dst << 16 in one word, so that a
+    // block reads the table with scalar loads
+    uint32_t run[kMaxRuns];
 };
 
 // int8 matrix-core path geometry: 128 x 128 output tiles, rows staged 64 at
@@ -197,9 +198,27 @@ __device__ __forceinline__ uint64_t mix_w(uint64_t x, int w)
 __device__ __forceinline__ uint64_t compact_key(uint64_t key, const MaskDesc &md)
 {
     uint64_t r = 0;
-    for (int i = 0; i < md.nrun; ++i)
-        r |= ((key >> md.rsrc[i]) & bits_mask(md.rwid[i])) << md.rdst[i];
+    for (int i = 0; i < md.nrun; ++i) {
+        const uint32_t w = md.run[i];
+        r |= ((key >> (w & 0xFF)) & bits_mask((int)((w >> 8) & 0xFF))) << (w >> 16);
+    }
     return r;
+}
+
+// compact_key of Q keys at once: each run of the mask is read once for all
+// of them (the run table is the same for the whole block).
+template <int Q>
+__device__ __forceinline__ void compact_keys(const uint64_t (&key)[Q], uint64_t (&r)[Q], const MaskDesc &md)
+{
+#pragma unroll
+    for (int q = 0; q < Q; ++q) r[q] = 0;
+    for (int i = 0; i < md.nrun; ++i) {
+        const uint32_t w = md.run[i];
+        const uint32_t src = w & 0xFF, dst = w >> 16;
+        const uint64_t msk = bits_mask((int)((w >> 8) & 0xFF));
+#pragma unroll
+        for (int q = 0; q < Q; ++q) r[q] |= ((key[q] >> src) & msk) << dst;
+    }
 }
 
 // Rows [r0, r1) of split s of at most S when R rows are used: whole 64-row

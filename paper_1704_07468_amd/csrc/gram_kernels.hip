@@ -69,11 +69,20 @@ __global__ __launch_bounds__(kCountThreads) void k_bucket_count(const MaskWork *
     const uint32_t nb = 1u << W.B;
     for (uint32_t i = threadIdx.x; i < nb; i += kCountThreads) hist[i] = 0;
     __syncthreads();
-    for (int q = 0; q < kCountTile / kCountThreads; ++q) {
-        const uint32_t t = t0 + q * kCountThreads + threadIdx.x;
-        if (t < W.T) {
-            const uint64_t h = mix_w(compact_key(glb(W.key)[t], W.md), W.w);
-            atomicAdd(&hist[(uint32_t)(h >> W.hb)], 1u);
+    constexpr int Q = 8;  // keys in flight per thread
+#pragma unroll 1
+    for (int h = 0; h < kCountTile / kCountThreads; h += Q) {
+        uint64_t key[Q], rk[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {  // every load issued before any is used
+            const uint32_t t = t0 + (h + q) * kCountThreads + threadIdx.x;
+            key[q] = t < W.T ? glb(W.key)[t] : 0ull;
+        }
+        compact_keys<Q>(key, rk, W.md);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t t = t0 + (h + q) * kCountThreads + threadIdx.x;
+            if (t < W.T) atomicAdd(&hist[(uint32_t)(mix_w(rk[q], W.w) >> W.hb)], 1u);
         }
     }
     __syncthreads();
@@ -101,17 +110,22 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
     for (uint32_t i = threadIdx.x; i < nb; i += kScatterThreads) hist[i] = 0;
     __syncthreads();
     uint32_t bk[Q], rk[Q];
-    uint64_t cp[Q];
+    uint64_t cp[Q], kv[Q];
     const uint64_t hmask = bits_mask(W.hb);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {  // every load issued before any is used
+        const uint32_t t = t0 + q * kScatterThreads + threadIdx.x;
+        kv[q] = t < W.T ? glb(W.key)[t] : 0ull;
+    }
+    compact_keys<Q>(kv, cp, W.md);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const uint32_t t = t0 + q * kScatterThreads + threadIdx.x;
         bk[q] = 0xFFFFFFFFu;
         if (t < W.T) {
-            const uint64_t kv = glb(W.key)[t];
-            const uint64_t h = mix_w(compact_key(kv, W.md), W.w);
+            const uint64_t h = mix_w(cp[q], W.w);
             bk[q] = (uint32_t)(h >> W.hb);
-            cp[q] = ((h & hmask) << W.sb) | (W.kshift ? (kv >> W.kshift) : (uint64_t)glb(W.sid)[t]);
+            cp[q] = ((h & hmask) << W.sb) | (W.kshift ? (kv[q] >> W.kshift) : (uint64_t)glb(W.sid)[t]);
             rk[q] = atomicAdd(&hist[bk[q]], 1u);
         }
     }

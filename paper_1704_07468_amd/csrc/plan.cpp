@@ -74,9 +74,8 @@ static MaskDesc make_mask(int g, int b, const int *removed, int m)
         if (drop[(size_t)j]) { ++j; continue; }
         int L = 0;
         while (j + L < g && !drop[(size_t)(j + L)]) ++L;
-        md.rsrc[md.nrun] = (uint8_t)((g - j - L) * b);
-        md.rwid[md.nrun] = (uint8_t)(L * b);
-        md.rdst[md.nrun] = (uint8_t)((g - m - q - L) * b);
+        const uint32_t src = (uint32_t)((g - j - L) * b), wid = (uint32_t)(L * b), dst = (uint32_t)((g - m - q - L) * b);
+        md.run[md.nrun] = src | wid << 8 | dst << 16;
         md.nrun += 1;
         q += L;
         j += L;
