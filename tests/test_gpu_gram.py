@@ -108,7 +108,7 @@ def test_gram_fig2_example(gk):
 
 
 @pytest.mark.parametrize("case", ["k_eq_g", "k_zero", "single_seq", "short_seqs", "sigma1", "gb64",
-                                  "many_buckets", "heavy_keys", "global_packed", "global_wide"])
+                                  "many_buckets", "heavy_keys", "global_packed", "global_wide", "many_short"])
 def test_gram_edge_cases(gk, case):
     rng = np.random.default_rng(99)
     if case == "k_eq_g":
@@ -138,6 +138,9 @@ def test_gram_edge_cases(gk, case):
         lens = np.full(60, 500, dtype=np.int32)
         seqs = np.where(rng.random(int(lens.sum())) < 0.95, 0, rng.integers(1, 36, int(lens.sum()))).astype(np.int8)
         d = wl.GramInput("global_wide", seqs, lens, 36, 8, 6)
+    elif case == "many_short":  # 4500 rows: an epilogue grid of 141 x 142 / 2 upper tiles
+        seqs, lens = wl.random_small(rng, 4500, 6, 14, 4)
+        d = wl.GramInput("many_short", seqs, lens, 4, 6, 4)
     run_and_compare(gk, d)
 
 
