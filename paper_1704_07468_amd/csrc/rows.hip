@@ -221,7 +221,7 @@ struct RowsFinArgs {
     int32_t chunk, nchunk;
 };
 
-constexpr int kRowsChunk = 2048;  // SVs per epilogue block
+constexpr int kRowsChunk = 512;  // SVs per epilogue block (enough blocks for one query)
 
 // One block per (query, chunk of SVs): Eq. 9 and Eq. 7 per entry, the
 // normalisation with K(sv,sv) and K(q,q), and the chunk's part of Eq. 1's
