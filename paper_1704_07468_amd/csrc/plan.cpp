@@ -562,7 +562,10 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             if (W.cb <= 32) bound_gpk += W.T / (kSortBlockMaxPk + 1);
             else bound_gwide += W.T / (kSortBlockMaxWide + 1);
         }
-        c.sgrid.wave_blocks = (uint32_t)std::min<size_t>((c.nbuck + kWaves - 1) / kWaves, 2048);
+        // one wave per bucket up to 65536 blocks (the class lists put the
+        // largest buckets first, so the first waves take the longest work);
+        // a persistent grid of 2048 blocks left its slowest waves as a tail
+        c.sgrid.wave_blocks = (uint32_t)std::min<size_t>((c.nbuck + kWaves - 1) / kWaves, 65536);
         c.sgrid.block_blocks = (uint32_t)std::min<uint64_t>(bound_block, 256);
         c.sgrid.global_blocks_pk = (uint32_t)std::min<uint64_t>(bound_gpk, 128);
         c.sgrid.global_blocks_wide = (uint32_t)std::min<uint64_t>(bound_gwide, 128);
