@@ -203,6 +203,11 @@ def test_gram_invalid_args(gk):
     with pytest.raises(gakco.GakcoError) as e:
         gk.gram(d.seqs, d.lens, 36, 11, 4)  # 11 * 6 bits > 64
     assert e.value.status == gakco.EUNSUPPORTED
+    # a row of N int32 counters must fit one block's LDS: refused before any launch
+    n_big = 40000
+    with pytest.raises(gakco.GakcoError) as e:
+        gk.gram(np.zeros(n_big, dtype=np.int8), np.ones(n_big, dtype=np.int32), 4, 1, 1, want_Nm=False)
+    assert e.value.status == gakco.EUNSUPPORTED
 
 
 def test_gram_tuning_invariance(gk):
