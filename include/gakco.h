@@ -80,6 +80,10 @@ const char *gakco_version(void);
  *                   block sort beside the wave sort, the int8 products
  *                   beside the accumulation); 0 = all on the caller's
  *                   stream.  Never while profiling or under graph capture.
+ *   "acc_slab"      columns of a Gram row per block of the row accumulation
+ *                   (0, the default: a whole row when its int32 counters fit
+ *                   the LDS, else the largest multiple of 64 that does);
+ *                   a multiple of 64, for tests and tuning
  *   "tau_b<B>_g<G>" dense_tau for jobs with B-bit symbols and this g (as
  *                   written by gakco_autotune)
  * Missing keys keep their defaults.  Not thread-safe: one context per host

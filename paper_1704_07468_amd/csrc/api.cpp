@@ -45,6 +45,12 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
     } else if (!strcmp(name, "bucket_avg")) {
         if (v < 16 || v > 4096) { set_error("bucket_avg must be in 16..4096"); return GAKCO_EINVAL; }
         ctx->bucket_avg = (int)v;
+    } else if (!strcmp(name, "acc_slab")) {
+        if (v != 0 && (v < 64 || v > (1 << 20) || v % 64)) {
+            set_error("acc_slab must be 0 or a multiple of 64 in 64..1048576");
+            return GAKCO_EINVAL;
+        }
+        ctx->acc_slab = (int)v;
     } else {
         set_error("unknown parameter '%s'", name);
         return GAKCO_EINVAL;

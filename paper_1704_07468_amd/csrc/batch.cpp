@@ -121,6 +121,7 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
     own.budget = ctx->budget;
     own.dense_tau = ctx->dense_tau;
     own.bucket_avg = ctx->bucket_avg;
+    own.acc_slab = ctx->acc_slab;
     own.pool_cap = ctx->pool_cap;
     own.lds_max = ctx->lds_max;
     own.class_tau = ctx->class_tau;

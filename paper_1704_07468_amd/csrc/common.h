@@ -141,8 +141,9 @@ struct AccWork {
     int32_t mfirst;  // first MaskWork index
     int32_t nmask;
     int32_t lev0, nlev;
-    int32_t Npad;    // LDS row stride
+    int32_t Npad;    // LDS row stride (the slab width, a multiple of 64)
     int32_t first;   // 1: first work of its (job, level): store the row, else add
+    int32_t slab, nslab;  // columns per block and blocks per row
 };
 
 // --------------------------------------------------------------------------

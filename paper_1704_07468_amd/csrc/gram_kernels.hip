@@ -163,10 +163,27 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
 // chunk's tails are laid end to end (a wave scan of their lengths) and the
 // lanes walk that sequence kAccWindow updates at a time (eight gathers in
 // flight per lane): a mark per tail start in LDS, a ballot of the marks and
-// a popcount below the lane give each update its tail without a search.  The loop has no block barrier.  The row is
-// then added into the int64 C_m.
+// a popcount below the lane give each update its tail without a search.  The
+// loop has no block barrier.  The row is then added into the int64 C_m.
+// When a row does not fit the LDS, each block takes a slab of its columns
+// [y0, y1) and cuts every tail to the entries of those sequences (a search
+// of the sequence-sorted entries); slabs below the diagonal have no work.
 constexpr int kAccWindow = 512;
 constexpr int kAccU = kAccWindow / 64;
+
+// First index in [lo, hi) whose entry's sequence is >= s (hi if none); the
+// entries of one group are sorted by sequence.
+__device__ __forceinline__ uint32_t first_seq_at_least(const uint32_t *E, uint32_t lo, uint32_t hi, uint32_t s,
+                                                       uint32_t sidmask)
+{
+    const gptr<const uint32_t> e = glb(E);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((e[mid] & sidmask) < s) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
                                                          const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
 {
@@ -177,8 +194,15 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     const int a = find_item(bprefix, nacc, blockIdx.x);
     const AccWork &A = aw[a];
     const JobDev &J = jobs[A.job];
-    const int X = (int)(blockIdx.x - bprefix[a]);
+    const int flat = (int)(blockIdx.x - bprefix[a]);
+    const int X = flat / A.nslab;
     const int N = J.N;
+    // this block's columns [y0, y1) of row X; it writes [max(X, y0), y1)
+    const int y0 = (flat - X * A.nslab) * A.slab, y1 = min(N, y0 + A.slab);
+    if (y1 <= X) return;  // the slab lies below the diagonal
+    const bool whole = A.nslab == 1;
+    const int ylo = max(X, y0);
+    const bool own_col = X >= y0;  // the diagonal entry is in this slab
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     const int sb = J.sb;
     const uint32_t sidmask = (uint32_t)bits_mask(sb);
@@ -189,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         if (A.first)
             for (int l = 0; l < A.nlev; ++l) {
                 const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
-                for (int Y = X + tid; Y < N; Y += kThreads) crow[Y] = 0;
+                for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = 0;
             }
         return;
     }
@@ -212,14 +236,24 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             const uint32_t tail = inf.y & lmask;  // entries from X's own to the group end
             if (tail) {
                 cx = inf.y >> (sb + 1);
-                off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad;
-                if (A.nlev == 1) dsum += cx * cx;
-                else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
+                // LDS index of column Y: level offset + Y - y0 (mod 2^32)
+                off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad - (uint32_t)y0;
+                if (own_col) {
+                    if (A.nlev == 1) dsum += cx * cx;
+                    else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
+                }
                 if (tail == 2) {
-                    atomicAdd(&acc[off + (inf.x & sidmask)], cx * (inf.x >> sb));
+                    const uint32_t ys = inf.x & sidmask;
+                    if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) atomicAdd(&acc[off + ys], cx * (inf.x >> sb));
                 } else if (tail > 2) {
-                    len = tail - 1;
-                    ebase = reinterpret_cast<uint64_t>(W.E + inf.x + 1);
+                    // entries [e0, e1): sequences above X in ascending order
+                    uint32_t e0 = inf.x + 1, e1 = inf.x + tail;
+                    if (!whole) {
+                        if (y0 > X + 1) e0 = first_seq_at_least(W.E, e0, e1, (uint32_t)y0, sidmask);
+                        if (y1 < N) e1 = first_seq_at_least(W.E, e0, e1, (uint32_t)y1, sidmask);
+                    }
+                    len = e1 - e0;
+                    ebase = reinterpret_cast<uint64_t>(W.E + e0);
                 }
             }
         }
@@ -269,18 +303,18 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         wave_sync();
     }
     if (A.nlev == 1) {
-        const uint32_t d = wave_incl_scan(dsum);
-        if (lane == 63 && d) atomicAdd(&acc[X], d);
+        const uint32_t d = wave_incl_scan(dsum);  // nonzero only when X is in the slab
+        if (lane == 63 && d) atomicAdd(&acc[X - y0], d);
     }
     __syncthreads();
     for (int l = 0; l < A.nlev; ++l) {
         const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
         const uint32_t *arow = acc + l * npad;
         if (A.first) {
-            for (int Y = X + tid; Y < N; Y += kThreads) crow[Y] = (int64_t)arow[Y];
+            for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = (int64_t)arow[Y - y0];
         } else {
-            for (int Y = X + tid; Y < N; Y += kThreads) {
-                const uint32_t v = arow[Y];
+            for (int Y = ylo + tid; Y < y1; Y += kThreads) {
+                const uint32_t v = arow[Y - y0];
                 if (v) crow[Y] += (int64_t)v;
             }
         }

@@ -218,9 +218,15 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         jp.o_P.assign(M1, 0);
         jp.Ntile = (jp.N + dense_tile() - 1) / dense_tile() * dense_tile();
         if (!jp.want_kernel) continue;
-        if ((size_t)jp.Npad * 4 > ctx->lds_max) {
-            set_error("N=%d needs %d bytes of LDS per row; %zu available", jp.N, jp.Npad * 4, ctx->lds_max);
-            return GAKCO_EUNSUPPORTED;
+        // row slabs: a block of the row accumulation keeps one slab of a
+        // row's int32 counters in LDS
+        {
+            const int cap = (int)std::min<size_t>(ctx->lds_max / 4 / 64 * 64, (size_t)1 << 20);
+            if (cap < 64) { set_error("no LDS for the row accumulation"); return GAKCO_EUNSUPPORTED; }
+            int S = jp.Npad;
+            if (ctx->acc_slab > 0) S = std::min(S, ctx->acc_slab);
+            jp.acc_slab = std::min(S, cap);
+            jp.acc_nslab = (jp.N + jp.acc_slab - 1) / jp.acc_slab;
         }
         jp.own_C = !jp.Cm_out && !jp.Nm_out;
         if (jp.own_C) jp.o_C = L.take(M1 * N * N * 8);
@@ -332,11 +338,13 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 w.nmask = cnt;
                 w.lev0 = lev;
                 w.nlev = 1;
-                w.Npad = jp.Npad;
+                w.Npad = jp.acc_slab;
+                w.slab = jp.acc_slab;
+                w.nslab = jp.acc_nslab;
                 w.first = stored[j][(size_t)lev] ? 0 : 1;
                 stored[j][(size_t)lev] = 1;
                 c.aw.push_back(w);
-                c.acc_lds = std::max(c.acc_lds, (size_t)jp.Npad * 4);
+                c.acc_lds = std::max(c.acc_lds, (size_t)jp.acc_slab * 4);
             }
         }
         c.nacc = (int)c.aw.size();
@@ -576,7 +584,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         c.nb_tc = ptc.back();
         put(c.d_ptc, ptc);
         std::vector<uint32_t> pa(1, 0);
-        for (auto &w : c.aw) pa.push_back(pa.back() + (uint32_t)p.jobs[(size_t)w.job].N);
+        for (auto &w : c.aw) pa.push_back(pa.back() + (uint32_t)p.jobs[(size_t)w.job].N * (uint32_t)w.nslab);
         if (c.nacc) memcpy(blob + c.d_acc, c.aw.data(), sizeof(AccWork) * c.aw.size());
         put(c.d_pacc, pa);
         c.nb_acc = pa.back();

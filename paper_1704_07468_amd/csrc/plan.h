@@ -23,6 +23,7 @@ struct gakco_ctx {
     size_t budget = 0;
     int dense_tau = 0;       // 0 = int8 matrix-core path off
     int bucket_avg = 512;    // target g-mers per hash bucket
+    int acc_slab = 0;        // columns per row-accumulation block (0: as many as the LDS holds)
     size_t pool_cap = 16ull << 30;  // per-chunk partition/sort buffers
     void *arena = nullptr;
     size_t arena_cap = 0;
@@ -114,7 +115,8 @@ struct JobPlan {
     std::vector<size_t> o_dense; // per level offset in the context's dense buffer
     std::vector<size_t> o_P;     // per level partial tiles of the split rows
     int dS = 1;                  // row splits per dense output tile
-    int Npad = 0;                // LDS row stride of the accumulation
+    int Npad = 0;                // N rounded up to 64
+    int acc_slab = 0, acc_nslab = 1;  // row-accumulation columns per block, blocks per row
     int Ntile = 0;               // sequences padded to the dense tile edge
     bool own_C = false;
     uint64_t *key_override = nullptr;  // write g-mers to caller buffers (stage entry point)

@@ -203,11 +203,43 @@ def test_gram_invalid_args(gk):
     with pytest.raises(gakco.GakcoError) as e:
         gk.gram(d.seqs, d.lens, 36, 11, 4)  # 11 * 6 bits > 64
     assert e.value.status == gakco.EUNSUPPORTED
-    # a row of N int32 counters must fit one block's LDS: refused before any launch
-    n_big = 40000
-    with pytest.raises(gakco.GakcoError) as e:
-        gk.gram(np.zeros(n_big, dtype=np.int8), np.ones(n_big, dtype=np.int32), 4, 1, 1, want_Nm=False)
-    assert e.value.status == gakco.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("slab", [64, 256])
+def test_gram_row_slabs_match_oracle(slab):
+    """Rows split into column slabs (each block a slab of a row, its tails
+    cut to the slab's sequences) give the oracle's exact integers."""
+    from paper_1704_07468_amd import gakco
+    ctx = gakco.Context(0, tune={"acc_slab": slab})
+    try:
+        for d in [wl.protein(N=600, lmin=5, lmax=200), wl.dna(N=300, length=60)]:
+            print("slab", slab, "case", d.name, "N=%d" % d.N, flush=True)
+            run_and_compare(ctx, d)
+    finally:
+        ctx.close()
+
+
+def test_gram_rows_beyond_lds():
+    """N = 40000 one-symbol sequences (g = 1, k = 1): a row of int32 counters
+    exceeds the LDS, so each row is taken in two column slabs; K(X,Y) is 1
+    exactly when the two symbols agree."""
+    import torch
+    from paper_1704_07468_amd import gakco
+    n = 40000
+    rng = np.random.default_rng(7)
+    seqs = rng.integers(0, 4, n).astype(np.int8)
+    ctx = gakco.Context(0, tune={"dense_tau": 0})
+    try:
+        r = ctx.gram(seqs, np.ones(n, dtype=np.int32), 4, 1, 1, want_Nm=False)
+        K = r["K"]
+        s = torch.as_tensor(seqs, device=K.device)
+        for r0 in range(0, n, 2000):
+            want = (s[r0:r0 + 2000, None] == s[None, :]).to(torch.float64)
+            assert torch.equal(K[r0:r0 + 2000], want), r0
+        del r, K
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
 
 
 def test_gram_tuning_invariance(gk):
@@ -216,7 +248,8 @@ def test_gram_tuning_invariance(gk):
     from paper_1704_07468_amd import gakco
     d = wl.protein(N=200, lmin=50, lmax=300)
     base = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
-    for tune in ({"bucket_avg": 64}, {"bucket_avg": 2000}, {"overlap": 0}, {"overlap": 1, "pool_mb": 16}):
+    for tune in ({"bucket_avg": 64}, {"bucket_avg": 2000}, {"overlap": 0}, {"overlap": 1, "pool_mb": 16},
+                 {"acc_slab": 128}):
         print("tune:", tune, flush=True)
         c2 = gakco.Context(0, tune=tune)
         for _ in range(2):
