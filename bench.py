@@ -15,6 +15,10 @@ Prints ONE JSON line:
                        its algorithmic bytes per launch over its mean launch
                        time, and the HBM traffic measured by rocprofv3 PMC
                        runs when those were taken from the current sources;
+  accumulate_lds       the row accumulation's sequence-pair updates per second
+                       over a probe's rate of random LDS atomic adds;
+  dense_mfma           the int8 count-matrix products' TOP/s over the dense
+                       int8 peak;
   cpu_baseline         the CPU oracle timed on a sub-Gram of the workload;
   serving              continuous-batching rows of the serving workload
                        (resident 20000 DNA support sequences, g=10, k=6) under
@@ -302,7 +306,9 @@ def main():
     prof = ctx.profile()
     sstat = {k: ctx.stat("sort_gmers_" + k) / P for k in ("wave", "wave_wide", "block", "block_wide", "global", "global_wide")}
     dense_rows = ctx.stat("dense_rows")
+    acc_updates = ctx.stat("acc_updates") / P
     ctx.set_param("profile", 0)
+    lds_peak = ctx.probe_lds_atomics(4096)  # reference rate of random LDS adds
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
@@ -333,6 +339,21 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tr is None else round(tr),
                 "algorithmic_bytes": round(per_launch), "mean_launch_ms": round(dk["mean_launch_ms"], 4)}
+    # the accumulation against its other roofs: LDS atomic adds (pair
+    # updates per second over the probe's rate) and, for the count-matrix
+    # groups, int8 MFMA
+    extra = {}
+    if "accumulate" in kern:
+        rate = acc_updates / (kern["accumulate"]["ms_per_step"] / 1e3)
+        extra["accumulate_lds"] = {"kernel": "k_accumulate", "updates_per_step": round(acc_updates),
+                                   "achieved": round(rate / 1e9, 1), "peak": round(lds_peak / 1e9, 1),
+                                   "unit": "G updates/s", "frac": round(rate / lds_peak, 4),
+                                   "peak_source": "k_lds_atomic_probe: random adds into a 4096-word LDS row"}
+    if "dense_syrk" in kern and dense_rows:
+        ops = ntile * ntile * dense_rows
+        tops = ops / (kern["dense_syrk"]["ms_per_step"] / 1e3) / 1e12
+        extra["dense_mfma"] = {"kernel": "k_dense_syrk", "rows": int(dense_rows), "achieved": round(tops, 1),
+                               "peak": 5000.0, "unit": "TOP/s", "frac": round(tops / 5000.0, 4)}
     if args.profile_phases:
         for k_, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
             a = alg.get(k_)
@@ -358,6 +379,7 @@ def main():
                                "outputs N_m int64 [4,N,N] + normalised K f64 [N,N]",
                    "N": N, "sigma": d.sigma, "g": d.g, "k": d.k, "T_gmers": T, "position_sets": sum(masks)},
         "roofline": roof,
+        **extra,
         "cpu_baseline": cpu,
         "serving": serving,
         "batched": batched,

@@ -99,9 +99,18 @@ gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value
  * "dense_tau", "bucket_avg", "arena_bytes", "dense_bytes"; with the profiler
  * on, "sort_gmers_<kind>" for kind in wave, wave_wide, block, block_wide,
  * global, global_wide: g-mers (summed over position sets) whose bucket was
- * sorted by that kernel, packed or 64-bit composites, since the last profile
- * reset (synchronises the device). */
+ * sorted by that kernel, packed or 64-bit composites, and "acc_updates":
+ * sequence-pair updates of the row accumulation (Algorithm 1
+ * countAndUpdate on the groups left to it, the diagonal terms included),
+ * since the last profile reset (synchronises the device). */
 gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *value);
+
+/* Reference rate for the row accumulation's LDS atomics: 2048 blocks of 256
+ * threads, each thread adding 1 to pseudo-random counters of an LDS row of
+ * row_words (a power of two in 64..8192) 4096 times, on the device's null
+ * stream; *updates_per_s receives adds per second.  GAKCO_EINVAL for a bad
+ * row_words or NULL pointers, GAKCO_EHIP on a runtime failure. */
+gakco_status gakco_probe_lds_atomics(gakco_ctx *ctx, int32_t row_words, double *updates_per_s);
 
 /* Event profiler (enable with the "profile" parameter): per launch phase of
  * the calls made on this context, the summed device time between HIP events

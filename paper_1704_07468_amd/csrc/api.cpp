@@ -3,6 +3,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 #include <map>
 
 #include "launch.h"
@@ -27,8 +28,8 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
         ctx->prof_on = v != 0;
         if (ctx->prof_on && !ctx->prof_stat) {
             GK_HIP(hipSetDevice(ctx->device));
-            GK_HIP(hipMalloc(&ctx->prof_stat, 8 * sizeof(unsigned long long)));
-            GK_HIP(hipMemset(ctx->prof_stat, 0, 8 * sizeof(unsigned long long)));
+            GK_HIP(hipMalloc(&ctx->prof_stat, kProfStatSlots * sizeof(unsigned long long)));
+            GK_HIP(hipMemset(ctx->prof_stat, 0, kProfStatSlots * sizeof(unsigned long long)));
         }
     } else if (!strcmp(name, "pool_mb")) {
         if (v < 16) { set_error("pool_mb must be >= 16"); return GAKCO_EINVAL; }
@@ -297,22 +298,32 @@ gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *val
     else if (!strcmp(name, "bucket_avg")) *value = ctx->bucket_avg;
     else if (!strcmp(name, "arena_bytes")) *value = (int64_t)ctx->arena_cap;
     else if (!strcmp(name, "dense_bytes")) *value = (int64_t)ctx->dense_cap;
-    else if (!strncmp(name, "sort_gmers_", 11)) {
-        // g-mers handled by each sort kernel since the last profile reset
+    else if (!strncmp(name, "sort_gmers_", 11) || !strcmp(name, "acc_updates")) {
+        // g-mers handled by each sort kernel, or pair updates of the row
+        // accumulation, since the last profile reset.  Slots: the six sort
+        // kinds, then kProfUpdSlots slots of pair updates (block b adds to
+        // slot b % kProfUpdSlots)
         static const char *kinds[6] = {"wave", "wave_wide", "block", "block_wide", "global", "global_wide"};
-        int k = -1;
-        for (int i = 0; i < 6; ++i)
+        int k = -1, nk = 1;
+        if (!strcmp(name, "acc_updates")) {
+            k = kProfUpdFirst;
+            nk = kProfUpdSlots;
+        }
+        for (int i = 0; i < 6 && k < 0; ++i)
             if (!strcmp(name + 11, kinds[i])) k = i;
         if (k < 0) { set_error("unknown statistic '%s'", name); return GAKCO_EINVAL; }
-        unsigned long long v = 0;
+        std::vector<unsigned long long> v((size_t)nk, 0ull);
         if (ctx->prof_stat) {
             if (hipSetDevice(ctx->device) != hipSuccess ||
-                hipMemcpy(&v, ctx->prof_stat + k, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) {
+                hipMemcpy(v.data(), ctx->prof_stat + k, sizeof(unsigned long long) * v.size(), hipMemcpyDeviceToHost) !=
+                    hipSuccess) {
                 set_error("reading the profiling counters failed");
                 return GAKCO_EHIP;
             }
         }
-        *value = (int64_t)v;
+        unsigned long long sum = 0;
+        for (auto x : v) sum += x;
+        *value = (int64_t)sum;
     }
     else { set_error("unknown statistic '%s'", name); return GAKCO_EINVAL; }
     return GAKCO_OK;
@@ -331,6 +342,18 @@ gakco_status gakco_profile_get(const gakco_ctx *ctx, int32_t phase, const char *
     return GAKCO_OK;
 }
 
+gakco_status gakco_probe_lds_atomics(gakco_ctx *ctx, int32_t row_words, double *updates_per_s)
+{
+    clear_error();
+    if (!ctx || !updates_per_s || row_words < 64 || row_words > 8192 || (row_words & (row_words - 1))) {
+        set_error("row_words must be a power of two in 64..8192");
+        return GAKCO_EINVAL;
+    }
+    GK_HIP(hipSetDevice(ctx->device));
+    GK_HIP(probe_lds_atomics(row_words, updates_per_s));
+    return GAKCO_OK;
+}
+
 void gakco_profile_reset(gakco_ctx *ctx)
 {
     if (!ctx) return;
@@ -339,7 +362,7 @@ void gakco_profile_reset(gakco_ctx *ctx)
         ctx->prof_n[i] = 0;
     }
     if (ctx->prof_stat && hipSetDevice(ctx->device) == hipSuccess)
-        (void)hipMemset(ctx->prof_stat, 0, 8 * sizeof(unsigned long long));
+        (void)hipMemset(ctx->prof_stat, 0, kProfStatSlots * sizeof(unsigned long long));
 }
 
 }  // extern "C"

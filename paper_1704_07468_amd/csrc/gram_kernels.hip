@@ -185,7 +185,8 @@ __device__ __forceinline__ uint32_t first_seq_at_least(const uint32_t *E, uint32
     return lo;
 }
 __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
-                                                         const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc)
+                                                         const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc,
+                                                         unsigned long long *updates)
 {
     extern __shared__ uint32_t acc[];
     __shared__ uint64_t tbase[kWaves][64];  // per tail: entry address - 4 * its start in the sequence
@@ -223,6 +224,8 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     __syncthreads();
     const uint32_t total = (uint32_t)A.nmask * ng;
     uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
+    uint32_t nupd = 0;           // this lane's diagonal and inline pair updates
+    unsigned long long wupd = 0;  // the wave's gathered pair updates (profiling count)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t q = c0 + lane;
         uint32_t len = 0;
@@ -241,10 +244,14 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
                 if (own_col) {
                     if (A.nlev == 1) dsum += cx * cx;
                     else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
+                    ++nupd;
                 }
                 if (tail == 2) {
                     const uint32_t ys = inf.x & sidmask;
-                    if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) atomicAdd(&acc[off + ys], cx * (inf.x >> sb));
+                    if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) {
+                        atomicAdd(&acc[off + ys], cx * (inf.x >> sb));
+                        ++nupd;
+                    }
                 } else if (tail > 2) {
                     // entries [e0, e1): sequences above X in ascending order
                     uint32_t e0 = inf.x + 1, e1 = inf.x + tail;
@@ -260,6 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         const uint32_t inc = wave_incl_scan(len);
         const uint32_t work = __builtin_amdgcn_readlane(inc, 63);
         if (work == 0) continue;  // wave-uniform
+        wupd += work;
         const uint32_t start = inc - len;  // this tail's first position in the sequence
         const uint64_t nz = __ballot(len > 0);
         if (len > 0) {  // tails in start order: k = nonempty tails below this lane
@@ -305,6 +313,10 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     if (A.nlev == 1) {
         const uint32_t d = wave_incl_scan(dsum);  // nonzero only when X is in the slab
         if (lane == 63 && d) atomicAdd(&acc[X - y0], d);
+    }
+    if (updates) {  // profiling count, spread over 256 slots by block
+        const uint32_t u = wave_incl_scan(nupd);
+        if (lane == 63) atomicAdd(updates + (blockIdx.x & 255u), wupd + (unsigned long long)u);
     }
     __syncthreads();
     for (int l = 0; l < A.nlev; ++l) {
@@ -510,11 +522,63 @@ hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix,
     return hipGetLastError();
 }
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
-                             uint32_t nblocks, size_t lds_bytes, hipStream_t st)
+                             uint32_t nblocks, size_t lds_bytes, unsigned long long *updates, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_accumulate, dim3(nblocks), dim3(kThreads), lds_bytes, st, jobs, items, aw, bprefix, nacc);
+    hipLaunchKernelGGL(k_accumulate, dim3(nblocks), dim3(kThreads), lds_bytes, st, jobs, items, aw, bprefix, nacc, updates);
     return hipGetLastError();
+}
+
+// Reference rate for the row accumulation: every thread adds 1 to row
+// counters at pseudo-random LDS addresses (a 32-bit LCG, Numerical Recipes
+// constants), iters times.  The row is summed afterwards so that the adds
+// are kept; the sum equals threads * iters and is stored only if it is not.
+__global__ __launch_bounds__(kThreads) void k_lds_atomic_probe(int row_words, int iters, uint32_t *sink)
+{
+    extern __shared__ uint32_t row[];
+    for (int i = threadIdx.x; i < row_words; i += kThreads) row[i] = 0;
+    __syncthreads();
+    uint32_t x = blockIdx.x * kThreads + threadIdx.x + 1u;
+    const uint32_t msk = (uint32_t)row_words - 1u;
+    for (int it = 0; it < iters; ++it) {
+        x = x * 1664525u + 1013904223u;
+        atomicAdd(&row[(x >> 12) & msk], 1u);
+    }
+    __syncthreads();
+    uint32_t sum = 0;
+    for (int i = threadIdx.x; i < row_words; i += kThreads) sum += row[i];
+    __shared__ uint32_t tot;
+    if (threadIdx.x == 0) tot = 0;
+    __syncthreads();
+    atomicAdd(&tot, sum);
+    __syncthreads();
+    if (threadIdx.x == 0 && tot != (uint32_t)(kThreads * iters)) sink[0] = tot;
+}
+
+hipError_t probe_lds_atomics(int row_words, double *updates_per_s)
+{
+    constexpr int kBlocks = 2048, kIters = 4096;
+    uint32_t *sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipMalloc(&sink, sizeof(uint32_t));
+    if (err == hipSuccess) err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
+    float ms = 0.f;
+    if (err == hipSuccess) {
+        const size_t lds = (size_t)row_words * 4;
+        hipLaunchKernelGGL(k_lds_atomic_probe, dim3(kBlocks), dim3(kThreads), lds, nullptr, row_words, kIters, sink);
+        (void)hipEventRecord(e0, nullptr);
+        hipLaunchKernelGGL(k_lds_atomic_probe, dim3(kBlocks), dim3(kThreads), lds, nullptr, row_words, kIters, sink);
+        (void)hipEventRecord(e1, nullptr);
+        err = hipGetLastError();
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (sink) (void)hipFree(sink);
+    if (err == hipSuccess) *updates_per_s = (double)kBlocks * kThreads * kIters / (ms * 1e-3);
+    return err;
 }
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st)
 {

@@ -29,7 +29,10 @@ hipError_t launch_sort_wave(const MaskWork *items, SortLists L, const SortGrid &
 hipError_t launch_sort_block(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_sort_global(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,
-                             uint32_t nblocks, size_t lds_bytes, hipStream_t st);
+                             uint32_t nblocks, size_t lds_bytes, unsigned long long *updates, hipStream_t st);
+// Random-address LDS atomic adds over a row of row_words (a power of two)
+// counters, as the row accumulation issues them: updates per second.
+hipError_t probe_lds_atomics(int row_words, double *updates_per_s);
 hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);
 hipError_t launch_dense_syrk(const DenseWork *dw, const uint32_t *bprefix, int nwork, uint32_t nblocks, hipStream_t st);
 hipError_t launch_dense_clear(const DenseWork *dw, int nwork, hipStream_t st);

@@ -678,6 +678,8 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         GK_HIP(hipStreamWaitEvent(st, ctx->join_ev[i], 0));
         return GAKCO_OK;
     };
+    // pair updates of the row accumulation (profiling count, spread slots)
+    unsigned long long *acc_upd = ctx->prof_on && ctx->prof_stat ? ctx->prof_stat + kProfUpdFirst : nullptr;
     const DenseWork *dw = reinterpret_cast<const DenseWork *>(d + p.d_dense);
     bool dense_done = false;
     size_t ci = 0;
@@ -715,7 +717,7 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
             }
             if (c.nacc)
                 GK_HIP(launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc), c.nacc,
-                                         c.nb_acc, c.acc_lds, st));
+                                         c.nb_acc, c.acc_lds, acc_upd, st));
             if (dense_done) GK_TRY(join(1));
             continue;
         }
@@ -724,7 +726,7 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         GK_PHASE(PH_SORT_GLOBAL, launch_sort_global(cm, L, c.sgrid, st));
         if (c.nacc)
             GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc),
-                                                 c.nacc, c.nb_acc, c.acc_lds, st));
+                                                 c.nacc, c.nb_acc, c.acc_lds, acc_upd, st));
     }
     if (p.n_dense && !dense_done) {
         GK_PHASE(PH_DENSE_SYRK, launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));

@@ -18,6 +18,11 @@ enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTE
                PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
                PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_COUNT };
 
+// profiling counter slots: six sort kinds, then the row accumulation's pair
+// updates spread over kProfUpdSlots slots (one per block residue) so that the
+// counting adds no same-address contention to the timed kernel
+constexpr int kProfUpdFirst = 8, kProfUpdSlots = 256, kProfStatSlots = kProfUpdFirst + kProfUpdSlots;
+
 struct gakco_ctx {
     int device = 0;
     size_t budget = 0;
@@ -35,7 +40,7 @@ struct gakco_ctx {
     bool dense_dirty = false;
     // event profiler
     bool prof_on = false;
-    unsigned long long *prof_stat = nullptr;  // device: g-mers per sort kernel class (profiling only)
+    unsigned long long *prof_stat = nullptr;  // device, profiling only: g-mers per sort kind, pair updates
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<std::pair<int, size_t>> ev_pending;  // (phase, first of two events)

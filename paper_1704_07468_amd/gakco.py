@@ -79,6 +79,7 @@ def lib():
                 "gakco_profile_phases": ([], i32),
                 "gakco_profile_get": ([P, i32, P, P, P], i32),
                 "gakco_profile_reset": ([P], None),
+                "gakco_probe_lds_atomics": ([P, i32, P], i32),
             }
             for name, (args, res) in sig.items():
                 fn = getattr(L, name, None)
@@ -147,6 +148,13 @@ class Context:
 
     def profile_reset(self):
         lib().gakco_profile_reset(self._h)
+
+    def probe_lds_atomics(self, row_words: int = 4096) -> float:
+        """Random-address LDS atomic adds per second (the row accumulation's
+        reference rate) over a row of row_words counters."""
+        v = ctypes.c_double()
+        _check(lib().gakco_probe_lds_atomics(self._h, row_words, ctypes.byref(v)))
+        return v.value
 
     def stat(self, name: str) -> int:
         v = ctypes.c_int64()
