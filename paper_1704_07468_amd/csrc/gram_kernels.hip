@@ -591,7 +591,7 @@ hipError_t launch_diag(const JobDev *jobs, const uint32_t *bprefix, int njobs, u
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    if (maxM < 8) hipLaunchKernelGGL((k_finalize<8, 2>), dim3(nblocks), dim3(512), 0, st, jobs, bprefix, njobs);
+    if (maxM < 8) hipLaunchKernelGGL((k_finalize<8, 1>), dim3(nblocks), dim3(1024), 0, st, jobs, bprefix, njobs);
     else if (maxM < 16) hipLaunchKernelGGL((k_finalize<16, 1>), dim3(nblocks), dim3(1024), 0, st, jobs, bprefix, njobs);
     else hipLaunchKernelGGL((k_finalize<65, 4>), dim3(nblocks), dim3(256), 0, st, jobs, bprefix, njobs);
     return hipGetLastError();
