@@ -36,8 +36,13 @@
  *   - the mask loop of Algorithm 1 runs over the C(g,m) m-subsets of
  *     positions (n_pos of them, upper bound exclusive).
  *
- * Parallel mode: Section 2.2 ("Parallelization") runs one thread per m; the
- * same is offered here (nthreads > 1) purely to time the paper's own design.
+ * Parallel modes (they change no arithmetic: every thread adds exact int64
+ * products into a private matrix and the matrices are summed at the end):
+ *   per level  Section 2.2 ("Parallelization"): one thread per m, the paper's
+ *              own parallel version, offered to time that design;
+ *   per mask   Section S:5.3 ("GaKCo-Parallel+"): the position sets of all
+ *              levels are dealt to the threads, which is how the tests run
+ *              the oracle at full workload sizes.
  *
  * Parity status: every function here is pinned by the CPU tests against
  * brute force on tiny inputs (pairwise Hamming distances, Eq. 4 feature-map
@@ -287,9 +292,67 @@ static void *orc_level_thread(void *arg)
     return NULL;
 }
 
-/* MISMATCHPROFILE(L, g, M): C_0..C_M, then N_0..N_M by Eq. 9. */
+/* Per-mask parallel mode (Section S:5.3): thread t takes every nthreads-th
+ * position set of the list of all levels' position sets and adds its
+ * products into a private [M+1][N][N] matrix. */
+typedef struct {
+    const orc_gmer_list *L;
+    int32_t N, M, tid, nthreads;
+    int64_t *C;  /* private [M+1][N][N], zeroed */
+    int rc;
+} orc_mask_job;
+
+static void *orc_mask_thread(void *arg)
+{
+    orc_mask_job *j = (orc_mask_job *)arg;
+    const size_t NN = (size_t)j->N * (size_t)j->N;
+    int64_t item = 0;
+    for (int32_t m = 0; m <= j->M && j->rc == ORC_OK; ++m) {
+        int32_t P[64];
+        for (int32_t q = 0; q < m; ++q) P[q] = q;
+        do {
+            if (item % j->nthreads == j->tid) j->rc = orc_add_mask(j->L, j->N, P, m, j->C + (size_t)m * NN);
+            ++item;
+        } while (j->rc == ORC_OK && m > 0 && orc_next_subset(P, m, j->L->g));
+    }
+    return NULL;
+}
+
+static int orc_profiles_per_mask(const orc_gmer_list *L, int32_t N, int32_t M, int32_t nthreads, int64_t *C)
+{
+    const size_t NN = (size_t)N * (size_t)N, tot = NN * (size_t)(M + 1);
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    orc_mask_job jobs[256];
+    int rc = ORC_OK;
+    int32_t started = 0;
+    /* thread 0 adds into C itself, the others into private zeroed copies */
+    memset(C, 0, sizeof(int64_t) * tot);
+    for (int32_t t = 0; t < nthreads; ++t) {
+        int64_t *priv = t ? (int64_t *)calloc(tot ? tot : 1, sizeof(int64_t)) : C;
+        if (!priv) { rc = ORC_ENOMEM; break; }
+        jobs[t] = (orc_mask_job){L, N, M, t, nthreads, priv, ORC_OK};
+        ++started;
+    }
+    if (rc == ORC_OK) {
+        for (int32_t t = 0; t < started; ++t) pthread_create(&th[t], NULL, orc_mask_thread, &jobs[t]);
+        for (int32_t t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    }
+    for (int32_t t = 0; t < started; ++t) {
+        if (rc == ORC_OK && jobs[t].rc != ORC_OK) rc = jobs[t].rc;
+        if (t == 0) continue;
+        if (rc == ORC_OK)
+            for (size_t e = 0; e < tot; ++e) C[e] += jobs[t].C[e];
+        free(jobs[t].C);
+    }
+    return rc;
+}
+
+/* MISMATCHPROFILE(L, g, M): C_0..C_M, then N_0..N_M by Eq. 9.
+ * nthreads <= 1: sequential; otherwise one thread per m (per_mask = 0) or
+ * the position sets dealt to nthreads threads (per_mask = 1). */
 int orc_mismatch_profile(const int8_t *seqs, const int32_t *lens, int32_t N, int32_t g,
-                         int32_t M, int32_t nthreads, int64_t *C_out, int64_t *Nm_out)
+                         int32_t M, int32_t nthreads, int32_t per_mask, int64_t *C_out, int64_t *Nm_out)
 {
     if (N < 0 || g < 1 || M < 0 || M > g || !Nm_out) return ORC_EINVAL;
     for (int32_t i = 0; i < N; ++i)
@@ -304,6 +367,8 @@ int orc_mismatch_profile(const int8_t *seqs, const int32_t *lens, int32_t N, int
     if (nthreads <= 1) {
         for (int32_t m = 0; m <= M && rc == ORC_OK; ++m)
             rc = orc_cumulative_profile(&L, N, m, C + (size_t)m * NN);
+    } else if (per_mask) {
+        rc = orc_profiles_per_mask(&L, N, M, nthreads, C);
     } else {
         /* one thread per m, as in the paper's parallel version */
         pthread_t th[65];
@@ -339,7 +404,7 @@ int orc_mismatch_profile(const int8_t *seqs, const int32_t *lens, int32_t N, int
  * normalisation.  Any output pointer may be NULL except that at least one of
  * K_out / Kn_out should be given for the call to be useful. */
 int orc_kernel(const int8_t *seqs, const int32_t *lens, int32_t N, int32_t g, int32_t k,
-               int32_t nthreads, int64_t *C_out, int64_t *Nm_out, int64_t *K_out,
+               int32_t nthreads, int32_t per_mask, int64_t *C_out, int64_t *Nm_out, int64_t *K_out,
                double *Kn_out)
 {
     if (N < 0 || g < 1 || k < 0 || k > g) return ORC_EINVAL;
@@ -352,7 +417,7 @@ int orc_kernel(const int8_t *seqs, const int32_t *lens, int32_t N, int32_t g, in
         if (!K_out) free(K);
         return ORC_ENOMEM;
     }
-    int rc = orc_mismatch_profile(seqs, lens, N, g, M, nthreads, C_out, Nm);
+    int rc = orc_mismatch_profile(seqs, lens, N, g, M, nthreads, per_mask, C_out, Nm);
     if (rc == ORC_OK) {
         for (size_t e = 0; e < NN; ++e) K[e] = 0;
         for (int32_t m = 0; m <= M; ++m) {
@@ -470,13 +535,55 @@ static void orc_rows_visitor(const orc_group *grp, int64_t first_rec, void *arg)
     }
 }
 
+/* The position sets of levels 0..M dealt to nthreads threads (Section S:5.3);
+ * thread tid adds the cross block and the diagonal of its sets into its own
+ * Cq [M+1][n_q][n_sv] and Cd [M+1][n_sv+n_q]. */
+typedef struct {
+    const orc_gmer_list *L;
+    int32_t n_sv, n_q, M, tid, nthreads;
+    int64_t *Cq, *Cd;
+    int rc;
+} orc_rows_job;
+
+static void *orc_rows_thread(void *arg)
+{
+    orc_rows_job *j = (orc_rows_job *)arg;
+    const int32_t NT = j->n_sv + j->n_q;
+    const size_t QS = (size_t)j->n_q * (size_t)j->n_sv;
+    int32_t *sid_buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(NT > 0 ? NT : 1));
+    int64_t *cnt_buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NT > 0 ? NT : 1));
+    if (!sid_buf || !cnt_buf) { j->rc = ORC_ENOMEM; free(sid_buf); free(cnt_buf); return NULL; }
+    int64_t item = 0;
+    for (int32_t m = 0; m <= j->M && j->rc == ORC_OK; ++m) {
+        int32_t P[64];
+        for (int32_t q = 0; q < m; ++q) P[q] = q;
+        orc_rows_ctx r = {j->Cq + (size_t)m * QS, j->Cd + (size_t)m * NT, j->n_sv, j->n_q};
+        do {
+            if (item % j->nthreads == j->tid) {
+                orc_rec_layout lay;
+                uint8_t *recs = orc_remove_positions(j->L, P, m, &lay);
+                if (!recs) { j->rc = ORC_ENOMEM; break; }
+                qsort_r(recs, (size_t)j->L->T, lay.stride, orc_rec_cmp, &lay);
+                orc_count_groups(recs, j->L->T, &lay, sid_buf, cnt_buf, orc_rows_visitor, &r);
+                free(recs);
+            }
+            ++item;
+        } while (m > 0 && orc_next_subset(P, m, j->L->g));
+    }
+    free(sid_buf);
+    free(cnt_buf);
+    return NULL;
+}
+
 /* Algorithm 1 on the union of the resident sequences and the queries,
  * keeping only the query-by-resident block and the diagonal; then Eq. 9,
  * Eq. 7, the cosine normalisation, and f(q) = sum_i alpha_i K-hat(sv_i, q) + b
- * (Eq. 1, alpha_i standing for alpha_i * y_i) summed in ascending i. */
+ * (Eq. 1, alpha_i standing for alpha_i * y_i) summed in ascending i.  With
+ * nthreads > 1 the position sets are dealt to threads (exact int64 sums). */
 int orc_rows(const int8_t *sv_seqs, const int32_t *sv_lens, int32_t n_sv,
              const int8_t *q_seqs, const int32_t *q_lens, int32_t n_q, int32_t g, int32_t k,
-             const double *alpha, double bias, double *Krows, int64_t *Nm_rows, double *decision)
+             const double *alpha, double bias, int32_t nthreads, double *Krows, int64_t *Nm_rows,
+             double *decision)
 {
     if (n_sv < 0 || n_q < 0 || g < 1 || k < 0 || k > g) return ORC_EINVAL;
     const int32_t M = g - k, NT = n_sv + n_q;
@@ -490,29 +597,42 @@ int orc_rows(const int8_t *sv_seqs, const int32_t *sv_lens, int32_t n_sv,
     int64_t *Cd = (int64_t *)calloc((size_t)(NT > 0 ? NT : 1) * (size_t)(M + 1), sizeof(int64_t));
     int64_t *Nq = (int64_t *)calloc((QS ? QS : 1) * (size_t)(M + 1), sizeof(int64_t));
     int64_t *Nd = (int64_t *)calloc((size_t)(NT > 0 ? NT : 1) * (size_t)(M + 1), sizeof(int64_t));
-    int32_t *sid_buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(NT > 0 ? NT : 1));
-    int64_t *cnt_buf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NT > 0 ? NT : 1));
     int rc = ORC_OK;
     orc_gmer_list L = {0, 0, NULL, NULL};
-    if (!seqs || !lens || !Cq || !Cd || !Nq || !Nd || !sid_buf || !cnt_buf) { rc = ORC_ENOMEM; goto done; }
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    orc_rows_job jobs[256];
+    int32_t started = 0;
+    if (!seqs || !lens || !Cq || !Cd || !Nq || !Nd) { rc = ORC_ENOMEM; goto done; }
     memcpy(seqs, sv_seqs, (size_t)sv_tot);
     memcpy(seqs + sv_tot, q_seqs, (size_t)q_tot);
     memcpy(lens, sv_lens, sizeof(int32_t) * (size_t)n_sv);
     memcpy(lens + n_sv, q_lens, sizeof(int32_t) * (size_t)n_q);
     if (orc_extract(seqs, lens, NT, g, &L) != ORC_OK) { rc = ORC_ENOMEM; goto done; }
-    for (int32_t m = 0; m <= M; ++m) {
-        int32_t P[64];
-        for (int32_t j = 0; j < m; ++j) P[j] = j;
-        orc_rows_ctx r = {Cq + (size_t)m * QS, Cd + (size_t)m * NT, n_sv, n_q};
-        do {
-            orc_rec_layout lay;
-            uint8_t *recs = orc_remove_positions(&L, P, m, &lay);
-            if (!recs) { rc = ORC_ENOMEM; goto done; }
-            qsort_r(recs, (size_t)L.T, lay.stride, orc_rec_cmp, &lay);
-            orc_count_groups(recs, L.T, &lay, sid_buf, cnt_buf, orc_rows_visitor, &r);
-            free(recs);
-        } while (m > 0 && orc_next_subset(P, m, g));
+    /* thread 0 adds into Cq / Cd directly, the others into private copies */
+    for (int32_t t = 0; t < nthreads; ++t) {
+        int64_t *pq = t ? (int64_t *)calloc((QS ? QS : 1) * (size_t)(M + 1), sizeof(int64_t)) : Cq;
+        int64_t *pd = t ? (int64_t *)calloc((size_t)(NT > 0 ? NT : 1) * (size_t)(M + 1), sizeof(int64_t)) : Cd;
+        if (!pq || !pd) { if (t) { free(pq); free(pd); } rc = ORC_ENOMEM; break; }
+        jobs[t] = (orc_rows_job){&L, n_sv, n_q, M, t, nthreads, pq, pd, ORC_OK};
+        ++started;
     }
+    if (rc == ORC_OK) {
+        for (int32_t t = 0; t < started; ++t) pthread_create(&th[t], NULL, orc_rows_thread, &jobs[t]);
+        for (int32_t t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    }
+    for (int32_t t = 0; t < started; ++t) {
+        if (rc == ORC_OK && jobs[t].rc != ORC_OK) rc = jobs[t].rc;
+        if (t == 0) continue;
+        if (rc == ORC_OK) {
+            for (size_t e = 0; e < QS * (size_t)(M + 1); ++e) Cq[e] += jobs[t].Cq[e];
+            for (size_t e = 0; e < (size_t)NT * (size_t)(M + 1); ++e) Cd[e] += jobs[t].Cd[e];
+        }
+        free(jobs[t].Cq);
+        free(jobs[t].Cd);
+    }
+    if (rc != ORC_OK) goto done;
     /* Eq. 9 on the cross block and on the diagonal */
     for (int32_t m = 0; m <= M; ++m) {
         for (size_t e = 0; e < QS; ++e) {
@@ -545,6 +665,6 @@ int orc_rows(const int8_t *sv_seqs, const int32_t *sv_lens, int32_t n_sv,
     if (Nm_rows) memcpy(Nm_rows, Nq, sizeof(int64_t) * QS * (size_t)(M + 1));
 done:
     orc_free_list(&L);
-    free(seqs); free(lens); free(Cq); free(Cd); free(Nq); free(Nd); free(sid_buf); free(cnt_buf);
+    free(seqs); free(lens); free(Cq); free(Cd); free(Nq); free(Nd);
     return rc;
 }

@@ -50,13 +50,13 @@ def _load():
             lib.orc_total_gmers.restype = i64
             lib.orc_gmers.argtypes = [P, P, i32, i32, P, P, i64]
             lib.orc_gmers.restype = i64
-            lib.orc_mismatch_profile.argtypes = [P, P, i32, i32, i32, i32, P, P]
+            lib.orc_mismatch_profile.argtypes = [P, P, i32, i32, i32, i32, i32, P, P]
             lib.orc_mismatch_profile.restype = ctypes.c_int
-            lib.orc_kernel.argtypes = [P, P, i32, i32, i32, i32, P, P, P, P]
+            lib.orc_kernel.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, P, P]
             lib.orc_kernel.restype = ctypes.c_int
             lib.orc_mask_groups.argtypes = [P, P, i32, i32, P, i32, P, P, i64, P, P, i64]
             lib.orc_mask_groups.restype = i64
-            lib.orc_rows.argtypes = [P, P, i32, P, P, i32, i32, i32, P, f64, P, P, P]
+            lib.orc_rows.argtypes = [P, P, i32, P, P, i32, i32, i32, P, f64, i32, P, P, P]
             lib.orc_rows.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -72,6 +72,11 @@ def _prep(seqs, lens):
     if seqs.size == 0:
         seqs = np.zeros(1, dtype=np.int8)
     return seqs, lens
+
+
+def host_threads(cap: int = 16) -> int:
+    """Threads for full-size oracle runs: the host's cores, at most `cap`."""
+    return max(1, min(cap, os.cpu_count() or 1))
 
 
 def binomial(n: int, r: int) -> int:
@@ -91,21 +96,27 @@ def gmers(seqs, lens, g):
     return sym[:T], sid[:T]
 
 
-def mismatch_profile(seqs, lens, g, M, threads: int = 1):
-    """(C, N): cumulative and exact mismatch profiles, each [M+1, N, N] int64."""
+def mismatch_profile(seqs, lens, g, M, threads: int = 1, per_mask: bool = False):
+    """(C, N): cumulative and exact mismatch profiles, each [M+1, N, N] int64.
+
+    threads > 1 runs one thread per m (Section 2.2), or with per_mask the
+    position sets dealt to `threads` threads (Section S:5.3)."""
     lib = _load()
     seqs, lens = _prep(seqs, lens)
     N = len(lens)
     C = np.zeros((M + 1, N, N), dtype=np.int64)
     Nm = np.zeros((M + 1, N, N), dtype=np.int64)
-    rc = lib.orc_mismatch_profile(_ptr(seqs), _ptr(lens), N, g, M, threads, _ptr(C), _ptr(Nm))
+    rc = lib.orc_mismatch_profile(_ptr(seqs), _ptr(lens), N, g, M, threads, int(per_mask), _ptr(C), _ptr(Nm))
     if rc != 0:
         raise RuntimeError("orc_mismatch_profile failed: %d" % rc)
     return C, Nm
 
 
-def kernel(seqs, lens, g, k, threads: int = 1, want_c: bool = True, want_nm: bool = True):
-    """dict with C [M+1,N,N], Nm [M+1,N,N], K [N,N] int64 and Kn [N,N] float64."""
+def kernel(seqs, lens, g, k, threads: int = 1, want_c: bool = True, want_nm: bool = True,
+           per_mask: bool = False):
+    """dict with C [M+1,N,N], Nm [M+1,N,N], K [N,N] int64 and Kn [N,N] float64.
+
+    threads / per_mask as in mismatch_profile."""
     lib = _load()
     seqs, lens = _prep(seqs, lens)
     N = len(lens)
@@ -114,7 +125,8 @@ def kernel(seqs, lens, g, k, threads: int = 1, want_c: bool = True, want_nm: boo
     Nm = np.zeros((M + 1, N, N), dtype=np.int64) if want_nm else None
     K = np.zeros((N, N), dtype=np.int64)
     Kn = np.zeros((N, N), dtype=np.float64)
-    rc = lib.orc_kernel(_ptr(seqs), _ptr(lens), N, g, k, threads, _ptr(C), _ptr(Nm), _ptr(K), _ptr(Kn))
+    rc = lib.orc_kernel(_ptr(seqs), _ptr(lens), N, g, k, threads, int(per_mask), _ptr(C), _ptr(Nm), _ptr(K),
+                        _ptr(Kn))
     if rc != 0:
         raise RuntimeError("orc_kernel failed: %d" % rc)
     return {"C": C, "Nm": Nm, "K": K, "Kn": Kn}
@@ -148,11 +160,12 @@ def mask_groups(seqs, lens, g, removed):
     return out
 
 
-def rows(sv_seqs, sv_lens, q_seqs, q_lens, g, k, alpha=None, bias: float = 0.0):
+def rows(sv_seqs, sv_lens, q_seqs, q_lens, g, k, alpha=None, bias: float = 0.0, threads: int = 1):
     """Kernel rows of queries against a resident set and Eq. 1 decision values.
 
     Returns dict Krows [n_q, n_sv] float64, Nm [M+1, n_q, n_sv] int64,
-    decision [n_q] float64 (None when alpha is None).
+    decision [n_q] float64 (None when alpha is None).  threads > 1 deals the
+    position sets to that many threads (Section S:5.3).
     """
     lib = _load()
     sv_seqs, sv_lens = _prep(sv_seqs, sv_lens)
@@ -163,7 +176,7 @@ def rows(sv_seqs, sv_lens, q_seqs, q_lens, g, k, alpha=None, bias: float = 0.0):
     dec = np.zeros(n_q, dtype=np.float64)
     a = None if alpha is None else np.ascontiguousarray(alpha, dtype=np.float64)
     rc = lib.orc_rows(_ptr(sv_seqs), _ptr(sv_lens), n_sv, _ptr(q_seqs), _ptr(q_lens), n_q, g, k,
-                      _ptr(a), float(bias), _ptr(Krows), _ptr(Nm), _ptr(dec))
+                      _ptr(a), float(bias), int(threads), _ptr(Krows), _ptr(Nm), _ptr(dec))
     if rc != 0:
         raise RuntimeError("orc_rows failed: %d" % rc)
     return {"Krows": Krows, "Nm": Nm, "decision": dec if alpha is not None else None}

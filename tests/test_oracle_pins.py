@@ -158,6 +158,63 @@ def test_fig2_gpairs1_groups():
     assert Nm[1, 0, 1] == sum(want.values())
 
 
+def _fig2_strings(fx, enc, names):
+    seqs = np.concatenate([np.array([enc[c] for c in fx["hand_worked"].get(n, fx.get(n))], dtype=np.int8)
+                           for n in names])
+    lens = np.array([len(fx["hand_worked"].get(n, fx.get(n))) for n in names], dtype=np.int32)
+    return seqs, lens
+
+
+def test_fig2_hand_worked_profiles():
+    """N_d for the Fig. 2 strings and the extra query Q, every pair, from
+    Eq. 5 worked by hand (k = 0, so every level d = 0..g is kept)."""
+    fx, enc, _, _ = load_fig2()
+    hw = fx["hand_worked"]
+    seqs, lens = _fig2_strings(fx, enc, ["S", "T", "Q"])
+    _, Nm = orc.mismatch_profile(seqs, lens, fx["g"], fx["g"])
+    idx = {"S": 0, "T": 1, "Q": 2}
+    for pair, want in hw["Nd"].items():
+        a, b = idx[pair[0]], idx[pair[1]]
+        np.testing.assert_array_equal(Nm[:, a, b], want, err_msg=pair)
+        np.testing.assert_array_equal(Nm[:, b, a], want, err_msg=pair)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fig2_hand_worked_normalised_kernel(k):
+    """K and the cosine-normalised K-hat of the Fig. 2 pair for k = 1, 2, 3
+    (hand-worked Eqs. 6-7).  A wrong normalisation -- dividing by the larger
+    diagonal entry, or by the product without the square root -- or a wrong
+    h_m fails here, while the unit diagonal alone would not catch it."""
+    fx, enc, seqs, lens = load_fig2()
+    w = fx["hand_worked"]["kernel"][str(k)]
+    r = orc.kernel(seqs, lens, fx["g"], k)
+    assert r["K"][0, 1] == w["K_ST"] and r["K"][1, 0] == w["K_ST"]
+    assert r["K"][0, 0] == w["K_SS"] and r["K"][1, 1] == w["K_TT"]
+    assert abs(r["Kn"][0, 1] - w["Khat_ST_value"]) <= 1e-15 * w["Khat_ST_value"]
+    assert r["Kn"][0, 0] == 1.0 and r["Kn"][1, 1] == 1.0
+
+
+def test_fig2_hand_worked_decision_value():
+    """Eq. 1 on the Fig. 2 strings as a resident set {S, T} with alpha*y =
+    (1, -2), b = 0.5, k = 2, and the query Q = CACAA: the rows and f(Q)
+    worked by hand."""
+    fx, enc, _, _ = load_fig2()
+    dv = fx["hand_worked"]["decision"]
+    sv_seqs, sv_lens = _fig2_strings(fx, enc, dv["resident"])
+    q_seqs, q_lens = _fig2_strings(fx, enc, ["Q"])
+    for threads in (1, 3):
+        r = orc.rows(sv_seqs, sv_lens, q_seqs, q_lens, fx["g"], dv["k"], alpha=np.array(dv["alpha_y"]),
+                     bias=dv["bias"], threads=threads)
+        kss = fx["hand_worked"]["kernel"][str(dv["k"])]["K_SS"]
+        ktt = fx["hand_worked"]["kernel"][str(dv["k"])]["K_TT"]
+        want_rows = [dv["K_QS"] / math.sqrt(kss * dv["K_QQ"]), dv["K_QT"] / math.sqrt(ktt * dv["K_QQ"])]
+        np.testing.assert_allclose(r["Krows"][0], want_rows, rtol=1e-15, atol=0)
+        assert abs(r["decision"][0] - dv["f_Q_value"]) <= 1e-14
+        M1 = fx["g"] - dv["k"] + 1
+        np.testing.assert_array_equal(r["Nm"][:, 0, 0], fx["hand_worked"]["Nd"]["QS"][:M1])
+        np.testing.assert_array_equal(r["Nm"][:, 0, 1], fx["hand_worked"]["Nd"]["QT"][:M1])
+
+
 # ------------------------------------------------------------- brute force --
 @pytest.mark.parametrize("case", range(len(tiny_cases())))
 def test_bruteforce_pairwise(case):
@@ -334,5 +391,20 @@ def test_threaded_equals_sequential():
     d = wl.protein(N=30, lmin=20, lmax=80)
     a = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=1)
     b = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=4)
-    np.testing.assert_array_equal(a["C"], b["C"])
-    np.testing.assert_array_equal(a["Kn"], b["Kn"])
+    c = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=5, per_mask=True)
+    for r in (b, c):
+        np.testing.assert_array_equal(a["C"], r["C"])
+        np.testing.assert_array_equal(a["Nm"], r["Nm"])
+        np.testing.assert_array_equal(a["Kn"], r["Kn"])
+
+
+def test_threaded_rows_equal_sequential():
+    rng = np.random.default_rng(32)
+    sv_seqs, sv_lens = wl.random_small(rng, 12, 8, 40, 4)
+    q_seqs, q_lens = wl.random_small(rng, 3, 3, 50, 4)
+    alpha = rng.standard_normal(12)
+    a = orc.rows(sv_seqs, sv_lens, q_seqs, q_lens, 6, 2, alpha=alpha, bias=0.1)
+    b = orc.rows(sv_seqs, sv_lens, q_seqs, q_lens, 6, 2, alpha=alpha, bias=0.1, threads=4)
+    np.testing.assert_array_equal(a["Nm"], b["Nm"])
+    np.testing.assert_array_equal(a["Krows"], b["Krows"])
+    np.testing.assert_array_equal(a["decision"], b["decision"])
