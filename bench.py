@@ -19,13 +19,25 @@ Prints ONE JSON line:
                        over a probe's rate of random LDS atomic adds;
   dense_mfma           the int8 count-matrix products' TOP/s over the dense
                        int8 peak;
-  cpu_baseline         the CPU oracle timed on a sub-Gram of the workload;
+  sort_accumulate      the partition, sort and accumulation kernels together:
+                       the method's bytes (three passes over 12-byte records
+                       per position set and g-mer, one write of every C_m)
+                       over their summed launch times, against HBM peak;
+  cpu_baseline         the CPU oracle on the whole workload with its position
+                       sets dealt to the host's cores, and single-threaded on
+                       a sub-Gram;
   serving              continuous-batching rows of the serving workload
-                       (resident 20000 DNA support sequences, g=10, k=6) under
-                       Poisson arrivals: p50/p99 latency and rows/s, beside
-                       the plain path (one gakco_rows call per query);
+                       (resident 20000 DNA support sequences, g=10, k=6): the
+                       server's saturation rate (a burst), then Poisson
+                       arrivals at 30/60/90 % of it -- p50/p99 latency and
+                       rows/s -- beside the plain path (one gakco_rows call
+                       per query), and the row kernel's pair updates/s;
   batched              the 64-job batched workload replayed from its captured
-                       hipGraph, beside the same jobs run one by one.
+                       hipGraph, with default and autotuned settings, beside
+                       the same jobs run one by one;
+  other_configs        the DNA (N=200) and text (N=2000, M=6) Gram workloads
+                       timed the same way, with their sort + accumulate
+                       fraction of HBM peak.
 """
 from __future__ import annotations
 
@@ -59,10 +71,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--profile-steps", type=int, default=5, help="profiled steps for the per-kernel times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2400, help="sequences in the oracle's sub-Gram")
+    ap.add_argument("--cpu-sample", type=int, default=1200,
+                    help="sequences in the single-threaded oracle's sub-Gram")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-queries", type=int, default=600)
+    ap.add_argument("--serving-queries", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the DNA and text Gram legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (scale for PMC byte counters)")
     ap.add_argument("--profile-phases", action="store_true", help="print the per-kernel table to stderr")
@@ -101,9 +115,10 @@ def algorithmic(d, masks, prof_stats, dense_rows, ntile):
         "bucket_count": 8 * T * S,
         "bucket_scatter": scatter,
         **sortb,
-        # every (mask, g-mer) info read once; every upper-triangle entry of
-        # every C_m read and written once
-        "accumulate": 8 * T * S + 16 * (M + 1) * tri,
+        # the method's bytes for this step: every (mask, g-mer) grouped
+        # (reduced key, sequence) record of 12 bytes read once, and every
+        # C_m written once (8 N^2 per level)
+        "accumulate": 12 * T * S + 8 * (M + 1) * N * N,
         # each count-matrix row read once (bytes); ops below
         "dense_syrk": ntile * dense_rows,
         "finalize": 8 * (M + 1) * tri + 8 * (M + 1) * N * N + 8 * N * N,
@@ -138,74 +153,162 @@ def note(msg):
 T_START = time.perf_counter()
 
 
-def cpu_baseline(d, n_sample):
+def host_cpu():
+    """(cores this process may use, at most 16 -- the host share of one GPU --,
+    the CPU model)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return max(1, min(16, n)), model
+
+
+def cpu_baseline(d, n_single):
+    """The oracle (Algorithm 1) on the whole workload with the position sets
+    dealt to every host core (Section S:5.3), and single-threaded on the
+    sub-Gram of the first n_single sequences (a bounded sample)."""
     from oracle import oracle as orc
-    n_sample = min(n_sample, d.N)
-    sub = d.subset(range(n_sample))
-    threads = d.M + 1  # the paper's parallel version: one thread per m
+    cores, model = host_cpu()
     t0 = time.perf_counter()
-    orc.kernel(sub.seqs, sub.lens, sub.g, sub.k, threads=threads, want_c=False)
+    orc.kernel(d.seqs, d.lens, d.g, d.k, threads=cores, per_mask=True, want_c=False)
     dt = time.perf_counter() - t0
-    return {"value": n_sample * n_sample / dt, "unit": "kernel entries/s", "cores": threads, "kind": "oracle",
-            "sample": "oracle (Algorithm 1, one thread per m) on the first %d of the %d protein sequences: "
-                      "%dx%d sub-Gram (N_m and K) in %.2f s" % (n_sample, d.N, n_sample, n_sample, dt)}
+    n_single = min(n_single, d.N)
+    sub = d.subset(range(n_single))
+    t0 = time.perf_counter()
+    orc.kernel(sub.seqs, sub.lens, sub.g, sub.k, threads=1, want_c=False)
+    dt1 = time.perf_counter() - t0
+    return {"value": d.N * d.N / dt, "unit": "kernel entries/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model,
+            "sample": "oracle (Algorithm 1, position sets dealt to %d threads) on the whole protein workload: "
+                      "%dx%d Gram (N_m and K) in %.2f s" % (cores, d.N, d.N, dt),
+            "single_thread": {"value": n_single * n_single / dt1, "unit": "kernel entries/s", "cores": 1,
+                              "sample": "the same oracle on one thread, sub-Gram of the first %d sequences "
+                                        "(%dx%d) in %.2f s" % (n_single, n_single, n_single, dt1)}}
 
 
-def serving_leg(gakco, wl, n_q):
+def _drive(srv, queries, tags, arrivals):
+    """Submit queries[i] (tag tags[i]) at arrivals[i] seconds from now (all at
+    once when arrivals is None) and collect every result."""
+    n = len(queries)
+    done = {}
+    t0 = time.perf_counter()
+    i = 0
+    if arrivals is None:
+        for q, t in zip(queries, tags):
+            srv.submit(q, t)
+        i = n
+    while len(done) < n:
+        now = time.perf_counter() - t0
+        while i < n and arrivals[i] <= now:
+            srv.submit(queries[i], tags[i])
+            i += 1
+        wait = 20000 if i >= n else max(20, min(200, int((arrivals[i] - now) * 1e6)))
+        for r in srv.poll(256, wait, rows=False):
+            done[r["tag"]] = r
+    return done, time.perf_counter() - t0
+
+
+def serving_leg(gakco, wl, n_q, lds_peak):
+    """The serving workload: plain path (one gakco_rows call per query, no
+    overlap) beside the continuous-batching server -- its saturation rate
+    from a burst of n_q queries, then Poisson arrivals at 30/60/90 % of that
+    rate, n_q measured queries per rate after n_q / 10 warm-up arrivals."""
     import numpy as np
+    import torch
     s = wl.serving_resident()
+    n_sv = s.sv.N
     ctx = gakco.Context(0)
     res = gakco.Resident(ctx, s.sv.seqs, s.sv.lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias)
     try:
-        q_seqs, q_lens = wl.serving_queries(n_q)
+        n_warm = max(50, n_q // 10)
+        q_seqs, q_lens = wl.serving_queries(n_q + n_warm)
         qoff = np.concatenate([[0], np.cumsum(q_lens)])
-        queries = [q_seqs[qoff[i]:qoff[i + 1]] for i in range(n_q)]
-        import torch
-        dev_q = [(torch.as_tensor(q).cuda(), torch.as_tensor(np.array([len(q)], dtype=np.int32)).cuda()) for q in queries]
-        note("serving: resident set built")
-        # plain: one rows call per query, no overlap
-        res.rows(*dev_q[0])
+        queries = [q_seqs[qoff[i]:qoff[i + 1]] for i in range(len(q_lens))]
+        note("serving: resident set built (%d queries, lengths %d..%d)" % (len(queries), q_lens.min(), q_lens.max()))
+        # plain: one rows call per query on device-resident queries
+        dev_q = [(torch.as_tensor(q).cuda(), torch.as_tensor(np.array([len(q)], dtype=np.int32)).cuda())
+                 for q in queries]
+        for q, l in dev_q[:n_warm]:
+            res.rows(q, l)
         torch.cuda.synchronize()
         lat = []
         t0 = time.perf_counter()
-        for q, l in dev_q:
+        for q, l in dev_q[n_warm:]:
             a = time.perf_counter()
             res.rows(q, l)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - a)
         plain_wall = time.perf_counter() - t0
-        plain_rate = n_q / plain_wall
-        note("serving: plain path %d queries in %.1f s" % (n_q, plain_wall))
-        # continuous batching under Poisson arrivals at 90% of the plain rate
-        # and at 3x it (queries arriving while others are on the device)
-        out = {"workload": "resident N_sv=20000 DNA l=200, g=10, k=6 (M=4); %d queries l~U{50..1000}" % n_q,
-               "unit": "ms", "plain": {"p50_ms": 1e3 * float(np.percentile(lat, 50)),
-                                       "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                                       "rows_per_s": n_q * s.sv.N / plain_wall}}
-        for label, rate in (("load_0.9x_plain", 0.9 * plain_rate), ("load_3x_plain", 3.0 * plain_rate)):
-            srv = gakco.Server(res, max_batch=256, n_streams=2)
-            try:
-                arr = wl.poisson_arrivals(n_q, rate)
-                done = {}
-                t0 = time.perf_counter()
-                i = 0
-                while len(done) < n_q:
-                    now = time.perf_counter() - t0
-                    while i < n_q and arr[i] <= now:
-                        srv.submit(queries[i], i)
-                        i += 1
-                    for r in srv.poll(256, 200 if i < n_q else 20000):
-                        done[r["tag"]] = r
-                wall = time.perf_counter() - t0
-                note("serving: %s %d queries in %.1f s" % (label, n_q, wall))
-                lat_s = [done[t]["t_done"] - done[t]["t_submit"] for t in range(n_q)]
-                out[label] = {"offered_qps": rate, "p50_ms": 1e3 * float(np.percentile(lat_s, 50)),
-                              "p99_ms": 1e3 * float(np.percentile(lat_s, 99)),
-                              "rows_per_s": n_q * s.sv.N / wall,
-                              "mean_batch": float(np.mean([done[t]["batch_size"] for t in range(n_q)])),
-                              "all_ok": all(done[t]["status"] == 0 for t in range(n_q))}
-            finally:
-                srv.close()
+        note("serving: plain path %d queries in %.2f s" % (n_q, plain_wall))
+        out = {"workload": "resident N_sv=20000 DNA l=200, g=10, k=6 (M=4); queries l~U{50..1000}, Poisson "
+                           "arrivals; %d measured queries per rate after %d warm-up" % (n_q, n_warm),
+               "unit": "ms",
+               "plain": {"p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                         "qps": n_q / plain_wall, "rows_per_s": n_q * n_sv / plain_wall}}
+        # the row kernel against its roofs, on one batch of 256 queries
+        bq = torch.as_tensor(np.concatenate(queries[n_warm:n_warm + 256])).cuda()
+        bl = torch.as_tensor(q_lens[n_warm:n_warm + 256]).cuda()
+        res.rows(bq, bl)
+        ctx.set_param("profile", 1)
+        ctx.profile_reset()
+        reps = 3
+        for _ in range(reps):
+            res.rows(bq, bl)
+        torch.cuda.synchronize()
+        prof = ctx.profile()
+        upd = ctx.stat("rows_updates") / reps
+        ctx.set_param("profile", 0)
+        rk_ms = prof["rows"][0] / max(1, prof["rows"][1])
+        rate = upd / (rk_ms / 1e3)
+        # bytes the row kernel must move: every gathered (sequence, count)
+        # entry (4 B), a 16-byte group lookup per (position set, query g-mer),
+        # every C_m row entry added once (4 B)
+        ng = int(np.maximum(q_lens[n_warm:n_warm + 256] - s.sv.g + 1, 0).sum())
+        npos = sum(math.comb(s.sv.g, m) for m in range(s.sv.g - s.sv.k + 1))
+        rbytes = 4 * upd + 16 * npos * ng + 4 * (s.sv.g - s.sv.k + 1) * 256 * n_sv
+        out["rows_kernel"] = {"kernel": "k_rows_accumulate", "batch": 256, "mean_launch_ms": round(rk_ms, 4),
+                              "updates_per_launch": round(upd), "achieved": round(rate / 1e9, 1),
+                              "peak": round(lds_peak / 1e9, 1), "unit": "G updates/s",
+                              "frac": round(rate / lds_peak, 4),
+                              "hbm": {"algorithmic_bytes": round(rbytes),
+                                      "achieved": round(rbytes / (rk_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": round(rbytes / (rk_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+                              "peak_source": "k_lds_atomic_probe: random adds into a 4096-word LDS row"}
+        srv = gakco.Server(res, max_batch=256, n_streams=2)
+        try:
+            meas = queries[n_warm:]
+            tags = list(range(n_q))
+            _drive(srv, queries[:n_warm], [10 ** 6 + i for i in range(n_warm)], None)  # warm-up burst
+            done, wall = _drive(srv, meas, tags, None)
+            sat = n_q / wall
+            out["server_saturation"] = {"qps": sat, "rows_per_s": n_q * n_sv / wall,
+                                        "mean_batch": float(np.mean([done[t]["batch_size"] for t in tags])),
+                                        "all_ok": all(done[t]["status"] == 0 for t in tags),
+                                        "vs_plain_rows_per_s": (n_q * n_sv / wall) / out["plain"]["rows_per_s"]}
+            note("serving: saturation %.0f queries/s (burst of %d)" % (sat, n_q))
+            for frac in (0.3, 0.6, 0.9):
+                rate_q = frac * sat
+                arr = wl.poisson_arrivals(n_warm + n_q, rate_q, seed=wl.SEED_BASE + 6 + int(frac * 10))
+                alltags = [2 * 10 ** 6 + i for i in range(n_warm)] + tags
+                done, wall = _drive(srv, queries[:n_warm] + meas, alltags, arr)
+                lat_s = [done[t]["t_done"] - done[t]["t_submit"] for t in tags]
+                span = max(done[t]["t_done"] for t in tags) - min(done[t]["t_submit"] for t in tags)
+                out["load_%d%%" % round(100 * frac)] = {
+                    "offered_qps": rate_q, "p50_ms": 1e3 * float(np.percentile(lat_s, 50)),
+                    "p99_ms": 1e3 * float(np.percentile(lat_s, 99)), "rows_per_s": n_q * n_sv / span,
+                    "mean_batch": float(np.mean([done[t]["batch_size"] for t in tags])),
+                    "all_ok": all(done[t]["status"] == 0 for t in tags)}
+                note("serving: %d%% of saturation, %d queries in %.2f s" % (round(100 * frac), n_q, wall))
+        finally:
+            srv.close()
         return out
     finally:
         res.close()
@@ -213,6 +316,9 @@ def serving_leg(gakco, wl, n_q):
 
 
 def batched_leg(gakco, wl):
+    """The 64-job batched workload: the jobs one by one on the plain path,
+    then one batch replayed from its captured hipGraph with the default
+    settings and with the settings gakco_autotune picks for these jobs."""
     import torch
     jobs_in = wl.batched()
     ctx = gakco.Context(0)
@@ -225,6 +331,7 @@ def batched_leg(gakco, wl):
         dev = [(torch.as_tensor(j["seqs"]).cuda(), torch.as_tensor(j["lens"]).cuda()) for j in plain]
         outs = [(torch.empty((j.N, j.N), dtype=torch.float64, device="cuda"),
                  torch.empty((j.M + 1, j.N, j.N), dtype=torch.int64, device="cuda")) for j in jobs_in]
+
         def run_plain():
             for j, (s, l), (K, Nm) in zip(jobs_in, dev, outs):
                 ctx.gram_into(s, l, j.N, j.sigma, j.g, j.k, K=K, Nm=Nm)
@@ -235,27 +342,87 @@ def batched_leg(gakco, wl):
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         note("batched: plain serial %.1f ms" % (1e3 * t_plain))
-        bjobs = mk()
-        plan = ctx.batch_plan(bjobs)
-        try:
-            plan.run()
-            torch.cuda.synchronize()
-            reps = 3
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                st = plan.run()
-            torch.cuda.synchronize()
-            t_graph = (time.perf_counter() - t0) / reps
-            same = all(torch.equal(b["Nm"], Nm) and torch.equal(b["K"], K) for b, (K, Nm) in zip(bjobs, outs))
-        finally:
-            plan.close()
+
+        def graph(c):
+            bjobs = mk()
+            plan = c.batch_plan(bjobs)
+            try:
+                plan.run()
+                torch.cuda.synchronize()
+                reps = 3
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    st = plan.run()
+                torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) / reps
+                same = all(torch.equal(b["Nm"], Nm) and torch.equal(b["K"], K) for b, (K, Nm) in zip(bjobs, outs))
+            finally:
+                plan.close()
+            return t, same, all(x == 0 for x in st)
+        t_graph, same, ok = graph(ctx)
+        note("batched: graph %.1f ms" % (1e3 * t_graph))
+        t0 = time.perf_counter()
+        table = ctx.autotune(mk(), reps=1)
+        t_tune = time.perf_counter() - t0
+        t_tuned, same_t, ok_t = graph(ctx)
+        note("batched: autotuned graph %.1f ms (tuning took %.1f s)" % (1e3 * t_tuned, t_tune))
         return {"workload": "64 jobs N~U{100..2000}, Sigma in {4,20,36}, l~U{50..600}, g in [6,10], k in [3,g-2]",
                 "unit": "kernel entries/s", "entries": entries,
-                "graph_replay": {"ms": 1e3 * t_graph, "value": entries / t_graph},
                 "plain_serial": {"ms": 1e3 * t_plain, "value": entries / t_plain},
-                "identical_results": bool(same), "status_ok": all(x == 0 for x in st)}
+                "graph_replay": {"ms": 1e3 * t_graph, "value": entries / t_graph, "vs_plain": t_plain / t_graph},
+                "graph_replay_autotuned": {"ms": 1e3 * t_tuned, "value": entries / t_tuned,
+                                           "vs_plain": t_plain / t_tuned, "tuning_s": round(t_tune, 2),
+                                           "table": __import__("json").loads(table)},
+                "identical_results": bool(same and same_t), "status_ok": bool(ok and ok_t)}
     finally:
         ctx.close()
+
+
+def config_leg(gakco, d, label, steps=10):
+    """Another Gram workload, timed like the headline one (device-resident
+    inputs, preallocated outputs), with its per-kernel profile and the
+    sort + accumulate fraction of HBM peak."""
+    import torch
+    dev = torch.device("cuda", 0)
+    seqs = torch.as_tensor(d.seqs).to(dev)
+    lens = torch.as_tensor(d.lens).to(dev)
+    N, M = d.N, d.M
+    K = torch.empty((N, N), dtype=torch.float64, device=dev)
+    Nm = torch.empty((M + 1, N, N), dtype=torch.int64, device=dev)
+    ctx = gakco.Context(0)
+    try:
+        for _ in range(2):
+            ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.set_param("profile", 1)
+        ctx.profile_reset()
+        P = 2
+        for _ in range(P):
+            ctx.gram_into(seqs, lens, N, d.sigma, d.g, d.k, K=K, Nm=Nm)
+        torch.cuda.synchronize()
+        prof = ctx.profile()
+        ctx.set_param("profile", 0)
+    finally:
+        ctx.close()
+    kern = {k_: round(v[0] / P, 4) for k_, v in prof.items() if v[1]}
+    T = int(sum(max(0, int(l) - d.g + 1) for l in d.lens))
+    S = sum(math.comb(d.g, m) for m in range(M + 1))
+    sa_kernels = ("bucket_count", "bucket_scan", "bucket_scatter", "sort_wave", "sort_block", "sort_global",
+                  "accumulate", "dense_syrk", "dense_clear")
+    sa_ms = sum(kern.get(k_, 0.0) for k_ in sa_kernels)
+    sa_bytes = 3 * 12 * T * S + 8 * (M + 1) * N * N
+    note("%s: %.3f ms/step" % (label, ms))
+    return {"workload": label, "N": N, "sigma": d.sigma, "g": d.g, "k": d.k, "T_gmers": T, "position_sets": S,
+            "ms_per_step": ms, "value": N * N / (ms / 1e3), "unit": "kernel entries/s",
+            "sort_accumulate": {"algorithmic_bytes": sa_bytes, "ms_per_step": round(sa_ms, 4),
+                                "achieved": round(sa_bytes / (sa_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(sa_bytes / (sa_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "kernels_ms_per_step": kern}
 
 
 def main():
@@ -354,6 +521,18 @@ def main():
         tops = ops / (kern["dense_syrk"]["ms_per_step"] / 1e3) / 1e12
         extra["dense_mfma"] = {"kernel": "k_dense_syrk", "rows": int(dense_rows), "achieved": round(tops, 1),
                                "peak": 5000.0, "unit": "TOP/s", "frac": round(tops / 5000.0, 4)}
+    # sort + accumulate as one phase of the path (the method's bytes over the
+    # summed launch times of its kernels): every (mask, g-mer) record of 12
+    # bytes read by the partition, written grouped and read once to
+    # accumulate, and every C_m written once
+    sa_kernels = ("bucket_count", "bucket_scan", "bucket_scatter", "sort_wave", "sort_block", "sort_global",
+                  "accumulate", "dense_syrk", "dense_clear")
+    sa_ms = sum(kern[k_]["ms_per_step"] for k_ in sa_kernels if k_ in kern)
+    sa_bytes = 3 * 12 * T * sum(masks) + 8 * (M + 1) * N * N
+    extra["sort_accumulate"] = {"kernels": [PHASE_KERNEL[k_] for k_ in sa_kernels if k_ in kern],
+                                "algorithmic_bytes": sa_bytes, "ms_per_step": round(sa_ms, 4),
+                                "achieved": round(sa_bytes / (sa_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(sa_bytes / (sa_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     if args.profile_phases:
         for k_, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
             a = alg.get(k_)
@@ -367,9 +546,12 @@ def main():
     if cpu:
         note("cpu baseline: " + cpu["sample"])
     batched = None if args.no_batched else batched_leg(gakco, wl)
-    if batched:
-        note("batched: graph %.1f ms" % batched["graph_replay"]["ms"])
-    serving = None if args.no_serving else serving_leg(gakco, wl, args.serving_queries)
+    configs = None
+    if not args.no_configs:
+        configs = {"dna": config_leg(gakco, wl.dna(), "DNA Gram: N=200, l=100, Sigma=4, g=6, k=4 (M=2)", steps=50),
+                   "text": config_leg(gakco, wl.text(), "text Gram: N=2000, l~U{200..1000}, Sigma=36 Markov-1, "
+                                                        "g=10, k=4 (M=6)", steps=5)}
+    serving = None if args.no_serving else serving_leg(gakco, wl, args.serving_queries, lds_peak)
     line = {
         "metric": "kernel entries/sec (Gram + query rows) bit-exact; serving p50/p99 latency vs plain",
         "value": value, "unit": "kernel entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -383,6 +565,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "batched": batched,
+        "other_configs": configs,
         "kernels_ms_per_step": {k_: round(v["ms_per_step"], 4) for k_, v in kern.items()},
     }
     print(json.dumps(line))

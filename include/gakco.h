@@ -84,6 +84,9 @@ const char *gakco_version(void);
  *                   (0, the default: a whole row when its int32 counters fit
  *                   the LDS, else the largest multiple of 64 that does);
  *                   a multiple of 64, for tests and tuning
+ *   "acc_mstep"     cap on the position sets the row accumulation sums in
+ *                   its 32-bit LDS row before adding it into C_m (0, the
+ *                   default: as many as the count bound allows), for tests
  *   "tau_b<B>_g<G>" dense_tau for jobs with B-bit symbols and this g (as
  *                   written by gakco_autotune)
  * Missing keys keep their defaults.  Not thread-safe: one context per host
@@ -102,7 +105,9 @@ gakco_status gakco_ctx_set_param(gakco_ctx *ctx, const char *name, int64_t value
  * sorted by that kernel, packed or 64-bit composites, and "acc_updates":
  * sequence-pair updates of the row accumulation (Algorithm 1
  * countAndUpdate on the groups left to it, the diagonal terms included),
- * since the last profile reset (synchronises the device). */
+ * and "rows_updates": resident entries gathered by the serving rows kernel
+ * (one (query g-mer, resident sequence) pair update each), since the last
+ * profile reset (synchronises the device). */
 gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *value);
 
 /* Reference rate for the row accumulation's LDS atomics: 2048 blocks of 256
@@ -136,9 +141,12 @@ void gakco_profile_reset(gakco_ctx *ctx);
  *   Nm_out  int64 [g-k+1][N][N] exact mismatch profiles N_m (nullable)
  *   Cm_out  int64 [g-k+1][N][N] cumulative profiles C_m (nullable)
  * Returns GAKCO_EINVAL for bad sizes or NULL seqs/lens, GAKCO_ERANGE for a
- * symbol outside [0, sigma), GAKCO_EUNSUPPORTED when g*b > 64 or a count
- * bound of the kernels would be exceeded, GAKCO_EBUDGET when the scratch and
- * outputs do not fit the context's budget, GAKCO_EHIP on a runtime failure.
+ * symbol outside [0, sigma), GAKCO_EUNSUPPORTED when g*b > 64, when a
+ * sequence has 65536 or more g-mers (one position set could overflow the
+ * accumulation's 32-bit counters), or past the other size limits (2^31
+ * g-mers, 2^24 sequences, reduced key + sequence id above 64 bits),
+ * GAKCO_EBUDGET when the scratch and outputs do not fit the context's budget,
+ * GAKCO_EHIP on a runtime failure.
  * ------------------------------------------------------------------------ */
 gakco_status gakco_gram(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N,
                         int32_t sigma, int32_t g, int32_t k, double *K_out, int64_t *Nm_out,
@@ -222,7 +230,10 @@ gakco_status gakco_autotune(gakco_ctx *ctx, const gakco_job *jobs_host, int32_t 
  * f(q) = b + sum_i alpha_i K-hat(sv_i, q) (Eq. 1), summed in a fixed
  * per-query order (chunks of 2048 consecutive i, each summed by a fixed
  * tree, then the chunk sums in ascending order) so that a query's result does
- * not depend on the other queries of the batch.
+ * not depend on the other queries of the batch.  GAKCO_EUNSUPPORTED when a
+ * query is past the 32-bit serving counters (see gakco_server_submit), or, in
+ * gakco_resident_create, when C(g,m) * (longest resident g-mers)^2 reaches
+ * 2^32.
  * ------------------------------------------------------------------------ */
 typedef struct gakco_resident gakco_resident;
 gakco_status gakco_resident_create(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens,
@@ -237,6 +248,59 @@ gakco_status gakco_rows(gakco_ctx *ctx, const gakco_resident *res, const int8_t 
                         double *decision, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Incremental Gram: a normalised kernel matrix that grows as sequences are
+ * appended, each append computing only the new rows (the counting approach
+ * suits adaptive training on a growing set, Section 3.2).  The sequences
+ * appended so far stay on the device as resident group tables, one segment
+ * per append.
+ * gakco_incr_append with n_new sequences (device seqs / lens, as in
+ * gakco_gram) onto N: K_out [N+n_new][N+n_new] (device, row-major) receives
+ * the normalised kernel of all N+n_new sequences in append order -- the
+ * N x N block copied from K_prev [N][N] (device; ignored when N = 0, and not
+ * the same buffer as K_out), the new rows from the serving join against every
+ * earlier segment, the new block from a Gram of the new sequences -- equal to
+ * gakco_gram on the concatenation.  GAKCO_EINVAL for NULL pointers, n_new < 1
+ * or K_prev missing / aliasing K_out; the other errors as gakco_gram and
+ * gakco_rows (a new sequence past the serving counters: GAKCO_EUNSUPPORTED).
+ * A failed append leaves the set as it was.  Synchronises the stream.
+ * ------------------------------------------------------------------------ */
+typedef struct gakco_incr gakco_incr;
+gakco_status gakco_incr_create(gakco_ctx *ctx, int32_t sigma, int32_t g, int32_t k, gakco_incr **out);
+gakco_status gakco_incr_append(gakco_incr *inc, const int8_t *seqs, const int32_t *lens, int32_t n_new,
+                               const double *K_prev, double *K_out, void *hip_stream);
+gakco_status gakco_incr_info(const gakco_incr *inc, int64_t *N, int32_t *segments);
+void gakco_incr_destroy(gakco_incr *inc);
+
+/* ------------------------------------------------------------------------
+ * gakco_svm_train -- the support-vector machine that consumes the kernel
+ * (Section 3.1 classifies with an SVM on the Gram matrix; Eq. 1 is its
+ * decision function f(x) = sum_i alpha_i y_i K(x_i, x) + b).  The bias is
+ * absorbed into the kernel (K + 1, so b = sum_i alpha_i y_i) and the dual
+ *     minimise 1/2 alpha^T Q alpha - sum_i alpha_i,  0 <= alpha_i <= C,
+ *     Q_ij = y_i y_j (K_ij + 1)
+ * is solved by dual coordinate descent (Hsieh et al., ICML 2008):
+ * coordinates 0..N-1 in order, each moved to its clipped minimiser; the run
+ * stops after the first epoch whose projected gradients span at most eps, or
+ * after max_epochs.  One block of the device runs it (the coordinates are
+ * sequential); every FP64 operation is separately rounded in a fixed order,
+ * so the result does not depend on the thread layout.
+ *   K              double [N][N] normalised kernel (e.g. gakco_gram's K_out), device
+ *   y              int8 [N] labels +1 / -1, device
+ *   alpha_out      double [N] multipliers alpha_i, device, nullable
+ *   dual_coef_out  double [N] alpha_i * y_i, device, nullable -- with bias the
+ *                  arguments gakco_resident_create takes (its support vectors
+ *                  are the i with alpha_i > 0)
+ *   bias_out       host double, nullable: b
+ *   epochs_out     host int32, nullable: epochs run
+ * GAKCO_EINVAL for N < 1, C <= 0, eps < 0, max_epochs < 1, NULL K / y or a
+ * label other than +1 / -1; GAKCO_EUNSUPPORTED for N > 8192 (the gradient
+ * lives in one block's registers); synchronises the stream.
+ * ------------------------------------------------------------------------ */
+gakco_status gakco_svm_train(gakco_ctx *ctx, const double *K, const int8_t *y, int32_t N, double C, double eps,
+                             int32_t max_epochs, double *alpha_out, double *dual_coef_out, double *bias_out,
+                             int32_t *epochs_out, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Continuous-batching server over a resident set.  Queries are HOST arrays
  * (copied at submit).  A scheduler thread admits queued requests into device
  * batches whenever a batch slot and HBM budget are free, so requests that
@@ -244,7 +308,13 @@ gakco_status gakco_rows(gakco_ctx *ctx, const gakco_resident *res, const int8_t 
  * `n_streams` batches are in flight on separate HIP streams.  Results are
  * returned by gakco_server_poll in completion order; K_row points into
  * server-owned memory that stays valid until the next poll on this server.
- * Timestamps are seconds on a monotonic clock.
+ * Timestamps are seconds on a monotonic clock.  gakco_server_create runs one
+ * warm-up batch per worker (up to max_batch queries of 1024 symbols, as far
+ * as the worker's share of hbm_budget allows) so that later batches of
+ * queries up to that length find their buffers sized.
+ * This differs from a context-based create: the server owns one context and
+ * stream per worker (n_streams of them) on `device`, so it takes the device
+ * instead of a context; t_submit is the request's arrival (its submit call).
  * ------------------------------------------------------------------------ */
 typedef struct gakco_server gakco_server;
 typedef struct {
@@ -257,6 +327,11 @@ typedef struct {
 } gakco_result;
 gakco_status gakco_server_create(const gakco_resident *res, int32_t device, int32_t max_batch,
                                  int32_t n_streams, size_t hbm_budget, gakco_server **out);
+/* gakco_server_submit copies the query; GAKCO_ERANGE for a symbol outside
+ * [0, sigma) and GAKCO_EUNSUPPORTED for a query past the 32-bit serving
+ * counters (C(g,m) * its g-mers * max(its g-mers, the longest resident
+ * sequence's) must stay below 2^32 for every m) -- either way nothing is
+ * queued, so a bad query never affects the batch it would have joined. */
 gakco_status gakco_server_submit(gakco_server *srv, const int8_t *q_host, int32_t len, uint64_t tag);
 gakco_status gakco_server_cancel(gakco_server *srv, uint64_t tag);
 gakco_status gakco_server_poll(gakco_server *srv, gakco_result *out, int32_t max, int32_t *n_out,

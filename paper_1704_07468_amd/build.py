@@ -22,6 +22,8 @@ SOURCES = [
     "batch.cpp",
     "rows.hip",
     "serve.cpp",
+    "svm.hip",
+    "incr.cpp",
 ]
 
 CFLAGS = [

@@ -46,6 +46,9 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
     } else if (!strcmp(name, "bucket_avg")) {
         if (v < 16 || v > 4096) { set_error("bucket_avg must be in 16..4096"); return GAKCO_EINVAL; }
         ctx->bucket_avg = (int)v;
+    } else if (!strcmp(name, "acc_mstep")) {
+        if (v < 0 || v > (1 << 20)) { set_error("acc_mstep must be in 0..1048576"); return GAKCO_EINVAL; }
+        ctx->acc_mstep = (int)v;
     } else if (!strcmp(name, "acc_slab")) {
         if (v != 0 && (v < 64 || v > (1 << 20) || v % 64)) {
             set_error("acc_slab must be 0 or a multiple of 64 in 64..1048576");
@@ -152,6 +155,11 @@ void gakco_ctx_destroy(gakco_ctx *ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->arena);
+    }
+    if (ctx->small) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->small);
     }
     delete ctx;
 }
@@ -298,7 +306,7 @@ gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *val
     else if (!strcmp(name, "bucket_avg")) *value = ctx->bucket_avg;
     else if (!strcmp(name, "arena_bytes")) *value = (int64_t)ctx->arena_cap;
     else if (!strcmp(name, "dense_bytes")) *value = (int64_t)ctx->dense_cap;
-    else if (!strncmp(name, "sort_gmers_", 11) || !strcmp(name, "acc_updates")) {
+    else if (!strncmp(name, "sort_gmers_", 11) || !strcmp(name, "acc_updates") || !strcmp(name, "rows_updates")) {
         // g-mers handled by each sort kernel, or pair updates of the row
         // accumulation, since the last profile reset.  Slots: the six sort
         // kinds, then kProfUpdSlots slots of pair updates (block b adds to
@@ -307,6 +315,9 @@ gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *val
         int k = -1, nk = 1;
         if (!strcmp(name, "acc_updates")) {
             k = kProfUpdFirst;
+            nk = kProfUpdSlots;
+        } else if (!strcmp(name, "rows_updates")) {
+            k = kProfRowsFirst;
             nk = kProfUpdSlots;
         }
         for (int i = 0; i < 6 && k < 0; ++i)

@@ -122,6 +122,7 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
     own.dense_tau = ctx->dense_tau;
     own.bucket_avg = ctx->bucket_avg;
     own.acc_slab = ctx->acc_slab;
+    own.acc_mstep = ctx->acc_mstep;
     own.pool_cap = ctx->pool_cap;
     own.lds_max = ctx->lds_max;
     own.class_tau = ctx->class_tau;

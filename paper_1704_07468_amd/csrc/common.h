@@ -144,6 +144,7 @@ struct AccWork {
     int32_t Npad;    // LDS row stride (the slab width, a multiple of 64)
     int32_t first;   // 1: first work of its (job, level): store the row, else add
     int32_t slab, nslab;  // columns per block and blocks per row
+    int32_t mstep;   // masks summed in the int32 LDS row between flushes (0: all)
 };
 
 // --------------------------------------------------------------------------

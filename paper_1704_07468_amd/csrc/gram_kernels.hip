@@ -219,13 +219,20 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         return;
     }
     const int npad = A.Npad;
-    for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
     for (int i = lane; i < kAccWindow; i += 64) mark[wid][i] = 0;
-    __syncthreads();
-    const uint32_t total = (uint32_t)A.nmask * ng;
-    uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
     uint32_t nupd = 0;           // this lane's diagonal and inline pair updates
     unsigned long long wupd = 0;  // the wave's gathered pair updates (profiling count)
+    // The masks are taken mstep at a time, the int32 row flushed into the
+    // int64 C_m after each step: one mask adds at most ng_X * ng_Y to an
+    // entry, and the planner picks mstep so that mstep * maxng^2 < 2^32.
+    const int mstep = A.mstep > 0 ? min(A.mstep, A.nmask) : A.nmask;
+#pragma unroll 1
+    for (int ms0 = 0; ms0 < A.nmask; ms0 += mstep) {
+    const int nmk = min(mstep, A.nmask - ms0);
+    for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
+    __syncthreads();
+    const uint32_t total = (uint32_t)nmk * ng;
+    uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t q = c0 + lane;
         uint32_t len = 0;
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         if (q < total) {
             const uint32_t s = q / ng;
             const uint32_t t = t0 + (q - s * ng);
-            const MaskWork &W = items[A.mfirst + s];
+            const MaskWork &W = items[A.mfirst + ms0 + (int)s];
             const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
             const uint32_t tail = inf.y & lmask;  // entries from X's own to the group end
             if (tail) {
@@ -314,15 +321,12 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         const uint32_t d = wave_incl_scan(dsum);  // nonzero only when X is in the slab
         if (lane == 63 && d) atomicAdd(&acc[X - y0], d);
     }
-    if (updates) {  // profiling count, spread over 256 slots by block
-        const uint32_t u = wave_incl_scan(nupd);
-        if (lane == 63) atomicAdd(updates + (blockIdx.x & 255u), wupd + (unsigned long long)u);
-    }
     __syncthreads();
+    const bool store = A.first && ms0 == 0;
     for (int l = 0; l < A.nlev; ++l) {
         const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
         const uint32_t *arow = acc + l * npad;
-        if (A.first) {
+        if (store) {
             for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = (int64_t)arow[Y - y0];
         } else {
             for (int Y = ylo + tid; Y < y1; Y += kThreads) {
@@ -330,6 +334,12 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
                 if (v) crow[Y] += (int64_t)v;
             }
         }
+    }
+    __syncthreads();  // the row is read before the next step clears it
+    }
+    if (updates) {  // profiling count, spread over 256 slots by block
+        const uint32_t u = wave_incl_scan(nupd);
+        if (lane == 63) atomicAdd(updates + (blockIdx.x & 255u), wupd + (unsigned long long)u);
     }
 }
 

@@ -132,12 +132,13 @@ gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one,
         uint64_t total = 0;
         for (int m = 0; m <= jp.M; ++m) total += (uint64_t)binom64(jp.g, m);
         if (total > (1u << 20)) { set_error("%llu position sets exceed the limit", (unsigned long long)total); return GAKCO_EUNSUPPORTED; }
+        // one position set adds at most ng_X * ng_Y to an entry of the row
+        // accumulation's uint32 counters; more sets are summed in steps
+        if ((uint64_t)maxng * maxng > 0xFFFFFFFFull) {
+            set_error("a sequence with %u g-mers exceeds the 32-bit row counters of one position set (limit 65535)", maxng);
+            return GAKCO_EUNSUPPORTED;
+        }
         for (int m = 0; m <= jp.M; ++m) {
-            const int64_t cgm = binom64(jp.g, m);
-            if ((double)cgm * (double)maxng * (double)maxng >= 2147483648.0) {
-                set_error("C(g,m)*maxng^2 overflows the int32 row counters (g=%d, m=%d, maxng=%u)", jp.g, m, maxng);
-                return GAKCO_EUNSUPPORTED;
-            }
             std::vector<int> P((size_t)m);
             for (int i = 0; i < m; ++i) P[(size_t)i] = i;
             while (true) {
@@ -251,12 +252,19 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
             const int ntile = jp.Ntile / dense_tile();
             const int tiles = ntile * (ntile + 1) / 2;
             jp.dS = std::max(1, std::min(kDenseMaxSplits, (1024 + tiles - 1) / tiles));
+            // a fixed scratch keeps one split per tile and the partial tiles of
+            // the heaviest levels (highest m first) within a quarter of it
+            if (ctx->fixed_arena) jp.dS = 1;
+            size_t part_left = ctx->fixed_arena ? ctx->budget / 4 : ~(size_t)0;
+            const size_t part_bytes = (size_t)tiles * dense_tile() * dense_tile() * 4;
             const uint64_t kc = (uint64_t)dense_kchunk();
-            for (int m = 0; m <= jp.M; ++m) {
+            for (int m = jp.M; m >= 0; --m) {
                 uint64_t c = (uint64_t)(want[(size_t)m] * scale);
                 c = std::min<uint64_t>(c, (uint64_t)jp.dS * dense_split_rows());
                 c = c / kc * kc;
                 if (c < kc) continue;
+                if (part_bytes * (size_t)jp.dS > part_left) continue;
+                part_left -= part_bytes * (size_t)jp.dS;
                 jp.dcap[(size_t)m] = (uint32_t)c;
                 jp.o_dense[(size_t)m] = p.dense_bytes;
                 p.dense_bytes += (size_t)jp.Ntile * c;
@@ -268,11 +276,13 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.mw.assign(nmask, MaskWork{});
     p.o_flags = L.take(p.nflags * 4);
     // chunks: greedy runs of masks whose buffers fit the pool
+    const size_t outb = ctx->fixed_arena ? 0 : p.output_bytes;  // caller outputs outside a fixed scratch
     const size_t fixed = L.size + (16u << 20);  // + descriptor headroom
-    const size_t reserved = fixed + p.dense_bytes + p.output_bytes;
+    const size_t reserved = fixed + p.dense_bytes + outb;
     if (reserved >= ctx->budget) {
-        set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB",
-                  fixed / 1e9, p.dense_bytes / 1e9, p.output_bytes / 1e9, ctx->budget / 1e9);
+        set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the %s %.3f GB", fixed / 1e9,
+                  p.dense_bytes / 1e9, outb / 1e9, ctx->fixed_arena ? "fixed scratch of" : "HBM budget",
+                  ctx->budget / 1e9);
         return GAKCO_EBUDGET;
     }
     const size_t pool_limit = std::min(ctx->budget - reserved, ctx->pool_cap);
@@ -343,6 +353,12 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 w.nslab = jp.acc_nslab;
                 w.first = stored[j][(size_t)lev] ? 0 : 1;
                 stored[j][(size_t)lev] = 1;
+                // masks per flush of the uint32 row: mstep * maxng^2 < 2^32
+                {
+                    const uint64_t sq = std::max<uint64_t>(1, (uint64_t)jp.maxng * jp.maxng);
+                    w.mstep = (int)std::min<uint64_t>((uint64_t)cnt, std::max<uint64_t>(1, 0xFFFFFFFFull / sq));
+                    if (ctx->acc_mstep > 0) w.mstep = std::min(w.mstep, ctx->acc_mstep);
+                }
                 c.aw.push_back(w);
                 c.acc_lds = std::max(c.acc_lds, (size_t)jp.acc_slab * 4);
             }
@@ -378,17 +394,32 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.desc_bytes = d.size;
     p.o_pool = L.take(p.pool_bytes);
     p.o_desc = L.take(p.desc_bytes);
-    if (L.size + p.dense_bytes + p.output_bytes > ctx->budget) {
-        set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the HBM budget %.3f GB",
-                  L.size / 1e9, p.dense_bytes / 1e9, p.output_bytes / 1e9, ctx->budget / 1e9);
+    if (L.size + (ctx->fixed_arena ? 256 : 0) + p.dense_bytes + outb > ctx->budget) {
+        set_error("scratch %.3f GB + count matrices %.3f GB + outputs %.3f GB exceed the %s %.3f GB", L.size / 1e9,
+                  p.dense_bytes / 1e9, outb / 1e9, ctx->fixed_arena ? "fixed scratch of" : "HBM budget",
+                  ctx->budget / 1e9);
         return GAKCO_EBUDGET;
     }
+    return GAKCO_OK;
+}
+
+gakco_status ctx_small_buffer(gakco_ctx *ctx, void **out)
+{
+    if (!ctx->small) {
+        if (ctx->fixed_arena) { set_error("no small buffer in a fixed-scratch call"); return GAKCO_EINVAL; }
+        GK_HIP(hipMalloc(&ctx->small, 4096));
+    }
+    *out = ctx->small;
     return GAKCO_OK;
 }
 
 static gakco_status reserve_arena(gakco_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->arena_cap) return GAKCO_OK;
+    if (ctx->fixed_arena) {
+        set_error("the call needs %zu bytes of scratch; the fixed scratch holds %zu", bytes, ctx->arena_cap);
+        return GAKCO_EBUDGET;
+    }
     if (ctx->arena) {
         GK_HIP(hipDeviceSynchronize());
         GK_HIP(hipFree(ctx->arena));
@@ -413,7 +444,19 @@ static uint32_t uniform_of(const std::vector<uint32_t> &pre)
 gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
 {
     GK_TRY(reserve_arena(ctx, p.lay.size));
-    if (p.dense_bytes > ctx->dense_cap) {
+    if (ctx->fixed_arena) {
+        // count matrices after the arena's layout, cleared by every call (the
+        // region is shared with calls of other shapes)
+        const size_t off = (p.lay.size + 255) / 256 * 256;
+        if (off + p.dense_bytes > ctx->arena_cap) {
+            set_error("scratch %zu + count matrices %zu bytes exceed the fixed scratch of %zu", off, p.dense_bytes,
+                      ctx->arena_cap);
+            return GAKCO_EBUDGET;
+        }
+        ctx->dense_buf = p.dense_bytes ? reinterpret_cast<int8_t *>(ctx->arena) + off : nullptr;
+        ctx->dense_cap = p.dense_bytes;
+        ctx->dense_dirty = p.dense_bytes > 0;
+    } else if (p.dense_bytes > ctx->dense_cap) {
         if (ctx->dense_buf) {
             GK_HIP(hipDeviceSynchronize());
             GK_HIP(hipFree(ctx->dense_buf));

@@ -21,7 +21,9 @@ enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTE
 // profiling counter slots: six sort kinds, then the row accumulation's pair
 // updates spread over kProfUpdSlots slots (one per block residue) so that the
 // counting adds no same-address contention to the timed kernel
-constexpr int kProfUpdFirst = 8, kProfUpdSlots = 256, kProfStatSlots = kProfUpdFirst + kProfUpdSlots;
+constexpr int kProfUpdFirst = 8, kProfUpdSlots = 256;
+constexpr int kProfRowsFirst = kProfUpdFirst + kProfUpdSlots;  // then the serving rows' pair updates
+constexpr int kProfStatSlots = kProfRowsFirst + kProfUpdSlots;
 
 struct gakco_ctx {
     int device = 0;
@@ -29,6 +31,7 @@ struct gakco_ctx {
     int dense_tau = 0;       // 0 = int8 matrix-core path off
     int bucket_avg = 512;    // target g-mers per hash bucket
     int acc_slab = 0;        // columns per row-accumulation block (0: as many as the LDS holds)
+    int acc_mstep = 0;       // cap on position sets per flush of the row accumulation (0: the count bound only)
     size_t pool_cap = 16ull << 30;  // per-chunk partition/sort buffers
     void *arena = nullptr;
     size_t arena_cap = 0;
@@ -56,6 +59,14 @@ struct gakco_ctx {
     // statistics of the last call
     int64_t last_dense_rows = 0;
     int64_t last_chunks = 0;
+    // fixed scratch (the allocation-free entry point): arena and count
+    // matrices share one caller-given region of arena_cap bytes, nothing is
+    // allocated or freed, and the caller's outputs do not count against the
+    // budget
+    bool fixed_arena = false;
+    // a small device buffer (4 KB) for per-call results of the training
+    // consumer, allocated on first use
+    void *small = nullptr;
 };
 
 namespace gk {
@@ -175,6 +186,12 @@ struct Plan {
     char *base = nullptr;  // arena base
 };
 
+gakco_status ctx_small_buffer(gakco_ctx *ctx, void **out);
+// Kernel rows of queries against a resident set (serving join); K_rows row
+// stride ldk (0: the resident set's size).
+gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t *q_seqs, const int32_t *q_lens,
+                      const int32_t *q_lens_host, int32_t n_q, double *K_rows, int64_t ldk, int64_t *Nm_rows,
+                      double *decision, hipStream_t st);
 gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one, int m_one);
 gakco_status plan_layout(gakco_ctx *ctx, Plan &p);
 gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st);  // arena + pointers + descriptor blob

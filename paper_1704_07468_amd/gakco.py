@@ -80,11 +80,17 @@ def lib():
                 "gakco_profile_get": ([P, i32, P, P, P], i32),
                 "gakco_profile_reset": ([P], None),
                 "gakco_probe_lds_atomics": ([P, i32, P], i32),
+                "gakco_svm_train": ([P, P, P, i32, f64, f64, i32, P, P, P, P, P], i32),
+                "gakco_incr_create": ([P, i32, i32, i32, P], i32),
+                "gakco_incr_append": ([P, P, P, i32, P, P, P], i32),
+                "gakco_incr_info": ([P, P, P], i32),
+                "gakco_incr_destroy": ([P], None),
             }
+            missing = [name for name in sig if getattr(L, name, None) is None]
+            if missing:
+                raise RuntimeError("libgakco.so lacks %s: rebuild it (__graft_entry__.build())" % ", ".join(missing))
             for name, (args, res) in sig.items():
-                fn = getattr(L, name, None)
-                if fn is None:
-                    continue
+                fn = getattr(L, name)
                 fn.argtypes = args
                 fn.restype = res
             _lib = L
@@ -160,6 +166,19 @@ class Context:
         v = ctypes.c_int64()
         _check(lib().gakco_ctx_stat(self._h, name.encode(), ctypes.byref(v)))
         return v.value
+
+    def svm_train(self, K, y, C: float = 1.0, eps: float = 1e-3, max_epochs: int = 10000):
+        """The SVM of Eq. 1 on a device kernel K [N,N] (f64) with labels y
+        (+1/-1): dict alpha, dual_coef (device f64 [N]), bias, epochs."""
+        N = int(K.shape[0])
+        K = K.contiguous()
+        y = torch.as_tensor(y).to(device=self.device, dtype=torch.int8).contiguous()
+        alpha = torch.empty(N, dtype=torch.float64, device=self.device)
+        dual = torch.empty(N, dtype=torch.float64, device=self.device)
+        b, ep = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().gakco_svm_train(self._h, _ptr(K), _ptr(y), N, float(C), float(eps), int(max_epochs),
+                                     _ptr(alpha), _ptr(dual), ctypes.byref(b), ctypes.byref(ep), _stream(self.device)))
+        return {"alpha": alpha, "dual_coef": dual, "bias": b.value, "epochs": ep.value}
 
     # ------------------------------------------------------------- batches --
     def _jobs(self, jobs):
@@ -335,6 +354,45 @@ class Resident:
             pass
 
 
+class IncrementalGram:
+    """A normalised Gram matrix that grows by appended batches of sequences;
+    `append` returns the new (N+n) x (N+n) matrix (device f64)."""
+
+    def __init__(self, ctx: Context, sigma: int, g: int, k: int):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().gakco_incr_create(ctx._h, sigma, g, k, ctypes.byref(h)))
+        self._h = h
+        self.K = None
+
+    @property
+    def N(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().gakco_incr_info(self._h, ctypes.byref(n), None))
+        return n.value
+
+    def append(self, seqs, lens):
+        seqs, lens = _dev_inputs(seqs, lens, self.ctx.device)
+        n_new = int(lens.numel())
+        Nt = self.N + n_new
+        out = torch.empty((Nt, Nt), dtype=torch.float64, device=self.ctx.device)
+        _check(lib().gakco_incr_append(self._h, _ptr(seqs), _ptr(lens), n_new, _ptr(self.K), _ptr(out),
+                                       _stream(self.ctx.device)))
+        self.K = out
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gakco_incr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Continuous-batching server over a resident set (host queries)."""
 
@@ -357,7 +415,9 @@ class Server:
         _check(rc)
         return True
 
-    def poll(self, max_results: int = 64, wait_us: int = 1000):
+    def poll(self, max_results: int = 64, wait_us: int = 1000, rows: bool = True):
+        """Finished requests (dicts); with rows=False the K rows are not copied
+        out (their "K_row" is None)."""
         import numpy as np
         arr = (Result * max_results)()
         n = ctypes.c_int32()
@@ -368,7 +428,7 @@ class Server:
         for i in range(n.value):
             r = arr[i]
             row = None
-            if r.K_row:
+            if r.K_row and rows:
                 row = np.ctypeslib.as_array(ctypes.cast(r.K_row, ctypes.POINTER(ctypes.c_double)),
                                             shape=(self.res.n_sv,)).copy()
             out.append({"tag": r.tag, "status": r.status, "decision": r.decision, "K_row": row,

@@ -18,15 +18,16 @@ from paper_1704_07468_amd import workloads as wl  # noqa: E402
 
 def test_accumulate_bytes_of_the_protein_workload():
     """The protein Gram (N = 3312, g = 7, k = 4: 64 position sets) has
-    885958 g-mers; the row accumulation must read one 8-byte info word per
-    (position set, g-mer) and write each upper-triangle entry of the four
-    C_m (16 bytes each, read and written): 804735488 bytes a Gram."""
+    885958 g-mers; the accumulation step of the method reads one 12-byte
+    grouped (reduced key, sequence) record per (position set, g-mer) and
+    writes every entry of the four C_m once (8 bytes each):
+    680415744 + 351019008 = 1031434752 bytes a Gram."""
     d = wl.protein()
     masks = [math.comb(d.g, m) for m in range(d.M + 1)]
     assert sum(masks) == 64
     alg, T = bench.algorithmic(d, masks, {"wave": 1}, 0, 3328)
     assert T == 885958
-    assert alg["accumulate"] == 804735488
+    assert alg["accumulate"] == 12 * 885958 * 64 + 8 * 4 * 3312 * 3312 == 1031434752
     tri = d.N * (d.N + 1) // 2
     # the epilogue reads the upper C_m entries and writes every N_m entry and K
     assert alg["finalize"] == 8 * (d.M + 1) * tri + 8 * (d.M + 1) * d.N * d.N + 8 * d.N * d.N

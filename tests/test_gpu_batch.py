@@ -107,6 +107,37 @@ def test_autotune_keeps_results_exact(gk):
         c2.close()
 
 
+def test_full_batched_config_vs_oracle(gk):
+    """All 64 jobs of the batched workload in one batch, each against the
+    oracle run now on the host's cores: jobs with N <= 500 in full (every N_m
+    and K-hat entry); every other job on the sub-Gram of 21 of its sequences
+    drawn at random (210 off-diagonal pairs and their diagonals), since an
+    entry depends only on its two sequences."""
+    from oracle import oracle as orc
+    inputs = wl.batched()
+    jobs = [{"seqs": d.seqs, "lens": d.lens, "sigma": d.sigma, "g": d.g, "k": d.k} for d in inputs]
+    status = gk.gram_batch(jobs)
+    assert status == [0] * len(jobs)
+    rng = np.random.default_rng(64)
+    th = orc.host_threads()
+    for d, j in zip(inputs, jobs):
+        print("job", d.name, "N=%d sigma=%d g=%d k=%d" % (d.N, d.sigma, d.g, d.k), flush=True)
+        if d.N <= 500:
+            idx = np.arange(d.N)
+            o = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=th, per_mask=True, want_c=False)
+        else:
+            idx = np.sort(rng.choice(d.N, size=21, replace=False))
+            sub = d.subset(idx.tolist())
+            o = orc.kernel(sub.seqs, sub.lens, sub.g, sub.k, threads=th, per_mask=True, want_c=False)
+        ti = __import__("torch").as_tensor(idx, device=j["Nm"].device)
+        got_nm = j["Nm"][:, ti][:, :, ti].cpu().numpy()
+        got_k = j["K"][ti][:, ti].cpu().numpy()
+        np.testing.assert_array_equal(got_nm, o["Nm"], err_msg=d.name)
+        want = o["Kn"]
+        assert (got_k[want == 0] == 0).all(), d.name
+        np.testing.assert_allclose(got_k[want != 0], want[want != 0], rtol=1e-12, atol=0, err_msg=d.name)
+
+
 def test_full_batched_config_equals_plain(gk):
     """The 64-job batched workload: every job equals the same job computed
     alone on the plain path."""

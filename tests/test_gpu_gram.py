@@ -296,6 +296,32 @@ def test_gram_dense_counts_above_int8(gk):
         c2.close()
 
 
+def test_gram_long_sequence_past_int32_bound(gk):
+    """A 6000-symbol sequence among shorter ones at g=10, k=4 (M=6): one
+    position set adds up to 5991^2 to an entry, so the 210 sets of m=6 are
+    summed in steps of at most 119 before each flush of the 32-bit row into
+    the int64 C_m.  Every C_m / N_m entry bit-exact against the oracle."""
+    rng = np.random.default_rng(41)
+    lens = np.array([6000] + rng.integers(200, 900, size=7).tolist(), dtype=np.int32)
+    seqs = rng.integers(0, 4, size=int(lens.sum())).astype(np.int8)
+    run_and_compare(gk, wl.GramInput("long_dna", seqs, lens, 4, 10, 4))
+
+
+@pytest.mark.parametrize("mstep", [1, 3])
+def test_gram_mask_steps_match_oracle(mstep):
+    """The row accumulation flushing its 32-bit row after every `mstep`
+    position sets (store on the first flush, add on later ones) gives the
+    oracle's exact integers."""
+    from paper_1704_07468_amd import gakco
+    ctx = gakco.Context(0, tune={"acc_mstep": mstep})
+    try:
+        for d in [wl.protein(N=250), wl.text(N=30, lmin=200, lmax=400)]:
+            print("mstep", mstep, "case", d.name, flush=True)
+            run_and_compare(ctx, d)
+    finally:
+        ctx.close()
+
+
 def test_gram_repeat_deterministic(gk):
     d = wl.protein(N=150, lmin=50, lmax=300)
     a = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
@@ -304,35 +330,36 @@ def test_gram_repeat_deterministic(gk):
     assert (a["K"] == b["K"]).all().item()
 
 
-def _sampled_full_config(gk, d, nsample, seed):
+def _full_config_every_entry(gk, d):
+    """The whole workload on the GPU against the oracle run now on the host's
+    cores (position sets dealt to threads, Section S:5.3): every C_m, N_m and
+    K-hat entry, plus the structural properties at full size."""
     import torch
-    r = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
-    Nm = r["Nm"]
+    from oracle import oracle as orc
+    print("case:", d.name, "N=%d full size, every entry" % d.N, flush=True)
+    r = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k, want_Cm=True)
     K = r["K"]
-    # properties at full size
     assert torch.equal(K, K.T)
-    assert torch.equal(Nm, Nm.transpose(1, 2))
     dg = torch.diagonal(K)
     assert torch.all((dg == 1.0) | (dg - 1.0).abs().le(1e-15))
-    assert (Nm >= 0).all().item()
-    rng = np.random.default_rng(seed)
-    xs = rng.integers(0, d.N, size=nsample)
-    ys = rng.integers(0, d.N, size=nsample)
-    Nm_h = Nm[:, torch.as_tensor(xs), torch.as_tensor(ys)].cpu().numpy()
-    K_h = K[torch.as_tensor(xs), torch.as_tensor(ys)].cpu().numpy()
-    for i, (x, y) in enumerate(zip(xs, ys)):
-        if x == y:
-            continue
-        nm, kk, kn = oracle().pair_entry(d.seq(int(x)), d.seq(int(y)), d.g, d.k)
-        np.testing.assert_array_equal(Nm_h[:, i], nm, err_msg="entry (%d,%d)" % (x, y))
-        assert abs(K_h[i] - kn) <= RTOL * abs(kn), (x, y, K_h[i], kn)
+    got_nm = r["Nm"].cpu().numpy()
+    got_cm = r["Cm"].cpu().numpy()
+    got_k = K.cpu().numpy()
+    del r, K
+    torch.cuda.empty_cache()
+    o = orc.kernel(d.seqs, d.lens, d.g, d.k, threads=orc.host_threads(), per_mask=True)
+    np.testing.assert_array_equal(got_nm, o["Nm"])
+    np.testing.assert_array_equal(got_cm, o["C"])
+    check_kn(got_k, o["Kn"])
 
 
-def test_gram_protein_full_size_sampled(gk):
-    """The benchmark workload (N=3312) in the benchmark's configuration; sampled
-    entries recomputed one by one by the oracle on the pair."""
-    _sampled_full_config(gk, wl.protein(), 150, 1)
+def test_gram_protein_full_size_every_entry(gk):
+    """The benchmark workload (N=3312, g=7, k=4) in the benchmark's launch
+    configuration: all 4 x 3312^2 C_m and N_m entries bit-exact, K-hat within
+    1e-12."""
+    _full_config_every_entry(gk, wl.protein())
 
 
-def test_gram_text_full_size_sampled(gk):
-    _sampled_full_config(gk, wl.text(), 20, 2)
+def test_gram_text_full_size_every_entry(gk):
+    """The text workload (N=2000, g=10, k=4, M=6, 848 position sets)."""
+    _full_config_every_entry(gk, wl.text())
