@@ -668,3 +668,67 @@ done:
     free(seqs); free(lens); free(Cq); free(Cd); free(Nq); free(Nd);
     return rc;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Training consumer: the support-vector machine of Eq. 1 on the kernel   */
+/* ---------------------------------------------------------------------- */
+/* The paper trains an SVM on the gapped k-mer kernel (Section 3.1) and
+ * classifies with f(x) = sum_i alpha_i y_i K(x_i, x) + b (Eq. 1); it does not
+ * fix the solver.  This is the soft-margin dual with the bias absorbed into
+ * the kernel (K'(x, x') = K(x, x') + 1, so that b = sum_i alpha_i y_i):
+ *     minimise  1/2 alpha^T Q alpha - sum_i alpha_i,  0 <= alpha_i <= C,
+ *     Q_ij = y_i y_j K'_ij,
+ * solved by dual coordinate descent (Hsieh et al., ICML 2008): coordinates in
+ * the order 0..N-1, each set to the clipped minimiser of the objective along
+ * it, with the gradient G = Q alpha - 1 kept up to date; an epoch is one pass,
+ * and the run stops after the first epoch in which the projected gradients
+ * span at most eps, or after max_epochs.
+ * K: [N][N] normalised kernel (row-major), y: labels +1 / -1.
+ * Outputs: alpha [N], dual_coef [N] = alpha_i y_i, *bias = sum_i alpha_i y_i
+ * (ascending i), *epochs = epochs run.  Returns ORC_EINVAL for a bad
+ * argument or a label other than +1 / -1. */
+int orc_svm_dcd(const double *K, const int8_t *y, int32_t N, double C, double eps, int32_t max_epochs,
+                double *alpha, double *dual_coef, double *bias, int32_t *epochs)
+{
+    if (N < 1 || !(C > 0.0) || eps < 0.0 || max_epochs < 1) return ORC_EINVAL;
+    for (int32_t i = 0; i < N; ++i)
+        if (y[i] != 1 && y[i] != -1) return ORC_EINVAL;
+    double *G = (double *)calloc((size_t)N, sizeof(double)); /* (Q alpha)_j */
+    if (!G) return ORC_ENOMEM;
+    for (int32_t i = 0; i < N; ++i) alpha[i] = 0.0;
+    int32_t ep = 0;
+    while (ep < max_epochs) {
+        double pgmax = -HUGE_VAL, pgmin = HUGE_VAL;
+        for (int32_t i = 0; i < N; ++i) {
+            const double qii = K[(size_t)i * N + i] + 1.0;
+            const double g = G[i] - 1.0;
+            double pg = g;
+            if (alpha[i] == 0.0) pg = fmin(g, 0.0);
+            else if (alpha[i] == C) pg = fmax(g, 0.0);
+            pgmax = fmax(pgmax, pg);
+            pgmin = fmin(pgmin, pg);
+            if (pg != 0.0) {
+                const double a_new = fmin(fmax(alpha[i] - g / qii, 0.0), C);
+                const double d = a_new - alpha[i];
+                alpha[i] = a_new;
+                if (d != 0.0)
+                    for (int32_t j = 0; j < N; ++j) {
+                        double q = K[(size_t)i * N + j] + 1.0;
+                        if (y[i] != y[j]) q = -q;
+                        G[j] = G[j] + d * q;
+                    }
+            }
+        }
+        ++ep;
+        if (pgmax - pgmin <= eps) break;
+    }
+    double b = 0.0;
+    for (int32_t i = 0; i < N; ++i) {
+        dual_coef[i] = alpha[i] * (double)y[i];
+        b += dual_coef[i];
+    }
+    *bias = b;
+    *epochs = ep;
+    free(G);
+    return ORC_OK;
+}

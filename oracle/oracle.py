@@ -58,6 +58,8 @@ def _load():
             lib.orc_mask_groups.restype = i64
             lib.orc_rows.argtypes = [P, P, i32, P, P, i32, i32, i32, P, f64, i32, P, P, P]
             lib.orc_rows.restype = ctypes.c_int
+            lib.orc_svm_dcd.argtypes = [P, P, i32, f64, f64, i32, P, P, P, P]
+            lib.orc_svm_dcd.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -196,3 +198,23 @@ def pair_entry(seq_x, seq_y, g, k):
     lens = np.array([len(sx), len(sy)], dtype=np.int32)
     r = kernel(seqs, lens, g, k, want_c=False)
     return r["Nm"][:, 0, 1].copy(), int(r["K"][0, 1]), float(r["Kn"][0, 1])
+
+
+def svm_dcd(K, y, C: float = 1.0, eps: float = 1e-8, max_epochs: int = 10000):
+    """The SVM of Eq. 1 trained on a normalised kernel K [N,N] with labels y
+    (+1/-1) by dual coordinate descent (bias absorbed as K + 1).
+
+    Returns dict alpha [N], dual_coef [N] (alpha_i y_i), bias, epochs."""
+    lib = _load()
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.int8)
+    N = len(y)
+    alpha = np.zeros(N, dtype=np.float64)
+    dual = np.zeros(N, dtype=np.float64)
+    b = ctypes.c_double()
+    ep = ctypes.c_int32()
+    rc = lib.orc_svm_dcd(_ptr(K), _ptr(y), N, float(C), float(eps), int(max_epochs), _ptr(alpha), _ptr(dual),
+                         ctypes.byref(b), ctypes.byref(ep))
+    if rc != 0:
+        raise RuntimeError("orc_svm_dcd failed: %d" % rc)
+    return {"alpha": alpha, "dual_coef": dual, "bias": b.value, "epochs": ep.value}

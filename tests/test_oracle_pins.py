@@ -408,3 +408,73 @@ def test_threaded_rows_equal_sequential():
     np.testing.assert_array_equal(a["Nm"], b["Nm"])
     np.testing.assert_array_equal(a["Krows"], b["Krows"])
     np.testing.assert_array_equal(a["decision"], b["decision"])
+
+
+# ---------------------------------------------------------------------- SVM --
+def _kkt_violation(K, y, alpha, C):
+    """Largest violation of the optimality conditions of the bias-absorbed
+    dual: with f_i = sum_j alpha_j y_j (K_ij + 1) (Eq. 1, b = sum alpha_j y_j),
+    y_i f_i >= 1 where alpha_i = 0, = 1 where 0 < alpha_i < C, <= 1 where
+    alpha_i = C."""
+    yf = y * ((K + 1.0) @ (alpha * y))
+    v = np.where(alpha <= 0.0, np.maximum(0.0, 1.0 - yf),
+                 np.where(alpha >= C, np.maximum(0.0, yf - 1.0), np.abs(yf - 1.0)))
+    return float(v.max())
+
+
+@pytest.mark.parametrize("C", [0.1, 1.0, 10.0])
+def test_svm_kkt_on_dna_config(C):
+    """The DNA workload's Gram and its seeded labels: the oracle's solution
+    satisfies the KKT conditions, stays in the box, and its decision values
+    from Eq. 1 equal sum_j dual_j K_ij + b."""
+    d = wl.dna()
+    K = orc.kernel(d.seqs, d.lens, d.g, d.k)["Kn"]
+    y = d.labels.astype(np.float64)
+    r = orc.svm_dcd(K, d.labels, C=C, eps=1e-9, max_epochs=200000)
+    assert r["epochs"] < 200000  # stopped by the projected-gradient rule
+    a = r["alpha"]
+    assert (a >= 0).all() and (a <= C).all()
+    assert _kkt_violation(K, y, a, C) <= 1e-6
+    np.testing.assert_array_equal(r["dual_coef"], a * y)
+    assert r["bias"] == pytest.approx(float(np.sum(a * y)), rel=0, abs=1e-12)
+
+
+@pytest.mark.parametrize("c,labels,C,want", [
+    (0.5, (1, -1), 10.0, 2.0),         # opposite labels: a = 1 / (1 - c)
+    (0.5, (1, -1), 1.0, 1.0),          # ... clipped at C
+    (0.5, (1, 1), 10.0, 2.0 / 7.0),    # same label: a = 1 / (3 + c)
+    (-0.2, (-1, 1), 5.0, 1.0 / 1.2),
+])
+def test_svm_two_points_closed_form(c, labels, C, want):
+    """Two points with K = [[1, c], [c, 1]]: by symmetry both multipliers
+    equal the minimiser a of the one-variable objective along alpha = (a, a),
+    a^2 (1 - c) - 2a for opposite labels, a^2 (3 + c) / ... for equal labels,
+    clipped to [0, C]."""
+    K = np.array([[1.0, c], [c, 1.0]])
+    r = orc.svm_dcd(K, np.array(labels, dtype=np.int8), C=C, eps=1e-13, max_epochs=100000)
+    np.testing.assert_allclose(r["alpha"], [want, want], rtol=1e-9, atol=0)
+
+
+def test_svm_matches_a_box_qp_solver():
+    """A random protein Gram (N=30): the dual objective of the oracle's
+    solution equals that of scipy's L-BFGS-B on the same box-constrained
+    quadratic program, and the multipliers agree."""
+    from scipy.optimize import minimize
+    d = wl.protein(N=30, lmin=20, lmax=120)
+    K = orc.kernel(d.seqs, d.lens, d.g, d.k)["Kn"]
+    y = np.where(np.random.default_rng(3).random(30) < 0.5, 1, -1).astype(np.int8)
+    C = 2.0
+    Q = (y[:, None] * y[None, :]) * (K + 1.0)
+    obj = lambda a: 0.5 * a @ Q @ a - a.sum()
+    jac = lambda a: Q @ a - 1.0
+    ref = minimize(obj, np.zeros(30), jac=jac, method="L-BFGS-B", bounds=[(0, C)] * 30,
+                   options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 100000})
+    r = orc.svm_dcd(K, y, C=C, eps=1e-12, max_epochs=100000)
+    assert obj(r["alpha"]) <= ref.fun + 1e-9 * abs(ref.fun)
+    assert abs(obj(r["alpha"]) - ref.fun) <= 1e-7 * abs(ref.fun)
+    np.testing.assert_allclose(r["alpha"], ref.x, rtol=0, atol=1e-4)
+
+
+def test_svm_rejects_bad_labels():
+    with pytest.raises(RuntimeError):
+        orc.svm_dcd(np.eye(3), np.array([1, 0, -1], dtype=np.int8))
