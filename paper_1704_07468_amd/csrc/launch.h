@@ -47,12 +47,13 @@ void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, 
                    const uint32_t *E, const uint4 *gtab);
 hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
                        int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
-                       hipStream_t st);
+                       unsigned long long *updates, hipStream_t st);
 hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef, const int64_t *hco, int64_t *Kd,
                                hipStream_t st);
 hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,
                                 const int64_t *Kd_sv, const int64_t *Kd_q, const double *alpha, double bias, double *K_rows,
-                                int64_t *Nm_rows, double *decision, double *partial, hipStream_t st);
+                                int64_t ldk, int64_t *Nm_rows, double *decision, double *partial, hipStream_t st);
+hipError_t launch_mirror_block(double *out, int64_t ld, int rows, int c0, int cols, hipStream_t st);
 size_t rows_partial_count(int nq, int nsv);
 hipError_t init_rows_attributes(size_t lds);
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);

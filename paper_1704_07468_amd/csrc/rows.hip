@@ -32,6 +32,7 @@ struct RowsArgs {
     const int32_t *lev_first;  // first mask of each level
     const int32_t *lev_count;
     uint32_t *C;               // [M+1][nq][nsv], zeroed; blocks add their partial rows
+    unsigned long long *updates;  // nullable (profiling): pair updates, spread over 256 slots
 };
 
 __device__ __forceinline__ void wave_sync_rows()
@@ -105,6 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     const ResMask *rm = A.rm + A.lev_first[level] + m0;
     const int sb = rm[0].sb;
     const uint32_t sidmask = (uint32_t)bits_mask(sb);
+    unsigned long long wupd = 0;  // the wave's gathered pair updates (profiling count)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t it = c0 + lane;
         uint32_t len = 0;
@@ -141,6 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
         const uint32_t inc = wave_incl_scan(len);
         const uint32_t work = __builtin_amdgcn_readlane(inc, 63);
         if (work == 0) continue;  // wave-uniform
+        wupd += work;
         const uint32_t start = inc - len;
         const uint64_t nz = __ballot(len > 0);
         if (len > 0) tbase[wid][lanes_below(nz)] = ebase - 4ull * start;
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
         }
         wave_sync_rows();
     }
+    if (A.updates && lane == 0 && wupd) atomicAdd(A.updates + (blockIdx.x & 255u), wupd);
     __syncthreads();
     const gptr<uint32_t> crow = glb(A.C) + ((size_t)level * A.nq + q) * A.nsv;
     for (int sv = s0 + tid; sv < s1; sv += kThreads) {
@@ -219,6 +223,7 @@ struct RowsFinArgs {
     double *decision;
     double *partial;  // [nq][nchunk] decision sums per SV chunk
     int32_t chunk, nchunk;
+    int64_t ldk;      // row stride of K_rows
 };
 
 constexpr int kRowsChunk = 512;  // SVs per epilogue block (enough blocks for one query)
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_finalize(RowsFinArgs A)
         }
         const int64_t ks = A.Kd_sv[sv];
         const double kh = (kq == 0 || ks == 0) ? 0.0 : (double)K / sqrt((double)ks * (double)kq);
-        if (A.K_rows) A.K_rows[(size_t)q * A.nsv + sv] = kh;
+        if (A.K_rows) A.K_rows[(size_t)q * A.ldk + sv] = kh;
         if (A.alpha) part += A.alpha[sv] * kh;
     }
     red[tid] = part;
@@ -290,11 +295,11 @@ void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, 
 
 hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
                        int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
-                       hipStream_t st)
+                       unsigned long long *updates, hipStream_t st)
 {
     if (nq <= 0) return hipSuccess;
     RowsArgs a{qkey, qgstart, nq, M, nsv, slab, (nsv + slab - 1) / slab, mchunk, reinterpret_cast<const ResMask *>(rm),
-               lev_first, lev_count, C};
+               lev_first, lev_count, C, updates};
     const unsigned nb = (unsigned)((size_t)nq * nitems * a.nslab);
     hipLaunchKernelGGL(k_rows_accumulate, dim3(nb), dim3(kThreads), (size_t)slab * 4, st, a);
     return hipGetLastError();
@@ -315,16 +320,44 @@ size_t rows_partial_count(int nq, int nsv) { return (size_t)nq * (size_t)((nsv +
 
 hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,
                                 const int64_t *Kd_sv, const int64_t *Kd_q, const double *alpha, double bias, double *K_rows,
-                                int64_t *Nm_rows, double *decision, double *partial, hipStream_t st)
+                                int64_t ldk, int64_t *Nm_rows, double *decision, double *partial, hipStream_t st)
 {
     if (nq <= 0) return hipSuccess;
     const int nchunk = (nsv + kRowsChunk - 1) / kRowsChunk;
-    RowsFinArgs a{C, nq, nsv, M, coef, hco, Kd_sv, Kd_q, alpha, bias, K_rows, Nm_rows, decision, partial, kRowsChunk, nchunk};
+    RowsFinArgs a{C, nq, nsv, M, coef, hco, Kd_sv, Kd_q, alpha, bias, K_rows, Nm_rows, decision, partial, kRowsChunk, nchunk,
+                  ldk > 0 ? ldk : (int64_t)nsv};
     const dim3 grid((unsigned)(nq * nchunk));
     if (M < 8) hipLaunchKernelGGL(k_rows_finalize<8>, grid, dim3(kThreads), 0, st, a);
     else if (M < 16) hipLaunchKernelGGL(k_rows_finalize<16>, grid, dim3(kThreads), 0, st, a);
     else hipLaunchKernelGGL(k_rows_finalize<65>, grid, dim3(kThreads), 0, st, a);
     if (decision) hipLaunchKernelGGL(k_rows_decision, dim3((nq + kThreads - 1) / kThreads), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// out[r][c0 + c] = out[c0 + c][r] for r < rows, c < cols (row stride ld):
+// the block above the diagonal from the block below it, through 32 x 32 LDS
+// tiles.
+__global__ __launch_bounds__(kThreads) void k_mirror_block(double *out, int64_t ld, int rows, int c0, int cols)
+{
+    __shared__ double tile[32][33];
+    const int tr = blockIdx.y * 32, tc = blockIdx.x * 32;  // tile origin in (row r, column c)
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+    for (int k = ty; k < 32; k += 8) {
+        const int c = tc + k, r = tr + tx;  // read out[c0 + c][r], coalesced along r
+        if (c < cols && r < rows) tile[k][tx] = out[(size_t)(c0 + c) * ld + r];
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {
+        const int r = tr + k, c = tc + tx;  // write out[r][c0 + c], coalesced along c
+        if (r < rows && c < cols) out[(size_t)r * ld + c0 + c] = tile[tx][k];
+    }
+}
+
+hipError_t launch_mirror_block(double *out, int64_t ld, int rows, int c0, int cols, hipStream_t st)
+{
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+    hipLaunchKernelGGL(k_mirror_block, grid, dim3(kThreads), 0, st, out, ld, rows, c0, cols);
     return hipGetLastError();
 }
 

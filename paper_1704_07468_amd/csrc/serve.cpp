@@ -63,12 +63,14 @@ static gakco_status rows_scratch(gakco_ctx *ctx, size_t bytes, char **out)
     std::lock_guard<std::mutex> lk(g_scratch_mu);
     RowsScratch &s = g_scratch[ctx];
     if (bytes > s.cap) {
+        // the callers synchronise their stream before returning, so the old
+        // buffer is idle; growth is geometric so that it stays rare
         if (s.p) {
-            GK_HIP(hipDeviceSynchronize());
             GK_HIP(hipFree(s.p));
             s.p = nullptr;
             s.cap = 0;
         }
+        bytes = std::max(bytes, s.cap + s.cap / 2);
         GK_HIP(hipMalloc(&s.p, bytes));
         s.cap = bytes;
     }
@@ -86,11 +88,32 @@ void rows_scratch_release(const gakco_ctx *ctx)
     }
 }
 
+// The serving counters are uint32 summed over all position sets of a level:
+// a query's own diagonal (at most C(g,m) * ng_q^2), its row entries (at most
+// C(g,m) * ng_q * ng_sv) and the resident diagonal (C(g,m) * ng_sv^2).
+static bool level_sum_fits(const gakco_resident *R, uint64_t ng_a, uint64_t ng_b)
+{
+    for (int m = 0; m <= R->M; ++m)
+        if ((double)binom64(R->g, m) * (double)ng_a * (double)ng_b > 4294967295.0) return false;
+    return true;
+}
+
+static gakco_status check_query_bounds(const gakco_resident *R, uint64_t ng_q)
+{
+    if (!level_sum_fits(R, ng_q, ng_q) || !level_sum_fits(R, ng_q, R->maxng)) {
+        set_error("a query with %llu g-mers exceeds the 32-bit serving counters (C(g,m) * g-mers^2 and C(g,m) * "
+                  "query g-mers * resident g-mers must stay below 2^32)", (unsigned long long)ng_q);
+        return GAKCO_EUNSUPPORTED;
+    }
+    return GAKCO_OK;
+}
+
 // Rows of n_q queries (device symbols and lengths; host lengths when known)
 // against a resident set, on stream st; synchronises st before returning.
-static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t *q_seqs, const int32_t *q_lens,
-                             const int32_t *q_lens_host, int32_t n_q, double *K_rows, int64_t *Nm_rows, double *decision,
-                             hipStream_t st)
+// K_rows has row stride ldk (0: n_sv).
+gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t *q_seqs, const int32_t *q_lens,
+                          const int32_t *q_lens_host, int32_t n_q, double *K_rows, int64_t ldk, int64_t *Nm_rows,
+                          double *decision, hipStream_t st)
 {
     if (!R || n_q < 1 || !q_seqs || !q_lens) { set_error("bad arguments"); return GAKCO_EINVAL; }
     Plan p;
@@ -101,11 +124,7 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     if (q_lens_host) jp.lens.assign(q_lens_host, q_lens_host + n_q);
     else GK_TRY(fetch_lens(jp, st));
     GK_TRY(plan_shape(ctx, jp, nullptr, 0));
-    for (int m = 0; m <= R->M; ++m)
-        if ((double)binom64(R->g, m) * (double)jp.maxng * (double)R->maxng >= 2147483648.0) {
-            set_error("C(g,m) * query g-mers * resident g-mers overflows the int32 row counters");
-            return GAKCO_EUNSUPPORTED;
-        }
+    GK_TRY(check_query_bounds(R, jp.maxng));
     const int M1 = R->M + 1;
     Layout l;
     const size_t o_diag = l.take((size_t)M1 * n_q * 4);
@@ -137,10 +156,11 @@ static gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8
     int nitems = 0;
     for (int m = 0; m <= R->M; ++m) nitems += (int)binom64(R->g, m);
     GK_HIP(launch_fill_u32(C, (size_t)M1 * n_q * R->n_sv, 0u, st));
+    unsigned long long *upd = ctx->prof_on && ctx->prof_stat ? ctx->prof_stat + kProfRowsFirst : nullptr;
     GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,
-                                  R->lev_count, C, st));
+                                  R->lev_count, C, upd, st));
     GK_PHASE(PH_ROWS_FINALIZE, launch_rows_finalize(C, n_q, R->n_sv, R->M, R->coef, R->hco, R->Kd, Kq, R->alpha, R->bias, K_rows,
-                                           Nm_rows, decision,
+                                           ldk, Nm_rows, decision,
                                                            reinterpret_cast<double *>(scr + o_part), st));
     return plan_check_errors(ctx, p, st);
 }
@@ -183,9 +203,12 @@ struct gakco_server {
     bool stop = false;
 };
 
+// Worker buffers grow geometrically (and are sized by a warm-up batch when
+// the server starts), so that steady-state batches never reallocate.
 static gakco_status grow_pinned(void **p, size_t *cap, size_t bytes)
 {
     if (bytes <= *cap) return GAKCO_OK;
+    bytes = std::max(bytes, *cap + *cap / 2);
     if (*p) GK_HIP(hipHostFree(*p));
     *p = nullptr;
     GK_HIP(hipHostMalloc(p, bytes, hipHostMallocDefault));
@@ -196,6 +219,7 @@ static gakco_status grow_pinned(void **p, size_t *cap, size_t bytes)
 static gakco_status grow_device(char **p, size_t *cap, size_t bytes)
 {
     if (bytes <= *cap) return GAKCO_OK;
+    bytes = std::max(bytes, *cap + *cap / 2);
     if (*p) GK_HIP(hipFree(*p));
     *p = nullptr;
     GK_HIP(hipMalloc(p, bytes));
@@ -238,7 +262,7 @@ static gakco_status run_batch(gakco_server *S, SrvWorker &W, std::vector<SrvRequ
     double *dK = reinterpret_cast<double *>(W.d_buf + o_K);
     double *dd = reinterpret_cast<double *>(W.d_buf + o_d);
     const gakco_status s = rows_run(W.ctx, R, reinterpret_cast<int8_t *>(W.d_buf + o_q),
-                                    reinterpret_cast<int32_t *>(W.d_buf + o_l), W.h_lens, nq, dK, nullptr, dd, W.st);
+                                    reinterpret_cast<int32_t *>(W.d_buf + o_l), W.h_lens, nq, dK, 0, nullptr, dd, W.st);
     if (s != GAKCO_OK && s != GAKCO_ERANGE) return s;
     GK_HIP(hipMemcpyAsync(W.h_out, dK, (size_t)nq * R->n_sv * 8, hipMemcpyDeviceToHost, W.st));
     GK_HIP(hipMemcpyAsync(W.h_out + (size_t)nq * R->n_sv, dd, (size_t)nq * 8, hipMemcpyDeviceToHost, W.st));
@@ -251,6 +275,33 @@ static gakco_status run_batch(gakco_server *S, SrvWorker &W, std::vector<SrvRequ
         r.r.status = s;  // a batch with a bad symbol is reported on all its queries
     }
     return GAKCO_OK;
+}
+
+// Sizes a worker's context arena, rows scratch and staging buffers with one
+// batch of as many 1024-symbol queries (pseudo-random codes) as max_batch and
+// the worker's budget allow, so that batches of queries up to that length
+// never reallocate (a reallocation frees device memory, which waits for the
+// whole device and so for the other workers' batches).  Best effort: a
+// failure leaves the buffers to grow on demand.
+static void warm_worker(gakco_server *S, SrvWorker &W, size_t wbudget, size_t npos)
+{
+    const gakco_resident *R = S->res;
+    const size_t len = 1024;
+    const size_t per = query_bytes(R, len, npos);
+    const int n = (int)std::min<size_t>((size_t)S->max_batch, per ? wbudget / per : 0);
+    if (n < 1) return;
+    std::vector<SrvRequest> batch((size_t)n);
+    uint32_t x = 0x2545F491u;
+    for (auto &r : batch) {
+        r.q.resize(len);
+        for (auto &c : r.q) {
+            x = x * 1664525u + 1013904223u;  // a 32-bit LCG (Numerical Recipes constants)
+            c = (int8_t)((x >> 16) % (uint32_t)R->sigma);
+        }
+    }
+    std::vector<SrvResult> out;
+    (void)run_batch(S, W, batch, out);
+    clear_error();
 }
 
 static void worker_loop(gakco_server *S, int wi)
@@ -340,6 +391,11 @@ gakco_status gakco_resident_create(gakco_ctx *ctx, const int8_t *seqs, const int
     R->device = ctx->device;
     R->n_sv = n_sv; R->sigma = sigma; R->g = g; R->k = k; R->M = jp.M; R->b = jp.b; R->sb = jp.sb;
     R->maxng = jp.maxng;
+    if (!level_sum_fits(R, jp.maxng, jp.maxng)) {
+        set_error("a resident sequence with %u g-mers exceeds the 32-bit diagonal counters (C(g,m) * g-mers^2 < 2^32)",
+                  jp.maxng);
+        return fail(GAKCO_EUNSUPPORTED);
+    }
     R->bias = bias;
     const int M1 = jp.M + 1;
     const size_t nm = jp.masks.size();
@@ -453,7 +509,7 @@ gakco_status gakco_rows(gakco_ctx *ctx, const gakco_resident *res, const int8_t 
     if (res->device != ctx->device) { set_error("resident set and context are on different devices"); return GAKCO_EINVAL; }
     GK_HIP(hipSetDevice(ctx->device));
     if (init_rows_attributes(ctx->lds_max) != hipSuccess) { set_error("hipFuncSetAttribute failed"); return GAKCO_EHIP; }
-    return rows_run(ctx, res, q_seqs, q_lens, nullptr, n_q, K_rows, Nm_rows, decision, (hipStream_t)hip_stream);
+    return rows_run(ctx, res, q_seqs, q_lens, nullptr, n_q, K_rows, 0, Nm_rows, decision, (hipStream_t)hip_stream);
 }
 
 gakco_status gakco_server_create(const gakco_resident *res, int32_t device, int32_t max_batch, int32_t n_streams,
@@ -491,6 +547,9 @@ gakco_status gakco_server_create(const gakco_resident *res, int32_t device, int3
             return s;
         }
     }
+    size_t npos = 0;
+    for (int m = 0; m <= res->M; ++m) npos += (size_t)binom64(res->g, m);
+    for (auto &W : S->workers) warm_worker(S, W, S->budget / (size_t)n_streams, npos);
     for (int i = 0; i < n_streams; ++i) S->workers[(size_t)i].th = std::thread(worker_loop, S, i);
     *out = S;
     return GAKCO_OK;
@@ -502,6 +561,9 @@ gakco_status gakco_server_submit(gakco_server *S, const int8_t *q_host, int32_t 
     if (!S || len < 0 || (len > 0 && !q_host)) { set_error("bad arguments"); return GAKCO_EINVAL; }
     for (int32_t i = 0; i < len; ++i)
         if (q_host[i] < 0 || q_host[i] >= S->res->sigma) { set_error("symbol %d at %d outside [0, sigma)", q_host[i], i); return GAKCO_ERANGE; }
+    // screened alone, so that an oversized query never fails the batch it
+    // would have joined
+    GK_TRY(check_query_bounds(S->res, len >= S->res->g ? (uint64_t)(len - S->res->g + 1) : 0u));
     SrvRequest r;
     r.tag = tag;
     r.q.assign(q_host, q_host + len);

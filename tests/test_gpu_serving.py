@@ -62,30 +62,32 @@ def test_rows_protein_resident(gk):
         res.close()
 
 
-def test_rows_full_resident_sampled(gk):
-    """The 20000-sequence resident set of the serving workload; sampled
-    entries recomputed by the oracle on (query, resident) pairs."""
+def test_rows_full_resident_full_rows(gk):
+    """The 20000-sequence resident set of the serving workload: two whole
+    query rows (every N_m and K-hat entry against all 20000 resident
+    sequences) and their Eq. 1 decision values against the oracle run now on
+    the host's cores."""
     from oracle import oracle as orc
     from paper_1704_07468_amd import gakco
     s = wl.serving_resident()
     res = gakco.Resident(gk, s.sv.seqs, s.sv.lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias)
     try:
-        q_seqs, q_lens = wl.serving_queries(4)
-        r = res.rows(q_seqs, q_lens)
+        q_seqs, q_lens = wl.serving_queries(2)
+        print("serving full rows: query lengths", q_lens.tolist(), flush=True)
+        r = res.rows(q_seqs, q_lens, want_nm=True)
+        got_nm = r["Nm"].cpu().numpy()
         K = r["K"].cpu().numpy()
         dec = r["decision"].cpu().numpy()
-        qoff = np.concatenate([[0], np.cumsum(q_lens)])
-        rng = np.random.default_rng(4)
-        for qi in range(4):
-            qs = q_seqs[qoff[qi]:qoff[qi + 1]]
-            for sv in rng.integers(0, s.sv.N, size=12):
-                _, _, kn = orc.pair_entry(qs, s.sv.seq(int(sv)), s.sv.g, s.sv.k)
-                assert abs(K[qi, sv] - kn) <= 1e-12 * abs(kn), (qi, sv)
-            # Eq. 1 from the row (same row, same alpha)
-            f = s.bias + float(np.dot(s.alpha, K[qi]))
-            assert abs(dec[qi] - f) <= 1e-12 * float(np.abs(s.alpha * K[qi]).sum()) + 1e-12
     finally:
         res.close()
+    o = orc.rows(s.sv.seqs, s.sv.lens, q_seqs, q_lens, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias,
+                 threads=orc.host_threads())
+    np.testing.assert_array_equal(got_nm, o["Nm"])
+    assert (K[o["Krows"] == 0] == 0).all()
+    nz = o["Krows"] != 0
+    np.testing.assert_allclose(K[nz], o["Krows"][nz], rtol=1e-12, atol=0)
+    tol = 1e-12 * (np.abs(s.alpha)[None, :] * np.abs(o["Krows"])).sum(axis=1) + 1e-15
+    assert (np.abs(dec - o["decision"]) <= tol).all()
 
 
 def test_server_alone_equals_mix(gk):
@@ -158,4 +160,41 @@ def test_server_cancel_and_budget(gk):
         assert got and got[0]["status"] == gakco.EBUDGET
         tiny.close()
     finally:
+        res.close()
+
+
+def test_server_oversized_query_fails_alone(gk):
+    """A query past the 32-bit serving counters (5000 symbols at g=10, k=6:
+    C(10,4) * 4991^2 >= 2^32) is refused at submit with EUNSUPPORTED; the
+    queries around it are admitted and return the rows they return alone."""
+    from paper_1704_07468_amd import gakco
+    s, res = small_resident(gk, n_sv=120, seed=3)
+    q_seqs, q_lens = wl.serving_queries(10, lmin=100, lmax=900)
+    qoff = np.concatenate([[0], np.cumsum(q_lens)])
+    queries = [q_seqs[qoff[i]:qoff[i + 1]] for i in range(10)]
+    big = np.random.default_rng(5).integers(0, 4, size=5000).astype(np.int8)
+    srv = gakco.Server(res, max_batch=16, n_streams=1)
+    try:
+        for i in range(5):
+            srv.submit(queries[i], i)
+        with pytest.raises(gakco.GakcoError) as e:
+            srv.submit(big, 99)
+        assert e.value.status == gakco.EUNSUPPORTED
+        for i in range(5, 10):
+            srv.submit(queries[i], i)
+        got = {}
+        t_end = time.time() + 60
+        while len(got) < 10 and time.time() < t_end:
+            for r in srv.poll(64, 100000):
+                got[r["tag"]] = r
+        assert sorted(got) == list(range(10))
+        direct = res.rows(q_seqs, q_lens)
+        for i in range(10):
+            assert got[i]["status"] == 0
+            assert np.array_equal(got[i]["K_row"], direct["K"][i].cpu().numpy()), i
+        with pytest.raises(gakco.GakcoError) as e:
+            res.rows(big, np.array([5000], dtype=np.int32))
+        assert e.value.status == gakco.EUNSUPPORTED
+    finally:
+        srv.close()
         res.close()
