@@ -153,6 +153,31 @@ gakco_status gakco_gram(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens,
                         int64_t *Cm_out, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * gakco_gram_noalloc -- gakco_gram for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid allocation).  It allocates and frees nothing: its scratch is a
+ * library-owned device array of GAKCO_NOALLOC_SCRATCH_BYTES (512 MiB) that
+ * every GPU the library runs on holds from the first call until the process
+ * ends.  It runs on the calling thread's current device, with no context:
+ * default tuning, no side stream, no profiler.
+ *   Arguments, layouts, outputs and errors as gakco_gram, except:
+ *   - the caller's outputs do not count against the scratch; the cumulative
+ *     profiles are summed in Nm_out (else Cm_out), and only when both are
+ *     NULL do they need (g-k+1) * N^2 * 8 bytes of the scratch;
+ *   - GAKCO_EBUDGET when the call's scratch (g-mer arrays, one position-set
+ *     chunk's partition buffers, count matrices, descriptors) exceeds the
+ *     array; nothing is launched then.
+ * Every call on a GPU shares that GPU's array and leaves its contents behind;
+ * each call clears what it needs cleared.  The library serialises its own
+ * calls on one device (they also synchronise the stream before returning);
+ * other work a caller enqueues on the same array concurrently would race.
+ * ------------------------------------------------------------------------ */
+#define GAKCO_NOALLOC_SCRATCH_BYTES (512ull << 20)
+gakco_status gakco_gram_noalloc(const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma,
+                                int32_t g, int32_t k, double *K_out, int64_t *Nm_out, int64_t *Cm_out,
+                                void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Stage entry points (the first steps of the Gram path on their own; used for
  * stage-level parity).
  *

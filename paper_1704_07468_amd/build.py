@@ -24,6 +24,7 @@ SOURCES = [
     "serve.cpp",
     "svm.hip",
     "incr.cpp",
+    "noalloc.hip",
 ]
 
 CFLAGS = [

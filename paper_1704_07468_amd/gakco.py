@@ -85,6 +85,7 @@ def lib():
                 "gakco_incr_append": ([P, P, P, i32, P, P, P], i32),
                 "gakco_incr_info": ([P, P, P], i32),
                 "gakco_incr_destroy": ([P], None),
+                "gakco_gram_noalloc": ([P, P, i32, i32, i32, i32, P, P, P, P], i32),
             }
             missing = [name for name in sig if getattr(L, name, None) is None]
             if missing:
@@ -446,6 +447,17 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_SCRATCH_BYTES = 512 << 20
+
+
+def gram_noalloc(seqs, lens, N: int, sigma: int, g: int, k: int, K=None, Nm=None, Cm=None, device: int = 0):
+    """gakco_gram_noalloc on device tensors already in place: the library
+    allocates no device memory (its scratch is a fixed device array)."""
+    with torch.cuda.device(device):
+        _check(lib().gakco_gram_noalloc(_ptr(seqs), _ptr(lens), int(N), int(sigma), int(g), int(k), _ptr(K), _ptr(Nm),
+                                        _ptr(Cm), _stream(device)))
 
 
 def version() -> str:
