@@ -25,6 +25,7 @@ SOURCES = [
     "svm.hip",
     "incr.cpp",
     "noalloc.hip",
+    "direct.hip",
 ]
 
 CFLAGS = [

@@ -41,6 +41,12 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
             return GAKCO_EINVAL;
         }
         ctx->class_tau[b * 100 + g] = (int)v;
+    } else if (!strcmp(name, "direct")) {
+        if (v < 0 || v > 2) { set_error("direct must be 0, 1 or 2"); return GAKCO_EINVAL; }
+        ctx->direct_mode = (int)v;
+    } else if (!strcmp(name, "excess_cap")) {
+        if (v < 0 || v > (int64_t)kExcessCap) { set_error("excess_cap must be in 0..%u", kExcessCap); return GAKCO_EINVAL; }
+        ctx->excess_cap = (uint32_t)v;
     } else if (!strcmp(name, "overlap")) {
         ctx->overlap = v != 0;
     } else if (!strcmp(name, "bucket_avg")) {
@@ -80,6 +86,30 @@ static gakco_status apply_json(gakco_ctx *ctx, const char *js)
     }
     return GAKCO_OK;
 }
+
+namespace gk {
+// Lays out, binds, launches and checks a planned call.  When the directly
+// addressed position sets hold more counts above 127 than the call's list
+// takes, the call is redone with those levels sorted instead (same result).
+gakco_status run_single(gakco_ctx *ctx, Plan &p, hipStream_t st)
+{
+    GK_TRY(plan_layout(ctx, p));
+    GK_TRY(plan_bind(ctx, p, st));
+    GK_TRY(plan_upload(p, st));
+    GK_TRY(plan_launch(ctx, p, st));
+    gakco_status s = plan_check_errors(ctx, p, st);
+    if (p.excess_overflow && ctx->direct_mode != 0) {
+        clear_error();
+        const int saved = ctx->direct_mode;
+        ctx->direct_mode = 0;
+        ctx->direct_fallbacks += 1;
+        p.excess_overflow = false;
+        s = run_single(ctx, p, st);
+        ctx->direct_mode = saved;
+    }
+    return s;
+}
+}  // namespace gk
 
 extern "C" {
 
@@ -200,11 +230,7 @@ gakco_status gakco_gram(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens,
     if (!seqs || !lens) { set_error("seqs and lens must not be NULL"); return GAKCO_EINVAL; }
     GK_TRY(fetch_lens(jp, st));
     GK_TRY(plan_shape(ctx, jp, nullptr, 0));
-    GK_TRY(plan_layout(ctx, p));
-    GK_TRY(plan_bind(ctx, p, st));
-    GK_TRY(plan_upload(p, st));
-    GK_TRY(plan_launch(ctx, p, st));
-    return plan_check_errors(ctx, p, st);
+    return run_single(ctx, p, st);
 }
 
 gakco_status gakco_extract(gakco_ctx *ctx, const int8_t *seqs, const int32_t *lens, int32_t N, int32_t sigma, int32_t g,
@@ -302,6 +328,10 @@ gakco_status gakco_ctx_stat(const gakco_ctx *ctx, const char *name, int64_t *val
     if (!ctx || !name || !value) { set_error("bad arguments"); return GAKCO_EINVAL; }
     if (!strcmp(name, "dense_rows")) *value = ctx->last_dense_rows;
     else if (!strcmp(name, "chunks")) *value = ctx->last_chunks;
+    else if (!strcmp(name, "excess")) *value = ctx->last_excess;
+    else if (!strcmp(name, "direct")) *value = ctx->direct_mode;
+    else if (!strcmp(name, "direct_levels")) *value = ctx->last_direct_levels;
+    else if (!strcmp(name, "direct_fallbacks")) *value = ctx->direct_fallbacks;
     else if (!strcmp(name, "dense_tau")) *value = ctx->dense_tau;
     else if (!strcmp(name, "bucket_avg")) *value = ctx->bucket_avg;
     else if (!strcmp(name, "arena_bytes")) *value = (int64_t)ctx->arena_cap;

@@ -94,11 +94,7 @@ gakco_status gakco_gram_batch(gakco_ctx *ctx, const gakco_job *jobs_host, int32_
     gakco_status first = prepare_jobs(ctx, jobs_host, n_jobs, st, p, keep, status);
     if (status.empty()) return first;
     if (!p.jobs.empty()) {
-        gakco_status s = plan_layout(ctx, p);
-        if (s == GAKCO_OK) s = plan_bind(ctx, p, st);
-        if (s == GAKCO_OK) s = plan_upload(p, st);
-        if (s == GAKCO_OK) s = plan_launch(ctx, p, st);
-        if (s == GAKCO_OK) s = plan_check_errors(ctx, p, st);
+        gakco_status s = run_single(ctx, p, st);
         for (size_t q = 0; q < keep.size(); ++q)
             status[(size_t)keep[q]] = (s == GAKCO_OK || s == GAKCO_ERANGE) ? p.jobs[q].status : s;
         if (first == GAKCO_OK) first = s;
@@ -123,6 +119,8 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
     own.bucket_avg = ctx->bucket_avg;
     own.acc_slab = ctx->acc_slab;
     own.acc_mstep = ctx->acc_mstep;
+    own.direct_mode = ctx->direct_mode;
+    own.excess_cap = ctx->excess_cap;
     own.pool_cap = ctx->pool_cap;
     own.lds_max = ctx->lds_max;
     own.class_tau = ctx->class_tau;
@@ -168,7 +166,32 @@ gakco_status gakco_batch_run(gakco_batch_plan *bp, void *hip_stream)
     GK_HIP(hipSetDevice(bp->own.device));
     hipStream_t st = (hipStream_t)hip_stream;
     GK_HIP(hipGraphLaunch(bp->exec, st));
-    const gakco_status s = plan_check_errors(&bp->own, bp->p, st);
+    gakco_status s = plan_check_errors(&bp->own, bp->p, st);
+    if (bp->p.excess_overflow) {
+        // more counts above 127 in directly addressed position sets than the
+        // captured list takes: redo the jobs once with those levels sorted, in
+        // a temporary context (the plan's own memory stays as the graph uses it)
+        gakco_ctx tmp;
+        tmp.device = bp->own.device;
+        tmp.budget = bp->own.budget;
+        tmp.dense_tau = bp->own.dense_tau;
+        tmp.bucket_avg = bp->own.bucket_avg;
+        tmp.acc_slab = bp->own.acc_slab;
+        tmp.acc_mstep = bp->own.acc_mstep;
+        tmp.pool_cap = bp->own.pool_cap;
+        tmp.lds_max = bp->own.lds_max;
+        tmp.class_tau = bp->own.class_tau;
+        tmp.direct_mode = 0;
+        bp->own.direct_fallbacks += 1;
+        Plan q;
+        q.jobs = bp->p.jobs;
+        clear_error();
+        s = run_single(&tmp, q, st);
+        if (tmp.arena) (void)hipFree(tmp.arena);
+        if (tmp.dense_buf) (void)hipFree(tmp.dense_buf);
+        for (size_t i = 0; i < q.jobs.size(); ++i) bp->p.jobs[i].status = q.jobs[i].status;
+        bp->p.excess_overflow = false;
+    }
     // a plan exists only when every job passed planning: job i is p.jobs[i]
     for (size_t i = 0; i < bp->status_out.size(); ++i)
         if (bp->status_out[i]) *bp->status_out[i] = bp->p.jobs[i].status;

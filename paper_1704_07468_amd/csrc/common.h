@@ -86,7 +86,7 @@ struct JobDev {
                              // kshift > 0 the sequence id sits above them (key >> kshift)
     int32_t kshift;          // g * b when g * b + sb <= 64 (and the keys are internal), else 0
     uint32_t *sid;           // [T] sequence of each g-mer
-    int32_t *err;            // bit 0: a symbol outside [0, sigma)
+    int32_t *err;            // bit 0: a symbol outside [0, sigma); bit 1: excess list full
     int64_t *C;              // [M+1][N][N] cumulative profiles (upper triangle accumulated)
     int64_t *Kd;             // [N] unnormalised K diagonal
     const int64_t *coef;     // [(M+1)*(M+1)] C(g-j, m-j) at [m*(M+1)+j]
@@ -95,6 +95,46 @@ struct JobDev {
     double *K_out;
     int64_t *Nm_out;
     int64_t *Cm_out;
+};
+
+// Direct-address grouping of a level whose reduced g-mers take at most
+// kDirectMaxKeys values (sigma^(g-m) of them): no partition and no sort.  A
+// position set's groups are indexed by the reduced g-mer itself (base-sigma
+// digits, first kept symbol most significant), so every possible reduced
+// g-mer is one row of the level's count matrix D, D[X][row] = how often
+// sequence X holds it (Section 2.2 step 3: the groups of equal reduced
+// g-mers and their per-sequence counts), and the level's whole C_m is D^T D
+// on the matrix cores.  Counts above 127 are stored as 127; the excess is
+// recorded and corrected exactly afterwards.
+constexpr uint32_t kDirectMaxKeys = 16384;
+
+struct DirectLevel {
+    int8_t *D;         // [Ntile][stride] sequence-major counts; rows [0, R) used
+    uint32_t stride;   // bytes per sequence (R rounded up to 64)
+    uint32_t R;        // rows: position sets of the level x Kp
+    uint32_t Kp;       // rows per position set: sigma^(g-m) rounded up to 16
+    int32_t job, level;
+    int32_t nd;        // kept symbols, g - m
+    int32_t b, sigma;  // symbol bits and alphabet size
+    int32_t pow2;      // 1: sigma = 2^b, the row is the compacted key itself
+};
+
+// One position set of a directly addressed level.
+struct DirectWork {
+    MaskDesc md;
+    int32_t dl;        // its DirectLevel
+    uint32_t row0;     // first count-matrix row of this position set
+    int32_t first;     // 1: the level's first position set (clears the level's C_m rows)
+    int32_t last;      // 1: the level's last position set (zeroes the rows past R)
+};
+
+// Counts above 127 of directly addressed position sets: (row, sequence,
+// count - 127, direct level) per entry.  Past cap entries the call is redone
+// without direct addressing.
+struct ExcessList {
+    uint4 *ent;
+    uint32_t *count;
+    uint32_t cap;
 };
 
 // Per (job, mask) work of the partition sort and its outputs.

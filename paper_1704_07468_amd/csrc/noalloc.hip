@@ -87,9 +87,5 @@ extern "C" gakco_status gakco_gram_noalloc(const int8_t *seqs, const int32_t *le
     jp.K_out = K_out; jp.Nm_out = Nm_out; jp.Cm_out = Cm_out;
     GK_TRY(fetch_lens(jp, st));
     GK_TRY(plan_shape(ctx, jp, nullptr, 0));
-    GK_TRY(plan_layout(ctx, p));
-    GK_TRY(plan_bind(ctx, p, st));
-    GK_TRY(plan_upload(p, st));
-    GK_TRY(plan_launch(ctx, p, st));
-    return plan_check_errors(ctx, p, st);
+    return run_single(ctx, p, st);
 }

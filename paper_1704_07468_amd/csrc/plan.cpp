@@ -192,6 +192,89 @@ static MaskBuf mask_buf(uint32_t T, int B)
 
 static int job_tau(const gakco_ctx *ctx, const JobPlan &jp) { return jp.tau >= 0 ? jp.tau : ctx->dense_tau; }
 
+// Rows [r0, r1) of each split, as split_range computes them on the device:
+// the largest split's row count for R rows over at most S splits.
+static uint32_t split_rows_max(uint32_t R, int S)
+{
+    const uint32_t used = std::max(1u, std::min((uint32_t)S, (R + kDenseMinSplitRows - 1) / kDenseMinSplitRows));
+    return ((R + used - 1) / used + (uint32_t)kDenseK - 1) / (uint32_t)kDenseK * (uint32_t)kDenseK;
+}
+
+// Which levels of a job are grouped by direct addressing (no sort): those
+// whose reduced g-mers take at most kDirectMaxKeys values, whose int8
+// products stay exact in int32 per row split, and -- in the automatic mode
+// -- whose modelled time (count-matrix products and writes) beats that of
+// sorting the level and updating its groups pair by pair (or as count rows
+// when they are dense anyway).  Moves the position sets of those levels
+// from jp.masks to jp.dmasks.
+static void plan_direct(const gakco_ctx *ctx, JobPlan &jp)
+{
+    const int M1 = jp.M + 1;
+    jp.direct.assign((size_t)M1, 0);
+    jp.dKp.assign((size_t)M1, 0);
+    jp.dR.assign((size_t)M1, 0);
+    jp.dstride.assign((size_t)M1, 0);
+    jp.dSd.assign((size_t)M1, 0);
+    jp.o_Dd.assign((size_t)M1, 0);
+    jp.o_Pd.assign((size_t)M1, 0);
+    if (!jp.dmasks.empty()) {  // planned before: restore the level order
+        jp.masks.insert(jp.masks.end(), jp.dmasks.begin(), jp.dmasks.end());
+        std::stable_sort(jp.masks.begin(), jp.masks.end(),
+                         [](const MaskDesc &a, const MaskDesc &b) { return a.level < b.level; });
+        jp.dmasks.clear();
+    }
+    if (ctx->direct_mode == 0 || !jp.want_kernel || !jp.ext_boff.empty() || !jp.ext_diag.empty() || jp.T == 0) return;
+    const int ntile = jp.Ntile / dense_tile();
+    const int tiles = ntile * (ntile + 1) / 2;
+    const double sq = (double)jp.maxng * (double)jp.maxng;
+    const double T = (double)jp.T, Nt = (double)jp.Ntile;
+    const int tau = job_tau(ctx, jp);
+    // measured rates on MI355X: ~30 ps per (position set, g-mer) through the
+    // partition and sort, ~8e11 pair updates/s in the row accumulation,
+    // ~5e14 int8 MACs/s in the count-matrix products, ~5e12 B/s of row writes
+    constexpr double kSortS = 3.0e-11, kUpd = 8.0e11, kMac = 5.0e14, kWrite = 5.0e12;
+    size_t bytes = 0;
+    for (int m = 0; m <= jp.M; ++m) {
+        uint64_t K = 1;
+        bool small = true;
+        for (int q = 0; q < jp.g - m && small; ++q) {
+            K *= (uint64_t)jp.sigma;
+            small = K <= kDirectMaxKeys;
+        }
+        if (!small) continue;
+        const uint64_t Kp = (K + 15) / 16 * 16;
+        const uint64_t nm = (uint64_t)binom64(jp.g, m);
+        const uint64_t R = nm * Kp;
+        if (R >= (1ull << 31)) continue;
+        // splits: about 1024 blocks of products, each split's int32 sums exact
+        // (at most 65536 rows of counts <= 127, or few enough position sets:
+        // one adds at most ng_X * ng_Y to an entry)
+        int S = std::max(1, std::min(kDenseMaxSplits, (1024 + tiles - 1) / tiles));
+        auto exact = [&](int s) {
+            const uint32_t per = split_rows_max((uint32_t)R, s);
+            return per <= kDenseSplitRows || ((double)(per / Kp + 2) * sq < 2147483647.0);
+        };
+        while (!exact(S) && S < kDenseMaxSplits) ++S;
+        if (!exact(S)) continue;
+        const double t_direct = (double)Kp * Nt * Nt * 0.5 / kMac + (double)Kp * Nt / kWrite;
+        const double lam = T / (double)K;  // g-mers per reduced g-mer
+        const double t_sort = T * kSortS + (tau > 0 && lam >= tau ? (double)K * Nt * Nt * 0.5 / kMac : T * lam * 0.5 / kUpd);
+        if (ctx->direct_mode == 1 && t_direct >= t_sort) continue;
+        const uint64_t stride = (R + 63) / 64 * 64;
+        const size_t lb = (size_t)jp.Ntile * stride + (size_t)tiles * S * dense_tile() * dense_tile() * 4;
+        if (bytes + lb > ctx->budget / 4) continue;
+        bytes += lb;
+        jp.direct[(size_t)m] = 1;
+        jp.dKp[(size_t)m] = (uint32_t)Kp;
+        jp.dR[(size_t)m] = (uint32_t)R;
+        jp.dstride[(size_t)m] = (uint32_t)stride;
+        jp.dSd[(size_t)m] = S;
+    }
+    std::vector<MaskDesc> keep;
+    for (auto &md : jp.masks) (jp.direct[(size_t)md.level] ? jp.dmasks : keep).push_back(md);
+    jp.masks.swap(keep);
+}
+
 gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
 {
     Layout &L = p.lay;
@@ -202,10 +285,16 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.maxM = 0;
     p.pool_bytes = 0;
     p.chunks.clear();
+    p.n_dlev = p.n_dwork = 0;
+    p.maxKp = 0;
+    p.excess_cap = 0;
+    p.excess_overflow = false;
     size_t nmask = 0;
     p.nflags = p.jobs.size();
     for (auto &jp : p.jobs) {
         const size_t N = (size_t)jp.N, M1 = (size_t)jp.M + 1;
+        jp.Ntile = (jp.N + dense_tile() - 1) / dense_tile() * dense_tile();
+        plan_direct(ctx, jp);
         if (!jp.key_override) {
             jp.o_key = L.take((size_t)jp.T * 8);
             jp.o_sid = L.take((size_t)jp.T * 4);
@@ -217,7 +306,6 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
         jp.dcap.assign(M1, 0);
         jp.o_dense.assign(M1, 0);
         jp.o_P.assign(M1, 0);
-        jp.Ntile = (jp.N + dense_tile() - 1) / dense_tile() * dense_tile();
         if (!jp.want_kernel) continue;
         // row slabs: a block of the row accumulation keeps one slab of a
         // row's int32 counters in LDS
@@ -259,6 +347,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
             const size_t part_bytes = (size_t)tiles * dense_tile() * dense_tile() * 4;
             const uint64_t kc = (uint64_t)dense_kchunk();
             for (int m = jp.M; m >= 0; --m) {
+                if (jp.direct[(size_t)m]) continue;
                 uint64_t c = (uint64_t)(want[(size_t)m] * scale);
                 c = std::min<uint64_t>(c, (uint64_t)jp.dS * dense_split_rows());
                 c = c / kc * kc;
@@ -272,7 +361,37 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 p.n_dense += 1;
             }
         }
+        // direct-address levels: count matrix and split partial tiles
+        {
+            const int ntile = jp.Ntile / dense_tile();
+            const size_t tiles = (size_t)ntile * (ntile + 1) / 2;
+            for (int m = 0; m <= jp.M; ++m) {
+                if (!jp.direct[(size_t)m]) continue;
+                jp.o_Dd[(size_t)m] = L.take((size_t)jp.Ntile * jp.dstride[(size_t)m]);
+                jp.o_Pd[(size_t)m] = L.take(tiles * (size_t)jp.dSd[(size_t)m] * dense_tile() * dense_tile() * 4);
+                p.n_dlev += 1;
+                p.maxKp = std::max(p.maxKp, jp.dKp[(size_t)m]);
+            }
+            p.n_dwork += (int)jp.dmasks.size();
+        }
     }
+    // counts above 127 in directly addressed position sets (their counter is
+    // the last flag word)
+    p.f_excess = p.nflags;
+    p.nflags += 1;
+    {
+        // a sequence with ng g-mers has at most ng / 128 reduced g-mers counted
+        // more than 127 times in one position set
+        uint64_t bound = 0;
+        for (auto &jp : p.jobs) {
+            if (jp.dmasks.empty()) continue;
+            uint64_t q = 0;
+            for (int X = 0; X < jp.N; ++X) q += (jp.gstart[(size_t)X + 1] - jp.gstart[(size_t)X]) >> 7;
+            bound += q * jp.dmasks.size();
+        }
+        p.excess_cap = (uint32_t)std::min<uint64_t>(bound, ctx->excess_cap ? ctx->excess_cap : kExcessCap);
+    }
+    p.o_excess = L.take((size_t)std::max(1u, p.excess_cap) * 16);
     p.mw.assign(nmask, MaskWork{});
     p.o_flags = L.take(p.nflags * 4);
     // chunks: greedy runs of masks whose buffers fit the pool
@@ -370,9 +489,13 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     const size_t nj = p.jobs.size();
     p.d_jobs = d.take(sizeof(JobDev) * nj, 64);
     p.d_masks = d.take(sizeof(MaskWork) * std::max<size_t>(1, nmask), 64);
-    p.d_dense = d.take(dense_work_size() * (size_t)std::max(1, p.n_dense), 64);
-    p.d_pdense = d.take(((size_t)p.n_dense + 1) * 4, 64);
-    p.d_pdtile = d.take(((size_t)p.n_dense + 1) * 4, 64);
+    p.d_dense = d.take(dense_work_size() * (size_t)std::max(1, p.n_dense + p.n_dlev), 64);
+    p.d_pdense = d.take(((size_t)p.n_dense + p.n_dlev + 1) * 4, 64);
+    p.d_pdtile = d.take(((size_t)p.n_dense + p.n_dlev + 1) * 4, 64);
+    p.d_dlev = d.take(sizeof(DirectLevel) * (size_t)std::max(1, p.n_dlev), 64);
+    p.d_dwork = d.take(sizeof(DirectWork) * (size_t)std::max(1, p.n_dwork), 64);
+    p.d_pdir = d.take(((size_t)p.n_dwork + 1) * 4, 64);
+    p.d_drows = d.take((size_t)std::max(1, p.n_dlev) * 4, 64);
     p.d_pv = d.take((nj + 1) * 4, 64);
     p.d_px = d.take((nj + 1) * 4, 64);
     p.d_pd = d.take((nj + 1) * 4, 64);
@@ -480,8 +603,11 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     char *blob = p.desc_host.data();
     auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
     JobDev *jd = reinterpret_cast<JobDev *>(blob + p.d_jobs);
-    std::vector<uint32_t> pv(1, 0), px(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0);
-    int di = 0;
+    std::vector<uint32_t> pv(1, 0), px(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0), pdir(1, 0);
+    int di = 0, dl_next = 0, dw_next = 0;
+    DirectLevel *dlev = reinterpret_cast<DirectLevel *>(blob + p.d_dlev);
+    DirectWork *dwork = reinterpret_cast<DirectWork *>(blob + p.d_dwork);
+    uint32_t *drows = reinterpret_cast<uint32_t *>(blob + p.d_drows);
     for (size_t j = 0; j < p.jobs.size(); ++j) {
         auto &jp = p.jobs[j];
         const int M1 = jp.M + 1;
@@ -495,9 +621,17 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             for (int q = 0; q < m; ++q) coef[(size_t)m * M1 + q] = binom64(jp.g - q, m - q);  // Eq. 9
         }
         DenseRef *dref = reinterpret_cast<DenseRef *>(blob + jp.o_dref);
+        std::vector<int> dl_of((size_t)M1, -1);
         for (int m = 0; m < M1; ++m) {
             dref[m] = DenseRef{};
-            if (jp.want_kernel && jp.dcap[(size_t)m]) {
+            if (jp.want_kernel && jp.direct[(size_t)m]) {
+                dref[m].P = reinterpret_cast<const int32_t *>(p.base + jp.o_Pd[(size_t)m]);
+                dref[m].count = reinterpret_cast<const uint32_t *>(dev_desc + p.d_drows) + dl_next;
+                dref[m].cap = jp.dR[(size_t)m];
+                dref[m].S = jp.dSd[(size_t)m];
+                dref[m].ntile = jp.Ntile / dense_tile();
+                dl_of[(size_t)m] = dl_next++;
+            } else if (jp.want_kernel && jp.dcap[(size_t)m]) {
                 dref[m].P = reinterpret_cast<const int32_t *>(p.base + jp.o_P[(size_t)m]);
                 dref[m].count = reinterpret_cast<const uint32_t *>(p.base + p.o_flags) + p.jobs.size() + jp.lev_base + m;
                 dref[m].cap = jp.dcap[(size_t)m];
@@ -528,6 +662,36 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             J.Cm_out = jp.Cm_out;
         }
         jd[j] = J;
+        for (int m = 0; m < M1; ++m) {
+            const int dl = dl_of[(size_t)m];
+            if (dl < 0) continue;
+            DirectLevel &L = dlev[dl];
+            L = DirectLevel{};
+            L.D = reinterpret_cast<int8_t *>(base + jp.o_Dd[(size_t)m]);
+            L.stride = jp.dstride[(size_t)m];
+            L.R = jp.dR[(size_t)m];
+            L.Kp = jp.dKp[(size_t)m];
+            L.job = (int)j;
+            L.level = m;
+            L.nd = jp.g - m;
+            L.b = jp.b;
+            L.sigma = jp.sigma;
+            L.pow2 = (1 << jp.b) == jp.sigma ? 1 : 0;
+            drows[dl] = L.R;
+            uint32_t row0 = 0;
+            for (size_t q = 0; q < jp.dmasks.size(); ++q) {
+                if (jp.dmasks[q].level != m) continue;
+                DirectWork &W = dwork[dw_next++];
+                W = DirectWork{};
+                W.md = jp.dmasks[q];
+                W.dl = dl;
+                W.row0 = row0;
+                W.first = row0 == 0 ? 1 : 0;
+                row0 += L.Kp;
+                W.last = row0 == L.R ? 1 : 0;
+                pdir.push_back(pdir.back() + (uint32_t)jp.Ntile);
+            }
+        }
         pv.push_back(pv.back() + (uint32_t)((jp.nsym + kThreads * 16 - 1) / (kThreads * 16)));
         px.push_back(px.back() + (jp.T + kThreads - 1) / kThreads);
         pd.push_back(pd.back() + (jp.want_kernel ? (uint32_t)((jp.N + kThreads - 1) / kThreads) : 0u));
@@ -547,6 +711,28 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             }
         }
     }
+    // the direct levels' int8 products come after every sort-path count
+    // matrix (only those are cleared after use)
+    for (size_t j = 0; j < p.jobs.size(); ++j) {
+        auto &jp = p.jobs[j];
+        if (!jp.want_kernel) continue;
+        const int ntile = jp.Ntile / dense_tile();
+        const uint32_t tiles = (uint32_t)(ntile * (ntile + 1) / 2);
+        for (int m = 0; m <= jp.M; ++m) {
+            if (!jp.direct[(size_t)m]) continue;
+            const DenseRef &R = reinterpret_cast<const DenseRef *>(blob + jp.o_dref)[m];
+            dense_work_fill(blob + p.d_dense + dense_work_size() * (size_t)di,
+                            reinterpret_cast<int8_t *>(base + jp.o_Dd[(size_t)m]), R.count, jp.dR[(size_t)m],
+                            jp.dstride[(size_t)m], jp.N, ntile, jp.dSd[(size_t)m],
+                            reinterpret_cast<int32_t *>(base + jp.o_Pd[(size_t)m]));
+            pdn.push_back(pdn.back() + tiles * (uint32_t)jp.dSd[(size_t)m]);
+            pdt.push_back(pdt.back() + tiles);
+            ++di;
+        }
+    }
+    put(p.d_pdir, pdir);
+    p.nb_dir = pdir.back();
+    p.uni_dir = uniform_of(pdir);
     // mask works, chunk by chunk (each chunk's buffers at the start of the pool)
     size_t j = 0;
     for (auto &c : p.chunks) {
@@ -651,7 +837,8 @@ gakco_status plan_upload(Plan &p, hipStream_t st)
 static const char *kPhaseNames[PH_COUNT] = {"fill", "validate", "extract", "bucket_count", "bucket_scan",
                                             "bucket_scatter", "sort_wave", "sort_block", "sort_global",
                                             "accumulate", "dense_syrk", "dense_clear",
-                                            "diag", "finalize", "rows_kdiag", "rows", "rows_finalize"};
+                                            "diag", "finalize", "rows_kdiag", "rows", "rows_finalize",
+                                            "direct_count", "direct_excess"};
 const char *phase_name(int phase) { return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : ""; }
 
 gakco_status prof_begin(gakco_ctx *ctx, hipStream_t st, size_t *slot)
@@ -702,6 +889,14 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     GK_PHASE(PH_FILL, launch_fill_u32(reinterpret_cast<uint32_t *>(p.base + p.o_flags), p.nflags, 0u, st));
     GK_PHASE(PH_VALIDATE, launch_validate(jobs, P(p.d_pv), nj, p.nb_v, st));
     GK_PHASE(PH_EXTRACT, launch_extract(jobs, P(p.d_px), nj, p.nb_x, st));
+    if (p.n_dwork) {
+        const DirectLevel *dlev = reinterpret_cast<const DirectLevel *>(d + p.d_dlev);
+        const ExcessList ex{reinterpret_cast<uint4 *>(p.base + p.o_excess),
+                            reinterpret_cast<uint32_t *>(p.base + p.o_flags) + p.f_excess, p.excess_cap};
+        GK_PHASE(PH_DIRECT, launch_direct_count(jobs, dlev, reinterpret_cast<const DirectWork *>(d + p.d_dwork),
+                                                P(p.d_pdir), p.n_dwork, p.uni_dir, p.nb_dir, p.maxKp, ex, st));
+        GK_PHASE(PH_DIRECT_EXCESS, launch_direct_excess(jobs, dlev, ex, st));
+    }
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on
     // Independent kernels overlap on the side stream: the block sort beside
     // the wave sort (different buckets), and, after the last chunk's sorts,
@@ -752,9 +947,9 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
             GK_HIP(launch_sort_wave(cm, L, c.sgrid, st));
             GK_HIP(launch_sort_global(cm, L, c.sgrid, st));
             GK_TRY(join(0));
-            if (last && p.n_dense) {
+            if (last && p.n_dense + p.n_dlev) {
                 GK_TRY(fork(1));
-                GK_HIP(launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, ctx->side));
+                GK_HIP(launch_dense_syrk(dw, P(p.d_pdense), p.n_dense + p.n_dlev, p.nb_dense, ctx->side));
                 GK_HIP(launch_dense_clear(dw, p.n_dense, ctx->side));
                 dense_done = true;
             }
@@ -771,8 +966,8 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
             GK_PHASE(PH_ACCUM, launch_accumulate(jobs, masks, reinterpret_cast<const AccWork *>(d + c.d_acc), P(c.d_pacc),
                                                  c.nacc, c.nb_acc, c.acc_lds, acc_upd, st));
     }
-    if (p.n_dense && !dense_done) {
-        GK_PHASE(PH_DENSE_SYRK, launch_dense_syrk(dw, P(p.d_pdense), p.n_dense, p.nb_dense, st));
+    if (p.n_dense + p.n_dlev && !dense_done) {
+        GK_PHASE(PH_DENSE_SYRK, launch_dense_syrk(dw, P(p.d_pdense), p.n_dense + p.n_dlev, p.nb_dense, st));
         GK_PHASE(PH_DENSE_CLEAR, launch_dense_clear(dw, p.n_dense, st));
     }
     if (p.n_dense) ctx->dense_dirty = false;
@@ -791,10 +986,19 @@ gakco_status plan_check_errors(gakco_ctx *ctx, Plan &p, hipStream_t st)
     GK_HIP(hipStreamSynchronize(st));
     GK_TRY(prof_collect(ctx));
     ctx->last_dense_rows = 0;
-    for (size_t i = p.jobs.size(); i < flags.size(); ++i) ctx->last_dense_rows += (uint32_t)flags[i];
+    for (size_t i = p.jobs.size(); i < p.f_excess; ++i) ctx->last_dense_rows += (uint32_t)flags[i];
+    ctx->last_excess = (uint32_t)flags[p.f_excess];
+    ctx->last_direct_levels = p.n_dlev;
     gakco_status first = GAKCO_OK;
     for (size_t j = 0; j < p.jobs.size(); ++j) {
-        if (flags[j] & 1) {
+        if (flags[j] & 2) {
+            p.excess_overflow = true;
+            p.jobs[j].status = GAKCO_EUNSUPPORTED;
+            if (first == GAKCO_OK) {
+                set_error("job %zu: more than %u counts above 127 in directly addressed position sets", j, p.excess_cap);
+                first = GAKCO_EUNSUPPORTED;
+            }
+        } else if (flags[j] & 1) {
             p.jobs[j].status = GAKCO_ERANGE;
             if (first == GAKCO_OK) {
                 set_error("job %zu: a symbol code lies outside [0, sigma=%d)", j, p.jobs[j].sigma);

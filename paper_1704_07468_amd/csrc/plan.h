@@ -16,7 +16,7 @@
 // Each phase is one kernel launch (or none) per chunk of a call.
 enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_SORT_WAVE, PH_SORT_BLOCK,
                PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
-               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_COUNT };
+               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_DIRECT, PH_DIRECT_EXCESS, PH_COUNT };
 
 // profiling counter slots: six sort kinds, then the row accumulation's pair
 // updates spread over kProfUpdSlots slots (one per block residue) so that the
@@ -24,6 +24,8 @@ enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTE
 constexpr int kProfUpdFirst = 8, kProfUpdSlots = 256;
 constexpr int kProfRowsFirst = kProfUpdFirst + kProfUpdSlots;  // then the serving rows' pair updates
 constexpr int kProfStatSlots = kProfRowsFirst + kProfUpdSlots;
+// entries of the clipped-count list of one call (a pairwise scan corrects them)
+constexpr uint32_t kExcessCap = 262144;
 
 struct gakco_ctx {
     int device = 0;
@@ -32,6 +34,8 @@ struct gakco_ctx {
     int bucket_avg = 512;    // target g-mers per hash bucket
     int acc_slab = 0;        // columns per row-accumulation block (0: as many as the LDS holds)
     int acc_mstep = 0;       // cap on position sets per flush of the row accumulation (0: the count bound only)
+    int direct_mode = 1;     // direct-address levels: 0 off, 1 where the cost model prefers them, 2 wherever possible
+    uint32_t excess_cap = 0; // cap on the clipped-count list (0: kExcessCap), for tests
     size_t pool_cap = 16ull << 30;  // per-chunk partition/sort buffers
     void *arena = nullptr;
     size_t arena_cap = 0;
@@ -59,6 +63,9 @@ struct gakco_ctx {
     // statistics of the last call
     int64_t last_dense_rows = 0;
     int64_t last_chunks = 0;
+    int64_t last_excess = 0;  // counts above 127 in directly addressed position sets
+    int64_t last_direct_levels = 0;  // levels grouped by direct addressing
+    int64_t direct_fallbacks = 0;    // calls redone without direct addressing (list overflow)
     // fixed scratch (the allocation-free entry point): arena and count
     // matrices share one caller-given region of arena_cap bytes, nothing is
     // allocated or freed, and the caller's outputs do not count against the
@@ -125,6 +132,13 @@ struct JobPlan {
     std::vector<int64_t> seq_off;
     std::vector<MaskDesc> masks;
     std::vector<int> level_B;  // bucket bits per level
+    // direct-address levels (no sort): their position sets, and per level the
+    // count-matrix geometry (0 where the level is sorted)
+    std::vector<MaskDesc> dmasks;
+    std::vector<char> direct;
+    std::vector<uint32_t> dKp, dR, dstride;
+    std::vector<int> dSd;           // row splits of its int8 products
+    std::vector<size_t> o_Dd, o_Pd; // arena offsets: count matrix, partial tiles
     // layout offsets (arena)
     size_t o_seqoff = 0, o_gstart = 0, o_key = 0, o_sid = 0, o_C = 0, o_Kd = 0, o_coef = 0, o_hco = 0, o_dref = 0;
     std::vector<uint32_t> dcap;  // per level dense row capacity (0 = level has no dense path)
@@ -181,6 +195,15 @@ struct Plan {
     size_t d_pv = 0, d_px = 0, d_pd = 0, d_pf = 0;
     uint32_t nb_v = 0, nb_x = 0, nb_d = 0, nb_f = 0, nb_dense = 0, nb_dtile = 0;
     int n_dense = 0, maxM = 0;
+    // direct-address levels of all jobs: level table, one work per position
+    // set (blocks: Ntile per work), the row counts their int8 products read,
+    // the excess list and its counter (the last flag word)
+    int n_dlev = 0, n_dwork = 0;
+    size_t d_dlev = 0, d_dwork = 0, d_pdir = 0, d_drows = 0;
+    uint32_t nb_dir = 0, uni_dir = 0, maxKp = 0;
+    size_t o_excess = 0, f_excess = 0;
+    uint32_t excess_cap = 0;
+    bool excess_overflow = false;  // set by plan_check_errors: redo without direct addressing
     size_t dense_bytes = 0, output_bytes = 0;
     std::vector<MaskWork> mw;
     char *base = nullptr;  // arena base
@@ -199,6 +222,7 @@ gakco_status plan_upload(Plan &p, hipStream_t st);
 gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st);
 gakco_status fetch_lens(JobPlan &jp, hipStream_t st);
 gakco_status plan_check_errors(gakco_ctx *ctx, Plan &p, hipStream_t st);
+gakco_status run_single(gakco_ctx *ctx, Plan &p, hipStream_t st);
 
 // Event profiler: prof_begin/prof_end bracket one phase on a stream (no-ops
 // unless the context's profiler is on); prof_collect adds the elapsed times

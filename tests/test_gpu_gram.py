@@ -26,6 +26,15 @@ def gk():
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def gk_sorted():
+    """Every level through the partition sort (direct addressing off)."""
+    from paper_1704_07468_amd import gakco
+    ctx = gakco.Context(0, tune={"direct": 0})
+    yield ctx
+    ctx.close()
+
+
 def oracle():
     from oracle import oracle as orc
     return orc
@@ -109,7 +118,10 @@ def test_gram_fig2_example(gk):
 
 @pytest.mark.parametrize("case", ["k_eq_g", "k_zero", "single_seq", "short_seqs", "sigma1", "gb64",
                                   "many_buckets", "heavy_keys", "global_packed", "global_wide", "many_short"])
-def test_gram_edge_cases(gk, case):
+@pytest.mark.parametrize("path", ["auto", "sorted"])
+def test_gram_edge_cases(gk, gk_sorted, case, path):
+    if path == "sorted":
+        gk = gk_sorted
     rng = np.random.default_rng(99)
     if case == "k_eq_g":
         d = wl.protein(N=50, lmin=5, lmax=80, g=5, k=5)
@@ -150,7 +162,7 @@ def test_gram_sort_classes_reached():
     64-bit composites."""
     from paper_1704_07468_amd import gakco
     rng = np.random.default_rng(99)
-    ctx = gakco.Context(0)
+    ctx = gakco.Context(0, tune={"direct": 0})
     try:
         ctx.set_param("profile", 1)
         seen = {}
