@@ -107,6 +107,7 @@ struct JobDev {
 // on the matrix cores.  Counts above 127 are stored as 127; the excess is
 // recorded and corrected exactly afterwards.
 constexpr uint32_t kDirectMaxKeys = 16384;
+constexpr int kDirectMasksPerBlock = 1;  // position sets of one level per block of the row writer (more measured slower)
 
 struct DirectLevel {
     int8_t *D;         // [Ntile][stride] sequence-major counts; rows [0, R) used

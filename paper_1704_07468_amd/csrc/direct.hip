@@ -25,66 +25,71 @@ __device__ __forceinline__ uint32_t direct_row(uint64_t rk, const DirectLevel &L
     return v;
 }
 
-// One block per (position set, sequence X < Ntile): LDS histogram of X's
-// reduced g-mers, then the Kp bytes of X's row segment written as 16-byte
-// stores (counts clipped at 127, the excess appended to the list).  Blocks
-// of padding sequences (X >= N) write zeros; the level's last position set
-// also zeroes the row tail [R, stride); its first position set clears X's
-// upper row of C_m, to which only the excess corrections add.
+// One block per (chunk of position sets of one level, sequence X < Ntile):
+// for each position set of the chunk, an LDS histogram of X's reduced
+// g-mers, then the Kp bytes of X's row segment written as 16-byte stores
+// (counts clipped at 127, the excess appended to the list).
+// Blocks of padding sequences (X >= N) write zeros; the level's last
+// position set also zeroes the row tail [R, stride); its first position set
+// clears X's upper row of C_m, to which only the excess corrections add.
 __global__ __launch_bounds__(kThreads) void k_direct_count(const JobDev *__restrict__ jobs,
                                                            const DirectLevel *__restrict__ dlev,
                                                            const DirectWork *__restrict__ dwork,
-                                                           const uint32_t *__restrict__ bprefix, int nwork,
+                                                           const uint2 *__restrict__ chunks,
+                                                           const uint32_t *__restrict__ bprefix, int nchunk,
                                                            uint32_t uniform, ExcessList ex)
 {
     extern __shared__ uint32_t hist[];
-    int wi;
+    int ci;
     uint32_t X;
-    map_block(bprefix, nwork, uniform, blockIdx.x, wi, X);
-    const DirectWork &W = dwork[wi];
-    const DirectLevel &L = dlev[W.dl];
+    map_block(bprefix, nchunk, uniform, blockIdx.x, ci, X);
+    const uint2 ch = chunks[ci];
+    const DirectLevel &L = dlev[dwork[ch.x].dl];
     const JobDev &J = jobs[L.job];
     const uint32_t N = (uint32_t)J.N, Kp = L.Kp;
     const int tid = threadIdx.x;
-    if (W.first && X < N) {
-        const gptr<int64_t> crow = glb(J.C) + ((size_t)L.level * N + X) * (size_t)N;
-        for (uint32_t Y = X + tid; Y < N; Y += kThreads) crow[Y] = 0;
-    }
-    for (uint32_t i = tid; i < Kp; i += kThreads) hist[i] = 0;
-    __syncthreads();
-    if (X < N) {
-        const uint32_t t0 = J.gstart[X], t1 = J.gstart[X + 1];
-        const gptr<const uint64_t> key = glb((const uint64_t *)J.key);
+    const uint32_t t0 = X < N ? J.gstart[X] : 0u, t1 = X < N ? J.gstart[X + 1] : 0u;
+    const gptr<const uint64_t> key = glb((const uint64_t *)J.key);
+#pragma unroll 1
+    for (uint32_t k = 0; k < ch.y; ++k) {
+        const DirectWork &W = dwork[ch.x + k];
+        for (uint32_t i = tid; i < Kp; i += kThreads) hist[i] = 0;
+        __syncthreads();
+        if (W.first && X < N) {
+            const gptr<int64_t> crow = glb(J.C) + ((size_t)L.level * N + X) * (size_t)N;
+            for (uint32_t Y = X + tid; Y < N; Y += kThreads) crow[Y] = 0;
+        }
         for (uint32_t t = t0 + tid; t < t1; t += kThreads) {
             // rows past Kp come only from symbols outside [0, sigma), which
             // fail the call; they are dropped here
             const uint32_t r = direct_row(compact_key(key[t], W.md), L);
             if (r < Kp) atomicAdd(&hist[r], 1u);
         }
-    }
-    __syncthreads();
-    const gptr<int8_t> out = glb(L.D) + (size_t)X * L.stride + W.row0;
-    const uint32_t n = Kp + (W.last ? L.stride - L.R : 0u);
-    for (uint32_t i = (uint32_t)tid * 16u; i < n; i += kThreads * 16u) {
-        uint32_t wv[4];
+        __syncthreads();
+        const gptr<int8_t> out = glb(L.D) + (size_t)X * L.stride + W.row0;
+        const uint32_t n = Kp + (W.last ? L.stride - L.R : 0u);
+        for (uint32_t i = (uint32_t)tid * 16u; i < n; i += kThreads * 16u) {
+            uint32_t wv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t v = 0;
+            for (int q = 0; q < 4; ++q) {
+                uint32_t v = 0;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t r = i + (uint32_t)(q * 4 + b);
-                uint32_t c = r < Kp ? hist[r] : 0u;
-                if (c > 127u) {
-                    const uint32_t e = g_atomic_add(glb(ex.count), 1u);
-                    if (e < ex.cap) st_u4(glb(ex.ent), e, W.row0 + r, X, c - 127u, (uint32_t)W.dl);
-                    else atomicOr(J.err, 2);
-                    c = 127u;
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t r = i + (uint32_t)(q * 4 + b);
+                    uint32_t c = r < Kp ? hist[r] : 0u;
+                    if (c > 127u) {
+                        const uint32_t e = g_atomic_add(glb(ex.count), 1u);
+                        if (e < ex.cap) st_u4(glb(ex.ent), e, W.row0 + r, X, c - 127u, (uint32_t)W.dl);
+                        else atomicOr(J.err, 2);
+                        c = 127u;
+                    }
+                    v |= c << (8 * b);
                 }
-                v |= c << (8 * b);
+                wv[q] = v;
             }
-            wv[q] = v;
+            *(gptr<u32x4>)(out + i) = u32x4{wv[0], wv[1], wv[2], wv[3]};
         }
-        *(gptr<u32x4>)(out + i) = u32x4{wv[0], wv[1], wv[2], wv[3]};
+        __syncthreads();
     }
 }
 
@@ -125,13 +130,13 @@ __global__ __launch_bounds__(kThreads) void k_direct_excess(const JobDev *__rest
     }
 }
 
-hipError_t launch_direct_count(const JobDev *jobs, const DirectLevel *dlev, const DirectWork *dwork,
-                               const uint32_t *bprefix, int nwork, uint32_t uniform, uint32_t nblocks, uint32_t maxKp,
+hipError_t launch_direct_count(const JobDev *jobs, const DirectLevel *dlev, const DirectWork *dwork, const uint2 *chunks,
+                               const uint32_t *bprefix, int nchunk, uint32_t uniform, uint32_t nblocks, uint32_t maxKp,
                                ExcessList ex, hipStream_t st)
 {
     if (!nblocks) return hipSuccess;
-    hipLaunchKernelGGL(k_direct_count, dim3(nblocks), dim3(kThreads), (size_t)maxKp * 4, st, jobs, dlev, dwork, bprefix,
-                       nwork, uniform, ex);
+    hipLaunchKernelGGL(k_direct_count, dim3(nblocks), dim3(kThreads), (size_t)maxKp * 4, st, jobs, dlev, dwork, chunks,
+                       bprefix, nchunk, uniform, ex);
     return hipGetLastError();
 }
 

@@ -59,8 +59,8 @@ hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const
 hipError_t launch_mirror_block(double *out, int64_t ld, int rows, int c0, int cols, hipStream_t st);
 size_t rows_partial_count(int nq, int nsv);
 hipError_t init_rows_attributes(size_t lds);
-hipError_t launch_direct_count(const JobDev *jobs, const DirectLevel *dlev, const DirectWork *dwork,
-                               const uint32_t *bprefix, int nwork, uint32_t uniform, uint32_t nblocks, uint32_t maxKp,
+hipError_t launch_direct_count(const JobDev *jobs, const DirectLevel *dlev, const DirectWork *dwork, const uint2 *chunks,
+                               const uint32_t *bprefix, int nchunk, uint32_t uniform, uint32_t nblocks, uint32_t maxKp,
                                ExcessList ex, hipStream_t st);
 hipError_t launch_direct_excess(const JobDev *jobs, const DirectLevel *dlev, ExcessList ex, hipStream_t st);
 hipError_t launch_finalize(const JobDev *jobs, const uint32_t *bprefix, int njobs, uint32_t nblocks, int maxM, hipStream_t st);

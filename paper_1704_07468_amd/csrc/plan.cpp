@@ -285,8 +285,8 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.maxM = 0;
     p.pool_bytes = 0;
     p.chunks.clear();
-    p.n_dlev = p.n_dwork = 0;
-    p.maxKp = 0;
+    p.n_dlev = p.n_dwork = p.n_dchunk = 0;
+    p.dclass.clear();
     p.excess_cap = 0;
     p.excess_overflow = false;
     size_t nmask = 0;
@@ -370,7 +370,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 jp.o_Dd[(size_t)m] = L.take((size_t)jp.Ntile * jp.dstride[(size_t)m]);
                 jp.o_Pd[(size_t)m] = L.take(tiles * (size_t)jp.dSd[(size_t)m] * dense_tile() * dense_tile() * 4);
                 p.n_dlev += 1;
-                p.maxKp = std::max(p.maxKp, jp.dKp[(size_t)m]);
+                p.n_dchunk += (int)((binom64(jp.g, m) + kDirectMasksPerBlock - 1) / kDirectMasksPerBlock);
             }
             p.n_dwork += (int)jp.dmasks.size();
         }
@@ -494,7 +494,8 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
     p.d_pdtile = d.take(((size_t)p.n_dense + p.n_dlev + 1) * 4, 64);
     p.d_dlev = d.take(sizeof(DirectLevel) * (size_t)std::max(1, p.n_dlev), 64);
     p.d_dwork = d.take(sizeof(DirectWork) * (size_t)std::max(1, p.n_dwork), 64);
-    p.d_pdir = d.take(((size_t)p.n_dwork + 1) * 4, 64);
+    p.d_dchunk = d.take(8 * (size_t)std::max(1, p.n_dchunk), 64);
+    p.d_pdir = d.take(((size_t)p.n_dchunk + 32) * 4, 64);
     p.d_drows = d.take((size_t)std::max(1, p.n_dlev) * 4, 64);
     p.d_pv = d.take((nj + 1) * 4, 64);
     p.d_px = d.take((nj + 1) * 4, 64);
@@ -603,7 +604,11 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     char *blob = p.desc_host.data();
     auto put = [&](size_t off, const std::vector<uint32_t> &v) { memcpy(blob + off, v.data(), v.size() * 4); };
     JobDev *jd = reinterpret_cast<JobDev *>(blob + p.d_jobs);
-    std::vector<uint32_t> pv(1, 0), px(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0), pdir(1, 0);
+    std::vector<uint32_t> pv(1, 0), px(1, 0), pd(1, 0), pf(1, 0), pdn(1, 0), pdt(1, 0);
+    struct HostChunk {
+        uint32_t w0, nw, kp, ntile;
+    };
+    std::vector<HostChunk> hchunks;
     int di = 0, dl_next = 0, dw_next = 0;
     DirectLevel *dlev = reinterpret_cast<DirectLevel *>(blob + p.d_dlev);
     DirectWork *dwork = reinterpret_cast<DirectWork *>(blob + p.d_dwork);
@@ -681,6 +686,9 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             uint32_t row0 = 0;
             for (size_t q = 0; q < jp.dmasks.size(); ++q) {
                 if (jp.dmasks[q].level != m) continue;
+                if (row0 / L.Kp % kDirectMasksPerBlock == 0)
+                    hchunks.push_back(HostChunk{(uint32_t)dw_next, 0u, L.Kp, (uint32_t)jp.Ntile});
+                hchunks.back().nw += 1;
                 DirectWork &W = dwork[dw_next++];
                 W = DirectWork{};
                 W.md = jp.dmasks[q];
@@ -689,7 +697,6 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
                 W.first = row0 == 0 ? 1 : 0;
                 row0 += L.Kp;
                 W.last = row0 == L.R ? 1 : 0;
-                pdir.push_back(pdir.back() + (uint32_t)jp.Ntile);
             }
         }
         pv.push_back(pv.back() + (uint32_t)((jp.nsym + kThreads * 16 - 1) / (kThreads * 16)));
@@ -730,9 +737,40 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             ++di;
         }
     }
-    put(p.d_pdir, pdir);
-    p.nb_dir = pdir.back();
-    p.uni_dir = uniform_of(pdir);
+    // row-writer chunks by counter-array size (powers of two, largest
+    // first), one launch each, so that a launch's LDS fits its chunks
+    {
+        auto cls = [](uint32_t kp) {
+            int c = 0;
+            while ((1u << c) < kp) ++c;
+            return c;
+        };
+        std::stable_sort(hchunks.begin(), hchunks.end(),
+                         [&](const HostChunk &a, const HostChunk &b) { return cls(a.kp) > cls(b.kp); });
+        uint2 *ch = reinterpret_cast<uint2 *>(blob + p.d_dchunk);
+        uint32_t *pre = reinterpret_cast<uint32_t *>(blob + p.d_pdir);
+        size_t pre_used = 0;
+        for (size_t i = 0; i < hchunks.size();) {
+            size_t e = i;
+            Plan::DirClass dc;
+            dc.first = (int)i;
+            dc.kp = 1u << cls(hchunks[i].kp);
+            std::vector<uint32_t> pr(1, 0);
+            while (e < hchunks.size() && cls(hchunks[e].kp) == cls(hchunks[i].kp)) {
+                ch[e] = make_uint2(hchunks[e].w0, hchunks[e].nw);
+                pr.push_back(pr.back() + hchunks[e].ntile);
+                ++e;
+            }
+            dc.nchunk = (int)(e - i);
+            dc.d_pre = p.d_pdir + pre_used * 4;
+            memcpy(pre + pre_used, pr.data(), pr.size() * 4);
+            pre_used += pr.size();
+            dc.nblocks = pr.back();
+            dc.uniform = uniform_of(pr);
+            p.dclass.push_back(dc);
+            i = e;
+        }
+    }
     // mask works, chunk by chunk (each chunk's buffers at the start of the pool)
     size_t j = 0;
     for (auto &c : p.chunks) {
@@ -893,8 +931,10 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         const DirectLevel *dlev = reinterpret_cast<const DirectLevel *>(d + p.d_dlev);
         const ExcessList ex{reinterpret_cast<uint4 *>(p.base + p.o_excess),
                             reinterpret_cast<uint32_t *>(p.base + p.o_flags) + p.f_excess, p.excess_cap};
-        GK_PHASE(PH_DIRECT, launch_direct_count(jobs, dlev, reinterpret_cast<const DirectWork *>(d + p.d_dwork),
-                                                P(p.d_pdir), p.n_dwork, p.uni_dir, p.nb_dir, p.maxKp, ex, st));
+        for (auto &dc : p.dclass)
+            GK_PHASE(PH_DIRECT, launch_direct_count(jobs, dlev, reinterpret_cast<const DirectWork *>(d + p.d_dwork),
+                                                    reinterpret_cast<const uint2 *>(d + p.d_dchunk) + dc.first,
+                                                    P(dc.d_pre), dc.nchunk, dc.uniform, dc.nblocks, dc.kp, ex, st));
         GK_PHASE(PH_DIRECT_EXCESS, launch_direct_excess(jobs, dlev, ex, st));
     }
     if (p.n_dense) ctx->dense_dirty = true;  // the bucket sort writes count rows from here on

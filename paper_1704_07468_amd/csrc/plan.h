@@ -198,9 +198,16 @@ struct Plan {
     // direct-address levels of all jobs: level table, one work per position
     // set (blocks: Ntile per work), the row counts their int8 products read,
     // the excess list and its counter (the last flag word)
-    int n_dlev = 0, n_dwork = 0;
-    size_t d_dlev = 0, d_dwork = 0, d_pdir = 0, d_drows = 0;
-    uint32_t nb_dir = 0, uni_dir = 0, maxKp = 0;
+    int n_dlev = 0, n_dwork = 0, n_dchunk = 0;
+    size_t d_dlev = 0, d_dwork = 0, d_dchunk = 0, d_pdir = 0, d_drows = 0;
+    // the row writer's launches: chunks of position sets grouped by rows per
+    // position set (LDS counters), largest first
+    struct DirClass {
+        int first = 0, nchunk = 0;
+        size_t d_pre = 0;
+        uint32_t nblocks = 0, uniform = 0, kp = 0;
+    };
+    std::vector<DirClass> dclass;
     size_t o_excess = 0, f_excess = 0;
     uint32_t excess_cap = 0;
     bool excess_overflow = false;  // set by plan_check_errors: redo without direct addressing
