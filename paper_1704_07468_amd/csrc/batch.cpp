@@ -121,6 +121,8 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
     own.acc_mstep = ctx->acc_mstep;
     own.direct_mode = ctx->direct_mode;
     own.excess_cap = ctx->excess_cap;
+    own.chunk_masks = ctx->chunk_masks;
+    own.overlap = ctx->overlap;
     own.pool_cap = ctx->pool_cap;
     own.lds_max = ctx->lds_max;
     own.class_tau = ctx->class_tau;
@@ -140,6 +142,20 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
     if (hipStreamSynchronize(st) != hipSuccess || hipStreamCreateWithFlags(&bp->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         set_error("stream setup for the batch graph failed");
         return fail(GAKCO_EHIP);
+    }
+    // the independent kernels of the plan (block beside wave sort, int8
+    // products beside the last accumulation) fork onto a second stream that
+    // joins the capture, so the graph keeps their overlap
+    if (own.overlap) {
+        bool ok = hipStreamCreateWithFlags(&own.side, hipStreamNonBlocking) == hipSuccess;
+        for (int i = 0; i < 2 && ok; ++i)
+            ok = hipEventCreateWithFlags(&own.fork_ev[i], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&own.join_ev[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            set_error("side stream setup for the batch graph failed");
+            return fail(GAKCO_EHIP);
+        }
+        own.capture_side = true;
     }
     if (hipStreamBeginCapture(bp->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         set_error("hipStreamBeginCapture failed");
@@ -207,6 +223,11 @@ void gakco_batch_plan_destroy(gakco_batch_plan *bp)
     if (bp->exec) (void)hipGraphExecDestroy(bp->exec);
     if (bp->graph) (void)hipGraphDestroy(bp->graph);
     if (bp->cap_stream) (void)hipStreamDestroy(bp->cap_stream);
+    if (bp->own.side) (void)hipStreamDestroy(bp->own.side);
+    for (int i = 0; i < 2; ++i) {
+        if (bp->own.fork_ev[i]) (void)hipEventDestroy(bp->own.fork_ev[i]);
+        if (bp->own.join_ev[i]) (void)hipEventDestroy(bp->own.join_ev[i]);
+    }
     if (bp->own.arena) (void)hipFree(bp->own.arena);
     if (bp->own.dense_buf) (void)hipFree(bp->own.dense_buf);
     for (auto e : bp->own.ev_pool) (void)hipEventDestroy(e);

@@ -433,6 +433,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                     return GAKCO_EBUDGET;
                 }
                 if (cur.nmask && pl.size + need + nbc * 4 * (1 + kSortClasses) + 4 * kSortCounters + 512 > pool_limit) close();
+                if (ctx->chunk_masks > 0 && cur.nmask >= ctx->chunk_masks) close();
                 if (!cur.nmask) cur.mfirst = gi;
                 cur.o_mask.push_back(pl.take(mb.size));
                 cur.nmask += 1;
@@ -945,7 +946,7 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
     // 0, or while the stream is being captured into a graph.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     GK_HIP(hipStreamIsCapturing(st, &cap));
-    const bool dual = ctx->side && ctx->overlap && !ctx->prof_on && cap == hipStreamCaptureStatusNone;
+    const bool dual = ctx->side && ctx->overlap && !ctx->prof_on && (cap == hipStreamCaptureStatusNone || ctx->capture_side);
     auto fork = [&](int i) -> gakco_status {
         GK_HIP(hipEventRecord(ctx->fork_ev[i], st));
         GK_HIP(hipStreamWaitEvent(ctx->side, ctx->fork_ev[i], 0));

@@ -36,6 +36,7 @@ struct gakco_ctx {
     int acc_mstep = 0;       // cap on position sets per flush of the row accumulation (0: the count bound only)
     int direct_mode = 1;     // direct-address levels: 0 off, 1 where the cost model prefers them, 2 wherever possible
     uint32_t excess_cap = 0; // cap on the clipped-count list (0: kExcessCap), for tests
+    int chunk_masks = 0;     // cap on position sets per chunk (0: as many as the pool holds)
     size_t pool_cap = 16ull << 30;  // per-chunk partition/sort buffers
     void *arena = nullptr;
     size_t arena_cap = 0;
@@ -59,6 +60,7 @@ struct gakco_ctx {
     // runs beside the wave sort, the int8 products beside the accumulation
     hipStream_t side = nullptr;
     bool overlap = true;
+    bool capture_side = false;  // the side stream also joins a graph capture (batch plans)
     hipEvent_t fork_ev[2] = {nullptr, nullptr}, join_ev[2] = {nullptr, nullptr};
     // statistics of the last call
     int64_t last_dense_rows = 0;
