@@ -47,6 +47,9 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
     } else if (!strcmp(name, "excess_cap")) {
         if (v < 0 || v > (int64_t)kExcessCap) { set_error("excess_cap must be in 0..%u", kExcessCap); return GAKCO_EINVAL; }
         ctx->excess_cap = (uint32_t)v;
+    } else if (!strcmp(name, "info4")) {
+        if (v < 0 || v > 1) { set_error("info4 must be 0 or 1"); return GAKCO_EINVAL; }
+        ctx->info4 = (int)v;
     } else if (!strcmp(name, "chunk_masks")) {
         if (v < 0 || v > (1 << 20)) { set_error("chunk_masks must be in 0..1048576"); return GAKCO_EINVAL; }
         ctx->chunk_masks = (int)v;

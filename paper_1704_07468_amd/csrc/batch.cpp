@@ -122,6 +122,7 @@ gakco_status gakco_batch_plan_create(gakco_ctx *ctx, const gakco_job *jobs_host,
     own.direct_mode = ctx->direct_mode;
     own.excess_cap = ctx->excess_cap;
     own.chunk_masks = ctx->chunk_masks;
+    own.info4 = ctx->info4;
     own.overlap = ctx->overlap;
     own.pool_cap = ctx->pool_cap;
     own.lds_max = ctx->lds_max;
@@ -198,6 +199,7 @@ gakco_status gakco_batch_run(gakco_batch_plan *bp, void *hip_stream)
         tmp.lds_max = bp->own.lds_max;
         tmp.class_tau = bp->own.class_tau;
         tmp.direct_mode = 0;
+        tmp.info4 = bp->own.info4;
         bp->own.direct_fallbacks += 1;
         Plan q;
         q.jobs = bp->p.jobs;

@@ -582,7 +582,8 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     const gptr<uint4> gtab = glb(W.gtab);
     const gptr<uint32_t> bgrp = glb(W.bgrp);
     const uint32_t T = W.T, Nseq = (uint32_t)W.N, dcap = W.dcap, dstride = W.dstride;
-    const int tau = W.tau, inl = W.inl;
+    const int tau = W.tau, inl = W.inl, i4 = W.i4;
+    const gptr<uint32_t> info4 = (gptr<uint32_t>)info, lenx = info4 + T;
     const uint64_t sidmask = bits_mask(sb);
     const int nwords = (int)((n + 63) >> 6);
     auto comp_at = [&](uint32_t i) -> uint64_t { return PK ? (kb[i] >> 32) : kb[i]; };
@@ -672,7 +673,10 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
         if (i < n) {
             const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
             if (!((u.rb >> lane) & 1ull)) {
-                if (idx < T) st_u2(info, idx, 0u, 0u);
+                if (idx < T) {
+                    if (i4) info4[idx] = 0u;
+                    else st_u2(info, idx, 0u, 0u);
+                }
             } else {
                 const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
                 const uint64_t c = comp_at(i);
@@ -692,7 +696,10 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
                     const uint32_t nx = i + a.cnt;
                     x = (uint32_t)(comp_at(nx) & sidmask) | ((a.gend - nx) << sb);
                 }
-                if (idx < T) st_u2(info, idx, x, y);
+                if (idx < T) {
+                    if (i4) info4[idx] = pack_info4(y ? a.len : 0u, a.cnt, ei, inl && a.len == 2, x, sb, lenx);
+                    else st_u2(info, idx, x, y);
+                }
                 dv = a.cnt * a.cnt;
                 dq = sid;
                 if (gtab && a.gs == i) {

@@ -169,6 +169,7 @@ struct MaskWork {
     int32_t tau;       // min distinct sequences of a dense group (0 = off)
     int32_t inl;       // 1: a run two entries from its group end carries the
                        // last entry in its info instead of its own index
+    int32_t i4;        // 1: 4-byte info records (pack_info4), 0: uint2 records
     int32_t kshift;    // > 0: each key carries its sequence id at this bit (the job's kshift)
     // resident tables (serving): per bucket its groups in hash-rest order
     uint4 *gtab;       // [T] (hash rest lo, hi, first entry, end entry) at bucket offset + group (nullable)
@@ -217,6 +218,31 @@ __device__ __forceinline__ uint2 ld_u2(gptr<const uint2> p, size_t i)
 __device__ __forceinline__ void st_u4(gptr<uint4> p, size_t i, uint32_t a, uint32_t b, uint32_t c, uint32_t d)
 {
     ((gptr<u32x4>)p)[i] = u32x4{a, b, c, d};
+}
+
+// Compact per-g-mer record of a run leader for the row accumulation (Gram
+// calls with at most 2^21 g-mers and sequence ids of at most 12 bits), 4
+// bytes instead of a uint2: bits 0-6 the entries from the run's own to its
+// group end (127: the length is in the side array at the run's entry index),
+// bit 7 set when the group's last run is carried inline, bits 8-10 the run's
+// count (0: 8 or more, read from the run's entry), bits 11-31 the payload:
+// the run's count for a group of one run, the last run's entry (sequence |
+// count << sb) when inline, else the run's entry index.  0: no record (not
+// a run leader, or a group summed on the matrix cores).
+constexpr uint32_t kInfo4MaxT = 1u << 21;
+__device__ __forceinline__ uint32_t pack_info4(uint32_t len, uint32_t cnt, uint32_t ei, bool inl, uint32_t last_entry,
+                                               int sb, __attribute__((address_space(1))) uint32_t *lenx)
+{
+    if (len == 0) return 0u;
+    if (len == 1) return 1u | (cnt << 11);
+    if (inl && len == 2 && cnt <= 7u && (last_entry >> sb) < (1u << (21 - sb)))
+        return 2u | (1u << 7) | (cnt << 8) | (last_entry << 11);
+    uint32_t lf = len;
+    if (len >= 127u) {
+        lf = 127u;
+        lenx[ei] = len;
+    }
+    return lf | ((cnt <= 7u ? cnt : 0u) << 8) | (ei << 11);
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
@@ -566,11 +592,19 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
             const uint32_t c1 = ((r + 2 < R) ? rpos[r + 2] : n) - p1;
             x = (uint32_t)(comp(p1) & sidmask) | (c1 << sb);
         }
-        // y: entries to the group end in the low sb+1 bits, the run count above
-        st_u2(info, gidx(p), x, len ? (len | (cnt << (sb + 1))) : 0u);
+        if (W.i4) {
+            ((gptr<uint32_t>)info)[gidx(p)] = pack_info4(len, cnt, e, W.inl && len == 2, x, sb,
+                                                         (gptr<uint32_t>)info + W.T);
+        } else {
+            // y: entries to the group end in the low sb+1 bits, the run count above
+            st_u2(info, gidx(p), x, len ? (len | (cnt << (sb + 1))) : 0u);
+        }
     }
     for (uint32_t i = tid; i < n; i += kThreads)
-        if (i > 0 && comp(i) == comp(i - 1)) st_u2(info, gidx(i), 0u, 0u);
+        if (i > 0 && comp(i) == comp(i - 1)) {
+            if (W.i4) ((gptr<uint32_t>)info)[gidx(i)] = 0u;
+            else st_u2(info, gidx(i), 0u, 0u);
+        }
     if (W.gtab) {
         for (uint32_t gi = tid; gi < G; gi += kThreads) {
             const uint32_t r0 = gsr[gi];

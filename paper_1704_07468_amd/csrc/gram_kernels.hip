@@ -242,10 +242,35 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             const uint32_t s = q / ng;
             const uint32_t t = t0 + (q - s * ng);
             const MaskWork &W = items[A.mfirst + ms0 + (int)s];
-            const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
-            const uint32_t tail = inf.y & lmask;  // entries from X's own to the group end
-            if (tail) {
+            // the run X has in this group: entries from its own to the group
+            // end (tail), its count, and either the group's last entry inline
+            // or its own entry index
+            uint32_t tail, xi = 0;
+            bool inl2 = false;
+            if (W.i4) {
+                const uint32_t v = glb((const uint32_t *)W.info)[t];
+                tail = v & 127u;
+                const uint32_t pay = v >> 11;
+                if (tail == 1) {
+                    cx = pay;
+                } else if (v & 128u) {
+                    cx = (v >> 8) & 7u;
+                    inl2 = true;
+                    xi = pay;
+                } else if (tail) {
+                    xi = pay;
+                    if (tail == 127u) tail = glb((const uint32_t *)W.info)[W.T + xi];
+                    cx = (v >> 8) & 7u;
+                    if (!cx) cx = glb((const uint32_t *)W.E)[xi] >> sb;
+                }
+            } else {
+                const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
+                tail = inf.y & lmask;
                 cx = inf.y >> (sb + 1);
+                xi = inf.x;
+                inl2 = tail == 2;
+            }
+            if (tail) {
                 // LDS index of column Y: level offset + Y - y0 (mod 2^32)
                 off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad - (uint32_t)y0;
                 if (own_col) {
@@ -253,15 +278,15 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
                     else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
                     ++nupd;
                 }
-                if (tail == 2) {
-                    const uint32_t ys = inf.x & sidmask;
+                if (inl2) {
+                    const uint32_t ys = xi & sidmask;
                     if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) {
-                        atomicAdd(&acc[off + ys], cx * (inf.x >> sb));
+                        atomicAdd(&acc[off + ys], cx * (xi >> sb));
                         ++nupd;
                     }
-                } else if (tail > 2) {
+                } else if (tail >= 2) {
                     // entries [e0, e1): sequences above X in ascending order
-                    uint32_t e0 = inf.x + 1, e1 = inf.x + tail;
+                    uint32_t e0 = xi + 1, e1 = xi + tail;
                     if (!whole) {
                         if (y0 > X + 1) e0 = first_seq_at_least(W.E, e0, e1, (uint32_t)y0, sidmask);
                         if (y1 < N) e1 = first_seq_at_least(W.E, e0, e1, (uint32_t)y1, sidmask);

@@ -820,6 +820,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             }
             if (!jp.ext_diag.empty()) W.diag = jp.ext_diag[(size_t)m];
             W.inl = jp.want_kernel ? 1 : 0;
+            W.i4 = (jp.want_kernel && ctx->info4 && jp.T <= kInfo4MaxT && jp.sb <= 12) ? 1 : 0;
             if (jp.want_kernel && jp.dcap[(size_t)m]) {
                 W.D = ctx->dense_buf + jp.o_dense[(size_t)m];
                 W.dcount = flags + p.jobs.size() + jp.lev_base + m;

@@ -37,6 +37,7 @@ struct gakco_ctx {
     int direct_mode = 1;     // direct-address levels: 0 off, 1 where the cost model prefers them, 2 wherever possible
     uint32_t excess_cap = 0; // cap on the clipped-count list (0: kExcessCap), for tests
     int chunk_masks = 0;     // cap on position sets per chunk (0: as many as the pool holds)
+    int info4 = 1;           // 4-byte per-g-mer run records where they fit (0: uint2 records)
     size_t pool_cap = 16ull << 30;  // per-chunk partition/sort buffers
     void *arena = nullptr;
     size_t arena_cap = 0;

@@ -261,7 +261,8 @@ def test_gram_tuning_invariance(gk):
     d = wl.protein(N=200, lmin=50, lmax=300)
     base = gk.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
     for tune in ({"bucket_avg": 64}, {"bucket_avg": 2000}, {"overlap": 0}, {"overlap": 1, "pool_mb": 16},
-                 {"acc_slab": 128}, {"chunk_masks": 1}, {"chunk_masks": 5, "overlap": 0}):
+                 {"acc_slab": 128}, {"chunk_masks": 1}, {"chunk_masks": 5, "overlap": 0}, {"info4": 0},
+                 {"info4": 0, "acc_slab": 64}):
         print("tune:", tune, flush=True)
         c2 = gakco.Context(0, tune=tune)
         for _ in range(2):
