@@ -32,12 +32,12 @@ __device__ __forceinline__ int bucket_class(uint32_t n, bool pk)
     if (n == 0) return -1;
     if (n <= (pk ? kSortWaveMaxPk : kSortWaveMaxWide)) {
         const int e = max(0, ceil_log2_u(n) - 6);  // log2 of elements per lane
-        return pk ? e : 4 + e;                      // packed 0..3, wide 4..6
+        return pk ? e : 5 + e;                      // packed 0..4, wide 5..8
     }
     if (n <= (pk ? kSortBlockMaxPk : kSortBlockMaxWide)) {
-        // log2 of waves per bucket (1024 packed / 512 wide elements a wave)
-        const int e = ceil_log2_u(n) - (pk ? 10 : 9);  // 0..4
-        return kSortClassWave + (pk ? e : 5 + e);
+        // log2 of waves per bucket (1024 packed / 512 wide elements a wave), 2..16
+        const int e = ceil_log2_u(n) - (pk ? 11 : 10);  // 0..3
+        return kSortClassWave + (pk ? e : 4 + e);
     }
     return kSortClassWave + kSortClassBlock + (pk ? 0 : 1);
 }
@@ -754,23 +754,28 @@ __device__ __forceinline__ void store_sorted(const uint64_t (&key)[EL], const ui
 }
 
 // ------------------------------------------------------ wave kernel --
-constexpr int kWaveWords = kSortWaveMaxPk / 64;
+// Two instances: the small one takes packed buckets of up to 512 g-mers and
+// wide ones of up to 256, the big one packed 1024 and wide 512 (8 KB of
+// elements per wave, fewer waves per CU).
 constexpr int kWaveSlots = 128;
 
+template <bool BIG>
 struct WaveLds {
-    uint64_t kb[kSortWaveMaxPk];  // packed: 512 words; wide: 256 words, then 256 indices
-    SegLds<kWaveWords, kWaveSlots> S;
+    static constexpr int KB = BIG ? 1024 : 512;      // packed elements
+    static constexpr int WIDE = BIG ? 512 : 256;     // wide elements (then their indices)
+    uint64_t kb[KB];
+    SegLds<KB / 64, kWaveSlots> S;
 };
 
-template <bool PK, int EL>
-__device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, WaveLds &lds, uint32_t *dl,
+template <bool BIG, bool PK, int EL>
+__device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, WaveLds<BIG> &lds, uint32_t *dl,
                                             const uint32_t *diag0)
 {
     const gptr<const uint32_t> boff = glb((const uint32_t *)W.boff);
     const uint32_t base = boff[bucket];
     const uint32_t n = boff[bucket + 1] - base;
     if (n == 0 || n > 64u * EL) return;
-    uint32_t *vb = reinterpret_cast<uint32_t *>(lds.kb + kSortWaveMaxWide);
+    uint32_t *vb = reinterpret_cast<uint32_t *>(lds.kb + WaveLds<BIG>::WIDE);
     {
         uint64_t key[EL];
         uint32_t val[EL];
@@ -779,12 +784,10 @@ __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, 
         store_sorted<PK, EL>(key, val, 0, n, lds.kb, vb);
     }
     wave_sync();
-    segment<PK, 1, kWaveWords, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S, 0, dl, diag0);
+    segment<PK, 1, WaveLds<BIG>::KB / 64, kWaveSlots>(W, bucket, base, n, lds.kb, vb, lds.S, 0, dl, diag0);
     wave_sync();
 }
 
-// Each wave takes the buckets of the wave classes in a fixed stride over
-// their concatenation, largest class first.
 // Zero / flush the block's LDS diagonal sums (L.ndiag words of dynamic LDS).
 template <int NT>
 __device__ __forceinline__ uint32_t *diag_lds_begin(const SortLists &L, uint32_t *dyn)
@@ -803,43 +806,53 @@ __device__ __forceinline__ void diag_lds_end(const SortLists &L, const uint32_t 
         if (dl[i]) g_atomic_add(glb(L.diag0) + i, dl[i]);
 }
 
+// Each wave takes the buckets of its instance's classes in a fixed stride
+// over their concatenation, largest class first.
+template <bool BIG>
 __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restrict__ items, SortLists L)
 {
-    __shared__ WaveLds lds[kWaves];
+    __shared__ WaveLds<BIG> lds[kWaves];
     extern __shared__ uint32_t dyn_lds[];
     uint32_t *dl = diag_lds_begin<kThreads>(L, dyn_lds);
-    // packed 512, wide 256, packed 256, wide 128, ..., packed 64 (class ids)
-    constexpr int order[kSortClassWave] = {3, 6, 2, 5, 1, 4, 0};
+    // class ids: packed 64..1024 are 0..4, wide 64..512 are 5..8
+    constexpr int NC = BIG ? 2 : 7;
+    constexpr int order_small[7] = {3, 7, 2, 6, 1, 5, 0};  // packed 512, wide 256, packed 256, ...
+    constexpr int order_big[2] = {4, 8};                   // packed 1024, wide 512
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // wave-uniform
     const uint32_t gw = blockIdx.x * kWaves + wid, nw = gridDim.x * kWaves;
-    uint32_t cum[kSortClassWave + 1];
+    uint32_t cum[NC + 1];
     cum[0] = 0;
     const gptr<const uint32_t> lcnt = glb((const uint32_t *)L.cnt), list = glb((const uint32_t *)L.list);
 #pragma unroll
-    for (int s = 0; s < kSortClassWave; ++s) cum[s + 1] = cum[s] + min(lcnt[order[s]], L.cap);
-    for (uint32_t t = gw; t < cum[kSortClassWave]; t += nw) {
+    for (int s = 0; s < NC; ++s) cum[s + 1] = cum[s] + min(lcnt[BIG ? order_big[s] : order_small[s]], L.cap);
+    for (uint32_t t = gw; t < cum[NC]; t += nw) {
         int s = 0;
 #pragma unroll
-        for (int q = 1; q < kSortClassWave; ++q) s += (t >= cum[q]) ? 1 : 0;
+        for (int q = 1; q < NC; ++q) s += (t >= cum[q]) ? 1 : 0;
         uint32_t off = 0;
         int c = 0;
 #pragma unroll
-        for (int q = 0; q < kSortClassWave; ++q) {
+        for (int q = 0; q < NC; ++q) {
             off = (q == s) ? cum[q] : off;
-            c = (q == s) ? order[q] : c;
+            c = (q == s) ? (BIG ? order_big[q] : order_small[q]) : c;
         }
         const uint32_t ent = list[(size_t)c * L.cap + (t - off)];
         const MaskWork &W = items[ent >> 12];
         const uint32_t bucket = ent & 4095u;
         if (bucket >= (1u << W.B)) continue;
-        switch (c) {
-        case 0: wave_bucket<true, 1>(W, bucket, lds[wid], dl, L.diag0); break;
-        case 1: wave_bucket<true, 2>(W, bucket, lds[wid], dl, L.diag0); break;
-        case 2: wave_bucket<true, 4>(W, bucket, lds[wid], dl, L.diag0); break;
-        case 3: wave_bucket<true, 8>(W, bucket, lds[wid], dl, L.diag0); break;
-        case 4: wave_bucket<false, 1>(W, bucket, lds[wid], dl, L.diag0); break;
-        case 5: wave_bucket<false, 2>(W, bucket, lds[wid], dl, L.diag0); break;
-        default: wave_bucket<false, 4>(W, bucket, lds[wid], dl, L.diag0); break;
+        if constexpr (BIG) {
+            if (c == 4) wave_bucket<true, true, 16>(W, bucket, lds[wid], dl, L.diag0);
+            else wave_bucket<true, false, 8>(W, bucket, lds[wid], dl, L.diag0);
+        } else {
+            switch (c) {
+            case 0: wave_bucket<false, true, 1>(W, bucket, lds[wid], dl, L.diag0); break;
+            case 1: wave_bucket<false, true, 2>(W, bucket, lds[wid], dl, L.diag0); break;
+            case 2: wave_bucket<false, true, 4>(W, bucket, lds[wid], dl, L.diag0); break;
+            case 3: wave_bucket<false, true, 8>(W, bucket, lds[wid], dl, L.diag0); break;
+            case 5: wave_bucket<false, false, 1>(W, bucket, lds[wid], dl, L.diag0); break;
+            case 6: wave_bucket<false, false, 2>(W, bucket, lds[wid], dl, L.diag0); break;
+            default: wave_bucket<false, false, 4>(W, bucket, lds[wid], dl, L.diag0); break;
+            }
         }
     }
     diag_lds_end<kThreads>(L, dl);
@@ -859,8 +872,8 @@ constexpr size_t seg_bytes() { return sizeof(SegLds<NWORDS, NSLOT>); }
 
 struct BlockLds {
     uint64_t buf[kSortBlockMaxPk];  // exchange buffers, then the sorted buckets
-    // per-group segmentation scratch (largest: 16 groups of 16 words)
-    uint64_t seg[(16 * seg_bytes<16, kBlockSlots / 16>() + 7) / 8];
+    // per-group segmentation scratch (largest: 8 groups of 32 words)
+    uint64_t seg[(8 * seg_bytes<32, kBlockSlots / 8>() + 7) / 8];
 };
 
 template <bool PK, int NW>
@@ -912,10 +925,10 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
     extern __shared__ uint32_t dyn_lds[];
     uint32_t *dl = diag_lds_begin<kSortBlockThreads>(L, dyn_lds);
     // class offsets within the block classes, largest first: packed 16384,
-    // wide 8192, packed 8192, wide 4096, ..., packed 1024, wide 512; buckets
+    // wide 8192, packed 8192, wide 4096, ..., packed 2048, wide 1024; buckets
     // per block = 16 / waves per bucket
-    constexpr int order[kSortClassBlock] = {4, 9, 3, 8, 2, 7, 1, 6, 0, 5};
-    constexpr int gsz[kSortClassBlock] = {1, 1, 2, 2, 4, 4, 8, 8, 16, 16};
+    constexpr int order[kSortClassBlock] = {3, 7, 2, 6, 1, 5, 0, 4};
+    constexpr int gsz[kSortClassBlock] = {1, 1, 2, 2, 4, 4, 8, 8};
     uint32_t cum[kSortClassBlock + 1];
     cum[0] = 0;
     const gptr<uint32_t> lcnt = glb(L.cnt);
@@ -946,15 +959,13 @@ __global__ __launch_bounds__(kSortBlockThreads) void k_sort_block(const MaskWork
         const int nb = (int)min((uint32_t)gs, cnt - first);
         const gptr<const uint32_t> ents = glb((const uint32_t *)L.list) + (size_t)c * L.cap + first;
         switch (oc) {
-        case 0: block_buckets<true, 1>(items, ents, nb, lds, dl, L.diag0); break;    // packed 1024
-        case 1: block_buckets<true, 2>(items, ents, nb, lds, dl, L.diag0); break;    // packed 2048
-        case 2: block_buckets<true, 4>(items, ents, nb, lds, dl, L.diag0); break;    // packed 4096
-        case 3: block_buckets<true, 8>(items, ents, nb, lds, dl, L.diag0); break;    // packed 8192
-        case 4: block_buckets<true, 16>(items, ents, nb, lds, dl, L.diag0); break;   // packed 16384
-        case 5: block_buckets<false, 1>(items, ents, nb, lds, dl, L.diag0); break;   // wide 512
-        case 6: block_buckets<false, 2>(items, ents, nb, lds, dl, L.diag0); break;   // wide 1024
-        case 7: block_buckets<false, 4>(items, ents, nb, lds, dl, L.diag0); break;   // wide 2048
-        case 8: block_buckets<false, 8>(items, ents, nb, lds, dl, L.diag0); break;   // wide 4096
+        case 0: block_buckets<true, 2>(items, ents, nb, lds, dl, L.diag0); break;    // packed 2048
+        case 1: block_buckets<true, 4>(items, ents, nb, lds, dl, L.diag0); break;    // packed 4096
+        case 2: block_buckets<true, 8>(items, ents, nb, lds, dl, L.diag0); break;    // packed 8192
+        case 3: block_buckets<true, 16>(items, ents, nb, lds, dl, L.diag0); break;   // packed 16384
+        case 4: block_buckets<false, 2>(items, ents, nb, lds, dl, L.diag0); break;   // wide 1024
+        case 5: block_buckets<false, 4>(items, ents, nb, lds, dl, L.diag0); break;   // wide 2048
+        case 6: block_buckets<false, 8>(items, ents, nb, lds, dl, L.diag0); break;   // wide 4096
         default: block_buckets<false, 16>(items, ents, nb, lds, dl, L.diag0); break; // wide 8192
         }
         __syncthreads();
@@ -1006,7 +1017,15 @@ hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hi
 
 hipError_t launch_sort_wave(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
 {
-    if (g.wave_blocks) hipLaunchKernelGGL(k_sort_wave, dim3(g.wave_blocks), dim3(kThreads), (size_t)L.ndiag * 4, st, items, L);
+    if (g.wave_blocks)
+        hipLaunchKernelGGL(k_sort_wave<false>, dim3(g.wave_blocks), dim3(kThreads), (size_t)L.ndiag * 4, st, items, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_wave_big(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st)
+{
+    if (g.wave_big_blocks)
+        hipLaunchKernelGGL(k_sort_wave<true>, dim3(g.wave_big_blocks), dim3(kThreads), (size_t)L.ndiag * 4, st, items, L);
     return hipGetLastError();
 }
 

@@ -16,15 +16,17 @@ constexpr int kCountTile = 16384;  // g-mers per 1024-thread block in the bucket
 constexpr int kCountThreads = 1024;
 constexpr int kMaxBucketBits = 12;
 
-// Bucket size classes of the per-bucket sort: seven wave classes (packed
-// composites 64..512 g-mers, wide ones 64..256), ten block classes (packed
-// 1024..16384, wide 512..8192) and two global-memory classes (packed, wide).
-constexpr uint32_t kSortWaveMaxPk = 512;
-constexpr uint32_t kSortWaveMaxWide = 256;
+// Bucket size classes of the per-bucket sort: nine wave classes (packed
+// composites 64..1024 g-mers, wide ones 64..512; the largest of each, packed
+// 1024 and wide 512, in a second wave kernel with more LDS per wave), eight
+// block classes (packed 2048..16384, wide 1024..8192) and two global-memory
+// classes (packed, wide).
+constexpr uint32_t kSortWaveMaxPk = 1024;
+constexpr uint32_t kSortWaveMaxWide = 512;
 constexpr uint32_t kSortBlockMaxPk = 16384;
 constexpr uint32_t kSortBlockMaxWide = 8192;
-constexpr int kSortClassWave = 7;
-constexpr int kSortClassBlock = 10;
+constexpr int kSortClassWave = 9;
+constexpr int kSortClassBlock = 8;
 constexpr int kSortClasses = kSortClassWave + kSortClassBlock + 2;
 constexpr int kSortTicketBlock = kSortClasses;  // counter slot of the block kernel's work tickets
 constexpr int kSortCounters = 32;               // counter words per chunk

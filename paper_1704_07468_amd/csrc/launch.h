@@ -23,12 +23,13 @@ hipError_t launch_bucket_count(const MaskWork *items, const uint32_t *bprefix, i
 struct SortLists;
 // Grid sizes of the per-bucket sort kernels (0 = not launched).
 struct SortGrid {
-    uint32_t wave_blocks = 0, block_blocks = 0, global_blocks_pk = 0, global_blocks_wide = 0;
+    uint32_t wave_blocks = 0, wave_big_blocks = 0, block_blocks = 0, global_blocks_pk = 0, global_blocks_wide = 0;
 };
 hipError_t launch_bucket_scan(const MaskWork *items, int nitems, SortLists L, hipStream_t st);
 hipError_t launch_bucket_scatter(const MaskWork *items, const uint32_t *bprefix, int nitems, uint32_t uniform, uint32_t nblocks,
                                  int maxB, hipStream_t st);
 hipError_t launch_sort_wave(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
+hipError_t launch_sort_wave_big(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_sort_block(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_sort_global(const MaskWork *items, SortLists L, const SortGrid &g, hipStream_t st);
 hipError_t launch_accumulate(const JobDev *jobs, const MaskWork *items, const AccWork *aw, const uint32_t *bprefix, int nacc,

@@ -777,7 +777,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
     for (auto &c : p.chunks) {
         size_t bc = 0;
         std::vector<uint32_t> pt(1, 0), ptc(1, 0);
-        uint64_t bound_block = 0, bound_gpk = 0, bound_gwide = 0;
+        uint64_t bound_big = 0, bound_block = 0, bound_gpk = 0, bound_gwide = 0;
         for (int q = 0; q < c.nmask; ++q) {
             const int gi = c.mfirst + q;
             while (gi >= p.jobs[j].mask_first + (int)p.jobs[j].masks.size()) ++j;
@@ -835,6 +835,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         // of a mask fall in the block and global classes
         for (int q = 0; q < c.nmask; ++q) {
             const MaskWork &W = p.mw[(size_t)(c.mfirst + q)];
+            bound_big += W.T / ((W.cb <= 32 ? kSortWaveMaxPk : kSortWaveMaxWide) / 2 + 1);
             bound_block += W.T / ((W.cb <= 32 ? kSortWaveMaxPk : kSortWaveMaxWide) + 1);
             if (W.cb <= 32) bound_gpk += W.T / (kSortBlockMaxPk + 1);
             else bound_gwide += W.T / (kSortBlockMaxWide + 1);
@@ -843,6 +844,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         // largest buckets first, so the first waves take the longest work);
         // a persistent grid of 2048 blocks left its slowest waves as a tail
         c.sgrid.wave_blocks = (uint32_t)std::min<size_t>((c.nbuck + kWaves - 1) / kWaves, 65536);
+        c.sgrid.wave_big_blocks = (uint32_t)std::min<uint64_t>((bound_big + kWaves - 1) / kWaves, 65536);
         c.sgrid.block_blocks = (uint32_t)std::min<uint64_t>(bound_block, 256);
         c.sgrid.global_blocks_pk = (uint32_t)std::min<uint64_t>(bound_gpk, 128);
         c.sgrid.global_blocks_wide = (uint32_t)std::min<uint64_t>(bound_gwide, 128);
@@ -875,7 +877,7 @@ gakco_status plan_upload(Plan &p, hipStream_t st)
 }
 
 static const char *kPhaseNames[PH_COUNT] = {"fill", "validate", "extract", "bucket_count", "bucket_scan",
-                                            "bucket_scatter", "sort_wave", "sort_block", "sort_global",
+                                            "bucket_scatter", "sort_wave", "sort_wave_big", "sort_block", "sort_global",
                                             "accumulate", "dense_syrk", "dense_clear",
                                             "diag", "finalize", "rows_kdiag", "rows", "rows_finalize",
                                             "direct_count", "direct_excess"};
@@ -984,11 +986,12 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
         GK_PHASE(PH_BSCAN, launch_bucket_scan(cm, c.nmask, L, st));
         GK_PHASE(PH_BSCATTER, launch_bucket_scatter(cm, P(c.d_pt), c.nmask, c.uni_t, c.nb_t, c.maxB, st));
         if (dual) {
-            GK_TRY(fork(0));
-            GK_HIP(launch_sort_block(cm, L, c.sgrid, ctx->side));
+            // the sorts run one after another: each fills the device, and
+            // side by side they measured slower than in sequence
             GK_HIP(launch_sort_wave(cm, L, c.sgrid, st));
+            GK_HIP(launch_sort_wave_big(cm, L, c.sgrid, st));
+            GK_HIP(launch_sort_block(cm, L, c.sgrid, st));
             GK_HIP(launch_sort_global(cm, L, c.sgrid, st));
-            GK_TRY(join(0));
             if (last && p.n_dense + p.n_dlev) {
                 GK_TRY(fork(1));
                 GK_HIP(launch_dense_syrk(dw, P(p.d_pdense), p.n_dense + p.n_dlev, p.nb_dense, ctx->side));
@@ -1002,6 +1005,7 @@ gakco_status plan_launch(gakco_ctx *ctx, Plan &p, hipStream_t st)
             continue;
         }
         GK_PHASE(PH_SORT_WAVE, launch_sort_wave(cm, L, c.sgrid, st));
+        GK_PHASE(PH_SORT_WAVE_BIG, launch_sort_wave_big(cm, L, c.sgrid, st));
         GK_PHASE(PH_SORT_BLOCK, launch_sort_block(cm, L, c.sgrid, st));
         GK_PHASE(PH_SORT_GLOBAL, launch_sort_global(cm, L, c.sgrid, st));
         if (c.nacc)
