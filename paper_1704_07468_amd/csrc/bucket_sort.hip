@@ -673,10 +673,7 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
         if (i < n) {
             const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
             if (!((u.rb >> lane) & 1ull)) {
-                if (idx < T) {
-                    if (i4) info4[idx] = 0u;
-                    else st_u2(info, idx, 0u, 0u);
-                }
+                if (idx < T && !i4) st_u2(info, idx, 0u, 0u);  // (4-byte records start zeroed)
             } else {
                 const RunAt a = run_at_w<NWORDS, NSLOT>(S, u, w, lane, i, n, R);
                 const uint64_t c = comp_at(i);
@@ -697,8 +694,12 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
                     x = (uint32_t)(comp_at(nx) & sidmask) | ((a.gend - nx) << sb);
                 }
                 if (idx < T) {
-                    if (i4) info4[idx] = pack_info4(y ? a.len : 0u, a.cnt, ei, inl && a.len == 2, x, sb, lenx);
-                    else st_u2(info, idx, x, y);
+                    if (i4) {
+                        const uint32_t rec = pack_info4(y ? a.len : 0u, a.cnt, ei, inl && a.len == 2, x, sb, lenx);
+                        if (rec) info4[idx] = rec;
+                    } else {
+                        st_u2(info, idx, x, y);
+                    }
                 }
                 dv = a.cnt * a.cnt;
                 dq = sid;

@@ -228,15 +228,21 @@ __device__ __forceinline__ void st_u4(gptr<uint4> p, size_t i, uint32_t a, uint3
 // group end (127: the length is in the side array at the run's entry index),
 // bit 7 set when the group's last run is carried inline, bits 8-10 the run's
 // count (0: 8 or more, read from the run's entry), bits 11-31 the payload:
-// the run's count for a group of one run, the last run's entry (sequence |
-// count << sb) when inline, else the run's entry index.  0: no record (not
-// a run leader, or a group summed on the matrix cores).
+// the run's count when it is its group's last run, the last run's entry
+// (sequence | count << sb) when inline, else the run's entry index.
+// The records start zeroed (the partition clears them) and only nonzero ones
+// are stored.  0: nothing beyond the g-mer's own diagonal term 1 -- not a run
+// leader, or the last run of its group with count 1 (most g-mers of the
+// sparse levels), whose self-pair 1 * 1 is that term.  A run summed on the
+// matrix cores stores 128 | count << 8 (bits 0-6 zero): the product adds its
+// count^2 to the diagonal, so the accumulation takes back the count's worth
+// of unit terms.
 constexpr uint32_t kInfo4MaxT = 1u << 21;
 __device__ __forceinline__ uint32_t pack_info4(uint32_t len, uint32_t cnt, uint32_t ei, bool inl, uint32_t last_entry,
                                                int sb, __attribute__((address_space(1))) uint32_t *lenx)
 {
-    if (len == 0) return 0u;
-    if (len == 1) return 1u | (cnt << 11);
+    if (len == 0) return 128u | (cnt << 8);  // count-matrix run (count <= 127)
+    if (len == 1) return cnt == 1u ? 0u : (1u | (cnt << 11));
     if (inl && len == 2 && cnt <= 7u && (last_entry >> sb) < (1u << (21 - sb)))
         return 2u | (1u << 7) | (cnt << 8) | (last_entry << 11);
     uint32_t lf = len;
@@ -595,18 +601,16 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
             x = (uint32_t)(comp(p1) & sidmask) | (c1 << sb);
         }
         if (W.i4) {
-            ((gptr<uint32_t>)info)[gidx(p)] = pack_info4(len, cnt, e, W.inl && len == 2, x, sb,
-                                                         (gptr<uint32_t>)info + W.T);
+            const uint32_t rec = pack_info4(len, cnt, e, W.inl && len == 2, x, sb, (gptr<uint32_t>)info + W.T);
+            if (rec) ((gptr<uint32_t>)info)[gidx(p)] = rec;
         } else {
             // y: entries to the group end in the low sb+1 bits, the run count above
             st_u2(info, gidx(p), x, len ? (len | (cnt << (sb + 1))) : 0u);
         }
     }
-    for (uint32_t i = tid; i < n; i += kThreads)
-        if (i > 0 && comp(i) == comp(i - 1)) {
-            if (W.i4) ((gptr<uint32_t>)info)[gidx(i)] = 0u;
-            else st_u2(info, gidx(i), 0u, 0u);
-        }
+    if (!W.i4)  // (4-byte records start zeroed)
+        for (uint32_t i = tid; i < n; i += kThreads)
+            if (i > 0 && comp(i) == comp(i - 1)) st_u2(info, gidx(i), 0u, 0u);
     if (W.gtab) {
         for (uint32_t gi = tid; gi < G; gi += kThreads) {
             const uint32_t r0 = gsr[gi];

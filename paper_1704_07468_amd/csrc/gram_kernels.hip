@@ -136,6 +136,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
     }
     __syncthreads();
     const bool narrow = W.cb <= 32;
+    if (W.i4) {  // the sort stores only nonzero 4-byte records: clear the tile's
+        const gptr<uint32_t> info4 = (gptr<uint32_t>)glb(W.info);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t t = t0 + q * kScatterThreads + threadIdx.x;
+            if (t < W.T) info4[t] = 0u;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (bk[q] != 0xFFFFFFFFu) {
@@ -222,6 +230,9 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     for (int i = lane; i < kAccWindow; i += 64) mark[wid][i] = 0;
     uint32_t nupd = 0;           // this lane's diagonal and inline pair updates
     unsigned long long wupd = 0;  // the wave's gathered pair updates (profiling count)
+    // 4-byte records (uniform over a job's masks) leave the diagonal's unit
+    // terms to a base of one per g-mer and mask
+    const bool i4 = items[A.mfirst].i4 != 0;
     // The masks are taken mstep at a time, the int32 row flushed into the
     // int64 C_m after each step: one mask adds at most ng_X * ng_Y to an
     // entry, and the planner picks mstep so that mstep * maxng^2 < 2^32.
@@ -231,8 +242,17 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     const int nmk = min(mstep, A.nmask - ms0);
     for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
     __syncthreads();
+    if (i4 && own_col) {  // every g-mer of X leads or joins one run per mask: 1 each
+        if (A.nlev == 1) {
+            if (tid == 0) atomicAdd(&acc[X - y0], (uint32_t)nmk * ng);
+        } else {
+            for (int s = tid; s < nmk; s += kThreads)
+                atomicAdd(&acc[(uint32_t)(items[A.mfirst + ms0 + s].md.level - A.lev0) * (uint32_t)npad + (uint32_t)(X - y0)], ng);
+        }
+        if (tid == 0) nupd += (uint32_t)nmk * ng;
+    }
     const uint32_t total = (uint32_t)nmk * ng;
-    uint32_t dsum = 0;  // this lane's count_X^2 terms (one level per work)
+    uint32_t dsum = 0;  // this lane's diagonal terms (one level per work)
     for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
         const uint32_t q = c0 + lane;
         uint32_t len = 0;
@@ -246,54 +266,57 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
             // end (tail), its count, and either the group's last entry inline
             // or its own entry index
             uint32_t tail, xi = 0;
+            uint32_t dterm = 0;  // X's diagonal term from this item, beyond the base
             bool inl2 = false;
-            if (W.i4) {
+            if (i4) {
                 const uint32_t v = glb((const uint32_t *)W.info)[t];
                 tail = v & 127u;
                 const uint32_t pay = v >> 11;
-                if (tail == 1) {
+                if (tail == 0) {
+                    dterm = 0u - (v >> 8);  // count-matrix run: count^2 comes from the product
+                } else if (tail == 1) {
                     cx = pay;
                 } else if (v & 128u) {
                     cx = (v >> 8) & 7u;
                     inl2 = true;
                     xi = pay;
-                } else if (tail) {
+                } else {
                     xi = pay;
                     if (tail == 127u) tail = glb((const uint32_t *)W.info)[W.T + xi];
                     cx = (v >> 8) & 7u;
                     if (!cx) cx = glb((const uint32_t *)W.E)[xi] >> sb;
                 }
+                if (tail) dterm = cx * cx - cx;
             } else {
                 const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
                 tail = inf.y & lmask;
                 cx = inf.y >> (sb + 1);
                 xi = inf.x;
                 inl2 = tail == 2;
+                if (tail) dterm = cx * cx;
             }
-            if (tail) {
-                // LDS index of column Y: level offset + Y - y0 (mod 2^32)
-                off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad - (uint32_t)y0;
-                if (own_col) {
-                    if (A.nlev == 1) dsum += cx * cx;
-                    else atomicAdd(&acc[off + (uint32_t)X], cx * cx);
+            // LDS index of column Y: level offset + Y - y0 (mod 2^32)
+            off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad - (uint32_t)y0;
+            if (own_col && dterm) {
+                if (A.nlev == 1) dsum += dterm;
+                else atomicAdd(&acc[off + (uint32_t)X], dterm);
+                if (!i4) ++nupd;
+            }
+            if (inl2) {
+                const uint32_t ys = xi & sidmask;
+                if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) {
+                    atomicAdd(&acc[off + ys], cx * (xi >> sb));
                     ++nupd;
                 }
-                if (inl2) {
-                    const uint32_t ys = xi & sidmask;
-                    if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) {
-                        atomicAdd(&acc[off + ys], cx * (xi >> sb));
-                        ++nupd;
-                    }
-                } else if (tail >= 2) {
-                    // entries [e0, e1): sequences above X in ascending order
-                    uint32_t e0 = xi + 1, e1 = xi + tail;
-                    if (!whole) {
-                        if (y0 > X + 1) e0 = first_seq_at_least(W.E, e0, e1, (uint32_t)y0, sidmask);
-                        if (y1 < N) e1 = first_seq_at_least(W.E, e0, e1, (uint32_t)y1, sidmask);
-                    }
-                    len = e1 - e0;
-                    ebase = reinterpret_cast<uint64_t>(W.E + e0);
+            } else if (tail >= 2) {
+                // entries [e0, e1): sequences above X in ascending order
+                uint32_t e0 = xi + 1, e1 = xi + tail;
+                if (!whole) {
+                    if (y0 > X + 1) e0 = first_seq_at_least(W.E, e0, e1, (uint32_t)y0, sidmask);
+                    if (y1 < N) e1 = first_seq_at_least(W.E, e0, e1, (uint32_t)y1, sidmask);
                 }
+                len = e1 - e0;
+                ebase = reinterpret_cast<uint64_t>(W.E + e0);
             }
         }
         const uint32_t inc = wave_incl_scan(len);
