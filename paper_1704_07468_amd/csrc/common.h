@@ -179,16 +179,21 @@ struct MaskWork {
     uint32_t *diag;    // [N] sum over runs of count^2 per sequence, this level (nullable)
 };
 
-// Row accumulation work: rows of one job over a range of masks.
+// Row accumulation work: rows of one job over a range of masks of one level.
+// The masks' buffers lie mstride bytes apart (equal-size slices of the
+// pool), so a mask's info and run-entry arrays are those of the first mask
+// plus its index times mstride.
 struct AccWork {
     int32_t job;
     int32_t mfirst;  // first MaskWork index
     int32_t nmask;
-    int32_t lev0, nlev;
+    int32_t level;
     int32_t Npad;    // LDS row stride (the slab width, a multiple of 64)
     int32_t first;   // 1: first work of its (job, level): store the row, else add
     int32_t slab, nslab;  // columns per block and blocks per row
     int32_t mstep;   // masks summed in the int32 LDS row between flushes (0: all)
+    int32_t pad;
+    int64_t mstride;
 };
 
 // --------------------------------------------------------------------------

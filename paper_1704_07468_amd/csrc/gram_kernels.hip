@@ -2,6 +2,8 @@
 // hash-bucket partition (count / scan / scatter), per-bucket LDS radix sort
 // with group segmentation, row-owned accumulation of the cumulative mismatch
 // profiles, and the inclusion-exclusion / kernel / normalisation epilogue.
+#include <type_traits>
+
 #include "common.h"
 #include "launch.h"
 
@@ -167,17 +169,19 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
 // count_X * count_Y to row[Y] (Algorithm 1 countAndUpdate, upper triangle).
 // X's own entry is count_X^2 on the diagonal, summed in registers; a run with
 // one more entry carries it in its info; longer tails are read from the run
-// entries.  Each wave consumes its own chunks of 64 (mask, g-mer) items; the
-// chunk's tails are laid end to end (a wave scan of their lengths) and the
-// lanes walk that sequence kAccWindow updates at a time (eight gathers in
-// flight per lane): a mark per tail start in LDS, a ballot of the marks and
-// a popcount below the lane give each update its tail without a search.  The
+// entries.  Each wave consumes its own chunks of 128 (mask, g-mer) items, two
+// per lane, whose records were loaded during the previous chunk; the chunk's
+// tails are laid end to end (a wave scan of their lengths) and the lanes walk
+// that sequence kAccWindow updates at a time (eight gathers in flight per
+// lane): one bit per tail start in LDS, read back as 64-bit words, and a
+// popcount below the lane give each update its tail without a search.  The
 // loop has no block barrier.  The row is then added into the int64 C_m.
 // When a row does not fit the LDS, each block takes a slab of its columns
 // [y0, y1) and cuts every tail to the entries of those sequences (a search
 // of the sequence-sorted entries); slabs below the diagonal have no work.
 constexpr int kAccWindow = 512;
 constexpr int kAccU = kAccWindow / 64;
+constexpr int kAccItems = 2;  // items per lane in one wave chunk
 
 // First index in [lo, hi) whose entry's sequence is >= s (hi if none); the
 // entries of one group are sorted by sequence.
@@ -192,18 +196,23 @@ __device__ __forceinline__ uint32_t first_seq_at_least(const uint32_t *E, uint32
     }
     return lo;
 }
-__global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
-                                                         const AccWork *__restrict__ aw, const uint32_t *__restrict__ bprefix, int nacc,
-                                                         unsigned long long *updates)
+constexpr int kAccTails = 64 * kAccItems;  // tails per wave chunk at most
+struct AccLds {
+    uint64_t tbase[kWaves][kAccTails];  // per tail: entry address - 4 * its start in the sequence
+    uint32_t tcx[kWaves][kAccTails];    // per tail: count_X
+    uint32_t mark[kWaves][kAccWindow / 32];  // tail starts in the current window, one bit each
+};
+
+// The block's work with 4-byte records (I4) or uint2 records.
+template <bool I4>
+__device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items,
+                                               const AccWork &A, int flat, uint32_t *acc, AccLds &L,
+                                               unsigned long long *updates)
 {
-    extern __shared__ uint32_t acc[];
-    __shared__ uint64_t tbase[kWaves][64];  // per tail: entry address - 4 * its start in the sequence
-    __shared__ uint2 tfac[kWaves][64];      // per tail: (count_X, row offset of its level)
-    __shared__ uint8_t mark[kWaves][kAccWindow];  // tail starts in the current window (zero between windows)
-    const int a = find_item(bprefix, nacc, blockIdx.x);
-    const AccWork &A = aw[a];
+    auto &tbase = L.tbase;
+    auto &tcx = L.tcx;
+    auto &mark = L.mark;
     const JobDev &J = jobs[A.job];
-    const int flat = (int)(blockIdx.x - bprefix[a]);
     const int X = flat / A.nslab;
     const int N = J.N;
     // this block's columns [y0, y1) of row X; it writes [max(X, y0), y1)
@@ -212,27 +221,31 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
     const bool whole = A.nslab == 1;
     const int ylo = max(X, y0);
     const bool own_col = X >= y0;  // the diagonal entry is in this slab
-    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const int sb = J.sb;
     const uint32_t sidmask = (uint32_t)bits_mask(sb);
     const uint32_t lmask = (uint32_t)bits_mask(sb + 1);
     const uint32_t t0 = J.gstart[X];
     const uint32_t ng = J.gstart[X + 1] - t0;
+    const gptr<int64_t> crow = glb(J.C) + ((size_t)A.level * N + X) * (size_t)N;
     if (ng == 0 || A.nmask == 0) {  // nothing to add: a stored row is 0
         if (A.first)
-            for (int l = 0; l < A.nlev; ++l) {
-                const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
-                for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = 0;
-            }
+            for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = 0;
         return;
     }
-    const int npad = A.Npad;
-    for (int i = lane; i < kAccWindow; i += 64) mark[wid][i] = 0;
+    // the first mask's arrays; mask s's are mstride * s bytes further
+    const MaskWork &W0 = items[A.mfirst];
+    const uint64_t info0 = reinterpret_cast<uint64_t>(W0.info), ent0 = reinterpret_cast<uint64_t>(W0.E);
+    const uint32_t T = W0.T;
+    const int64_t mstride = A.mstride;
+    // 4-byte records leave the diagonal's unit terms to a base of one per
+    // g-mer and mask
+    using Rec = std::conditional_t<I4, uint32_t, uint64_t>;
+    if (lane < kAccWindow / 32) mark[wid][lane] = 0;
     uint32_t nupd = 0;           // this lane's diagonal and inline pair updates
     unsigned long long wupd = 0;  // the wave's gathered pair updates (profiling count)
-    // 4-byte records (uniform over a job's masks) leave the diagonal's unit
-    // terms to a base of one per g-mer and mask
-    const bool i4 = items[A.mfirst].i4 != 0;
+    uint32_t *const accy = acc - y0;  // column Y at accy[Y]
     // The masks are taken mstep at a time, the int32 row flushed into the
     // int64 C_m after each step: one mask adds at most ng_X * ng_Y to an
     // entry, and the planner picks mstep so that mstep * maxng^2 < 2^32.
@@ -240,147 +253,185 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
 #pragma unroll 1
     for (int ms0 = 0; ms0 < A.nmask; ms0 += mstep) {
     const int nmk = min(mstep, A.nmask - ms0);
-    for (int i = tid; i < A.nlev * npad; i += kThreads) acc[i] = 0;
+    for (int i = tid; i < A.Npad; i += kThreads) acc[i] = 0;
     __syncthreads();
-    if (i4 && own_col) {  // every g-mer of X leads or joins one run per mask: 1 each
-        if (A.nlev == 1) {
-            if (tid == 0) atomicAdd(&acc[X - y0], (uint32_t)nmk * ng);
-        } else {
-            for (int s = tid; s < nmk; s += kThreads)
-                atomicAdd(&acc[(uint32_t)(items[A.mfirst + ms0 + s].md.level - A.lev0) * (uint32_t)npad + (uint32_t)(X - y0)], ng);
-        }
-        if (tid == 0) nupd += (uint32_t)nmk * ng;
+    if (I4 && own_col && tid == 0) {  // every g-mer of X leads or joins one run per mask: 1 each
+        atomicAdd(&acc[X - y0], (uint32_t)nmk * ng);
+        nupd += (uint32_t)nmk * ng;
     }
+    uint32_t dsum = 0;  // this lane's diagonal terms
+    // item q = (mask ms0 + q / ng, g-mer t0 + q % ng): its mask's byte offset
+    // and its record; the next chunk's records are loaded while this
+    // chunk's tails are walked
     const uint32_t total = (uint32_t)nmk * ng;
-    uint32_t dsum = 0;  // this lane's diagonal terms (one level per work)
-    for (uint32_t c0 = (uint32_t)wid * 64; c0 < total; c0 += kThreads) {
-        const uint32_t q = c0 + lane;
-        uint32_t len = 0;
-        uint64_t ebase = 0;
-        uint32_t cx = 0, off = 0;
-        if (q < total) {
-            const uint32_t s = q / ng;
-            const uint32_t t = t0 + (q - s * ng);
-            const MaskWork &W = items[A.mfirst + ms0 + (int)s];
-            // the run X has in this group: entries from its own to the group
-            // end (tail), its count, and either the group's last entry inline
-            // or its own entry index
-            uint32_t tail, xi = 0;
-            uint32_t dterm = 0;  // X's diagonal term from this item, beyond the base
-            bool inl2 = false;
-            if (i4) {
-                const uint32_t v = glb((const uint32_t *)W.info)[t];
-                tail = v & 127u;
-                const uint32_t pay = v >> 11;
-                if (tail == 0) {
-                    dterm = 0u - (v >> 8);  // count-matrix run: count^2 comes from the product
-                } else if (tail == 1) {
-                    cx = pay;
-                } else if (v & 128u) {
-                    cx = (v >> 8) & 7u;
-                    inl2 = true;
-                    xi = pay;
-                } else {
-                    xi = pay;
-                    if (tail == 127u) tail = glb((const uint32_t *)W.info)[W.T + xi];
-                    cx = (v >> 8) & 7u;
-                    if (!cx) cx = glb((const uint32_t *)W.E)[xi] >> sb;
-                }
-                if (tail) dterm = cx * cx - cx;
+    auto item_mask = [&](uint32_t q, uint32_t &t) -> int64_t {
+        const uint32_t s = q / ng;
+        t = t0 + (q - s * ng);
+        return (int64_t)(ms0 + (int)s) * mstride;
+    };
+    auto load_rec = [&](uint32_t q) -> Rec {
+        if (q >= total) return 0;
+        uint32_t t;
+        const int64_t mo = item_mask(q, t);
+        return *(gptr<const Rec>)(const Rec *)(info0 + (uint64_t)mo + sizeof(Rec) * (uint64_t)t);
+    };
+    // One item: its diagonal term and inline pair go to the row at once;
+    // a longer tail is returned as (length, address of its first entry).
+    auto item = [&](uint32_t q, Rec rec, uint32_t &len, uint64_t &ebase, uint32_t &cx) {
+        len = 0;
+        ebase = 0;
+        cx = 0;
+        if (q >= total) return;
+        uint32_t t;
+        const int64_t mo = item_mask(q, t);
+        const uint64_t ents = ent0 + (uint64_t)mo;  // this mask's run entries
+        // the run X has in this group: entries from its own to the group
+        // end (tail), its count, and either the group's last entry inline
+        // or its own entry index
+        uint32_t tail, xi = 0;
+        uint32_t dterm = 0;  // X's diagonal term from this item, beyond the base
+        bool inl2 = false;
+        if constexpr (I4) {
+            const uint32_t v = rec;
+            tail = v & 127u;
+            const uint32_t pay = v >> 11;
+            if (tail == 0) {
+                dterm = 0u - (v >> 8);  // count-matrix run: count^2 comes from the product
+            } else if (tail == 1) {
+                cx = pay;
+            } else if (v & 128u) {
+                cx = (v >> 8) & 7u;
+                inl2 = true;
+                xi = pay;
             } else {
-                const uint2 inf = ld_u2(glb((const uint2 *)W.info), t);
-                tail = inf.y & lmask;
-                cx = inf.y >> (sb + 1);
-                xi = inf.x;
-                inl2 = tail == 2;
-                if (tail) dterm = cx * cx;
+                xi = pay;
+                if (tail == 127u) tail = *(gptr<const uint32_t>)(info0 + (uint64_t)mo + 4ull * ((uint64_t)T + xi));
+                cx = (v >> 8) & 7u;
+                if (!cx) cx = *(gptr<const uint32_t>)(ents + 4ull * xi) >> sb;
             }
-            // LDS index of column Y: level offset + Y - y0 (mod 2^32)
-            off = (uint32_t)(W.md.level - A.lev0) * (uint32_t)npad - (uint32_t)y0;
-            if (own_col && dterm) {
-                if (A.nlev == 1) dsum += dterm;
-                else atomicAdd(&acc[off + (uint32_t)X], dterm);
-                if (!i4) ++nupd;
-            }
-            if (inl2) {
-                const uint32_t ys = xi & sidmask;
-                if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) {
-                    atomicAdd(&acc[off + ys], cx * (xi >> sb));
-                    ++nupd;
-                }
-            } else if (tail >= 2) {
-                // entries [e0, e1): sequences above X in ascending order
-                uint32_t e0 = xi + 1, e1 = xi + tail;
-                if (!whole) {
-                    if (y0 > X + 1) e0 = first_seq_at_least(W.E, e0, e1, (uint32_t)y0, sidmask);
-                    if (y1 < N) e1 = first_seq_at_least(W.E, e0, e1, (uint32_t)y1, sidmask);
-                }
-                len = e1 - e0;
-                ebase = reinterpret_cast<uint64_t>(W.E + e0);
-            }
+            if (tail) dterm = cx * cx - cx;
+        } else {
+            const uint32_t y = (uint32_t)(rec >> 32);
+            tail = y & lmask;
+            cx = y >> (sb + 1);
+            xi = (uint32_t)rec;
+            inl2 = tail == 2;
+            if (tail) dterm = cx * cx;
         }
-        const uint32_t inc = wave_incl_scan(len);
+        if (own_col && dterm) {
+            dsum += dterm;
+            if (!I4) ++nupd;
+        }
+        if (inl2) {
+            const uint32_t ys = xi & sidmask;
+            if (whole || (ys >= (uint32_t)y0 && ys < (uint32_t)y1)) {
+                atomicAdd(&accy[ys], cx * (xi >> sb));
+                ++nupd;
+            }
+        } else if (tail >= 2) {
+            // entries [e0, e1): sequences above X in ascending order
+            const uint32_t *E = reinterpret_cast<const uint32_t *>(ents);
+            uint32_t e0 = xi + 1, e1 = xi + tail;
+            if (!whole) {
+                if (y0 > X + 1) e0 = first_seq_at_least(E, e0, e1, (uint32_t)y0, sidmask);
+                if (y1 < N) e1 = first_seq_at_least(E, e0, e1, (uint32_t)y1, sidmask);
+            }
+            len = e1 - e0;
+            ebase = ents + 4ull * e0;
+        }
+    };
+    constexpr uint32_t kStep = kThreads * kAccItems;  // items per block round
+    Rec rnext[kAccItems];
+#pragma unroll
+    for (int i = 0; i < kAccItems; ++i) rnext[i] = load_rec((uint32_t)(wid * kAccTails + i * 64 + lane));
+    for (uint32_t c0 = (uint32_t)wid * kAccTails; c0 < total; c0 += kStep) {
+        uint32_t len[kAccItems], cxv[kAccItems];
+        uint64_t eb[kAccItems];
+        uint32_t lsum = 0;
+#pragma unroll
+        for (int i = 0; i < kAccItems; ++i) {
+            const uint32_t q = c0 + (uint32_t)(i * 64 + lane);
+            const Rec rec = rnext[i];
+            rnext[i] = load_rec(q + kStep);
+            item(q, rec, len[i], eb[i], cxv[i]);
+            lsum += len[i];
+        }
+        // the chunk's tails laid end to end in (lane, item) order
+        const uint32_t inc = wave_incl_scan(lsum);
         const uint32_t work = __builtin_amdgcn_readlane(inc, 63);
         if (work == 0) continue;  // wave-uniform
         wupd += work;
-        const uint32_t start = inc - len;  // this tail's first position in the sequence
-        const uint64_t nz = __ballot(len > 0);
-        if (len > 0) {  // tails in start order: k = nonempty tails below this lane
-            const uint32_t k = lanes_below(nz);
-            tbase[wid][k] = ebase - 4ull * start;
-            tfac[wid][k] = make_uint2(cx, off);
+        uint32_t start[kAccItems];
+        {
+            uint32_t kk = 0;  // nonempty tails of the lanes below
+#pragma unroll
+            for (int i = 0; i < kAccItems; ++i) kk += lanes_below(__ballot(len[i] > 0));
+            uint32_t s = inc - lsum;
+#pragma unroll
+            for (int i = 0; i < kAccItems; ++i) {
+                start[i] = s;
+                s += len[i];
+                if (len[i] > 0) {
+                    tbase[wid][kk] = eb[i] - 4ull * start[i];
+                    tcx[wid][kk] = cxv[i];
+                    ++kk;
+                }
+            }
         }
         uint32_t done = 0;  // tails started before the window
 #pragma unroll 1
         for (uint32_t w = 0; w < work; w += kAccWindow) {
-            const bool here = len > 0 && start >= w && start < w + kAccWindow;
-            if (here) mark[wid][start - w] = 1;
+#pragma unroll
+            for (int i = 0; i < kAccItems; ++i)
+                if (len[i] > 0 && start[i] >= w && start[i] < w + kAccWindow)
+                    atomicOr(&mark[wid][(start[i] - w) >> 5], 1u << ((start[i] - w) & 31u));
             wave_sync();
             uint64_t st[kAccU];
 #pragma unroll
-            for (int u = 0; u < kAccU; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
+            for (int u = 0; u < kAccU; ++u) st[u] = ((uint64_t)mark[wid][2 * u + 1] << 32) | mark[wid][2 * u];
             wave_sync();
-            if (here) mark[wid][start - w] = 0;
-            uint32_t k[kAccU];
+            if (lane < kAccWindow / 32) mark[wid][lane] = 0;
+            // sub-steps past the work are skipped (uniform conditions)
+            {
+                uint32_t k[kAccU], ent[kAccU];
 #pragma unroll
-            for (int u = 0; u < kAccU; ++u) {
-                k[u] = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
-                done += (uint32_t)__popcll(st[u]);
-            }
-            uint32_t ent[kAccU];
+                for (int u = 0; u < kAccU; ++u) {
+                    if (w + 64u * u < work) {
+                        k[u] = done + lanes_below(st[u]) + (uint32_t)((st[u] >> lane) & 1ull) - 1u;
+                        done += (uint32_t)__popcll(st[u]);
+                    }
+                }
 #pragma unroll
-            for (int u = 0; u < kAccU; ++u) {
-                const uint32_t p = w + 64u * u + (uint32_t)lane;
-                ent[u] = 0;
-                if (p < work) ent[u] = *(gptr<const uint32_t>)(tbase[wid][k[u]] + 4ull * p);
-            }
+                for (int u = 0; u < kAccU; ++u) {
+                    if (w + 64u * u < work) {
+                        const uint32_t p = min(w + 64u * u + (uint32_t)lane, work - 1u);
+                        ent[u] = *(gptr<const uint32_t>)(tbase[wid][k[u]] + 4ull * p);
+                    }
+                }
 #pragma unroll
-            for (int u = 0; u < kAccU; ++u) {
-                const uint32_t p = w + 64u * u + (uint32_t)lane;
-                if (p < work) {
-                    const uint2 f = tfac[wid][k[u]];
-                    atomicAdd(&acc[f.y + (ent[u] & sidmask)], f.x * (ent[u] >> sb));
+                for (int u = 0; u < kAccU; ++u) {
+                    if (w + 64u * u < work) {
+                        // counts stay below 2^16 (g-mers per sequence): 24-bit products
+                        if (w + 64u * u + (uint32_t)lane < work)
+                            atomicAdd(&accy[ent[u] & sidmask], __umul24(tcx[wid][k[u]], ent[u] >> sb));
+                    }
                 }
             }
         }
         wave_sync();
     }
-    if (A.nlev == 1) {
+    {
         const uint32_t d = wave_incl_scan(dsum);  // nonzero only when X is in the slab
         if (lane == 63 && d) atomicAdd(&acc[X - y0], d);
     }
     __syncthreads();
     const bool store = A.first && ms0 == 0;
-    for (int l = 0; l < A.nlev; ++l) {
-        const gptr<int64_t> crow = glb(J.C) + ((size_t)(A.lev0 + l) * N + X) * (size_t)N;
-        const uint32_t *arow = acc + l * npad;
-        if (store) {
-            for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = (int64_t)arow[Y - y0];
-        } else {
-            for (int Y = ylo + tid; Y < y1; Y += kThreads) {
-                const uint32_t v = arow[Y - y0];
-                if (v) crow[Y] += (int64_t)v;
-            }
+    if (store) {
+        for (int Y = ylo + tid; Y < y1; Y += kThreads) crow[Y] = (int64_t)acc[Y - y0];
+    } else {
+        for (int Y = ylo + tid; Y < y1; Y += kThreads) {
+            const uint32_t v = acc[Y - y0];
+            if (v) crow[Y] += (int64_t)v;
         }
     }
     __syncthreads();  // the row is read before the next step clears it
@@ -389,6 +440,20 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(const JobDev *__restric
         const uint32_t u = wave_incl_scan(nupd);
         if (lane == 63) atomicAdd(updates + (blockIdx.x & 255u), wupd + (unsigned long long)u);
     }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_accumulate(
+    const JobDev *__restrict__ jobs, const MaskWork *__restrict__ items, const AccWork *__restrict__ aw,
+    const uint32_t *__restrict__ bprefix, int nacc, unsigned long long *updates)
+{
+    extern __shared__ uint32_t acc[];
+    __shared__ AccLds L;
+    const int a = find_item(bprefix, nacc, blockIdx.x);
+    const AccWork &A = aw[a];
+    const int flat = (int)(blockIdx.x - bprefix[a]);
+    // the record format is the job's (uniform over its masks)
+    if (A.nmask > 0 && items[A.mfirst].i4) accumulate_row<true>(jobs, items, A, flat, acc, L, updates);
+    else accumulate_row<false>(jobs, items, A, flat, acc, L, updates);
 }
 
 // -------------------------------------------------------------- epilogue --

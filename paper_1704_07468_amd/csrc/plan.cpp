@@ -466,8 +466,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 w.job = (int)j;
                 w.mfirst = first;
                 w.nmask = cnt;
-                w.lev0 = lev;
-                w.nlev = 1;
+                w.level = lev;
                 w.Npad = jp.acc_slab;
                 w.slab = jp.acc_slab;
                 w.nslab = jp.acc_nslab;
@@ -856,6 +855,18 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         put(c.d_ptc, ptc);
         std::vector<uint32_t> pa(1, 0);
         for (auto &w : c.aw) pa.push_back(pa.back() + (uint32_t)p.jobs[(size_t)w.job].N * (uint32_t)w.nslab);
+        // the masks of a work are consecutive equal-size pool slices: one
+        // stride between their buffers
+        for (auto &w : c.aw) {
+            const MaskWork *mw = &p.mw[(size_t)w.mfirst];
+            w.mstride = w.nmask > 1 ? (int64_t)((const char *)mw[1].info - (const char *)mw[0].info) : 0;
+            for (int i = 1; i < w.nmask; ++i)
+                if ((const char *)mw[i].info - (const char *)mw[0].info != (int64_t)i * w.mstride ||
+                    (const char *)mw[i].E - (const char *)mw[0].E != (int64_t)i * w.mstride) {
+                    set_error("internal: the position sets of an accumulation work are not evenly spaced");
+                    return GAKCO_EUNSUPPORTED;
+                }
+        }
         if (c.nacc) memcpy(blob + c.d_acc, c.aw.data(), sizeof(AccWork) * c.aw.size());
         put(c.d_pacc, pa);
         c.nb_acc = pa.back();
