@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
         const int c = bucket_class(bcnt[b], pk);
         if (c >= 0) {
             const uint32_t pos = cbase[c] + atomicAdd(&ccnt[c], 1u);
-            if (pos < L.cap) list[(size_t)c * L.cap + pos] = ((uint32_t)q << 12) | b;
+            if (pos < L.cap) list[(size_t)c * L.cap + pos] = ((uint32_t)q << kListBucketBits) | b;
         }
     }
 }
@@ -575,6 +575,7 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     // otherwise alias the descriptor and force reloads after every store
     const int sb = W.sb;
     const gptr<uint32_t> E = glb(W.E);
+    const gptr<uint16_t> E16 = glb((uint16_t *)W.E);
     const gptr<uint2> info = glb(W.info);
     const gptr<int8_t> D = glb(W.D);
     const gptr<uint32_t> dcount = glb(W.dcount);
@@ -679,7 +680,8 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
                 const uint64_t c = comp_at(i);
                 const uint32_t sid = (uint32_t)(c & sidmask);
                 const uint32_t ei = base + a.r;
-                E[ei] = sid | (a.cnt << sb);
+                if (i4) store_entry16(E16, T, ei, sid, a.cnt, sb);
+                else E[ei] = sid | (a.cnt << sb);
                 uint32_t y = a.len | (a.cnt << (sb + 1));
                 if (dense && a.gs < n && bit_at(S.cbm, a.gs)) {
                     const uint32_t row = S.slot[cand_slot(S, a.gs)];
@@ -838,8 +840,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_wave(const MaskWork *__restri
             c = (q == s) ? (BIG ? order_big[q] : order_small[q]) : c;
         }
         const uint32_t ent = list[(size_t)c * L.cap + (t - off)];
-        const MaskWork &W = items[ent >> 12];
-        const uint32_t bucket = ent & 4095u;
+        const MaskWork &W = items[ent >> kListBucketBits];
+        const uint32_t bucket = ent & kListBucketMask;
         if (bucket >= (1u << W.B)) continue;
         if constexpr (BIG) {
             if (c == 4) wave_bucket<true, true, 16>(W, bucket, lds[wid], dl, L.diag0);
@@ -893,8 +895,8 @@ __device__ __forceinline__ void block_buckets(const MaskWork *__restrict__ items
     const int gi = wave / NW, wg = wave % NW;
     // this group's bucket (none: n = 0, the first bucket's mask stands in)
     const uint32_t ent = ents[gi < nb ? gi : 0];
-    const MaskWork &W = items[ent >> 12];
-    const uint32_t bucket = ent & 4095u;
+    const MaskWork &W = items[ent >> kListBucketBits];
+    const uint32_t bucket = ent & kListBucketMask;
     uint32_t base = 0, n = 0;
     if (gi < nb && bucket < (1u << W.B)) {
         const gptr<const uint32_t> boff = glb((const uint32_t *)W.boff);
@@ -987,8 +989,8 @@ __global__ __launch_bounds__(kThreads) void k_sort_global(const MaskWork *__rest
     const uint32_t cnt = min(glb(L.cnt)[cls], L.cap);
     for (uint32_t t = blockIdx.x; t < cnt; t += gridDim.x) {
         const uint32_t ent = glb(L.list)[(size_t)cls * L.cap + t];
-        const MaskWork &W = items[ent >> 12];
-        const uint32_t bucket = ent & 4095u;
+        const MaskWork &W = items[ent >> kListBucketBits];
+        const uint32_t bucket = ent & kListBucketMask;
         if (bucket >= (1u << W.B)) continue;
         const uint32_t base = glb(W.boff)[bucket];
         const uint32_t n = glb(W.boff)[bucket + 1] - base;

@@ -14,7 +14,11 @@ constexpr int kTile = 4096;      // g-mers per block in the partition scatter
 constexpr int kScatterThreads = 512;  // its threads: 8 g-mers each, 8 waves per SIMD
 constexpr int kCountTile = 16384;  // g-mers per 1024-thread block in the bucket count
 constexpr int kCountThreads = 1024;
-constexpr int kMaxBucketBits = 12;
+constexpr int kMaxBucketBits = 14;
+// a sort-list entry is (mask in the chunk) << kListBucketBits | bucket
+constexpr int kListBucketBits = kMaxBucketBits;
+constexpr uint32_t kListBucketMask = (1u << kListBucketBits) - 1u;
+constexpr int kMaxChunkMasks = 1 << (32 - kListBucketBits);
 
 // Bucket size classes of the per-bucket sort: nine wave classes (packed
 // composites 64..1024 g-mers, wide ones 64..512; the largest of each, packed
@@ -242,6 +246,19 @@ __device__ __forceinline__ void st_u4(gptr<uint4> p, size_t i, uint32_t a, uint3
 // matrix cores stores 128 | count << 8 (bits 0-6 zero): the product adds its
 // count^2 to the diagonal, so the accumulation takes back the count's worth
 // of unit terms.
+// Run entries of the same calls are 16 bits: sequence | count << sb, the
+// count field 0 when the count needs more than 16 - sb bits; the count is
+// then in the escape half of the entry array (16-bit slot T + entry).
+__device__ __forceinline__ void store_entry16(gptr<uint16_t> E16, uint32_t T, uint32_t e, uint32_t sid, uint32_t cnt, int sb)
+{
+    if (cnt < (1u << (16 - sb))) {
+        E16[e] = (uint16_t)(sid | (cnt << sb));
+    } else {
+        E16[e] = (uint16_t)sid;
+        E16[T + e] = (uint16_t)cnt;  // at most 65535 g-mers per sequence
+    }
+}
+
 constexpr uint32_t kInfo4MaxT = 1u << 21;
 __device__ __forceinline__ uint32_t pack_info4(uint32_t len, uint32_t cnt, uint32_t ei, bool inl, uint32_t last_entry,
                                                int sb, __attribute__((address_space(1))) uint32_t *lenx)
@@ -590,7 +607,8 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         const uint32_t gi = last_le(gsr, G, r);
         const uint32_t re = (gi + 1 < G) ? gsr[gi + 1] : R;
         const uint32_t e = ebase + r;
-        E[e] = sid | (cnt << sb);
+        if (W.i4) store_entry16(glb((uint16_t *)W.E), W.T, e, sid, cnt, sb);
+        else E[e] = sid | (cnt << sb);
         uint32_t len = re - r;
         if (dense_on) {
             const uint32_t row = gaux[gi];

@@ -185,10 +185,10 @@ constexpr int kAccItems = 2;  // items per lane in one wave chunk
 
 // First index in [lo, hi) whose entry's sequence is >= s (hi if none); the
 // entries of one group are sorted by sequence.
-__device__ __forceinline__ uint32_t first_seq_at_least(const uint32_t *E, uint32_t lo, uint32_t hi, uint32_t s,
-                                                       uint32_t sidmask)
+template <typename Ent>
+__device__ __forceinline__ uint32_t first_seq_at_least(const Ent *E, uint32_t lo, uint32_t hi, uint32_t s, uint32_t sidmask)
 {
-    const gptr<const uint32_t> e = glb(E);
+    const gptr<const Ent> e = glb(E);
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if ((e[mid] & sidmask) < s) lo = mid + 1;
@@ -242,6 +242,10 @@ __device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, 
     // 4-byte records leave the diagonal's unit terms to a base of one per
     // g-mer and mask
     using Rec = std::conditional_t<I4, uint32_t, uint64_t>;
+    // and 16-bit run entries (count field 0: the count is in the escape
+    // slot T entries further)
+    using Ent = std::conditional_t<I4, uint16_t, uint32_t>;
+    constexpr uint32_t ES = sizeof(Ent);
     if (lane < kAccWindow / 32) mark[wid][lane] = 0;
     uint32_t nupd = 0;           // this lane's diagonal and inline pair updates
     unsigned long long wupd = 0;  // the wave's gathered pair updates (profiling count)
@@ -307,7 +311,10 @@ __device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, 
                 xi = pay;
                 if (tail == 127u) tail = *(gptr<const uint32_t>)(info0 + (uint64_t)mo + 4ull * ((uint64_t)T + xi));
                 cx = (v >> 8) & 7u;
-                if (!cx) cx = *(gptr<const uint32_t>)(ents + 4ull * xi) >> sb;
+                if (!cx) {
+                    cx = (uint32_t)*(gptr<const uint16_t>)(ents + 2ull * xi) >> sb;
+                    if (!cx) cx = *(gptr<const uint16_t>)(ents + 2ull * ((uint64_t)T + xi));
+                }
             }
             if (tail) dterm = cx * cx - cx;
         } else {
@@ -330,14 +337,14 @@ __device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, 
             }
         } else if (tail >= 2) {
             // entries [e0, e1): sequences above X in ascending order
-            const uint32_t *E = reinterpret_cast<const uint32_t *>(ents);
+            const Ent *E = reinterpret_cast<const Ent *>(ents);
             uint32_t e0 = xi + 1, e1 = xi + tail;
             if (!whole) {
                 if (y0 > X + 1) e0 = first_seq_at_least(E, e0, e1, (uint32_t)y0, sidmask);
                 if (y1 < N) e1 = first_seq_at_least(E, e0, e1, (uint32_t)y1, sidmask);
             }
             len = e1 - e0;
-            ebase = ents + 4ull * e0;
+            ebase = ents + ES * (uint64_t)e0;
         }
     };
     constexpr uint32_t kStep = kThreads * kAccItems;  // items per block round
@@ -372,7 +379,7 @@ __device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, 
                 start[i] = s;
                 s += len[i];
                 if (len[i] > 0) {
-                    tbase[wid][kk] = eb[i] - 4ull * start[i];
+                    tbase[wid][kk] = eb[i] - ES * (uint64_t)start[i];
                     tcx[wid][kk] = cxv[i];
                     ++kk;
                 }
@@ -405,15 +412,20 @@ __device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, 
                 for (int u = 0; u < kAccU; ++u) {
                     if (w + 64u * u < work) {
                         const uint32_t p = min(w + 64u * u + (uint32_t)lane, work - 1u);
-                        ent[u] = *(gptr<const uint32_t>)(tbase[wid][k[u]] + 4ull * p);
+                        ent[u] = *(gptr<const Ent>)(const Ent *)(tbase[wid][k[u]] + ES * (uint64_t)p);
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kAccU; ++u) {
                     if (w + 64u * u < work) {
                         // counts stay below 2^16 (g-mers per sequence): 24-bit products
-                        if (w + 64u * u + (uint32_t)lane < work)
-                            atomicAdd(&accy[ent[u] & sidmask], __umul24(tcx[wid][k[u]], ent[u] >> sb));
+                        const uint32_t p = w + 64u * u + (uint32_t)lane;
+                        if (p < work) {
+                            uint32_t cy = ent[u] >> sb;
+                            if (I4 && cy == 0)  // escaped count
+                                cy = *(gptr<const uint16_t>)(const uint16_t *)(tbase[wid][k[u]] + 2ull * ((uint64_t)T + p));
+                            atomicAdd(&accy[ent[u] & sidmask], __umul24(tcx[wid][k[u]], cy));
+                        }
                     }
                 }
             }

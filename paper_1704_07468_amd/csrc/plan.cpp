@@ -434,6 +434,7 @@ gakco_status plan_layout(gakco_ctx *ctx, Plan &p)
                 }
                 if (cur.nmask && pl.size + need + nbc * 4 * (1 + kSortClasses) + 4 * kSortCounters + 512 > pool_limit) close();
                 if (ctx->chunk_masks > 0 && cur.nmask >= ctx->chunk_masks) close();
+                if (cur.nmask >= kMaxChunkMasks) close();  // the sort lists' mask field
                 if (!cur.nmask) cur.mfirst = gi;
                 cur.o_mask.push_back(pl.take(mb.size));
                 cur.nmask += 1;

@@ -277,6 +277,23 @@ def test_gram_tuning_invariance(gk):
         c2.close()
 
 
+@pytest.mark.parametrize("bucket_avg", [16, 32])
+def test_gram_many_bucket_bits(bucket_avg):
+    """Partitions into 2^13 and 2^14 buckets per position set (the widest the
+    sort lists encode) give the oracle's integers."""
+    from paper_1704_07468_amd import gakco
+    d = wl.protein(N=600, lmin=300, lmax=500)
+    c2 = gakco.Context(0, tune={"bucket_avg": bucket_avg})
+    try:
+        r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k, want_Cm=True)
+        o = oracle().kernel(d.seqs, d.lens, d.g, d.k)
+        np.testing.assert_array_equal(r["Cm"].cpu().numpy(), o["C"])
+        np.testing.assert_array_equal(r["Nm"].cpu().numpy(), o["Nm"])
+        check_kn(r["K"].cpu().numpy(), o["Kn"])
+    finally:
+        c2.close()
+
+
 @pytest.mark.parametrize("tau", [0, 2, 16, 64])
 def test_gram_dense_path_parity(gk, tau):
     """The int8 matrix-core path (groups with >= tau distinct sequences) gives
@@ -312,6 +329,33 @@ def test_gram_dense_counts_above_int8(gk):
         np.testing.assert_array_equal(r["Cm"].cpu().numpy(), o["C"])
     finally:
         c2.close()
+
+
+def test_gram_run_counts_past_entry_field(gk):
+    """With 2050 sequences the sequence id takes 12 of a 16-bit run entry's
+    bits, leaving 4 for the count: runs of 16 or more equal g-mers (repeated
+    motifs) carry their count in the entries' escape slots, for the tails that
+    gather them and for the run's own diagonal term.  Bit-exact against the
+    oracle, on the sparse path and with every group on the matrix cores."""
+    from paper_1704_07468_amd import gakco
+    rng = np.random.default_rng(17)
+    parts = [rng.integers(0, 20, int(n)).astype(np.int8) for n in rng.integers(12, 30, 2040)]
+    motif = rng.integers(0, 20, 4).astype(np.int8)
+    for r in (5, 20, 40, 80, 150, 300, 33, 17, 64, 100):  # runs of up to ~300 equal g-mers
+        parts.append(np.tile(motif, r))
+    seqs, lens = np.concatenate(parts), np.array([len(p) for p in parts], dtype=np.int32)
+    d = wl.GramInput("motif_runs", seqs, lens, 20, 5, 3)
+    o = oracle().kernel(d.seqs, d.lens, d.g, d.k)
+    for tau in (192, 2):
+        print("tau:", tau, flush=True)
+        c2 = gakco.Context(0, tune={"dense_tau": tau})
+        try:
+            r = c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k, want_Cm=True)
+            np.testing.assert_array_equal(r["Cm"].cpu().numpy(), o["C"])
+            np.testing.assert_array_equal(r["Nm"].cpu().numpy(), o["Nm"])
+            check_kn(r["K"].cpu().numpy(), o["Kn"])
+        finally:
+            c2.close()
 
 
 def test_gram_long_sequence_past_int32_bound(gk):
