@@ -563,7 +563,9 @@ __device__ __forceinline__ void diag_add(gptr<uint32_t> diag, uint32_t nseq, uin
 // count^2 per run to its sequence's diagonal counter.  n = 0 does nothing but
 // takes part in the barriers: every barrier is reached by every wave of the
 // block, whatever its bucket.
-template <bool PK, int NW, int NWORDS, int NSLOT>
+// LP > 0: the sorted elements are keys composite << LP | position in the
+// bucket, the g-mer indices in vb by position.
+template <bool PK, int NW, int NWORDS, int NSLOT, int LP = 0>
 __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint32_t base, uint32_t n, const uint64_t *kb,
                                         const uint32_t *vb, SegLds<NWORDS, NSLOT> &S, int wave, uint32_t *dl,
                                         const uint32_t *diag0)
@@ -587,7 +589,10 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     const gptr<uint32_t> info4 = (gptr<uint32_t>)info, lenx = info4 + T;
     const uint64_t sidmask = bits_mask(sb);
     const int nwords = (int)((n + 63) >> 6);
-    auto comp_at = [&](uint32_t i) -> uint64_t { return PK ? (kb[i] >> 32) : kb[i]; };
+    auto comp_at = [&](uint32_t i) -> uint64_t {
+        if constexpr (LP > 0) return kb[i] >> LP;
+        else return PK ? (kb[i] >> 32) : kb[i];
+    };
 #pragma unroll 1
     for (int w = wave; w < nwords; w += NW) {
         const uint32_t i = (uint32_t)w * 64u + (uint32_t)lane;
@@ -672,7 +677,9 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
         const WordAt u = word_at(S, w);
         uint32_t dv = 0, dq = 0;  // this lane's diagonal term count^2 and its sequence
         if (i < n) {
-            const uint32_t idx = PK ? (uint32_t)kb[i] : vb[i];
+            uint32_t idx;
+            if constexpr (LP > 0) idx = vb[(uint32_t)kb[i] & ((1u << LP) - 1u)];
+            else idx = PK ? (uint32_t)kb[i] : vb[i];
             if (!((u.rb >> lane) & 1ull)) {
                 if (idx < T && !i4) st_u2(info, idx, 0u, 0u);  // (4-byte records start zeroed)
             } else {
@@ -779,6 +786,35 @@ __device__ __forceinline__ void wave_bucket(const MaskWork &W, uint32_t bucket, 
     const uint32_t n = boff[bucket + 1] - base;
     if (n == 0 || n > 64u * EL) return;
     uint32_t *vb = reinterpret_cast<uint32_t *>(lds.kb + WaveLds<BIG>::WIDE);
+    if constexpr (!PK) {
+        // wide composites short enough to share 63 bits with the position in
+        // the bucket: sort those keys on the packed network (one compare, no
+        // index to carry), the g-mer indices wait in LDS by position
+        constexpr int LP = 6 + (EL >= 8 ? 3 : EL >= 4 ? 2 : EL >= 2 ? 1 : 0);
+        if (W.cb + LP <= 63) {
+            const gptr<const uint64_t> comp = glb((const uint64_t *)W.comp);
+            const gptr<const uint32_t> gidx = glb((const uint32_t *)W.idx);
+            const int lane = __lane_id();
+            uint64_t key[EL];
+            uint32_t val[EL];
+#pragma unroll
+            for (int e = 0; e < EL; ++e) {
+                const uint32_t i = (uint32_t)(e * 64 + lane);
+                key[e] = ~0ull;  // padding, above every real key
+                val[e] = 0;
+                if (i < n) {
+                    key[e] = (comp[base + i] << LP) | i;
+                    vb[i] = gidx[base + i];
+                }
+            }
+            bitonic_sort<true, EL, 1>(key, val, nullptr, nullptr, 0);
+            store_sorted<true, EL>(key, val, 0, n, lds.kb, vb);
+            wave_sync();
+            segment<false, 1, WaveLds<BIG>::KB / 64, kWaveSlots, LP>(W, bucket, base, n, lds.kb, vb, lds.S, 0, dl, diag0);
+            wave_sync();
+            return;
+        }
+    }
     {
         uint64_t key[EL];
         uint32_t val[EL];
