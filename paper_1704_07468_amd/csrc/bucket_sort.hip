@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_bucket_scan(const MaskWork *__rest
     if (threadIdx.x < kSortClasses) ccnt[threadIdx.x] = 0;
     if (threadIdx.x < 6) gsum[threadIdx.x] = 0;
     __syncthreads();
-    const bool pk = W.cb <= 32;
+    const bool pk = W.cb + W.ib <= 64;
     for (uint32_t b = threadIdx.x; b < nb; b += kThreads) {
         const uint32_t n = bcnt[b];
         const int c = bucket_class(n, pk);
@@ -140,8 +140,9 @@ __device__ __forceinline__ void lane_pair(uint32_t x, uint32_t &a, uint32_t &b)
 
 // Element order: packed words compare as integers; wide ones by composite,
 // then g-mer index.  Real elements are pairwise distinct (distinct indices)
-// and the padding (all ones, index 0xFFFFFFFF, which no g-mer has) is
-// strictly above them, so one comparison decides a pair.
+// and the padding (all ones: an index field of all ones, or index
+// 0xFFFFFFFF, which no g-mer has) is strictly above them, so one comparison
+// decides a pair.
 template <bool PK>
 __device__ __forceinline__ bool el_less(uint64_t ak, uint32_t av, uint64_t bk, uint32_t bv)
 {
@@ -588,10 +589,12 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
     const int tau = W.tau, inl = W.inl, i4 = W.i4;
     const gptr<uint32_t> info4 = (gptr<uint32_t>)info, lenx = info4 + T;
     const uint64_t sidmask = bits_mask(sb);
+    const int ib = W.ib;
+    const uint64_t ibmask = bits_mask(ib);
     const int nwords = (int)((n + 63) >> 6);
     auto comp_at = [&](uint32_t i) -> uint64_t {
         if constexpr (LP > 0) return kb[i] >> LP;
-        else return PK ? (kb[i] >> 32) : kb[i];
+        else return PK ? (kb[i] >> ib) : kb[i];
     };
 #pragma unroll 1
     for (int w = wave; w < nwords; w += NW) {
@@ -679,7 +682,7 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
         if (i < n) {
             uint32_t idx;
             if constexpr (LP > 0) idx = vb[(uint32_t)kb[i] & ((1u << LP) - 1u)];
-            else idx = PK ? (uint32_t)kb[i] : vb[i];
+            else idx = PK ? (uint32_t)(kb[i] & ibmask) : vb[i];
             if (!((u.rb >> lane) & 1ull)) {
                 if (idx < T && !i4) st_u2(info, idx, 0u, 0u);  // (4-byte records start zeroed)
             } else {
@@ -1034,14 +1037,14 @@ __global__ __launch_bounds__(kThreads) void k_sort_global(const MaskWork *__rest
         const gptr<uint32_t> ix = glb(W.idx), ix2 = glb(W.idx2);
         int which = 0;
         // packed words carry their index: the index arrays ride along unused
-        block_radix_sort<K>(gc + base, ix + base, gc2 + base, ix2 + base, n, W.cb, ss, which, PK ? 32 : 0);
+        block_radix_sort<K>(gc + base, ix + base, gc2 + base, ix2 + base, n, W.cb, ss, which, PK ? W.ib : 0);
         __syncthreads();
         const gptr<K> fk = (which ? gc2 : gc) + base;
         const gptr<uint32_t> fv = (which ? ix2 : ix) + base;
         const gptr<uint32_t> fr = (gptr<uint32_t>)(which ? gc : gc2);
         const gptr<uint32_t> fx = (which ? ix : ix2) + base;
         // scratch: this bucket's slice of the free composite array (2n words)
-        block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket, PK ? 32 : 0);
+        block_segment(fk, fv, n, fr + 2 * (size_t)base, fr + 2 * (size_t)base + n, fx, W, base, ss.wsum, bucket, PK ? W.ib : 0);
         __syncthreads();
     }
 }

@@ -155,13 +155,14 @@ struct MaskWork {
     int32_t hb;  // remaining hash bits, w - B
     int32_t sb;  // sequence-id bits
     int32_t cb;  // composite sort bits, hb + sb
+    int32_t ib;  // index bits of a packed word: ceil(log2(T + 1)), so no index field is all ones
     const uint64_t *key;
     const uint32_t *sid;
     uint32_t *bcnt;   // [2^B]
     uint32_t *boff;   // [2^B + 1]
     uint32_t *bcur;   // [2^B]
-    uint64_t *comp;   // [T] composite (hash rest, sequence) of each bucketed g-mer; when it
-                      // fits 32 bits, packed with its g-mer index: composite << 32 | index
+    uint64_t *comp;   // [T] composite (hash rest, sequence) of each bucketed g-mer; when
+                      // cb + ib <= 64, packed with its g-mer index: composite << ib | index
     uint32_t *idx;    // [T] g-mer index of a wide composite
     uint64_t *comp2;  // [T] ping-pong buffers for buckets sorted in global memory
     uint32_t *idx2;   // [T]
@@ -545,7 +546,9 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
 {
     // cshift = 32: fk holds packed words (composite << 32 | g-mer index)
     auto comp = [&](uint32_t i) -> uint64_t { return (uint64_t)fk[i] >> cshift; };
-    auto gidx = [&](uint32_t i) -> uint32_t { return cshift ? (uint32_t)(uint64_t)fk[i] : (uint32_t)fv[i]; };
+    auto gidx = [&](uint32_t i) -> uint32_t {
+        return cshift ? (uint32_t)((uint64_t)fk[i] & bits_mask(cshift)) : (uint32_t)fv[i];
+    };
     const gptr<uint32_t> E = glb(W.E);
     const gptr<uint2> info = glb(W.info);
     const gptr<int8_t> D = glb(W.D);

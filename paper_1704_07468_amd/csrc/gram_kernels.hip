@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
         if (c) hist[i] = g_atomic_add(glb(W.bcur) + i, c);
     }
     __syncthreads();
-    const bool narrow = W.cb <= 32;
+    const bool narrow = W.cb + W.ib <= 64;
     if (W.i4) {  // the sort stores only nonzero 4-byte records: clear the tile's
         const gptr<uint32_t> info4 = (gptr<uint32_t>)glb(W.info);
 #pragma unroll
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bucket_scatter(const MaskWo
             const uint32_t pos = hist[bk[q]] + rk[q];
             const uint32_t t = t0 + q * kScatterThreads + threadIdx.x;
             if (narrow) {
-                glb(W.comp)[pos] = (cp[q] << 32) | t;
+                glb(W.comp)[pos] = (cp[q] << W.ib) | t;
             } else {
                 glb(W.comp)[pos] = cp[q];
                 glb(W.idx)[pos] = t;

@@ -795,6 +795,7 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
             W.hb = W.w - W.B;
             W.sb = jp.sb;
             W.cb = W.hb + W.sb;
+            W.ib = std::max(1, ceil_log2((uint64_t)jp.T + 1));
             W.key = jp.dev.key;
             W.kshift = jp.dev.kshift;
             W.sid = jp.dev.sid;
@@ -835,9 +836,10 @@ gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st)
         // of a mask fall in the block and global classes
         for (int q = 0; q < c.nmask; ++q) {
             const MaskWork &W = p.mw[(size_t)(c.mfirst + q)];
-            bound_big += W.T / ((W.cb <= 32 ? kSortWaveMaxPk : kSortWaveMaxWide) / 2 + 1);
-            bound_block += W.T / ((W.cb <= 32 ? kSortWaveMaxPk : kSortWaveMaxWide) + 1);
-            if (W.cb <= 32) bound_gpk += W.T / (kSortBlockMaxPk + 1);
+            const bool pk = W.cb + W.ib <= 64;
+            bound_big += W.T / ((pk ? kSortWaveMaxPk : kSortWaveMaxWide) / 2 + 1);
+            bound_block += W.T / ((pk ? kSortWaveMaxPk : kSortWaveMaxWide) + 1);
+            if (pk) bound_gpk += W.T / (kSortBlockMaxPk + 1);
             else bound_gwide += W.T / (kSortBlockMaxWide + 1);
         }
         // one wave per bucket up to 65536 blocks (the class lists put the

@@ -173,8 +173,10 @@ def test_gram_sort_classes_reached():
         # one hot key of a few thousand g-mers per position set: wide buckets of 1024..8192
         seqs_m = np.where(rng.random(int(lens_w.sum())) < 0.7, 0,
                           rng.integers(1, 36, int(lens_w.sum()))).astype(np.int8)
-        for name, (sq, ln, sig, g, k) in {"packed": (seqs, lens, 2, 4, 2), "wide": (seqs_w, lens_w, 36, 8, 6),
-                                          "wide_mid": (seqs_m, lens_w, 36, 8, 6),
+        # g = 10 over 36 symbols: 60-bit keys, composites too wide to pack with
+        # their index for m <= 1
+        for name, (sq, ln, sig, g, k) in {"packed": (seqs, lens, 2, 4, 2), "wide": (seqs_w, lens_w, 36, 10, 8),
+                                          "wide_mid": (seqs_m, lens_w, 36, 10, 8),
                                           "protein": (wl.protein(N=400).seqs, wl.protein(N=400).lens, 20, 7, 4)}.items():
             ctx.profile_reset()
             ctx.gram(sq, ln, sig, g, k)
@@ -187,13 +189,13 @@ def test_gram_sort_classes_reached():
         assert seen["wide_mid"]["block_wide"] > 0
     finally:
         ctx.close()
-    # larger buckets put the 64-bit composites of m=0 into the multi-wave
+    # larger buckets put the wide composites of m=0 into the multi-wave
     # block classes (the results of this geometry are checked in
     # test_gram_tuning_invariance)
     c2 = gakco.Context(0, tune={"bucket_avg": 2000})
     try:
         c2.set_param("profile", 1)
-        d = wl.protein(N=200, lmin=50, lmax=300)
+        d = wl.text(N=60, lmin=300, lmax=500)
         c2.gram(d.seqs, d.lens, d.sigma, d.g, d.k)
         assert c2.stat("sort_gmers_block_wide") > 0
     finally:
@@ -275,6 +277,13 @@ def test_gram_tuning_invariance(gk):
             assert (r["Nm"] == base["Nm"]).all().item()
             assert (r["K"] == base["K"]).all().item()
         c2.close()
+    # wide composites in the block classes (large buckets)
+    t = wl.text(N=60, lmin=300, lmax=500)
+    base = gk.gram(t.seqs, t.lens, t.sigma, t.g, t.k)
+    c2 = gakco.Context(0, tune={"bucket_avg": 2000})
+    r = c2.gram(t.seqs, t.lens, t.sigma, t.g, t.k)
+    assert (r["Nm"] == base["Nm"]).all().item()
+    c2.close()
 
 
 @pytest.mark.parametrize("bucket_avg", [16, 32])
