@@ -395,7 +395,8 @@ __device__ __forceinline__ void accumulate_row(const JobDev *__restrict__ jobs, 
             wave_sync();
             uint64_t st[kAccU];
 #pragma unroll
-            for (int u = 0; u < kAccU; ++u) st[u] = ((uint64_t)mark[wid][2 * u + 1] << 32) | mark[wid][2 * u];
+            for (int u = 0; u < kAccU; ++u) st[u] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)mark[wid][2 * u + 1]) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)mark[wid][2 * u]);  // wave-uniform
             wave_sync();
             if (lane < kAccWindow / 32) mark[wid][lane] = 0;
             // sub-steps past the work are skipped (uniform conditions)

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
 {
     extern __shared__ uint32_t acc[];
     __shared__ uint64_t tbase[kWaves][64];  // per group range: entry address - 4 * its start in the sequence
-    __shared__ uint8_t mark[kWaves][kRowsWindow];  // range starts in the current window (zero between windows)
+    __shared__ uint32_t mark[kWaves][kRowsWindow / 32];  // range starts in the current window, one bit each
     const int per_item = A.nq * A.nslab;
     int idx = (int)(blockIdx.x / per_item);
     const int rem = (int)(blockIdx.x % per_item);
@@ -98,7 +98,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     const int s0 = sl * A.slab, s1 = min(A.nsv, s0 + A.slab);
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     for (int i = tid; i < s1 - s0; i += kThreads) acc[i] = 0;
-    for (int i = lane; i < kRowsWindow; i += 64) mark[wid][i] = 0;
+    if (lane < kRowsWindow / 32) mark[wid][lane] = 0;
+    uint32_t *const accy = acc - s0;  // SV sv at accy[sv]
     __syncthreads();
     const uint32_t t0 = A.qgstart[q];
     const uint32_t ng = A.qgstart[q + 1] - t0;
@@ -151,13 +152,14 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
 #pragma unroll 1
         for (uint32_t w = 0; w < work; w += kRowsWindow) {
             const bool here = len > 0 && start >= w && start < w + kRowsWindow;
-            if (here) mark[wid][start - w] = 1;
+            if (here) atomicOr(&mark[wid][(start - w) >> 5], 1u << ((start - w) & 31u));
             wave_sync_rows();
             uint64_t st[kRowsU];
 #pragma unroll
-            for (int u = 0; u < kRowsU; ++u) st[u] = __ballot(mark[wid][u * 64 + lane] != 0);
+            for (int u = 0; u < kRowsU; ++u) st[u] = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)mark[wid][2 * u + 1]) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)mark[wid][2 * u]);  // wave-uniform
             wave_sync_rows();
-            if (here) mark[wid][start - w] = 0;
+            if (lane < kRowsWindow / 32) mark[wid][lane] = 0;
             // A position past the end (last window only) has k = the last
             // range, so clamping it to work - 1 re-reads that range's last
             // entry: every load is valid and none waits on a branch.
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
 #pragma unroll
             for (int u = 0; u < kRowsU; ++u) {
                 const uint32_t p = w + 64u * u + (uint32_t)lane;
-                if (p < work) atomicAdd(&acc[(ent[u] & sidmask) - (uint32_t)s0], ent[u] >> sb);
+                if (p < work) atomicAdd(&accy[ent[u] & sidmask], ent[u] >> sb);
             }
         }
         wave_sync_rows();
