@@ -61,6 +61,7 @@ PHASE_KERNEL = {
     "sort_wave_big": "k_sort_wave<true>", "sort_block": "k_sort_block", "sort_global": "k_sort_global",
     "accumulate": "k_accumulate", "dense_syrk": "k_dense_syrk", "dense_clear": "k_dense_clear",
     "diag": "k_diag", "finalize": "k_finalize", "direct_count": "k_direct_count", "direct_excess": "k_direct_excess",
+    "rows_qdiag": "k_query_diag",
 }
 
 # headline workloads (--workload); the protein Gram is the measured metric's

@@ -49,6 +49,8 @@ void dense_work_fill(void *dst, int8_t *Dt, const uint32_t *count, uint32_t cap,
 size_t res_mask_size();
 void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, const uint32_t *boff, const uint32_t *bgrp,
                    const uint32_t *E, const uint4 *gtab);
+hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int nq, int nmask, int tbits, const void *rm,
+                             uint32_t *diag, hipStream_t st);
 hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
                        int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
                        unsigned long long *updates, hipStream_t st);

@@ -16,7 +16,7 @@
 // Each phase is one kernel launch (or none) per chunk of a call.
 enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_SORT_WAVE, PH_SORT_WAVE_BIG, PH_SORT_BLOCK,
                PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
-               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_DIRECT, PH_DIRECT_EXCESS, PH_COUNT };
+               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_DIRECT, PH_DIRECT_EXCESS, PH_ROWS_QDIAG, PH_COUNT };
 
 // profiling counter slots: six sort kinds, then the row accumulation's pair
 // updates spread over kProfUpdSlots slots (one per block residue) so that the

@@ -188,6 +188,91 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
     }
 }
 
+// Diagonal counters of the queries: for each query q and position set of
+// level m, the sum over its reduced g-mers u of count_q(u)^2 (the self-pairs
+// of Algorithm 1's countAndUpdate), added into diag[m][q].  One block per
+// (query, group of position sets); per set, a histogram of the query's
+// reduced g-mers in LDS: indexed by the reduced g-mer itself when its width
+// fits the table, else an open-addressing table keyed by its (bijective)
+// hash.  The table has at least twice as many slots as the query has g-mers.
+struct QDiagArgs {
+    const uint64_t *qkey;     // query g-mers, packed
+    const uint32_t *qgstart;  // [nq + 1]
+    int32_t nq, nmask, mpb;   // queries, position sets, sets per block
+    int32_t tbits;            // table slots: 1 << tbits
+    const ResMask *rm;        // the resident set's position sets (level order)
+    uint32_t *diag;           // [M+1][nq], zeroed
+};
+
+__global__ __launch_bounds__(kThreads) void k_query_diag(QDiagArgs A)
+{
+    extern __shared__ uint64_t qtab[];  // [slots] hashed keys, then [slots] counts
+    __shared__ uint32_t wsum[kWaves];
+    const uint32_t slots = 1u << A.tbits;
+    uint64_t *tk = qtab;
+    uint32_t *tc = reinterpret_cast<uint32_t *>(qtab + slots);
+    const int nch = (A.nmask + A.mpb - 1) / A.mpb;
+    const int q = (int)(blockIdx.x / (unsigned)nch), ch = (int)(blockIdx.x % (unsigned)nch);
+    const uint32_t t0 = A.qgstart[q], ng = A.qgstart[q + 1] - t0;
+    if (ng == 0) return;  // no g-mers: nothing to add
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const gptr<const uint64_t> key = glb(A.qkey) + t0;
+    const int s1 = min(A.nmask, (ch + 1) * A.mpb);
+#pragma unroll 1
+    for (int s = ch * A.mpb; s < s1; ++s) {
+        const ResMask &R = A.rm[s];
+        const MaskDesc md = R.md;
+        const int w = R.w;
+        const bool direct = w <= A.tbits;  // reduced g-mers index the table
+        for (uint32_t i = tid; i < slots; i += kThreads) {
+            tc[i] = 0;
+            if (!direct) tk[i] = ~0ull;  // empty (a hash of w < 64 bits is never all ones)
+        }
+        __syncthreads();
+        for (uint32_t t = tid; t < ng; t += kThreads) {
+            const uint64_t rk = compact_key(key[t], md);
+            if (direct) {
+                atomicAdd(&tc[(uint32_t)rk], 1u);
+            } else {
+                const uint64_t h = mix_w(rk, w);
+                uint32_t slot = (uint32_t)h & (slots - 1u);
+                while (true) {  // at most half the slots are taken: a free one is reached
+                    const uint64_t prev = atomicCAS((unsigned long long *)&tk[slot], ~0ull, (unsigned long long)h);
+                    if (prev == ~0ull || prev == h) break;
+                    slot = (slot + 1u) & (slots - 1u);
+                }
+                atomicAdd(&tc[slot], 1u);
+            }
+        }
+        __syncthreads();
+        uint32_t sq = 0;
+        for (uint32_t i = tid; i < slots; i += kThreads) {
+            const uint32_t c = tc[i];
+            sq += c * c;
+        }
+        sq = wave_incl_scan(sq);
+        if (lane == 63) wsum[wid] = sq;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t tot = 0;
+            for (int i = 0; i < kWaves; ++i) tot += wsum[i];
+            if (tot) g_atomic_add(glb(A.diag) + (size_t)md.level * A.nq + q, tot);
+        }
+        __syncthreads();  // the table and the sums are reused by the next set
+    }
+}
+
+hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int nq, int nmask, int tbits, const void *rm,
+                             uint32_t *diag, hipStream_t st)
+{
+    if (nq <= 0 || nmask <= 0) return hipSuccess;
+    constexpr int mpb = 4;
+    QDiagArgs a{qkey, qgstart, nq, nmask, mpb, tbits, reinterpret_cast<const ResMask *>(rm), diag};
+    const unsigned nb = (unsigned)((size_t)nq * (size_t)((nmask + mpb - 1) / mpb));
+    hipLaunchKernelGGL(k_query_diag, dim3(nb), dim3(kThreads), (size_t)12u << tbits, st, a);
+    return hipGetLastError();
+}
+
 // K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.  The
 // per-level values of up to MM levels stay in registers.
 template <int MM>

@@ -125,6 +125,15 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     else GK_TRY(fetch_lens(jp, st));
     GK_TRY(plan_shape(ctx, jp, nullptr, 0));
     GK_TRY(check_query_bounds(R, jp.maxng));
+    // The queries' diagonal counters come from per-query LDS histograms when
+    // a query's g-mers fit a table of at most 4096 slots (twice as many as
+    // g-mers) and no reduced g-mer is 64 bits wide; the plan then only
+    // validates and extracts.  Otherwise the bucket sort of the queries'
+    // g-mers sums them.
+    int qd_bits = 8;
+    while ((1u << qd_bits) < 2u * jp.maxng) ++qd_bits;
+    const bool qdiag = qd_bits <= 12 && R->g * R->b < 64;
+    if (qdiag) jp.masks.clear();
     const int M1 = R->M + 1;
     Layout l;
     const size_t o_diag = l.take((size_t)M1 * n_q * 4);
@@ -140,6 +149,9 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     GK_TRY(plan_upload(p, st));
     GK_HIP(launch_fill_u32(diag, (size_t)M1 * n_q, 0u, st));
     GK_TRY(plan_launch(ctx, p, st));
+    int nitems = 0;
+    for (int m = 0; m <= R->M; ++m) nitems += (int)binom64(R->g, m);
+    if (qdiag) GK_PHASE(PH_ROWS_QDIAG, launch_query_diag(jp.dev.key, jp.dev.gstart, n_q, nitems, qd_bits, R->rm, diag, st));
     int64_t *Kq = reinterpret_cast<int64_t *>(scr + o_kq);
     uint32_t *C = reinterpret_cast<uint32_t *>(scr + o_C);
     GK_PHASE(PH_ROWS_KDIAG, launch_kdiag_counts(diag, n_q, R->M, R->coef, R->hco, Kq, st));
@@ -153,8 +165,6 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     const size_t third = (R->n_sv + 2) / 3;
     const int slab = (int)std::min<size_t>((size_t)R->n_sv, std::min<size_t>(8192, std::max<size_t>(4096, third)));
     const int mchunk = 1;
-    int nitems = 0;
-    for (int m = 0; m <= R->M; ++m) nitems += (int)binom64(R->g, m);
     GK_HIP(launch_fill_u32(C, (size_t)M1 * n_q * R->n_sv, 0u, st));
     unsigned long long *upd = ctx->prof_on && ctx->prof_stat ? ctx->prof_stat + kProfRowsFirst : nullptr;
     GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,

@@ -46,6 +46,34 @@ def test_rows_match_oracle(gk):
         res.close()
 
 
+@pytest.mark.parametrize("case", ["histogram", "long_query_sorted"])
+def test_rows_query_diagonal_paths(gk, case):
+    """The queries' self-kernel K(q,q) (through the cosine normalisation of
+    their rows): per-query LDS histograms for queries of up to 2048 g-mers
+    (with a constant query, a query shorter than g and ordinary ones), the
+    bucket sort of the queries' g-mers for a longer query."""
+    from oracle import oracle as orc
+    s, res = small_resident(gk, seed=3)
+    try:
+        rng = np.random.default_rng(5)
+        if case == "histogram":
+            parts = [np.zeros(500, np.int8), rng.integers(0, 4, 300).astype(np.int8),
+                     rng.integers(0, 4, 7).astype(np.int8), np.tile(rng.integers(0, 4, 3).astype(np.int8), 200)]
+        else:
+            parts = [rng.integers(0, 4, 2600).astype(np.int8), np.zeros(40, np.int8)]
+        q_seqs = np.concatenate(parts)
+        q_lens = np.array([len(x) for x in parts], dtype=np.int32)
+        r = res.rows(q_seqs, q_lens, want_nm=True)
+        o = orc.rows(s.sv.seqs, s.sv.lens, q_seqs, q_lens, s.sv.g, s.sv.k, alpha=s.alpha, bias=0.3)
+        np.testing.assert_array_equal(r["Nm"].cpu().numpy(), o["Nm"])
+        K = r["K"].cpu().numpy()
+        assert (K[o["Krows"] == 0] == 0).all()
+        nz = o["Krows"] != 0
+        np.testing.assert_allclose(K[nz], o["Krows"][nz], rtol=1e-12, atol=0)
+    finally:
+        res.close()
+
+
 def test_rows_protein_resident(gk):
     """A protein resident set (5-bit symbols, skewed composition)."""
     from oracle import oracle as orc
