@@ -61,7 +61,7 @@ PHASE_KERNEL = {
     "sort_wave_big": "k_sort_wave<true>", "sort_block": "k_sort_block", "sort_global": "k_sort_global",
     "accumulate": "k_accumulate", "dense_syrk": "k_dense_syrk", "dense_clear": "k_dense_clear",
     "diag": "k_diag", "finalize": "k_finalize", "direct_count": "k_direct_count", "direct_excess": "k_direct_excess",
-    "rows_qdiag": "k_query_diag",
+    "rows_qdiag": "k_query_diag", "rows_count": "k_count_rows", "rows_gemm": "k_rows_gemm",
 }
 
 # headline workloads (--workload); the protein Gram is the measured metric's
@@ -279,6 +279,7 @@ def serving_leg(gakco, wl, n_q, lds_peak):
         upd = ctx.stat("rows_updates") / reps
         ctx.set_param("profile", 0)
         rk_ms = prof["rows"][0] / max(1, prof["rows"][1])
+        gm = prof.get("rows_gemm", (0.0, 0))
         rate = upd / (rk_ms / 1e3)
         # bytes the row kernel must move: every gathered (sequence, count)
         # entry (4 B), a 16-byte group lookup per (position set, query g-mer),
@@ -294,6 +295,19 @@ def serving_leg(gakco, wl, n_q, lds_peak):
                                       "achieved": round(rbytes / (rk_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                                       "unit": "GB/s", "frac": round(rbytes / (rk_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
                               "peak_source": "k_lds_atomic_probe: random adds into a 4096-word LDS row"}
+        if gm[1]:
+            # the top level as an int8 product: 2 ops per (query, resident
+            # sequence, count column) of the padded 256-query tile
+            M_ = s.sv.g - s.sv.k
+            b_ = max(1, math.ceil(math.log2(s.sv.sigma)))
+            cols = math.comb(s.sv.g, M_) * (1 << ((s.sv.g - M_) * b_))
+            g_ms = gm[0] / gm[1]
+            ops = 2.0 * 256 * n_sv * cols
+            out["dense_level_joined"] = {"kernel": "k_rows_gemm", "level": M_, "count_columns": cols,
+                                         "mean_launch_ms": round(g_ms, 4),
+                                         "achieved": round(ops / (g_ms / 1e3) / 1e12, 1), "peak": 5000.0,
+                                         "unit": "TOP/s (int8)", "frac": round(ops / (g_ms / 1e3) / 5e15, 4),
+                                         "count_rows_ms": round(prof.get("rows_count", (0.0, 1))[0] / max(1, prof.get("rows_count", (0.0, 1))[1]), 4)}
         srv = gakco.Server(res, max_batch=256, n_streams=2)
         try:
             meas = queries[n_warm:]
@@ -321,6 +335,36 @@ def serving_leg(gakco, wl, n_q, lds_peak):
                 note("serving: %d%% of saturation, %d queries in %.2f s" % (round(100 * frac), n_q, wall))
         finally:
             srv.close()
+        # reference: the same server with the top level always on the sparse
+        # walk (small batches are as efficient as large ones there, so its
+        # latency stays low up to its lower saturation)
+        if out.get("dense_level_joined"):
+            ctx0 = gakco.Context(0, tune={"rows_dense": 0})
+            res0 = gakco.Resident(ctx0, s.sv.seqs, s.sv.lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias)
+            srv0 = gakco.Server(res0, max_batch=256, n_streams=2)
+            try:
+                meas = queries[n_warm:]
+                tags = list(range(n_q))
+                _drive(srv0, queries[:n_warm], [10 ** 6 + i for i in range(n_warm)], None)
+                done, wall = _drive(srv0, meas, tags, None)
+                sat0 = n_q / wall
+                ref = {"server_saturation_qps": sat0}
+                for frac in (0.9,):
+                    arr = wl.poisson_arrivals(n_warm + n_q, frac * sat0, seed=wl.SEED_BASE + 6 + int(frac * 10))
+                    alltags = [2 * 10 ** 6 + i for i in range(n_warm)] + tags
+                    done, wall = _drive(srv0, queries[:n_warm] + meas, alltags, arr)
+                    lat_s = [done[t]["t_done"] - done[t]["t_submit"] for t in tags]
+                    ref["load_%d%%" % round(100 * frac)] = {
+                        "offered_qps": frac * sat0, "p50_ms": 1e3 * float(np.percentile(lat_s, 50)),
+                        "p99_ms": 1e3 * float(np.percentile(lat_s, 99)),
+                        "mean_batch": float(np.mean([done[t]["batch_size"] for t in tags])),
+                        "all_ok": all(done[t]["status"] == 0 for t in tags)}
+                out["sparse_walk_only"] = ref
+                note("serving: sparse-walk-only server saturates at %.0f queries/s" % sat0)
+            finally:
+                srv0.close()
+                res0.close()
+                ctx0.close()
         return out
     finally:
         res.close()

@@ -87,6 +87,18 @@ const char *gakco_version(void);
  *   "acc_mstep"     cap on the position sets the row accumulation sums in
  *                   its 32-bit LDS row before adding it into C_m (0, the
  *                   default: as many as the count bound allows), for tests
+ *   "rows_slabs"    slabs of the resident set per block of the serving rows
+ *                   kernel (0, the default: two halves of at most 16384
+ *                   sequences each, at least 4096); 1..64, for tuning
+ *   "rows_dense"    1 (default): a resident set's top level whose reduced
+ *                   g-mers take at most 12 bits is joined as an int8
+ *                   product of count rows (query batch x resident set)
+ *                   instead of the sparse walk, when the resident set has
+ *                   at least "rows_dense_min_sv" sequences (default 2048)
+ *                   and no count above 127 at that level, for batches of at
+ *                   least "rows_dense_min_q" queries (default 72); the
+ *                   resident count rows take n_sv * C(g, M) * 2^w bytes of
+ *                   device memory; 0 = always the sparse walk
  *   "tau_b<B>_g<G>" dense_tau for jobs with B-bit symbols and this g (as
  *                   written by gakco_autotune)
  * Missing keys keep their defaults.  Not thread-safe: one context per host

@@ -58,6 +58,18 @@ static gakco_status apply_param(gakco_ctx *ctx, const char *name, int64_t v)
     } else if (!strcmp(name, "bucket_avg")) {
         if (v < 16 || v > 4096) { set_error("bucket_avg must be in 16..4096"); return GAKCO_EINVAL; }
         ctx->bucket_avg = (int)v;
+    } else if (!strcmp(name, "rows_dense")) {
+        if (v < 0 || v > 1) { set_error("rows_dense must be 0 or 1"); return GAKCO_EINVAL; }
+        ctx->rows_dense = (int)v;
+    } else if (!strcmp(name, "rows_dense_min_sv")) {
+        if (v < 1 || v > (1 << 24)) { set_error("rows_dense_min_sv must be in 1..2^24"); return GAKCO_EINVAL; }
+        ctx->rows_dense_min_sv = (int)v;
+    } else if (!strcmp(name, "rows_dense_min_q")) {
+        if (v < 1 || v > (1 << 24)) { set_error("rows_dense_min_q must be in 1..2^24"); return GAKCO_EINVAL; }
+        ctx->rows_dense_min_q = (int)v;
+    } else if (!strcmp(name, "rows_slabs")) {
+        if (v < 0 || v > 64) { set_error("rows_slabs must be in 0..64"); return GAKCO_EINVAL; }
+        ctx->rows_slabs = (int)v;
     } else if (!strcmp(name, "acc_mstep")) {
         if (v < 0 || v > (1 << 20)) { set_error("acc_mstep must be in 0..1048576"); return GAKCO_EINVAL; }
         ctx->acc_mstep = (int)v;

@@ -51,9 +51,15 @@ void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, 
                    const uint32_t *E, const uint4 *gtab);
 hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int nq, int nmask, int tbits, const void *rm,
                              uint32_t *diag, hipStream_t st);
+hipError_t launch_count_rows(const uint64_t *key, const uint32_t *gstart, int nseq, const void *rm, int nset, int w,
+                             int8_t *out, size_t stride, uint32_t *flag, hipStream_t st);
+hipError_t launch_rows_gemm(const int8_t *Q, const int8_t *D, size_t stride, int nq, int nsv, int S, const uint32_t *qflag,
+                            uint32_t *C, hipStream_t st);
+int rows_gemm_tile_q();
+int rows_gemm_tile_sv();
 hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
                        int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
-                       unsigned long long *updates, hipStream_t st);
+                       unsigned long long *updates, int dense_level, const uint32_t *qflag, hipStream_t st);
 hipError_t launch_kdiag_counts(const uint32_t *diag, int n, int M, const int64_t *coef, const int64_t *hco, int64_t *Kd,
                                hipStream_t st);
 hipError_t launch_rows_finalize(const uint32_t *C, int nq, int nsv, int M, const int64_t *coef, const int64_t *hco,

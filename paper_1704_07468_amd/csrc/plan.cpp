@@ -894,7 +894,8 @@ static const char *kPhaseNames[PH_COUNT] = {"fill", "validate", "extract", "buck
                                             "bucket_scatter", "sort_wave", "sort_wave_big", "sort_block", "sort_global",
                                             "accumulate", "dense_syrk", "dense_clear",
                                             "diag", "finalize", "rows_kdiag", "rows", "rows_finalize",
-                                            "direct_count", "direct_excess", "rows_qdiag"};
+                                            "direct_count", "direct_excess", "rows_qdiag", "rows_count",
+                                            "rows_gemm"};
 const char *phase_name(int phase) { return (phase >= 0 && phase < PH_COUNT) ? kPhaseNames[phase] : ""; }
 
 gakco_status prof_begin(gakco_ctx *ctx, hipStream_t st, size_t *slot)

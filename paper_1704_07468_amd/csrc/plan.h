@@ -16,7 +16,8 @@
 // Each phase is one kernel launch (or none) per chunk of a call.
 enum GkPhase { PH_FILL, PH_VALIDATE, PH_EXTRACT, PH_BCOUNT, PH_BSCAN, PH_BSCATTER, PH_SORT_WAVE, PH_SORT_WAVE_BIG, PH_SORT_BLOCK,
                PH_SORT_GLOBAL, PH_ACCUM, PH_DENSE_SYRK, PH_DENSE_CLEAR, PH_DIAG, PH_FINALIZE,
-               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_DIRECT, PH_DIRECT_EXCESS, PH_ROWS_QDIAG, PH_COUNT };
+               PH_ROWS_KDIAG, PH_ROWS, PH_ROWS_FINALIZE, PH_DIRECT, PH_DIRECT_EXCESS, PH_ROWS_QDIAG,
+               PH_ROWS_COUNT, PH_ROWS_GEMM, PH_COUNT };
 
 // profiling counter slots: six sort kinds, then the row accumulation's pair
 // updates spread over kProfUpdSlots slots (one per block residue) so that the
@@ -34,6 +35,10 @@ struct gakco_ctx {
     int bucket_avg = 512;    // target g-mers per hash bucket
     int acc_slab = 0;        // columns per row-accumulation block (0: as many as the LDS holds)
     int acc_mstep = 0;       // cap on position sets per flush of the row accumulation (0: the count bound only)
+    int rows_slabs = 0;      // resident slabs of the serving rows kernel (0: halves of 4096..16384 sequences)
+    int rows_dense = 1;      // 1: join the resident set's top level on the matrix cores when it qualifies
+    int rows_dense_min_sv = 2048;  // ... for resident sets of at least this many sequences
+    int rows_dense_min_q = 72;     // ... and query batches of at least this many queries
     int direct_mode = 1;     // direct-address levels: 0 off, 1 where the cost model prefers them, 2 wherever possible
     uint32_t excess_cap = 0; // cap on the clipped-count list (0: kExcessCap), for tests
     int chunk_masks = 0;     // cap on position sets per chunk (0: as many as the pool holds)

@@ -33,6 +33,8 @@ struct RowsArgs {
     const int32_t *lev_count;
     uint32_t *C;               // [M+1][nq][nsv], zeroed; blocks add their partial rows
     unsigned long long *updates;  // nullable (profiling): pair updates, spread over 256 slots
+    int32_t dense_level;       // level joined on the matrix cores (-1: none) ...
+    const uint32_t *qflag;     // ... except for the queries flagged here
 };
 
 __device__ __forceinline__ void wave_sync_rows()
@@ -95,6 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_rows_accumulate(RowsArgs A)
         idx -= nch;
     }
     if (mc <= 0) return;
+    if (level == A.dense_level && !A.qflag[q]) return;  // on the matrix cores
     const int s0 = sl * A.slab, s1 = min(A.nsv, s0 + A.slab);
     const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
     for (int i = tid; i < s1 - s0; i += kThreads) acc[i] = 0;
@@ -273,6 +276,205 @@ hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------ dense top level --
+// A level whose reduced g-mers index at most 4096 values per position set can
+// be joined on the matrix cores instead: count rows Q (queries) and D
+// (resident sequences), one column per (position set, reduced g-mer) of the
+// level, int8 counts; the level's C rows are Q D^T (the same sum over groups
+// of count_q * count_sv as Algorithm 1's countAndUpdate).  A count above 127
+// is clipped and flags its sequence: a flagged resident set does not use this
+// path, a flagged query takes the level through the sparse walk instead.
+
+// One block per (sequence, 8 position sets of the level): an LDS histogram of
+// the sequence's reduced g-mers per set, written as its 2^w-byte segment of
+// the count row (16-byte stores).
+constexpr int kCountRowSets = 8;
+__global__ __launch_bounds__(kThreads) void k_count_rows(const uint64_t *__restrict__ key,
+                                                         const uint32_t *__restrict__ gstart, int nseq,
+                                                         const ResMask *__restrict__ rm, int nset, int w,
+                                                         int8_t *__restrict__ out, size_t stride,
+                                                         uint32_t *__restrict__ flag)
+{
+    extern __shared__ uint32_t hist[];
+    const uint32_t bins = 1u << w;
+    const int nch = (nset + kCountRowSets - 1) / kCountRowSets;
+    const int x = (int)(blockIdx.x / (unsigned)nch), ch = (int)(blockIdx.x % (unsigned)nch);
+    const uint32_t t0 = gstart[x], t1 = gstart[x + 1];
+    const int tid = threadIdx.x;
+    const gptr<const uint64_t> gk = glb(key);
+    bool over = false;
+    const int s1 = min(nset, (ch + 1) * kCountRowSets);
+#pragma unroll 1
+    for (int s = ch * kCountRowSets; s < s1; ++s) {
+        const MaskDesc md = rm[s].md;
+        for (uint32_t i = tid; i < bins; i += kThreads) hist[i] = 0;
+        __syncthreads();
+        for (uint32_t t = t0 + tid; t < t1; t += kThreads) atomicAdd(&hist[(uint32_t)compact_key(gk[t], md)], 1u);
+        __syncthreads();
+        const gptr<int8_t> row = glb(out) + (size_t)x * stride + (size_t)s * bins;
+        for (uint32_t i = (uint32_t)tid * 16u; i < bins; i += kThreads * 16u) {
+            uint32_t wv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    uint32_t c = hist[i + (uint32_t)(q * 4 + b)];
+                    if (c > 127u) {
+                        c = 127u;
+                        over = true;
+                    }
+                    v |= c << (8 * b);
+                }
+                wv[q] = v;
+            }
+            *(gptr<u32x4>)(row + i) = u32x4{wv[0], wv[1], wv[2], wv[3]};
+        }
+        __syncthreads();  // the histogram is reused by the next set
+    }
+    if (over) atomicOr(flag + x, 1u);
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+constexpr int kGemmBM = 256;  // queries per block (every query of a 256-batch)
+constexpr int kGemmBN = 128;  // resident sequences per block
+constexpr int kGemmBK = 64;   // count columns per step
+constexpr int kGemmRow = kGemmBK + 16;  // padded LDS row (80 bytes: 16-byte reads without conflicts)
+constexpr int kGemmNT = kGemmBN / 32;   // MFMA column tiles per wave
+
+struct RowsGemmArgs {
+    const int8_t *Q;         // [nq_pad][stride] query count rows
+    const int8_t *D;         // [nsv_pad][stride] resident count rows
+    size_t stride;           // bytes per row (a multiple of kGemmBK)
+    int32_t nq, nsv;         // real rows
+    int32_t ntq, ntsv, S;    // query tiles, sequence tiles, column splits
+    const uint32_t *qflag;   // [nq] 1: the query takes the sparse walk for this level
+    uint32_t *C;             // [nq][nsv] the level's C rows (added to)
+};
+
+// v_mfma_i32_32x32x32_i8 layout as in the Gram products: lane l supplies row
+// (l % 32) and 16 consecutive columns from 16 * (l / 32); accumulator v of
+// lane l is element (8 (v / 4) + 4 (l / 32) + v % 4, l % 32).  One block =
+// 256 queries x 128 resident sequences x one split of the columns; blocks
+// are ordered split-major so that the blocks running together share the
+// query slab in L2 while every resident row is streamed from HBM once per
+// query tile.  Wave w computes queries [64 w, 64 w + 64) as 2 x 4 MFMA
+// tiles; slabs are double-buffered through LDS with 16-byte loads, two
+// steps in flight.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_gemm(RowsGemmArgs A)
+{
+    __shared__ __attribute__((aligned(16))) int8_t sA[2][kGemmBM][kGemmRow];
+    __shared__ __attribute__((aligned(16))) int8_t sB[2][kGemmBN][kGemmRow];
+    const int per_split = A.ntq * A.ntsv;
+    const int sp = (int)blockIdx.x / per_split;
+    const int rem = (int)blockIdx.x - sp * per_split;
+    const int I = rem / A.ntsv, J = rem - I * A.ntsv;
+    // this split's columns [c0, c1), whole steps
+    const size_t nsteps = A.stride / kGemmBK;
+    const size_t per = (nsteps + A.S - 1) / A.S;
+    const size_t c0 = (size_t)sp * per * kGemmBK, c1 = min(A.stride, c0 + per * kGemmBK);
+    if (c0 >= c1) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = tid >> 2, lc = (tid & 3) * 16;  // staging: rows lr + 64 j, 16-byte column lc
+    const gptr<const int8_t> ga = glb(A.Q) + (size_t)(I * kGemmBM + lr) * A.stride + lc;
+    const gptr<const int8_t> gb = glb(A.D) + (size_t)(J * kGemmBN + lr) * A.stride + lc;
+    const size_t s64 = (size_t)64 * A.stride;
+    struct Slab {
+        v4i a[kGemmBM / 64], b[kGemmBN / 64];
+    };
+    auto gload = [&](size_t c, Slab &x) {
+#pragma unroll
+        for (int j = 0; j < kGemmBM / 64; ++j) x.a[j] = *(gptr<const v4i>)(ga + (size_t)j * s64 + c);
+#pragma unroll
+        for (int j = 0; j < kGemmBN / 64; ++j) x.b[j] = *(gptr<const v4i>)(gb + (size_t)j * s64 + c);
+    };
+    auto lstore = [&](int buf, const Slab &x) {
+#pragma unroll
+        for (int j = 0; j < kGemmBM / 64; ++j) *reinterpret_cast<v4i *>(&sA[buf][lr + 64 * j][lc]) = x.a[j];
+#pragma unroll
+        for (int j = 0; j < kGemmBN / 64; ++j) *reinterpret_cast<v4i *>(&sB[buf][lr + 64 * j][lc]) = x.b[j];
+    };
+    v16i acc[2][kGemmNT];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < kGemmNT; ++j) acc[i][j] = v16i{};
+    const int fr = lane & 31, fk = 16 * (lane >> 5);
+    auto compute = [&](int buf) {
+#pragma unroll
+        for (int kk = 0; kk < kGemmBK; kk += 32) {
+            v4i a[2], b[kGemmNT];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v4i *>(&sA[buf][wave * 64 + 32 * i + fr][kk + fk]);
+#pragma unroll
+            for (int j = 0; j < kGemmNT; ++j) b[j] = *reinterpret_cast<const v4i *>(&sB[buf][32 * j + fr][kk + fk]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < kGemmNT; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    // loads past the split's last step re-read that step (never outside the rows)
+    const size_t last = c1 - kGemmBK;
+    Slab x0, x1;
+    gload(c0, x0);
+    gload(min(c0 + kGemmBK, last), x1);
+    lstore(0, x0);
+    __syncthreads();
+    auto step = [&](size_t c, int buf, Slab &ld, const Slab &st) {
+        gload(min(c + 2 * kGemmBK, last), ld);
+        compute(buf);
+        lstore(buf ^ 1, st);
+        __syncthreads();
+    };
+    size_t c = c0;
+#pragma unroll 1
+    while (true) {
+        step(c, 0, x0, x1);
+        c += kGemmBK;
+        if (c >= c1) break;
+        step(c, 1, x1, x0);
+        c += kGemmBK;
+        if (c >= c1) break;
+    }
+    const gptr<uint32_t> C = glb(A.C);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < kGemmNT; ++j) {
+            const int sv = J * kGemmBN + 32 * j + (lane & 31);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int q = I * kGemmBM + wave * 64 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (q < A.nq && sv < A.nsv && acc[i][j][v] != 0 && !A.qflag[q])
+                    g_atomic_add(C + (size_t)q * A.nsv + sv, (uint32_t)acc[i][j][v]);
+            }
+        }
+}
+
+hipError_t launch_count_rows(const uint64_t *key, const uint32_t *gstart, int nseq, const void *rm, int nset, int w,
+                             int8_t *out, size_t stride, uint32_t *flag, hipStream_t st)
+{
+    if (nseq <= 0 || nset <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((size_t)nseq * (size_t)((nset + kCountRowSets - 1) / kCountRowSets));
+    hipLaunchKernelGGL(k_count_rows, dim3(nb), dim3(kThreads), (size_t)4u << w, st, key, gstart, nseq,
+                       reinterpret_cast<const ResMask *>(rm), nset, w, out, stride, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_gemm(const int8_t *Q, const int8_t *D, size_t stride, int nq, int nsv, int S, const uint32_t *qflag,
+                            uint32_t *C, hipStream_t st)
+{
+    if (nq <= 0 || nsv <= 0) return hipSuccess;
+    RowsGemmArgs a{Q, D, stride, nq, nsv, (nq + kGemmBM - 1) / kGemmBM, (nsv + kGemmBN - 1) / kGemmBN, S, qflag, C};
+    const unsigned nb = (unsigned)((size_t)a.ntq * a.ntsv * S);
+    hipLaunchKernelGGL(k_rows_gemm, dim3(nb), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+}
+int rows_gemm_tile_q() { return kGemmBM; }
+int rows_gemm_tile_sv() { return kGemmBN; }
+
 // K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.  The
 // per-level values of up to MM levels stay in registers.
 template <int MM>
@@ -382,11 +584,11 @@ void res_mask_fill(void *dst, const MaskDesc &md, int w, int B, int hb, int sb, 
 
 hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
                        int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,
-                       unsigned long long *updates, hipStream_t st)
+                       unsigned long long *updates, int dense_level, const uint32_t *qflag, hipStream_t st)
 {
     if (nq <= 0) return hipSuccess;
     RowsArgs a{qkey, qgstart, nq, M, nsv, slab, (nsv + slab - 1) / slab, mchunk, reinterpret_cast<const ResMask *>(rm),
-               lev_first, lev_count, C, updates};
+               lev_first, lev_count, C, updates, dense_level, qflag};
     const unsigned nb = (unsigned)((size_t)nq * nitems * a.nslab);
     hipLaunchKernelGGL(k_rows_accumulate, dim3(nb), dim3(kThreads), (size_t)slab * 4, st, a);
     return hipGetLastError();

@@ -43,6 +43,13 @@ struct gakco_resident {
     const int64_t *Kd = nullptr;
     const double *alpha = nullptr;
     double bias = 0.0;
+    // the top level joined on the matrix cores (dense_level < 0: none):
+    // count rows [nsv_pad][dense_stride], one 2^dense_w-byte segment per
+    // position set of the level (descriptors at dense_rm)
+    int dense_level = -1, dense_w = 0, dense_nset = 0;
+    size_t dense_stride = 0;
+    const void *dense_rm = nullptr;
+    int8_t *D = nullptr;
 };
 
 static double now_s()
@@ -111,6 +118,10 @@ static gakco_status check_query_bounds(const gakco_resident *R, uint64_t ng_q)
 // Rows of n_q queries (device symbols and lengths; host lengths when known)
 // against a resident set, on stream st; synchronises st before returning.
 // K_rows has row stride ldk (0: n_sv).
+namespace gk {
+hipError_t init_rows_attributes(size_t lds);
+}
+
 gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t *q_seqs, const int32_t *q_lens,
                           const int32_t *q_lens_host, int32_t n_q, double *K_rows, int64_t ldk, int64_t *Nm_rows,
                           double *decision, hipStream_t st)
@@ -140,6 +151,13 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     const size_t o_kq = l.take((size_t)n_q * 8);
     const size_t o_C = l.take((size_t)M1 * n_q * R->n_sv * 4);
     const size_t o_part = l.take(rows_partial_count(n_q, R->n_sv) * 8);
+    // a batch large enough joins the dense top level on the matrix cores:
+    // the queries' count rows (padded to the product's query tile) and their
+    // clipping flags
+    const bool dense = R->D && n_q >= ctx->rows_dense_min_q;
+    const size_t tq = (size_t)rows_gemm_tile_q();
+    const size_t o_Q = dense ? l.take(((size_t)n_q + tq - 1) / tq * tq * R->dense_stride) : 0;
+    const size_t o_qf = dense ? l.take((size_t)n_q * 4) : 0;
     char *scr = nullptr;
     GK_TRY(rows_scratch(ctx, l.size, &scr));
     uint32_t *diag = reinterpret_cast<uint32_t *>(scr + o_diag);
@@ -158,17 +176,36 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     // grid: (level, position set) x query x SV slab, so that even one query
     // spreads over the whole device; one set per block measured faster at
     // every batch size (1..160 queries) than chunks of several sets, whose
-    // partial rows are fewer but whose blocks run longer.  Slabs of about a
-    // third of the SVs (4096..8192 of them: a 16..32 KB LDS row): an inner
-    // slab binary-searches its two edges in a group's entries, an outer one
-    // only one, and three slabs measured best for 20000 SVs
-    const size_t third = (R->n_sv + 2) / 3;
-    const int slab = (int)std::min<size_t>((size_t)R->n_sv, std::min<size_t>(8192, std::max<size_t>(4096, third)));
+    // partial rows are fewer but whose blocks run longer.  Slabs of about
+    // half the SVs (4096..16384 of them: a 16..64 KB LDS row): every slab
+    // repeats the group lookups of its query's g-mers and cuts each group at
+    // its edges, so fewer slabs save lookups until the LDS row limits the
+    // blocks per CU; for 20000 SVs two slabs measured 30.4 ms per 256-query
+    // batch, three 32.3, four 35.7, one 80.4
+    const size_t half = (R->n_sv + 1) / 2;
+    int slab = (int)std::min<size_t>((size_t)R->n_sv, std::min<size_t>(16384, std::max<size_t>(4096, half)));
+    if (ctx->rows_slabs > 0) slab = (int)std::max<size_t>(64, ((size_t)R->n_sv + ctx->rows_slabs - 1) / ctx->rows_slabs);
+    if ((size_t)slab * 4 > ctx->lds_max) { set_error("SV slab of %d exceeds the LDS", slab); return GAKCO_EUNSUPPORTED; }
+    if ((size_t)slab * 4 > 32768) GK_HIP(init_rows_attributes(ctx->lds_max));  // rows beyond the default LDS limit
     const int mchunk = 1;
     GK_HIP(launch_fill_u32(C, (size_t)M1 * n_q * R->n_sv, 0u, st));
+    int8_t *Q = dense ? reinterpret_cast<int8_t *>(scr + o_Q) : nullptr;
+    uint32_t *qflag = dense ? reinterpret_cast<uint32_t *>(scr + o_qf) : nullptr;
+    if (dense) {
+        GK_HIP(launch_fill_u32(qflag, (size_t)n_q, 0u, st));
+        GK_PHASE(PH_ROWS_COUNT, launch_count_rows(jp.dev.key, jp.dev.gstart, n_q, R->dense_rm, R->dense_nset, R->dense_w, Q,
+                                                  R->dense_stride, qflag, st));
+    }
     unsigned long long *upd = ctx->prof_on && ctx->prof_stat ? ctx->prof_stat + kProfRowsFirst : nullptr;
     GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,
-                                  R->lev_count, C, upd, st));
+                                  R->lev_count, C, upd, dense ? R->dense_level : -1, qflag, st));
+    if (dense) {
+        // column splits so that the product has about six blocks per CU (two rounds)
+        const size_t tiles = (((size_t)n_q + tq - 1) / tq) * (((size_t)R->n_sv + rows_gemm_tile_sv() - 1) / rows_gemm_tile_sv());
+        const int S = (int)std::max<size_t>(1, std::min<size_t>(R->dense_stride / 64, (1536 + tiles - 1) / tiles));
+        GK_PHASE(PH_ROWS_GEMM, launch_rows_gemm(Q, R->D, R->dense_stride, n_q, R->n_sv, S, qflag,
+                                                C + (size_t)R->dense_level * n_q * R->n_sv, st));
+    }
     GK_PHASE(PH_ROWS_FINALIZE, launch_rows_finalize(C, n_q, R->n_sv, R->M, R->coef, R->hco, R->Kd, Kq, R->alpha, R->bias, K_rows,
                                            ldk, Nm_rows, decision,
                                                            reinterpret_cast<double *>(scr + o_part), st));
@@ -481,7 +518,54 @@ gakco_status gakco_resident_create(gakco_ctx *ctx, const int8_t *seqs, const int
         set_error("self-kernel launch failed");
         return fail(GAKCO_EHIP);
     }
-    if ((s = plan_check_errors(ctx, p, st)) != GAKCO_OK) return fail(s);
+    // The top level on the matrix cores when its reduced g-mers index at
+    // most 4096 values per position set and the set is large enough: the
+    // resident count rows, kept unless some count exceeds 127.
+    const int L = jp.M, wL = (g - L) * jp.b;
+    uint32_t *dflag = nullptr;
+    if (ctx->rows_dense && wL >= 6 && wL <= 12 && n_sv >= ctx->rows_dense_min_sv) {
+        const int nset = (int)binom64(g, L);
+        const size_t stride = (size_t)nset << wL;
+        const size_t tile = (size_t)rows_gemm_tile_sv();
+        const size_t nsv_pad = ((size_t)n_sv + tile - 1) / tile * tile;
+        if (l.size + nsv_pad * stride <= ctx->budget && hipMalloc(&R->D, nsv_pad * stride) == hipSuccess &&
+            hipMalloc(&dflag, (size_t)n_sv * 4) == hipSuccess) {
+            R->dense_level = L;
+            R->dense_w = wL;
+            R->dense_nset = nset;
+            R->dense_stride = stride;
+            R->dense_rm = mem + o_rm + res_mask_size() * (size_t)lf[(size_t)L];
+            if (launch_fill_u32(dflag, (size_t)n_sv, 0u, st) != hipSuccess ||
+                launch_count_rows(jp.dev.key, jp.dev.gstart, n_sv, R->dense_rm, nset, wL, R->D, stride, dflag, st) !=
+                    hipSuccess) {
+                (void)hipFree(dflag);
+                set_error("count-row launch failed");
+                return fail(GAKCO_EHIP);
+            }
+        } else {
+            (void)hipGetLastError();  // no room: the level stays on the sparse walk
+            if (R->D) (void)hipFree(R->D);
+            R->D = nullptr;
+        }
+    }
+    if ((s = plan_check_errors(ctx, p, st)) != GAKCO_OK) {
+        if (dflag) (void)hipFree(dflag);
+        return fail(s);
+    }
+    if (dflag) {
+        std::vector<uint32_t> fl((size_t)n_sv);
+        const hipError_t e = hipMemcpy(fl.data(), dflag, (size_t)n_sv * 4, hipMemcpyDeviceToHost);
+        (void)hipFree(dflag);
+        if (e != hipSuccess) { set_error("count-row flags: %s", hipGetErrorString(e)); return fail(GAKCO_EHIP); }
+        bool over = false;
+        for (uint32_t f : fl) over |= f != 0;
+        if (over) {  // a count above 127: the level stays on the sparse walk
+            (void)hipFree(R->D);
+            R->D = nullptr;
+            R->dense_level = -1;
+        }
+    }
+    if (R->D) R->bytes += ((size_t)n_sv + rows_gemm_tile_sv() - 1) / rows_gemm_tile_sv() * rows_gemm_tile_sv() * R->dense_stride;
     (void)hipStreamDestroy(st);
     *out = R;
     return GAKCO_OK;
@@ -490,10 +574,11 @@ gakco_status gakco_resident_create(gakco_ctx *ctx, const int8_t *seqs, const int
 void gakco_resident_destroy(gakco_resident *R)
 {
     if (!R) return;
-    if (R->mem) {
+    if (R->mem || R->D) {
         (void)hipSetDevice(R->device);
         (void)hipDeviceSynchronize();
-        (void)hipFree(R->mem);
+        if (R->mem) (void)hipFree(R->mem);
+        if (R->D) (void)hipFree(R->D);
     }
     delete R;
 }

@@ -74,6 +74,45 @@ def test_rows_query_diagonal_paths(gk, case):
         res.close()
 
 
+@pytest.mark.parametrize("case", ["dense", "query_over_127", "resident_over_127"])
+def test_rows_dense_top_level(case):
+    """The top level (m = 4: 4096 reduced 6-mers per position set) joined as
+    an int8 product of count rows: the same rows as the oracle.  A query with
+    a count above 127 at that level (a constant query) takes it through the
+    sparse walk; a resident set with such a count keeps the level sparse."""
+    from oracle import oracle as orc
+    from paper_1704_07468_amd import gakco
+    ctx = gakco.Context(0, tune={"rows_dense_min_sv": 1, "rows_dense_min_q": 1})
+    ctx.set_param("profile", 1)
+    s = wl.serving_resident(n_sv=70, seed=wl.SEED_BASE + 51)
+    sv_seqs, sv_lens = s.sv.seqs, s.sv.lens
+    if case == "resident_over_127":
+        sv_seqs = np.concatenate([sv_seqs, np.zeros(300, np.int8)])
+        sv_lens = np.concatenate([sv_lens, np.array([300], np.int32)])
+    alpha = np.resize(s.alpha, len(sv_lens))
+    res = gakco.Resident(ctx, sv_seqs, sv_lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=alpha, bias=0.3)
+    try:
+        q_seqs, q_lens = wl.serving_queries(9, lmin=5, lmax=400)
+        if case == "query_over_127":
+            q_seqs = np.concatenate([q_seqs, np.zeros(280, np.int8)])
+            q_lens = np.concatenate([q_lens, np.array([280], np.int32)])
+        ctx.profile_reset()
+        r = res.rows(q_seqs, q_lens, want_nm=True)
+        gemm = ctx.profile().get("rows_gemm", (0.0, 0))[1]
+        assert (gemm > 0) == (case != "resident_over_127"), gemm
+        o = orc.rows(sv_seqs, sv_lens, q_seqs, q_lens, s.sv.g, s.sv.k, alpha=alpha, bias=0.3)
+        np.testing.assert_array_equal(r["Nm"].cpu().numpy(), o["Nm"])
+        K = r["K"].cpu().numpy()
+        assert (K[o["Krows"] == 0] == 0).all()
+        nz = o["Krows"] != 0
+        np.testing.assert_allclose(K[nz], o["Krows"][nz], rtol=1e-12, atol=0)
+        tol = 1e-12 * (np.abs(alpha)[None, :] * np.abs(o["Krows"])).sum(axis=1) + 1e-15
+        assert (np.abs(r["decision"].cpu().numpy() - o["decision"]) <= tol).all()
+    finally:
+        res.close()
+        ctx.close()
+
+
 def test_rows_protein_resident(gk):
     """A protein resident set (5-bit symbols, skewed composition)."""
     from oracle import oracle as orc
