@@ -55,7 +55,7 @@ hipError_t launch_count_rows(const uint64_t *key, const uint32_t *gstart, int ns
                              int8_t *out, size_t stride, uint32_t *flag, hipStream_t st);
 hipError_t launch_rows_gemm(const int8_t *Q, const int8_t *D, size_t stride, int nq, int nsv, int S, const uint32_t *qflag,
                             uint32_t *C, hipStream_t st);
-int rows_gemm_tile_q();
+int rows_gemm_tile_q(int nq);
 int rows_gemm_tile_sv();
 hipError_t launch_rows(const uint64_t *qkey, const uint32_t *qgstart, int nq, int M, int nsv, int slab, int mchunk,
                        int nitems, const void *rm, const int32_t *lev_first, const int32_t *lev_count, uint32_t *C,

@@ -38,7 +38,7 @@ struct gakco_ctx {
     int rows_slabs = 0;      // resident slabs of the serving rows kernel (0: halves of 4096..16384 sequences)
     int rows_dense = 1;      // 1: join the resident set's top level on the matrix cores when it qualifies
     int rows_dense_min_sv = 2048;  // ... for resident sets of at least this many sequences
-    int rows_dense_min_q = 72;     // ... and query batches of at least this many queries
+    int rows_dense_min_q = 56;     // ... and query batches of at least this many queries
     int direct_mode = 1;     // direct-address levels: 0 off, 1 where the cost model prefers them, 2 wherever possible
     uint32_t excess_cap = 0; // cap on the clipped-count list (0: kExcessCap), for tests
     int chunk_masks = 0;     // cap on position sets per chunk (0: as many as the pool holds)

@@ -337,7 +337,6 @@ __global__ __launch_bounds__(kThreads) void k_count_rows(const uint64_t *__restr
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
-constexpr int kGemmBM = 256;  // queries per block (every query of a 256-batch)
 constexpr int kGemmBN = 128;  // resident sequences per block
 constexpr int kGemmBK = 64;   // count columns per step
 constexpr int kGemmRow = kGemmBK + 16;  // padded LDS row (80 bytes: 16-byte reads without conflicts)
@@ -356,15 +355,18 @@ struct RowsGemmArgs {
 // v_mfma_i32_32x32x32_i8 layout as in the Gram products: lane l supplies row
 // (l % 32) and 16 consecutive columns from 16 * (l / 32); accumulator v of
 // lane l is element (8 (v / 4) + 4 (l / 32) + v % 4, l % 32).  One block =
-// 256 queries x 128 resident sequences x one split of the columns; blocks
-// are ordered split-major so that the blocks running together share the
-// query slab in L2 while every resident row is streamed from HBM once per
-// query tile.  Wave w computes queries [64 w, 64 w + 64) as 2 x 4 MFMA
-// tiles; slabs are double-buffered through LDS with 16-byte loads, two
-// steps in flight.
+// BM queries (256, or 128 for smaller batches) x 128 resident sequences x
+// one split of the columns; blocks are ordered split-major so that the
+// blocks running together share the query slab in L2 while every resident
+// row is streamed from HBM once per query tile.  Wave w computes queries
+// [w BM/4, (w + 1) BM/4) as (BM/128) x 4 MFMA tiles; slabs are
+// double-buffered through LDS with 16-byte loads, two steps in flight.
+template <int BM>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_rows_gemm(RowsGemmArgs A)
 {
-    __shared__ __attribute__((aligned(16))) int8_t sA[2][kGemmBM][kGemmRow];
+    constexpr int WR = BM / kWaves;  // query rows per wave
+    constexpr int MT = WR / 32;      // MFMA row tiles per wave
+    __shared__ __attribute__((aligned(16))) int8_t sA[2][BM][kGemmRow];
     __shared__ __attribute__((aligned(16))) int8_t sB[2][kGemmBN][kGemmRow];
     const int per_split = A.ntq * A.ntsv;
     const int sp = (int)blockIdx.x / per_split;
@@ -377,40 +379,40 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     if (c0 >= c1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = tid >> 2, lc = (tid & 3) * 16;  // staging: rows lr + 64 j, 16-byte column lc
-    const gptr<const int8_t> ga = glb(A.Q) + (size_t)(I * kGemmBM + lr) * A.stride + lc;
+    const gptr<const int8_t> ga = glb(A.Q) + (size_t)(I * BM + lr) * A.stride + lc;
     const gptr<const int8_t> gb = glb(A.D) + (size_t)(J * kGemmBN + lr) * A.stride + lc;
     const size_t s64 = (size_t)64 * A.stride;
     struct Slab {
-        v4i a[kGemmBM / 64], b[kGemmBN / 64];
+        v4i a[BM / 64], b[kGemmBN / 64];
     };
     auto gload = [&](size_t c, Slab &x) {
 #pragma unroll
-        for (int j = 0; j < kGemmBM / 64; ++j) x.a[j] = *(gptr<const v4i>)(ga + (size_t)j * s64 + c);
+        for (int j = 0; j < BM / 64; ++j) x.a[j] = *(gptr<const v4i>)(ga + (size_t)j * s64 + c);
 #pragma unroll
         for (int j = 0; j < kGemmBN / 64; ++j) x.b[j] = *(gptr<const v4i>)(gb + (size_t)j * s64 + c);
     };
     auto lstore = [&](int buf, const Slab &x) {
 #pragma unroll
-        for (int j = 0; j < kGemmBM / 64; ++j) *reinterpret_cast<v4i *>(&sA[buf][lr + 64 * j][lc]) = x.a[j];
+        for (int j = 0; j < BM / 64; ++j) *reinterpret_cast<v4i *>(&sA[buf][lr + 64 * j][lc]) = x.a[j];
 #pragma unroll
         for (int j = 0; j < kGemmBN / 64; ++j) *reinterpret_cast<v4i *>(&sB[buf][lr + 64 * j][lc]) = x.b[j];
     };
-    v16i acc[2][kGemmNT];
+    v16i acc[MT][kGemmNT];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < kGemmNT; ++j) acc[i][j] = v16i{};
     const int fr = lane & 31, fk = 16 * (lane >> 5);
     auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < kGemmBK; kk += 32) {
-            v4i a[2], b[kGemmNT];
+            v4i a[MT], b[kGemmNT];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v4i *>(&sA[buf][wave * 64 + 32 * i + fr][kk + fk]);
+            for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const v4i *>(&sA[buf][wave * WR + 32 * i + fr][kk + fk]);
 #pragma unroll
             for (int j = 0; j < kGemmNT; ++j) b[j] = *reinterpret_cast<const v4i *>(&sB[buf][32 * j + fr][kk + fk]);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < MT; ++i)
 #pragma unroll
                 for (int j = 0; j < kGemmNT; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
         }
@@ -440,13 +442,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     }
     const gptr<uint32_t> C = glb(A.C);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < kGemmNT; ++j) {
             const int sv = J * kGemmBN + 32 * j + (lane & 31);
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int q = I * kGemmBM + wave * 64 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int q = I * BM + wave * WR + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 if (q < A.nq && sv < A.nsv && acc[i][j][v] != 0 && !A.qflag[q])
                     g_atomic_add(C + (size_t)q * A.nsv + sv, (uint32_t)acc[i][j][v]);
             }
@@ -463,17 +465,21 @@ hipError_t launch_count_rows(const uint64_t *key, const uint32_t *gstart, int ns
     return hipGetLastError();
 }
 
+// Query tile of a batch of nq queries: 128 up to 128 queries, else 256.
+int rows_gemm_tile_q(int nq) { return nq <= 128 ? 128 : 256; }
+int rows_gemm_tile_sv() { return kGemmBN; }
+
 hipError_t launch_rows_gemm(const int8_t *Q, const int8_t *D, size_t stride, int nq, int nsv, int S, const uint32_t *qflag,
                             uint32_t *C, hipStream_t st)
 {
     if (nq <= 0 || nsv <= 0) return hipSuccess;
-    RowsGemmArgs a{Q, D, stride, nq, nsv, (nq + kGemmBM - 1) / kGemmBM, (nsv + kGemmBN - 1) / kGemmBN, S, qflag, C};
+    const int bm = rows_gemm_tile_q(nq);
+    RowsGemmArgs a{Q, D, stride, nq, nsv, (nq + bm - 1) / bm, (nsv + kGemmBN - 1) / kGemmBN, S, qflag, C};
     const unsigned nb = (unsigned)((size_t)a.ntq * a.ntsv * S);
-    hipLaunchKernelGGL(k_rows_gemm, dim3(nb), dim3(kThreads), 0, st, a);
+    if (bm == 128) hipLaunchKernelGGL(k_rows_gemm<128>, dim3(nb), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_rows_gemm<256>, dim3(nb), dim3(kThreads), 0, st, a);
     return hipGetLastError();
 }
-int rows_gemm_tile_q() { return kGemmBM; }
-int rows_gemm_tile_sv() { return kGemmBN; }
 
 // K(x,x) from the per-level diagonal counters: Eq. 9 then Eq. 7.  The
 // per-level values of up to MM levels stay in registers.

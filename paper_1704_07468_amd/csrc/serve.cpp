@@ -155,7 +155,7 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     // the queries' count rows (padded to the product's query tile) and their
     // clipping flags
     const bool dense = R->D && n_q >= ctx->rows_dense_min_q;
-    const size_t tq = (size_t)rows_gemm_tile_q();
+    const size_t tq = (size_t)rows_gemm_tile_q(n_q);
     const size_t o_Q = dense ? l.take(((size_t)n_q + tq - 1) / tq * tq * R->dense_stride) : 0;
     const size_t o_qf = dense ? l.take((size_t)n_q * 4) : 0;
     char *scr = nullptr;
