@@ -53,6 +53,7 @@ hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int 
                              uint32_t *diag, hipStream_t st);
 hipError_t launch_count_rows(const uint64_t *key, const uint32_t *gstart, int nseq, const void *rm, int nset, int w,
                              int8_t *out, size_t stride, uint32_t *flag, hipStream_t st);
+// S column splits (S <= 0: chosen from the device's resident blocks)
 hipError_t launch_rows_gemm(const int8_t *Q, const int8_t *D, size_t stride, int nq, int nsv, int S, const uint32_t *qflag,
                             uint32_t *C, hipStream_t st);
 int rows_gemm_tile_q(int nq);

@@ -9,6 +9,8 @@
 // g-mers of q this is count_q * count_sv per reduced g-mer, i.e. the q-by-sv
 // entries of Algorithm 1's countAndUpdate.  Rows of C_m then go through
 // Eq. 9, Eq. 7, the cosine normalisation and Eq. 1's decision value.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -285,6 +287,16 @@ hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int 
 // is clipped and flags its sequence: a flagged resident set does not use this
 // path, a flagged query takes the level through the sparse walk instead.
 
+// Count rows are stored in tiles of 128 rows: the 64 columns [64 k, 64 k + 64)
+// of a tile's rows form one contiguous 8 KB block (row-major inside), and a
+// tile's blocks follow in column order, so the matrix-core product streams
+// each operand tile in 8 KB pieces.  Row x, column c lies at this offset
+// (stride = columns per row, a multiple of 64).
+__device__ __forceinline__ size_t count_tile_offset(int x, size_t c, size_t stride)
+{
+    return ((size_t)(x >> 7) * 128u) * stride + (c >> 6) * 8192u + (size_t)(x & 127) * 64u + (c & 63u);
+}
+
 // One block per (sequence, 8 position sets of the level): an LDS histogram of
 // the sequence's reduced g-mers per set, written as its 2^w-byte segment of
 // the count row (16-byte stores).
@@ -311,7 +323,6 @@ __global__ __launch_bounds__(kThreads) void k_count_rows(const uint64_t *__restr
         __syncthreads();
         for (uint32_t t = t0 + tid; t < t1; t += kThreads) atomicAdd(&hist[(uint32_t)compact_key(gk[t], md)], 1u);
         __syncthreads();
-        const gptr<int8_t> row = glb(out) + (size_t)x * stride + (size_t)s * bins;
         for (uint32_t i = (uint32_t)tid * 16u; i < bins; i += kThreads * 16u) {
             uint32_t wv[4];
 #pragma unroll
@@ -328,7 +339,7 @@ __global__ __launch_bounds__(kThreads) void k_count_rows(const uint64_t *__restr
                 }
                 wv[q] = v;
             }
-            *(gptr<u32x4>)(row + i) = u32x4{wv[0], wv[1], wv[2], wv[3]};
+            *(gptr<u32x4>)(glb(out) + count_tile_offset(x, (size_t)s * bins + i, stride)) = u32x4{wv[0], wv[1], wv[2], wv[3]};
         }
         __syncthreads();  // the histogram is reused by the next set
     }
@@ -343,8 +354,8 @@ constexpr int kGemmRow = kGemmBK + 16;  // padded LDS row (80 bytes: 16-byte rea
 constexpr int kGemmNT = kGemmBN / 32;   // MFMA column tiles per wave
 
 struct RowsGemmArgs {
-    const int8_t *Q;         // [nq_pad][stride] query count rows
-    const int8_t *D;         // [nsv_pad][stride] resident count rows
+    const int8_t *Q;         // [nq_pad][stride] query count rows (tiled, count_tile_offset)
+    const int8_t *D;         // [nsv_pad][stride] resident count rows (tiled)
     size_t stride;           // bytes per row (a multiple of kGemmBK)
     int32_t nq, nsv;         // real rows
     int32_t ntq, ntsv, S;    // query tiles, sequence tiles, column splits
@@ -358,7 +369,8 @@ struct RowsGemmArgs {
 // BM queries (256, or 128 for smaller batches) x 128 resident sequences x
 // one split of the columns; blocks are ordered split-major so that the
 // blocks running together share the query slab in L2 while every resident
-// row is streamed from HBM once per query tile.  Wave w computes queries
+// row is streamed from HBM once per query tile, in 8 KB pieces of the tiled
+// layout.  Wave w computes queries
 // [w BM/4, (w + 1) BM/4) as (BM/128) x 4 MFMA tiles; slabs are
 // double-buffered through LDS with 16-byte loads, two steps in flight.
 template <int BM>
@@ -379,23 +391,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     if (c0 >= c1) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = tid >> 2, lc = (tid & 3) * 16;  // staging: rows lr + 64 j, 16-byte column lc
-    const gptr<const int8_t> ga = glb(A.Q) + (size_t)(I * BM + lr) * A.stride + lc;
-    const gptr<const int8_t> gb = glb(A.D) + (size_t)(J * kGemmBN + lr) * A.stride + lc;
-    const size_t s64 = (size_t)64 * A.stride;
-    struct Slab {
-        v4i a[BM / 64], b[kGemmBN / 64];
+    // tiled count rows: row r, step column c (a multiple of 64) at
+    // (r / 128) 128 stride + 128 c + 64 (r % 128)
+    const gptr<const int8_t> ga = glb(A.Q) + (size_t)I * BM * A.stride + lr * 64 + lc;
+    const gptr<const int8_t> gb = glb(A.D) + (size_t)J * kGemmBN * A.stride + lr * 64 + lc;
+    const size_t s128 = (size_t)128 * A.stride;
+    struct SlabA {
+        v4i a[BM / 64];
     };
-    auto gload = [&](size_t c, Slab &x) {
-#pragma unroll
-        for (int j = 0; j < BM / 64; ++j) x.a[j] = *(gptr<const v4i>)(ga + (size_t)j * s64 + c);
-#pragma unroll
-        for (int j = 0; j < kGemmBN / 64; ++j) x.b[j] = *(gptr<const v4i>)(gb + (size_t)j * s64 + c);
+    struct SlabB {
+        v4i b[kGemmBN / 64];
     };
-    auto lstore = [&](int buf, const Slab &x) {
+    auto gload_a = [&](size_t c, SlabA &x) {
 #pragma unroll
-        for (int j = 0; j < BM / 64; ++j) *reinterpret_cast<v4i *>(&sA[buf][lr + 64 * j][lc]) = x.a[j];
+        for (int j = 0; j < BM / 64; ++j) x.a[j] = *(gptr<const v4i>)(ga + (size_t)(j >> 1) * s128 + (j & 1) * 4096 + 128 * c);
+    };
+    auto gload_b = [&](size_t c, SlabB &x) {
 #pragma unroll
-        for (int j = 0; j < kGemmBN / 64; ++j) *reinterpret_cast<v4i *>(&sB[buf][lr + 64 * j][lc]) = x.b[j];
+        for (int j = 0; j < kGemmBN / 64; ++j) x.b[j] = *(gptr<const v4i>)(gb + j * 4096 + 128 * c);
+    };
+    auto lstore = [&](int buf, const SlabA &xa, const SlabB &xb) {
+#pragma unroll
+        for (int j = 0; j < BM / 64; ++j) *reinterpret_cast<v4i *>(&sA[buf][lr + 64 * j][lc]) = xa.a[j];
+#pragma unroll
+        for (int j = 0; j < kGemmBN / 64; ++j) *reinterpret_cast<v4i *>(&sB[buf][lr + 64 * j][lc]) = xb.b[j];
     };
     v16i acc[MT][kGemmNT];
 #pragma unroll
@@ -417,26 +436,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                 for (int j = 0; j < kGemmNT; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
         }
     };
-    // loads past the split's last step re-read that step (never outside the rows)
+    // Step s: its slabs in LDS buffer s % 2; the query slab of step s + 2
+    // (from L2, shared with the split's other blocks) and the resident slab
+    // of step s + 3 (streamed from HBM: one more step in flight) are loaded
+    // into the register slabs that step s - 1 has stored.  Loads past the
+    // split's last step re-read that step (never outside the rows).
     const size_t last = c1 - kGemmBK;
-    Slab x0, x1;
-    gload(c0, x0);
-    gload(min(c0 + kGemmBK, last), x1);
-    lstore(0, x0);
+    auto at = [&](int k) { return min(c0 + (size_t)k * kGemmBK, last); };
+    SlabA a0, a1;
+    SlabB b0, b1, b2, b3;
+    gload_a(at(0), a0);
+    gload_b(at(0), b0);
+    gload_a(at(1), a1);
+    gload_b(at(1), b1);
+    gload_b(at(2), b2);
+    lstore(0, a0, b0);
     __syncthreads();
-    auto step = [&](size_t c, int buf, Slab &ld, const Slab &st) {
-        gload(min(c + 2 * kGemmBK, last), ld);
+    auto step = [&](size_t c, int buf, SlabA &lda, const SlabA &sta, SlabB &ldb, const SlabB &stb) {
+        gload_b(min(c + 3 * kGemmBK, last), ldb);
+        gload_a(min(c + 2 * kGemmBK, last), lda);
         compute(buf);
-        lstore(buf ^ 1, st);
+        lstore(buf ^ 1, sta, stb);
         __syncthreads();
     };
     size_t c = c0;
 #pragma unroll 1
     while (true) {
-        step(c, 0, x0, x1);
+        step(c, 0, a0, a1, b3, b1);
         c += kGemmBK;
         if (c >= c1) break;
-        step(c, 1, x1, x0);
+        step(c, 1, a1, a0, b0, b2);
+        c += kGemmBK;
+        if (c >= c1) break;
+        step(c, 0, a0, a1, b1, b3);
+        c += kGemmBK;
+        if (c >= c1) break;
+        step(c, 1, a1, a0, b2, b0);
         c += kGemmBK;
         if (c >= c1) break;
     }
@@ -469,12 +504,43 @@ hipError_t launch_count_rows(const uint64_t *key, const uint32_t *gstart, int ns
 int rows_gemm_tile_q(int nq) { return nq <= 128 ? 128 : 256; }
 int rows_gemm_tile_sv() { return kGemmBN; }
 
+// Column splits of the product: every block runs about as long, so the
+// launch takes ceil(blocks / resident) rounds of one split's length; the
+// split count minimising rounds / S (the smallest on ties) keeps the last
+// round full.
+static int gemm_splits(const void *kernel, int tiles, size_t stride)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess || ncu <= 0 || per_cu <= 0) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    const long long resident = (long long)ncu * per_cu;
+    const int smax = (int)std::min<size_t>(32, std::max<size_t>(1, stride / kGemmBK));
+    int best = 1;
+    double best_t = 1e30;
+    for (int S = 1; S <= smax; ++S) {
+        const double t = (double)(((long long)tiles * S + resident - 1) / resident) / S;
+        if (t < best_t - 1e-12) {
+            best_t = t;
+            best = S;
+        }
+    }
+    return best;
+}
+
 hipError_t launch_rows_gemm(const int8_t *Q, const int8_t *D, size_t stride, int nq, int nsv, int S, const uint32_t *qflag,
                             uint32_t *C, hipStream_t st)
 {
     if (nq <= 0 || nsv <= 0) return hipSuccess;
     const int bm = rows_gemm_tile_q(nq);
-    RowsGemmArgs a{Q, D, stride, nq, nsv, (nq + bm - 1) / bm, (nsv + kGemmBN - 1) / kGemmBN, S, qflag, C};
+    const int ntq = (nq + bm - 1) / bm, ntsv = (nsv + kGemmBN - 1) / kGemmBN;
+    if (S <= 0)
+        S = gemm_splits(bm == 128 ? reinterpret_cast<const void *>(&k_rows_gemm<128>) : reinterpret_cast<const void *>(&k_rows_gemm<256>),
+                        ntq * ntsv, stride);
+    RowsGemmArgs a{Q, D, stride, nq, nsv, ntq, ntsv, S, qflag, C};
     const unsigned nb = (unsigned)((size_t)a.ntq * a.ntsv * S);
     if (bm == 128) hipLaunchKernelGGL(k_rows_gemm<128>, dim3(nb), dim3(kThreads), 0, st, a);
     else hipLaunchKernelGGL(k_rows_gemm<256>, dim3(nb), dim3(kThreads), 0, st, a);

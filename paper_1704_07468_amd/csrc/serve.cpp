@@ -44,8 +44,9 @@ struct gakco_resident {
     const double *alpha = nullptr;
     double bias = 0.0;
     // the top level joined on the matrix cores (dense_level < 0: none):
-    // count rows [nsv_pad][dense_stride], one 2^dense_w-byte segment per
-    // position set of the level (descriptors at dense_rm)
+    // count rows of nsv_pad sequences x dense_stride columns (128-row tiles
+    // of 8 KB column blocks), one 2^dense_w-column segment per position set
+    // of the level (descriptors at dense_rm)
     int dense_level = -1, dense_w = 0, dense_nset = 0;
     size_t dense_stride = 0;
     const void *dense_rm = nullptr;
@@ -200,10 +201,8 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     GK_PHASE(PH_ROWS, launch_rows(jp.dev.key, jp.dev.gstart, n_q, R->M, R->n_sv, slab, mchunk, nitems, R->rm, R->lev_first,
                                   R->lev_count, C, upd, dense ? R->dense_level : -1, qflag, st));
     if (dense) {
-        // column splits so that the product has about six blocks per CU (two rounds)
-        const size_t tiles = (((size_t)n_q + tq - 1) / tq) * (((size_t)R->n_sv + rows_gemm_tile_sv() - 1) / rows_gemm_tile_sv());
-        const int S = (int)std::max<size_t>(1, std::min<size_t>(R->dense_stride / 64, (1536 + tiles - 1) / tiles));
-        GK_PHASE(PH_ROWS_GEMM, launch_rows_gemm(Q, R->D, R->dense_stride, n_q, R->n_sv, S, qflag,
+        // column splits chosen by the launcher (whole rounds of resident blocks)
+        GK_PHASE(PH_ROWS_GEMM, launch_rows_gemm(Q, R->D, R->dense_stride, n_q, R->n_sv, 0, qflag,
                                                 C + (size_t)R->dense_level * n_q * R->n_sv, st));
     }
     GK_PHASE(PH_ROWS_FINALIZE, launch_rows_finalize(C, n_q, R->n_sv, R->M, R->coef, R->hco, R->Kd, Kq, R->alpha, R->bias, K_rows,
