@@ -96,7 +96,7 @@ const char *gakco_version(void);
  *                   instead of the sparse walk, when the resident set has
  *                   at least "rows_dense_min_sv" sequences (default 2048)
  *                   and no count above 127 at that level, for batches of at
- *                   least "rows_dense_min_q" queries (default 56); the
+ *                   least "rows_dense_min_q" queries (default 28); the
  *                   resident count rows take n_sv * C(g, M) * 2^w bytes of
  *                   device memory; 0 = always the sparse walk
  *   "tau_b<B>_g<G>" dense_tau for jobs with B-bit symbols and this g (as

@@ -38,7 +38,7 @@ struct gakco_ctx {
     int rows_slabs = 0;      // resident slabs of the serving rows kernel (0: halves of 4096..16384 sequences)
     int rows_dense = 1;      // 1: join the resident set's top level on the matrix cores when it qualifies
     int rows_dense_min_sv = 2048;  // ... for resident sets of at least this many sequences
-    int rows_dense_min_q = 56;     // ... and query batches of at least this many queries
+    int rows_dense_min_q = 28;     // ... and query batches of at least this many queries
     int direct_mode = 1;     // direct-address levels: 0 off, 1 where the cost model prefers them, 2 wherever possible
     uint32_t excess_cap = 0; // cap on the clipped-count list (0: kExcessCap), for tests
     int chunk_masks = 0;     // cap on position sets per chunk (0: as many as the pool holds)
@@ -225,11 +225,18 @@ struct Plan {
 };
 
 gakco_status ctx_small_buffer(gakco_ctx *ctx, void **out);
+// Optional ordering of one rows call's device work among others: enter()
+// before its first kernel is queued, leave() once all of its kernels are.
+struct RowsGate {
+    void (*enter)(void *arg, hipStream_t st);
+    void (*leave)(void *arg, hipStream_t st);
+    void *arg;
+};
 // Kernel rows of queries against a resident set (serving join); K_rows row
 // stride ldk (0: the resident set's size).
 gakco_status rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t *q_seqs, const int32_t *q_lens,
                       const int32_t *q_lens_host, int32_t n_q, double *K_rows, int64_t ldk, int64_t *Nm_rows,
-                      double *decision, hipStream_t st);
+                      double *decision, hipStream_t st, const RowsGate *gate = nullptr);
 gakco_status plan_shape(gakco_ctx *ctx, JobPlan &jp, const int32_t *removed_one, int m_one);
 gakco_status plan_layout(gakco_ctx *ctx, Plan &p);
 gakco_status plan_bind(gakco_ctx *ctx, Plan &p, hipStream_t st);  // arena + pointers + descriptor blob

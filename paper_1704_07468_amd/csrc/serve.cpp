@@ -9,8 +9,11 @@
 //
 // The server admits submitted queries into device batches whenever one of
 // its workers is free: each worker owns a context (arena), a HIP stream and
-// staging buffers, so up to n_streams batches are on the device at once and
-// requests arriving meanwhile wait only for the next free worker.  The
+// staging buffers, so up to n_streams batches are in flight at once (the
+// kernels of batches large enough for the dense join in admission order, one
+// batch after another, while the other workers prepare the next batches and
+// copy results back) and requests arriving meanwhile wait only for the next
+// free worker.  The
 // batch size is bounded by max_batch and by the worker's share of the HBM
 // budget.  Every query's result depends only on the query (integer counts
 // exact, per-query fixed-order sums), so it is the same alone and in any mix.
@@ -125,7 +128,7 @@ hipError_t init_rows_attributes(size_t lds);
 
 gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t *q_seqs, const int32_t *q_lens,
                           const int32_t *q_lens_host, int32_t n_q, double *K_rows, int64_t ldk, int64_t *Nm_rows,
-                          double *decision, hipStream_t st)
+                          double *decision, hipStream_t st, const RowsGate *gate)
 {
     if (!R || n_q < 1 || !q_seqs || !q_lens) { set_error("bad arguments"); return GAKCO_EINVAL; }
     Plan p;
@@ -166,6 +169,7 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     GK_TRY(plan_layout(ctx, p));
     GK_TRY(plan_bind(ctx, p, st));
     GK_TRY(plan_upload(p, st));
+    if (gate) gate->enter(gate->arg, st);
     GK_HIP(launch_fill_u32(diag, (size_t)M1 * n_q, 0u, st));
     GK_TRY(plan_launch(ctx, p, st));
     int nitems = 0;
@@ -208,6 +212,7 @@ gakco_status gk::rows_run(gakco_ctx *ctx, const gakco_resident *R, const int8_t 
     GK_PHASE(PH_ROWS_FINALIZE, launch_rows_finalize(C, n_q, R->n_sv, R->M, R->coef, R->hco, R->Kd, Kq, R->alpha, R->bias, K_rows,
                                            ldk, Nm_rows, decision,
                                                            reinterpret_cast<double *>(scr + o_part), st));
+    if (gate) gate->leave(gate->arg, st);
     return plan_check_errors(ctx, p, st);
 }
 
@@ -233,6 +238,7 @@ struct SrvWorker {
     size_t d_cap = 0;
     double *h_out = nullptr;   // pinned K rows + decisions
     size_t h_ocap = 0;
+    hipEvent_t ev = nullptr;   // recorded once a batch's kernels are queued
     std::thread th;
 };
 
@@ -247,6 +253,59 @@ struct gakco_server {
     std::vector<SrvResult> polled;  // results returned by the last poll (their rows stay valid)
     std::vector<SrvWorker> workers;
     bool stop = false;
+    // Batches that take the dense join take tickets in admission order; a
+    // ticketed batch's kernels wait for the previous ticket's
+    // (hipStreamWaitEvent on its worker's event), so such batches run on
+    // the device one after another, each at full speed, while the workers'
+    // host preparation and result copies overlap them.
+    uint64_t next_ticket = 0;  // under mu
+    std::mutex order_mu;
+    std::condition_variable order_cv;
+    uint64_t queued_ticket = 0;  // last ticket whose kernels are queued
+    hipEvent_t queued_ev = nullptr;  // recorded after them (nullptr: none to wait for)
+};
+
+// One batch's place in the device order (ticket 0: unordered).
+struct BatchTurn {
+    gakco_server *S;
+    SrvWorker *W;
+    uint64_t ticket;
+    bool entered = false, left = false;
+    void wait_turn()
+    {
+        std::unique_lock<std::mutex> lk(S->order_mu);
+        S->order_cv.wait(lk, [&] { return S->queued_ticket + 1 == ticket; });
+    }
+    static void enter(void *a, hipStream_t st)
+    {
+        auto *t = static_cast<BatchTurn *>(a);
+        t->wait_turn();
+        hipEvent_t e;
+        {
+            std::lock_guard<std::mutex> lk(t->S->order_mu);
+            e = t->S->queued_ev;
+        }
+        if (e) (void)hipStreamWaitEvent(st, e, 0);
+        t->entered = true;
+    }
+    static void leave(void *a, hipStream_t st)
+    {
+        auto *t = static_cast<BatchTurn *>(a);
+        if (t->left) return;
+        if (!t->entered) t->wait_turn();  // an early failure still passes its turn on
+        const bool rec = t->entered && hipEventRecord(t->W->ev, st) == hipSuccess;
+        {
+            std::lock_guard<std::mutex> lk(t->S->order_mu);
+            if (rec) t->S->queued_ev = t->W->ev;
+            t->S->queued_ticket = t->ticket;
+        }
+        t->S->order_cv.notify_all();
+        t->left = true;
+    }
+    ~BatchTurn()
+    {
+        if (ticket) leave(this, W->st);
+    }
 };
 
 // Worker buffers grow geometrically (and are sized by a warm-up batch when
@@ -282,8 +341,11 @@ static size_t query_bytes(const gakco_resident *R, size_t len, size_t npos)
     return (size_t)(R->M + 1) * R->n_sv * 4 + (size_t)R->n_sv * 8 + 64 + len + ng * 48 * std::min<size_t>(npos, 64);
 }
 
-static gakco_status run_batch(gakco_server *S, SrvWorker &W, std::vector<SrvRequest> &batch, std::vector<SrvResult> &out)
+static gakco_status run_batch(gakco_server *S, SrvWorker &W, std::vector<SrvRequest> &batch, std::vector<SrvResult> &out,
+                              uint64_t ticket)
 {
+    BatchTurn turn{S, &W, ticket};
+    const RowsGate gate{&BatchTurn::enter, &BatchTurn::leave, &turn};
     const gakco_resident *R = S->res;
     const int nq = (int)batch.size();
     size_t tot = 0;
@@ -308,7 +370,8 @@ static gakco_status run_batch(gakco_server *S, SrvWorker &W, std::vector<SrvRequ
     double *dK = reinterpret_cast<double *>(W.d_buf + o_K);
     double *dd = reinterpret_cast<double *>(W.d_buf + o_d);
     const gakco_status s = rows_run(W.ctx, R, reinterpret_cast<int8_t *>(W.d_buf + o_q),
-                                    reinterpret_cast<int32_t *>(W.d_buf + o_l), W.h_lens, nq, dK, 0, nullptr, dd, W.st);
+                                    reinterpret_cast<int32_t *>(W.d_buf + o_l), W.h_lens, nq, dK, 0, nullptr, dd, W.st,
+                                    ticket ? &gate : nullptr);
     if (s != GAKCO_OK && s != GAKCO_ERANGE) return s;
     GK_HIP(hipMemcpyAsync(W.h_out, dK, (size_t)nq * R->n_sv * 8, hipMemcpyDeviceToHost, W.st));
     GK_HIP(hipMemcpyAsync(W.h_out + (size_t)nq * R->n_sv, dd, (size_t)nq * 8, hipMemcpyDeviceToHost, W.st));
@@ -346,7 +409,7 @@ static void warm_worker(gakco_server *S, SrvWorker &W, size_t wbudget, size_t np
         }
     }
     std::vector<SrvResult> out;
-    (void)run_batch(S, W, batch, out);
+    (void)run_batch(S, W, batch, out, 0);
     clear_error();
 }
 
@@ -361,6 +424,7 @@ static void worker_loop(gakco_server *S, int wi)
     while (true) {
         std::vector<SrvRequest> batch;
         std::vector<SrvResult> rejected;
+        uint64_t ticket = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_req.wait(lk, [&] { return S->stop || !S->queue.empty(); });
@@ -383,10 +447,13 @@ static void worker_loop(gakco_server *S, int wi)
                 batch.push_back(std::move(S->queue.front()));
                 S->queue.pop_front();
             }
+            // batches large enough for the dense join fill the device alone
+            // and go in order; smaller ones gain from running side by side
+            if (!batch.empty() && R->D && (int)batch.size() >= W.ctx->rows_dense_min_q) ticket = ++S->next_ticket;
         }
         std::vector<SrvResult> out;
         const double t0 = now_s();
-        gakco_status s = batch.empty() ? GAKCO_OK : run_batch(S, W, batch, out);
+        gakco_status s = batch.empty() ? GAKCO_OK : run_batch(S, W, batch, out, ticket);
         const double t1 = now_s();
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -628,8 +695,9 @@ gakco_status gakco_server_create(const gakco_resident *res, int32_t device, int3
     S->workers.resize((size_t)n_streams);
     for (auto &W : S->workers) {
         gakco_status s = gakco_ctx_create(device, S->budget / (size_t)n_streams, nullptr, &W.ctx);
-        if (s == GAKCO_OK && hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking) != hipSuccess) {
-            set_error("hipStreamCreate failed");
+        if (s == GAKCO_OK && (hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking) != hipSuccess ||
+                              hipEventCreateWithFlags(&W.ev, hipEventDisableTiming) != hipSuccess)) {
+            set_error("hipStreamCreate / hipEventCreate failed");
             s = GAKCO_EHIP;
         }
         if (s == GAKCO_OK && init_rows_attributes(W.ctx->lds_max) != hipSuccess) {
@@ -734,6 +802,7 @@ gakco_status gakco_server_destroy(gakco_server *S)
             (void)hipStreamSynchronize(W.st);
             (void)hipStreamDestroy(W.st);
         }
+        if (W.ev) (void)hipEventDestroy(W.ev);
         if (W.ctx) {
             rows_scratch_release(W.ctx);
             gakco_ctx_destroy(W.ctx);
