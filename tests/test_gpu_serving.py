@@ -197,6 +197,40 @@ def test_server_alone_equals_mix(gk):
         res.close()
 
 
+def test_server_ordered_dense_batches():
+    """Batches large enough for the dense top-level join run on the device
+    in admission order (each waits for the previous one's kernels); a burst
+    that forms such batches on two workers returns the rows and decision
+    values of the synchronous call, bit for bit, and every request ends."""
+    from paper_1704_07468_amd import gakco
+    ctx = gakco.Context(0, tune={"rows_dense_min_sv": 1})
+    s = wl.serving_resident(n_sv=300, seed=wl.SEED_BASE + 57)
+    res = gakco.Resident(ctx, s.sv.seqs, s.sv.lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=s.alpha, bias=0.3)
+    n = 160
+    q_seqs, q_lens = wl.serving_queries(n, lmin=20, lmax=600)
+    qoff = np.concatenate([[0], np.cumsum(q_lens)])
+    srv = gakco.Server(res, max_batch=48, n_streams=2)
+    try:
+        for i in range(n):
+            srv.submit(q_seqs[qoff[i]:qoff[i + 1]], i)
+        got = {}
+        t_end = time.time() + 60
+        while len(got) < n and time.time() < t_end:
+            for r in srv.poll(64, 100000):
+                got[r["tag"]] = r
+        assert len(got) == n
+        assert all(r["status"] == 0 for r in got.values())
+        assert max(r["batch_size"] for r in got.values()) >= 28  # the dense join was taken
+        direct = res.rows(q_seqs, q_lens)
+        for i in range(n):
+            assert np.array_equal(got[i]["K_row"], direct["K"][i].cpu().numpy()), i
+            assert got[i]["decision"] == direct["decision"][i].item(), i
+    finally:
+        srv.close()
+        res.close()
+        ctx.close()
+
+
 def test_server_cancel_and_budget(gk):
     from paper_1704_07468_amd import gakco
     s, res = small_resident(gk, n_sv=200, seed=2)
