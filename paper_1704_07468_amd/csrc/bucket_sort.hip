@@ -696,7 +696,7 @@ __device__ __forceinline__ void segment(const MaskWork &W, uint32_t bucket, uint
                 if (dense && a.gs < n && bit_at(S.cbm, a.gs)) {
                     const uint32_t row = S.slot[cand_slot(S, a.gs)];
                     if (row != 0xFFFFFFFFu) {
-                        if (sid < Nseq && row < dcap) D[(size_t)sid * (size_t)dstride + row] = (int8_t)a.cnt;
+                        if (sid < Nseq && row < dcap) D[tiled_offset(sid, row, dstride)] = (int8_t)a.cnt;
                         y = 0;
                     }
                 }

@@ -169,7 +169,7 @@ struct MaskWork {
     uint32_t *E;      // [T] run entries: sequence | count << sb, grouped, sequence-sorted
     uint2 *info;      // [T] per g-mer: (entry index, entries to group end) for run leaders
     // int8 matrix-core path for groups with many distinct sequences
-    int8_t *D;         // level's count matrix, sequence-major: D[sid * dstride + row] (nullable)
+    int8_t *D;         // level's count matrix, sequence-major, tiled: D[tiled_offset(sid, row, dstride)] (nullable)
     uint32_t *dcount;  // rows used
     uint32_t dcap;     // row capacity
     uint32_t dstride;  // bytes per sequence
@@ -319,6 +319,17 @@ __device__ __forceinline__ void compact_keys(const uint64_t (&key)[Q], uint64_t 
 #pragma unroll
         for (int q = 0; q < Q; ++q) r[q] |= ((key[q] >> src) & msk) << dst;
     }
+}
+
+// int8 count matrices of the matrix-core products (one row of `stride`
+// counts per sequence, stride a multiple of 64) are stored in tiles of 128
+// sequences: columns [64 k, 64 k + 64) of a tile's sequences form one
+// contiguous 8 KB block (sequence-major inside), and a tile's blocks follow
+// in column order, so a product step reads each operand tile as one block.
+// Sequence x, column c lies at this offset.
+__device__ __forceinline__ size_t tiled_offset(uint32_t x, size_t c, size_t stride)
+{
+    return ((size_t)(x >> 7) * 128u) * stride + (c >> 6) * 8192u + (size_t)(x & 127u) * 64u + (c & 63u);
 }
 
 // Rows [r0, r1) of split s of at most S when R rows are used: whole 64-row
@@ -616,7 +627,7 @@ __device__ __forceinline__ void block_segment(KP fk, VP fv, uint32_t n, UP rpos,
         if (dense_on) {
             const uint32_t row = gaux[gi];
             if (row != 0xFFFFFFFFu) {
-                D[(size_t)sid * (size_t)W.dstride + row] = (int8_t)cnt;
+                D[tiled_offset(sid, row, W.dstride)] = (int8_t)cnt;
                 len = 0;
             }
         }

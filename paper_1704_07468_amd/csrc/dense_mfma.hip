@@ -7,8 +7,10 @@
 // and the contribution of all of them is D_m^T D_m.  Counts are <= 127, so
 // int8 operands with int32 accumulation are exact for up to
 // 2^31 / 127^2 = 133144 rows; each split of at most 65536 rows keeps its
-// exact int32 partial tile, and the epilogue adds the splits into C_m.  D is stored sequence-major (Dt[X][r]) so every MFMA operand
-// is 16 contiguous bytes along r.  Only tiles on or above the diagonal are
+// exact int32 partial tile, and the epilogue adds the splits into C_m.  D is
+// stored sequence-major in tiles of 128 sequences (tiled_offset): a step's
+// operand slab of a tile is one contiguous 8 KB block, and every MFMA
+// operand is 16 contiguous bytes along r.  Only tiles on or above the diagonal are
 // computed; the epilogue mirrors the upper triangle.
 #include "common.h"
 #include "launch.h"
@@ -24,7 +26,7 @@ constexpr int kDRow = kDK + 16;       // padded LDS row: 80 bytes keeps 16-byte 
 constexpr uint32_t kDSplitRows = kDenseSplitRows;
 
 struct DenseWork {
-    int8_t *Dt;              // [Npad][stride] counts, zero beyond the used rows
+    int8_t *Dt;              // [Npad][stride] counts (tiled_offset layout), zero beyond the used rows
     const uint32_t *count;   // rows used (device counter)
     uint32_t cap;            // row capacity (<= S * kDSplitRows)
     uint32_t stride;         // bytes per sequence (multiple of kDK, >= cap)
@@ -69,18 +71,20 @@ __global__ __launch_bounds__(kThreads) void k_dense_syrk(const DenseWork *__rest
     const int wx = wave & 1, wy = wave >> 1;
     // staging: thread -> (row, 16-byte column) pairs of the 128 x 64 slabs
     const int lr = tid >> 2, lc = (tid & 3) * 16;  // rows lr and lr + 64
-    const gptr<const int8_t> ga = glb((const int8_t *)W.Dt) + (size_t)(I * kDTile + lr) * W.stride + lc;
-    const gptr<const int8_t> gb = glb((const int8_t *)W.Dt) + (size_t)(J * kDTile + lr) * W.stride + lc;
-    const size_t s64 = (size_t)64 * W.stride;
+    // tiled layout: sequence tile I, 64-row step r at I 128 stride + 128 r,
+    // sequence lr + 64 j of the tile 64 (lr + 64 j) further
+    const gptr<const int8_t> ga = glb((const int8_t *)W.Dt) + (size_t)I * kDTile * W.stride + lr * 64 + lc;
+    const gptr<const int8_t> gb = glb((const int8_t *)W.Dt) + (size_t)J * kDTile * W.stride + lr * 64 + lc;
     // operand slabs of one 64-row step, in registers on their way to LDS
     struct Slab {
         v4i a0, a1, b0, b1;
     };
     auto gload = [&](uint32_t r, Slab &x) {
-        x.a0 = *(gptr<const v4i>)(ga + r);
-        x.a1 = *(gptr<const v4i>)(ga + s64 + r);
-        x.b0 = *(gptr<const v4i>)(gb + r);
-        x.b1 = *(gptr<const v4i>)(gb + s64 + r);
+        const size_t o = (size_t)r * 128u;  // r is a multiple of 64
+        x.a0 = *(gptr<const v4i>)(ga + o);
+        x.a1 = *(gptr<const v4i>)(ga + 4096 + o);
+        x.b0 = *(gptr<const v4i>)(gb + o);
+        x.b1 = *(gptr<const v4i>)(gb + 4096 + o);
     };
     auto lstore = [&](int buf, const Slab &x) {
         *reinterpret_cast<v4i *>(&sA[buf][lr][lc]) = x.a0;
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_dense_clear(const DenseWork *__res
     const size_t total = (size_t)W.N * nv;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < total; i += (size_t)gridDim.x * kThreads) {
         const size_t x = i / nv, q = i - x * nv;
-        *(gptr<v4i>)(glb(W.Dt) + x * W.stride + q * 16) = v4i{0, 0, 0, 0};
+        *(gptr<v4i>)(glb(W.Dt) + tiled_offset((uint32_t)x, q * 16, W.stride)) = v4i{0, 0, 0, 0};
     }
     (void)nwork;
 }

@@ -66,7 +66,9 @@ __global__ __launch_bounds__(kThreads) void k_direct_count(const JobDev *__restr
             if (r < Kp) atomicAdd(&hist[r], 1u);
         }
         __syncthreads();
-        const gptr<int8_t> out = glb(L.D) + (size_t)X * L.stride + W.row0;
+        // X's row segment [row0, row0 + n): 16-byte pieces of the tiled layout
+        // (row0 and Kp are multiples of 16)
+        const gptr<int8_t> D = glb(L.D);
         const uint32_t n = Kp + (W.last ? L.stride - L.R : 0u);
         for (uint32_t i = (uint32_t)tid * 16u; i < n; i += kThreads * 16u) {
             uint32_t wv[4];
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_direct_count(const JobDev *__restr
                 }
                 wv[q] = v;
             }
-            *(gptr<u32x4>)(out + i) = u32x4{wv[0], wv[1], wv[2], wv[3]};
+            *(gptr<u32x4>)(D + tiled_offset(X, (size_t)W.row0 + i, L.stride)) = u32x4{wv[0], wv[1], wv[2], wv[3]};
         }
         __syncthreads();
     }
@@ -113,13 +115,13 @@ __global__ __launch_bounds__(kThreads) void k_direct_excess(const JobDev *__rest
         const uint32_t N = (uint32_t)J.N, r = e.x, Z = e.y;
         const uint64_t eZ = e.z;
         const gptr<uint64_t> C = glb(reinterpret_cast<uint64_t *>(J.C)) + (size_t)L.level * N * N;
-        const gptr<const uint8_t> col = glb((const uint8_t *)L.D) + r;
+        const gptr<const uint8_t> D = glb((const uint8_t *)L.D);
         for (uint32_t Y = threadIdx.x; Y < N; Y += kThreads) {
             if (Y == Z) {
                 g_atomic_add(C + (size_t)Z * N + Z, eZ * (2u * 127u + eZ));
                 continue;
             }
-            const uint64_t a = col[(size_t)Y * L.stride];
+            const uint64_t a = D[tiled_offset(Y, r, L.stride)];
             if (a) g_atomic_add(C + (size_t)min(Y, Z) * N + max(Y, Z), a * eZ);
         }
         for (uint32_t j = i + 1 + threadIdx.x; j < n; j += kThreads) {

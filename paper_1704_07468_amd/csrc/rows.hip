@@ -287,16 +287,6 @@ hipError_t launch_query_diag(const uint64_t *qkey, const uint32_t *qgstart, int 
 // is clipped and flags its sequence: a flagged resident set does not use this
 // path, a flagged query takes the level through the sparse walk instead.
 
-// Count rows are stored in tiles of 128 rows: the 64 columns [64 k, 64 k + 64)
-// of a tile's rows form one contiguous 8 KB block (row-major inside), and a
-// tile's blocks follow in column order, so the matrix-core product streams
-// each operand tile in 8 KB pieces.  Row x, column c lies at this offset
-// (stride = columns per row, a multiple of 64).
-__device__ __forceinline__ size_t count_tile_offset(int x, size_t c, size_t stride)
-{
-    return ((size_t)(x >> 7) * 128u) * stride + (c >> 6) * 8192u + (size_t)(x & 127) * 64u + (c & 63u);
-}
-
 // One block per (sequence, 8 position sets of the level): an LDS histogram of
 // the sequence's reduced g-mers per set, written as its 2^w-byte segment of
 // the count row (16-byte stores).
@@ -339,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_count_rows(const uint64_t *__restr
                 }
                 wv[q] = v;
             }
-            *(gptr<u32x4>)(glb(out) + count_tile_offset(x, (size_t)s * bins + i, stride)) = u32x4{wv[0], wv[1], wv[2], wv[3]};
+            *(gptr<u32x4>)(glb(out) + tiled_offset((uint32_t)x, (size_t)s * bins + i, stride)) = u32x4{wv[0], wv[1], wv[2], wv[3]};
         }
         __syncthreads();  // the histogram is reused by the next set
     }
@@ -354,7 +344,7 @@ constexpr int kGemmRow = kGemmBK + 16;  // padded LDS row (80 bytes: 16-byte rea
 constexpr int kGemmNT = kGemmBN / 32;   // MFMA column tiles per wave
 
 struct RowsGemmArgs {
-    const int8_t *Q;         // [nq_pad][stride] query count rows (tiled, count_tile_offset)
+    const int8_t *Q;         // [nq_pad][stride] query count rows (tiled_offset layout)
     const int8_t *D;         // [nsv_pad][stride] resident count rows (tiled)
     size_t stride;           // bytes per row (a multiple of kGemmBK)
     int32_t nq, nsv;         // real rows
