@@ -116,7 +116,7 @@ constexpr uint32_t kDirectMaxKeys = 16384;
 constexpr int kDirectMasksPerBlock = 1;  // position sets of one level per block of the row writer (more measured slower)
 
 struct DirectLevel {
-    int8_t *D;         // [Ntile][stride] sequence-major counts; rows [0, R) used
+    int8_t *D;         // [Ntile][stride] sequence-major counts (tiled_offset layout); rows [0, R) used
     uint32_t stride;   // bytes per sequence (R rounded up to 64)
     uint32_t R;        // rows: position sets of the level x Kp
     uint32_t Kp;       // rows per position set: sigma^(g-m) rounded up to 16
