@@ -133,28 +133,42 @@ def test_rows_full_resident_full_rows(gk):
     """The 20000-sequence resident set of the serving workload: two whole
     query rows (every N_m and K-hat entry against all 20000 resident
     sequences) and their Eq. 1 decision values against the oracle run now on
-    the host's cores."""
+    the host's cores -- sent alone (the sparse walk over every level) and as
+    two rows of a 256-query batch (the benchmark's batch: the top level
+    joined on the matrix cores with 256-query tiles and column splits)."""
     from oracle import oracle as orc
     from paper_1704_07468_amd import gakco
     s = wl.serving_resident()
     res = gakco.Resident(gk, s.sv.seqs, s.sv.lens, s.sv.sigma, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias)
+    pick = [3, 200]
     try:
-        q_seqs, q_lens = wl.serving_queries(2)
+        qb_seqs, qb_lens = wl.serving_queries(256)
+        qoff = np.concatenate([[0], np.cumsum(qb_lens)])
+        q_seqs = np.concatenate([qb_seqs[qoff[i]:qoff[i + 1]] for i in pick])
+        q_lens = qb_lens[pick]
         print("serving full rows: query lengths", q_lens.tolist(), flush=True)
         r = res.rows(q_seqs, q_lens, want_nm=True)
-        got_nm = r["Nm"].cpu().numpy()
-        K = r["K"].cpu().numpy()
-        dec = r["decision"].cpu().numpy()
+        alone = (r["Nm"].cpu().numpy(), r["K"].cpu().numpy(), r["decision"].cpu().numpy())
+        del r
+        gk.set_param("profile", 1)
+        gk.profile_reset()
+        rb = res.rows(qb_seqs, qb_lens, want_nm=True)
+        assert gk.profile().get("rows_gemm", (0.0, 0))[1] > 0  # the batch took the dense join
+        gk.set_param("profile", 0)
+        batch = (rb["Nm"][:, pick].cpu().numpy(), rb["K"][pick].cpu().numpy(), rb["decision"][pick].cpu().numpy())
+        del rb
     finally:
+        gk.set_param("profile", 0)
         res.close()
     o = orc.rows(s.sv.seqs, s.sv.lens, q_seqs, q_lens, s.sv.g, s.sv.k, alpha=s.alpha, bias=s.bias,
                  threads=orc.host_threads())
-    np.testing.assert_array_equal(got_nm, o["Nm"])
-    assert (K[o["Krows"] == 0] == 0).all()
-    nz = o["Krows"] != 0
-    np.testing.assert_allclose(K[nz], o["Krows"][nz], rtol=1e-12, atol=0)
     tol = 1e-12 * (np.abs(s.alpha)[None, :] * np.abs(o["Krows"])).sum(axis=1) + 1e-15
-    assert (np.abs(dec - o["decision"]) <= tol).all()
+    nz = o["Krows"] != 0
+    for got_nm, K, dec in (alone, batch):
+        np.testing.assert_array_equal(got_nm, o["Nm"])
+        assert (K[o["Krows"] == 0] == 0).all()
+        np.testing.assert_allclose(K[nz], o["Krows"][nz], rtol=1e-12, atol=0)
+        assert (np.abs(dec - o["decision"]) <= tol).all()
 
 
 def test_server_alone_equals_mix(gk):
