@@ -373,6 +373,13 @@ gakco_status gakco_server_submit(gakco_server *srv, const int8_t *q_host, int32_
 gakco_status gakco_server_cancel(gakco_server *srv, uint64_t tag);
 gakco_status gakco_server_poll(gakco_server *srv, gakco_result *out, int32_t max, int32_t *n_out,
                                int32_t wait_us);
+/* Sets a tuning parameter (names and ranges as gakco_ctx_set_param) on every
+ * worker's context, e.g. "rows_dense_min_q" to keep batches below a size on
+ * the sparse walk, which bounds a batch's time at moderate load.  Waits until
+ * no batch is running and admits none meanwhile, so every batch runs with
+ * one setting; queued requests stay queued.  GAKCO_EINVAL for an unknown name
+ * or a value out of range (then no worker is changed). */
+gakco_status gakco_server_set_param(gakco_server *srv, const char *name, int64_t value);
 /* Stops admission, finishes in-flight batches, cancels what is still queued
  * and frees everything. */
 gakco_status gakco_server_destroy(gakco_server *srv);

@@ -253,6 +253,7 @@ struct gakco_server {
     std::vector<SrvResult> polled;  // results returned by the last poll (their rows stay valid)
     std::vector<SrvWorker> workers;
     bool stop = false;
+    int running = 0;  // batches taken and not yet finished (under mu)
     // Batches that take the dense join take tickets in admission order; a
     // ticketed batch's kernels wait for the previous ticket's
     // (hipStreamWaitEvent on its worker's event), so such batches run on
@@ -450,6 +451,7 @@ static void worker_loop(gakco_server *S, int wi)
             // batches large enough for the dense join fill the device alone
             // and go in order; smaller ones gain from running side by side
             if (!batch.empty() && R->D && (int)batch.size() >= W.ctx->rows_dense_min_q) ticket = ++S->next_ticket;
+            if (!batch.empty()) ++S->running;
         }
         std::vector<SrvResult> out;
         const double t0 = now_s();
@@ -468,6 +470,7 @@ static void worker_loop(gakco_server *S, int wi)
                 rr.r.batch_size = (int32_t)batch.size();
                 S->done.push_back(std::move(rr));
             }
+            if (!batch.empty()) --S->running;
         }
         S->cv_done.notify_all();
         S->cv_req.notify_all();
@@ -736,6 +739,19 @@ gakco_status gakco_server_submit(gakco_server *S, const int8_t *q_host, int32_t 
         S->queue.push_back(std::move(r));
     }
     S->cv_req.notify_one();
+    return GAKCO_OK;
+}
+
+gakco_status gakco_server_set_param(gakco_server *S, const char *name, int64_t value)
+{
+    clear_error();
+    if (!S || !name) { set_error("bad arguments"); return GAKCO_EINVAL; }
+    std::unique_lock<std::mutex> lk(S->mu);  // held: no batch is admitted meanwhile
+    S->cv_done.wait(lk, [&] { return S->running == 0; });
+    // the first worker's context validates it (an error changes nothing);
+    // the others, alike, then take it
+    GK_TRY(gakco_ctx_set_param(S->workers[0].ctx, name, value));
+    for (size_t i = 1; i < S->workers.size(); ++i) GK_TRY(gakco_ctx_set_param(S->workers[i].ctx, name, value));
     return GAKCO_OK;
 }
 

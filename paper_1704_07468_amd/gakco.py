@@ -73,6 +73,7 @@ def lib():
                 "gakco_server_submit": ([P, P, i32, ctypes.c_uint64], i32),
                 "gakco_server_cancel": ([P, ctypes.c_uint64], i32),
                 "gakco_server_poll": ([P, P, i32, P, i32], i32),
+                "gakco_server_set_param": ([P, ctypes.c_char_p, i64], i32),
                 "gakco_server_destroy": ([P], i32),
                 "gakco_ctx_stat": ([P, ctypes.c_char_p, P], i32),
                 "gakco_autotune": ([P, P, i32, i32, P, ctypes.c_char_p, sz], i32),
@@ -402,6 +403,10 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().gakco_server_create(resident._h, device, max_batch, n_streams, hbm_budget, ctypes.byref(h)))
         self._h = h
+
+    def set_param(self, name: str, value: int):
+        """A tuning parameter on every worker (waits until no batch runs)."""
+        _check(lib().gakco_server_set_param(self._h, name.encode(), int(value)))
 
     def submit(self, q, tag: int):
         import numpy as np

@@ -239,6 +239,20 @@ def test_server_ordered_dense_batches():
         for i in range(n):
             assert np.array_equal(got[i]["K_row"], direct["K"][i].cpu().numpy()), i
             assert got[i]["decision"] == direct["decision"][i].item(), i
+        # the join switched off on every worker: the same rows from the sparse walk
+        with pytest.raises(gakco.GakcoError):
+            srv.set_param("no_such_param", 1)
+        srv.set_param("rows_dense_min_q", 1 << 20)
+        for i in range(n):
+            srv.submit(q_seqs[qoff[i]:qoff[i + 1]], 1000 + i)
+        again = {}
+        t_end = time.time() + 60
+        while len(again) < n and time.time() < t_end:
+            for r in srv.poll(64, 100000):
+                again[r["tag"] - 1000] = r
+        assert len(again) == n and all(r["status"] == 0 for r in again.values())
+        for i in range(n):
+            assert np.array_equal(again[i]["K_row"], got[i]["K_row"]), i
     finally:
         srv.close()
         res.close()
